@@ -1,0 +1,62 @@
+"""The seeded generators give the same bytes on every machine, and the shapes and
+structure the workloads call for."""
+import hashlib
+import json
+import os
+
+import numpy as np
+
+from workloads import gen
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "inputs_sha256.json")
+
+
+def _d(a):
+    return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()
+
+
+def test_input_digests_match():
+    want = json.load(open(GOLD))
+    for key, dig in want.items():
+        name, seed = key.split("/")
+        if name == "degenerate_int_4096":
+            v = gen.degenerate_int(4096, int(seed))
+        else:
+            v = gen.make(name, int(seed))
+        if isinstance(v, tuple):
+            assert _d(v[0]) == dig["xy"] and _d(v[1]) == dig["offsets"], key
+        else:
+            assert _d(v) == dig["xy"], key
+
+
+def test_planted_structure():
+    xy = gen.make("c2", 201)
+    assert xy.shape == (4096, 2) and xy.dtype == np.float64
+    r = np.abs(xy[:, 1] - (0.7 * xy[:, 0] + 2.0))
+    inl = int((r < 0.3).sum())
+    assert 2253 <= inl <= 2253 + 40  # 55 % inliers plus outliers that land near the line
+    assert np.all(np.abs(xy[:, 0]) <= 10) and np.all(np.abs(xy[:, 1]) <= 20 + 1)
+
+
+def test_degenerate_int_structure():
+    xy = gen.make("c3b", 302)
+    assert xy.shape == (16384, 2)
+    assert np.all(xy == np.round(xy)) and xy.min() >= 0 and xy.max() <= 1023
+    _, counts = np.unique(xy[:, 0], return_counts=True)
+    vertical_pairs = int((counts * (counts - 1) // 2).sum())
+    assert vertical_pairs > 120_000
+    coincident = len(xy) - len(np.unique(xy, axis=0))
+    assert coincident > 0
+
+
+def test_hough_patches_structure():
+    xy, off = gen.hough_patches(500, 9)
+    n = np.diff(off)
+    assert off[0] == 0 and off[-1] == len(xy)
+    assert n.min() >= 32 and n.max() <= 512
+    assert xy.min() >= 0 and xy.max() <= 63 and np.all(xy == np.round(xy))
+
+
+def test_ln_matches_libm():
+    s = np.geomspace(1e-300, 1.0, 20001)
+    assert np.max(np.abs(gen.ln(s) - np.log(s)) / np.abs(np.log(s) + 1e-300)) < 1e-15
