@@ -1,0 +1,176 @@
+"""Throughput of the exact 2D LMS search on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2]
+
+A step is one complete solve (prep, seed evaluation, FP32 screen, FP64
+recheck, finalize) of one point set whose coordinates are already resident in
+HBM. The default workload is the headline one: a planted line with n = 4096
+points, 45 % uniform outliers and h = 2049. That is 8,386,560 candidate pair
+slopes per step. The input is synthetic: the paper's random point sets are not
+published.
+
+Printed as one JSON line: candidate slopes per second (the headline value),
+solves per second, the screen kernel's fraction of the VALU issue peak
+measured with HIP events on the solve's stream, and the CPU oracle timed on a
+bounded sample of the same workload on the host's cores.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "candidate slopes/sec and LMS solves/sec at n=4096; learned vs plain speedup"
+
+# VALU issue peak of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one 32-bit
+# lane-op per lane per clock (packed FP32 is not used).
+VALU_PEAK_LANE_OPS = 256 * 64 * 2.4e9
+# Algorithmic lane-ops per FP32 residual: band test = FMA + |d| <= t compare;
+# one-sided tests = FMA + four compares.
+OPS_BAND, OPS_DIR = 2, 5
+
+
+def parse_args():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3a", "c3b"])
+    ap.add_argument("--seed", type=int, default=None)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="target wall time of the CPU-oracle sample (0 = skip)")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="only run a plain device copy of this size (HBM counter scale)")
+    return ap.parse_args()
+
+
+def cpu_baseline(xy, target_s):
+    """The oracle as it stands, on a random sample of the workload's pairs."""
+    import numpy as np
+    import oracle
+    from workloads.gen import Stream
+
+    n = len(xy)
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
+    st = Stream(99, 990)
+
+    def sample(m):
+        a = st.integers(m, 0, n - 1)
+        b = st.integers(m, 0, n - 2)
+        b = b + (b >= a)
+        return np.stack([a, b], 1)
+
+    probe = max(threads * 8, 64)
+    t = time.perf_counter()
+    oracle.eval_pairs(xy, sample(probe), nthreads=threads)
+    rate = probe / max(time.perf_counter() - t, 1e-6)
+    m = int(min(max(rate * target_s, probe), 5_000_000))
+    t = time.perf_counter()
+    oracle.eval_pairs(xy, sample(m), nthreads=threads)
+    dt = time.perf_counter() - t
+    return {"value": m / dt, "unit": "candidate slopes/s", "cores": threads, "kind": "oracle",
+            "sample": f"{m} random pairs of the same n={n} input, full FP64 sort per pair "
+                      f"({dt:.1f} s wall)"}
+
+
+def main():
+    args = parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the pair range would be split across GPUs; see DESIGN.md).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1510_01041_amd as lms
+    from workloads import gen
+
+    dev = torch.device("cuda:0")
+    if args.calibrate_copy_mib:
+        nb = args.calibrate_copy_mib << 20
+        a = torch.empty(nb // 4, dtype=torch.float32, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(args.steps):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration": "copy", "bytes_read": nb, "bytes_written": nb,
+                          "launches": args.steps}))
+        return
+
+    cfg = gen.CONFIGS[args.workload]
+    seed = cfg["seeds"][0] if args.seed is None else args.seed
+    xy = gen.make(args.workload, seed)
+    n = len(xy)
+    h = gen.default_h(n)
+    pairs = n * (n - 1) // 2
+    d = torch.from_numpy(xy).to(dev)
+    out = torch.empty(lms.RESULT_BYTES, dtype=torch.uint8, device=dev)
+
+    for _ in range(args.warmup):
+        lms.solve_async(d, 0, out)
+    torch.cuda.synchronize()
+    first = lms.parse(out)
+    if first.status < 0:
+        raise SystemExit(f"solve failed: {lms.status_str(first.status)}")
+
+    lms.profile_begin()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        lms.solve_async(d, 0, out)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    n_prof, stage_ms = lms.profile_end()
+    r = lms.parse(out)
+
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    screen_ms = stage_ms["screen"] / max(n_prof, 1)
+    ops = OPS_BAND * r.point_evals + OPS_DIR * r.dir_evals
+    achieved = ops / (screen_ms * 1e-3)
+
+    parity = "not checked"
+    gold_path = os.path.join(ROOT, "tests", "golden", "oracle_results.json")
+    if os.path.exists(gold_path):
+        g = json.load(open(gold_path)).get(f"{args.workload}/{seed}")
+        if g:
+            same = (r.width == float.fromhex(g["width"]) and r.theta1 == float.fromhex(g["theta1"]))
+            parity = "bitwise equal to stored oracle" if same else \
+                f"MISMATCH vs stored oracle width {float.fromhex(g['width'])!r}"
+
+    line = {
+        "metric": METRIC,
+        "value": pairs / (ms_step * 1e-3),
+        "unit": "candidate slopes/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 screen, f64 recheck", "data": "synthetic",
+        "config": {"workload": f"{args.workload}: " + (
+            f"planted line y=0.7x+2+N(0,0.05^2), n={n}, {cfg.get('f_out', 0):.0%} uniform "
+            f"outliers" if cfg["kind"] == "planted" else
+            f"integer points in [0,1023]^2, n={n}, 30% duplicated x"),
+            "n": n, "h": h, "pairs": pairs, "seed": seed},
+        "solves_per_sec": 1e3 / ms_step,
+        "stages_ms_per_solve": {k: v / max(n_prof, 1) for k, v in stage_ms.items()},
+        "roofline": {"bound": "alu", "kernel": "k_screen", "achieved": achieved / 1e12,
+                     "peak": VALU_PEAK_LANE_OPS / 1e12, "unit": "T lane-op/s",
+                     "frac": achieved / VALU_PEAK_LANE_OPS, "traffic": None,
+                     "ops_per_launch": ops},
+        "search": {"survivors": r.survivors, "band_pass": r.band_pass,
+                   "vertical": r.vertical, "band_evals": r.point_evals,
+                   "dir_evals": r.dir_evals,
+                   "evals_per_pair": r.point_evals / max(r.candidates, 1)},
+        "result": {"half_width": r.half_width, "theta1": r.theta1, "theta2": r.theta2,
+                   "parity": parity},
+    }
+    if args.cpu_seconds > 0:
+        line["cpu_baseline"] = cpu_baseline(xy, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

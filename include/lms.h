@@ -1,0 +1,140 @@
+/* Exact 2D least-median-of-squares (LMS) line fitting on AMD Instinct MI355X
+ * (gfx950). C ABI.
+ *
+ * Method: Shapira & Hassner, "GPU-Based Computation of 2D Least Median of
+ * Squares with Applications to Fast and Robust Line Detection", arXiv
+ * 1510.01041.
+ *   - Section 1, Eq. (1): the LMS line y = theta1*x + theta2 minimises the
+ *     median of the squared residuals r_k = y_k - theta1*x_k - theta2.
+ *   - Section 3.1: equivalently, the thinnest vertical slab holding h points;
+ *     the line bisects it.
+ *   - Sections 3.2-3.4 and Algorithm 1: the optimal slope is the slope of a
+ *     pair of points (a vertex of the dual line arrangement), so an exhaustive
+ *     search over all n(n-1)/2 pair slopes is exact.
+ *
+ * Conventions shared by every entry point:
+ *   - Points are n interleaved FP64 pairs (x0, y0, x1, y1, ...), in DEVICE
+ *     memory unless the name says "host". The caller owns every input and
+ *     output buffer. The library owns only a workspace per (device, stream),
+ *     which it grows on demand and releases in lms_shutdown().
+ *   - h is the number of points the slab must hold; h = 0 selects the low
+ *     median floor(n/2) + 1. Valid range: 2 <= h <= n.
+ *   - Supported sizes: 2 <= n <= LMS_MAX_N.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream). All
+ *     device work is enqueued on it. The call returns once the work is
+ *     enqueued; the results are valid after the stream is synchronised.
+ *   - Argument errors are detected on the host before anything is enqueued,
+ *     and return a negative status; lms_last_error() then holds a message.
+ *     Data-dependent conditions (non-finite input, all x equal) are detected
+ *     on the device and reported in the result's `status` field.
+ *   - Calls on different streams may run concurrently. Calls on one stream are
+ *     ordered. The library is thread-safe.
+ */
+#ifndef LMS_H
+#define LMS_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LMS_MAX_N 16384
+
+typedef enum {
+  LMS_OK = 0,
+  LMS_OK_DEGENERATE = 1,  /* all x equal: no pair has a finite slope; theta1 := 0 */
+  LMS_ERR_ARG = -1,       /* bad argument (host check) */
+  LMS_ERR_NONFINITE = -2, /* a coordinate is NaN or infinite (device check) */
+  LMS_ERR_DEVICE = -3,    /* a HIP call failed */
+  LMS_ERR_NOMEM = -4,     /* workspace allocation failed */
+  LMS_ERR_CAPACITY = -5   /* more screen survivors than the workspace holds */
+} lms_status;
+
+/* Result of one solve. 112 bytes, written to device memory by lms_solve.
+ * On a negative status the FP64 fields are NaN. */
+typedef struct lms_result {
+  double theta1;     /* slope of the LMS line (a pair slope; 0 if degenerate) */
+  double theta2;     /* intercept: midpoint of the narrowest window */
+  double half_width; /* w = (z_hi - z_lo)/2; the LMS criterion is w*w */
+  double width;      /* z_hi - z_lo: vertical height of the thinnest slab */
+  double z_lo, z_hi; /* window ends, z = fma(-theta1, x, y) */
+  int32_t pair_i, pair_j; /* a pair (i < j) whose slope attains the result */
+  int32_t status;         /* lms_status */
+  int32_t h;              /* h actually used */
+  uint64_t candidates;    /* non-vertical pairs, n(n-1)/2 - vertical */
+  uint64_t vertical;      /* pairs with x_i == x_j, skipped */
+  uint64_t survivors;     /* pairs the FP32 screen passed to the FP64 check */
+  uint64_t point_evals;   /* FP32 residuals of the band test (FMA + one compare each) */
+  uint64_t dir_evals;     /* FP32 residuals of the one-sided tests (FMA + four compares) */
+  uint64_t band_pass;     /* pairs that passed the band test */
+} lms_result;
+
+/* Flags for lms_options.flags */
+#define LMS_F_NO_PRUNE 1u /* no width bound: the screen keeps every pair whose anchored
+                             window can hold h points at all (slow; for tests) */
+
+typedef struct lms_options {
+  uint32_t struct_size; /* sizeof(lms_options) */
+  uint32_t flags;       /* LMS_F_* */
+  int32_t seed_pairs;   /* random pair slopes evaluated exactly before the screen
+                           to set the initial width bound (default 255; >= 0) */
+  int32_t reserved;
+  const double* d_seed_theta; /* optional device array of extra seed slopes (any
+                                 real values; they only tighten the initial bound) */
+  int64_t n_seed_theta;       /* length of d_seed_theta */
+} lms_options;
+
+/* Exact LMS line of one point set (Eq. (1); Algorithm 1's exhaustive search
+ * over pair slopes).
+ * d_xy: device, n x 2 FP64 interleaved. d_out: device, one lms_result.
+ * opt may be NULL (defaults). The result is bit-identical to the FP64
+ * reference search on the same input: the slab width, slope and window of the
+ * canonical minimiser, ordered by (width, theta1, z_lo). */
+lms_status lms_solve(const double* d_xy, int64_t n, int64_t h, lms_result* d_out,
+                     const lms_options* opt, void* stream);
+
+/* Synchronous convenience: host input, host output. Copies the points to the
+ * device, solves on a library-owned stream and copies the result back. */
+lms_status lms_solve_host(const double* xy, int64_t n, int64_t h, lms_result* out,
+                          const lms_options* opt);
+
+/* F(theta) at m given slopes: for each slope the narrowest window of h
+ * consecutive values of z_k = fma(-theta, x_k, y_k) (the bracelet at that
+ * dual u-coordinate, Section 3.2; Algorithm 1's per-vertex sort and window).
+ * d_theta: device, m FP64. d_out: device, m x 3 FP64 (width, z_lo, z_hi);
+ * among equally narrow windows the lowest. */
+lms_status lms_eval_slopes(const double* d_xy, int64_t n, int64_t h, const double* d_theta,
+                           int64_t m, double* d_out, void* stream);
+
+/* Verdict of the FP32 screen for m given pairs against a width bound W (an
+ * FP64 value that the optimal slab width is known not to exceed). For each
+ * pair (d_pairs[2t], d_pairs[2t+1]), anchored on its first member, writes
+ * d_verdict[t] = 1 if the screen
+ * keeps the pair for the FP64 check, 0 if it proves that no anchored window of
+ * width <= W exists at the pair's slope, 2 if the pair is vertical, -1 if an
+ * index is outside [0, n).
+ * Exposes the pruning test of lms_solve for soundness testing. */
+lms_status lms_screen_pairs(const double* d_xy, int64_t n, int64_t h, double W,
+                            const int32_t* d_pairs, int64_t m, int32_t* d_verdict,
+                            void* stream);
+
+/* Stage timing. Between lms_profile_begin() and lms_profile_end(), every
+ * lms_solve records HIP events on its own stream around its five stages
+ * (prep, seed evaluation, FP32 screen, FP64 recheck, finalize); the events add
+ * no synchronisation. lms_profile_end() waits for those events, writes the
+ * summed milliseconds per stage to ms[0..LMS_NSTAGES) and returns the number
+ * of solves timed (negative status on a HIP error). */
+#define LMS_NSTAGES 5
+void lms_profile_begin(void);
+int64_t lms_profile_end(double* ms);
+
+const char* lms_status_str(int status);
+/* Message for the last failing call on this thread ("" if none). */
+const char* lms_last_error(void);
+/* Frees every cached workspace. Call only when no work is in flight. */
+void lms_shutdown(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,229 @@
+"""Exact 2D least-median-of-squares line search on MI355X (gfx950).
+
+Thin ctypes binding over liblms.so (C ABI in include/lms.h). Every step of
+the search runs in the library's HIP kernels; this module only marshals
+arguments. PyTorch supplies device memory and streams, and the library shares
+torch's HIP runtime. If the library is missing, the call fails: there is no
+CPU fallback.
+
+Method: arXiv 1510.01041, Eq. (1) and Algorithm 1. The LMS line
+y = theta1*x + theta2 minimises the h-th smallest squared residual. It
+bisects the thinnest vertical slab holding h points, and its slope is the
+slope of a pair of points.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblms.so")
+
+LMS_OK, LMS_OK_DEGENERATE = 0, 1
+LMS_ERR_ARG, LMS_ERR_NONFINITE, LMS_ERR_DEVICE, LMS_ERR_NOMEM, LMS_ERR_CAPACITY = -1, -2, -3, -4, -5
+LMS_F_NO_PRUNE = 1
+MAX_N = 16384
+RESULT_BYTES = 112
+
+
+class _Result(ctypes.Structure):
+    _fields_ = [("theta1", ctypes.c_double), ("theta2", ctypes.c_double),
+                ("half_width", ctypes.c_double), ("width", ctypes.c_double),
+                ("z_lo", ctypes.c_double), ("z_hi", ctypes.c_double),
+                ("pair_i", ctypes.c_int32), ("pair_j", ctypes.c_int32),
+                ("status", ctypes.c_int32), ("h", ctypes.c_int32),
+                ("candidates", ctypes.c_uint64), ("vertical", ctypes.c_uint64),
+                ("survivors", ctypes.c_uint64), ("point_evals", ctypes.c_uint64),
+                ("dir_evals", ctypes.c_uint64), ("band_pass", ctypes.c_uint64)]
+
+
+assert ctypes.sizeof(_Result) == RESULT_BYTES
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("flags", ctypes.c_uint32),
+                ("seed_pairs", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("d_seed_theta", ctypes.c_void_p), ("n_seed_theta", ctypes.c_int64)]
+
+
+@dataclass
+class LmsResult:
+    theta1: float
+    theta2: float
+    half_width: float
+    width: float
+    z_lo: float
+    z_hi: float
+    pair_i: int
+    pair_j: int
+    status: int
+    h: int
+    candidates: int
+    vertical: int
+    survivors: int
+    point_evals: int
+    dir_evals: int
+    band_pass: int
+
+
+class LmsError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def load():
+    """Load liblms.so (built by __graft_entry__.build()); raises if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise LmsError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
+    L.lms_solve.argtypes = [vp, i64, i64, vp, ctypes.POINTER(_Options), vp]
+    L.lms_solve.restype = i32
+    L.lms_solve_host.argtypes = [vp, i64, i64, ctypes.POINTER(_Result), ctypes.POINTER(_Options)]
+    L.lms_solve_host.restype = i32
+    L.lms_eval_slopes.argtypes = [vp, i64, i64, vp, i64, vp, vp]
+    L.lms_eval_slopes.restype = i32
+    L.lms_screen_pairs.argtypes = [vp, i64, i64, ctypes.c_double, vp, i64, vp, vp]
+    L.lms_screen_pairs.restype = i32
+    L.lms_status_str.argtypes = [i32]
+    L.lms_status_str.restype = ctypes.c_char_p
+    L.lms_last_error.argtypes = []
+    L.lms_last_error.restype = ctypes.c_char_p
+    L.lms_profile_begin.argtypes = []
+    L.lms_profile_begin.restype = None
+    L.lms_profile_end.argtypes = [ctypes.POINTER(ctypes.c_double)]
+    L.lms_profile_end.restype = ctypes.c_int64
+    L.lms_shutdown.argtypes = []
+    L.lms_shutdown.restype = None
+    _lib = L
+    return L
+
+
+def status_str(s: int) -> str:
+    return load().lms_status_str(s).decode()
+
+
+def last_error() -> str:
+    return load().lms_last_error().decode()
+
+
+def _check(st: int):
+    if st < 0:
+        raise LmsError(f"{status_str(st)}: {last_error()}")
+
+
+def _points(xy: torch.Tensor) -> torch.Tensor:
+    if not (isinstance(xy, torch.Tensor) and xy.is_cuda and xy.dtype == torch.float64
+            and xy.dim() == 2 and xy.shape[1] == 2):
+        raise ValueError("xy must be a CUDA float64 tensor of shape (n, 2)")
+    return xy.contiguous()
+
+
+def _stream(stream) -> int:
+    s = torch.cuda.current_stream() if stream is None else stream
+    return s.cuda_stream
+
+
+def _options(flags=0, seed_pairs=None, seed_theta: torch.Tensor | None = None):
+    o = _Options()
+    o.struct_size = ctypes.sizeof(_Options)
+    o.flags = flags
+    o.seed_pairs = 255 if seed_pairs is None else int(seed_pairs)
+    if seed_theta is not None:
+        if not (seed_theta.is_cuda and seed_theta.dtype == torch.float64 and seed_theta.dim() == 1
+                and seed_theta.is_contiguous()):
+            raise ValueError("seed_theta must be a contiguous CUDA float64 vector")
+        o.d_seed_theta = seed_theta.data_ptr()
+        o.n_seed_theta = seed_theta.numel()
+    return o
+
+
+def parse(raw: torch.Tensor) -> LmsResult:
+    """Decode a 112-byte lms_result (device or host uint8 tensor)."""
+    b = bytes(raw.detach().to("cpu").numpy().tobytes())
+    r = _Result.from_buffer_copy(b)
+    return LmsResult(**{f: getattr(r, f) for f, _ in _Result._fields_})
+
+
+def solve_async(xy: torch.Tensor, h: int = 0, out: torch.Tensor | None = None, *,
+                no_prune: bool = False, seed_pairs: int | None = None,
+                seed_theta: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Enqueue one exact LMS solve; returns the device uint8[112] result buffer."""
+    xy = _points(xy)
+    if out is None:
+        out = torch.empty(RESULT_BYTES, dtype=torch.uint8, device=xy.device)
+    opt = _options(LMS_F_NO_PRUNE if no_prune else 0, seed_pairs, seed_theta)
+    st = load().lms_solve(xy.data_ptr(), xy.shape[0], h, out.data_ptr(), ctypes.byref(opt),
+                          _stream(stream))
+    _check(st)
+    return out
+
+
+def solve(xy: torch.Tensor, h: int = 0, **kw) -> LmsResult:
+    """Exact LMS line of an (n, 2) CUDA float64 point tensor (synchronises)."""
+    return parse(solve_async(xy, h, **kw))
+
+
+def solve_host(xy, h: int = 0) -> LmsResult:
+    """Synchronous solve of a host (n, 2) float64 array via lms_solve_host."""
+    import numpy as np
+    a = np.ascontiguousarray(np.asarray(xy, dtype=np.float64))
+    r = _Result()
+    o = _options()
+    st = load().lms_solve_host(a.ctypes.data, a.shape[0], h, ctypes.byref(r), ctypes.byref(o))
+    res = LmsResult(**{f: getattr(r, f) for f, _ in _Result._fields_})
+    if st < 0 and res.status >= 0:
+        _check(st)
+    return res
+
+
+def eval_slopes(xy: torch.Tensor, theta: torch.Tensor, h: int = 0, stream=None) -> torch.Tensor:
+    """F(theta) per slope: an (m, 3) tensor of (width, z_lo, z_hi)."""
+    xy = _points(xy)
+    theta = theta.to(device=xy.device, dtype=torch.float64).contiguous()
+    out = torch.empty((theta.numel(), 3), dtype=torch.float64, device=xy.device)
+    st = load().lms_eval_slopes(xy.data_ptr(), xy.shape[0], h, theta.data_ptr(), theta.numel(),
+                                out.data_ptr(), _stream(stream))
+    _check(st)
+    return out
+
+
+def screen_pairs(xy: torch.Tensor, pairs: torch.Tensor, W: float, h: int = 0,
+                 stream=None) -> torch.Tensor:
+    """FP32 screen verdicts (1 keep, 0 reject, 2 vertical) for (m, 2) pairs."""
+    xy = _points(xy)
+    pairs = pairs.to(device=xy.device, dtype=torch.int32).contiguous()
+    out = torch.empty(pairs.shape[0], dtype=torch.int32, device=xy.device)
+    st = load().lms_screen_pairs(xy.data_ptr(), xy.shape[0], h, float(W), pairs.data_ptr(),
+                                 pairs.shape[0], out.data_ptr(), _stream(stream))
+    _check(st)
+    return out
+
+
+STAGES = ("prep", "seed", "screen", "recheck", "finalize")
+
+
+def profile_begin():
+    """Start recording HIP events around each solve's stages."""
+    load().lms_profile_begin()
+
+
+def profile_end() -> tuple[int, dict]:
+    """Stop recording; returns (solves timed, {stage: summed ms})."""
+    ms = (ctypes.c_double * len(STAGES))()
+    n = load().lms_profile_end(ms)
+    _check(int(n) if n < 0 else 0)
+    return int(n), {k: ms[i] for i, k in enumerate(STAGES)}
+
+
+def shutdown():
+    if _lib is not None:
+        _lib.lms_shutdown()

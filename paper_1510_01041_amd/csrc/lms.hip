@@ -1,0 +1,1043 @@
+// Exact 2D least-median-of-squares line search for gfx950 (MI355X).
+//
+// Method (arXiv 1510.01041): the LMS line is the bisector of the thinnest
+// vertical slab holding h points (Section 3.1, Eq. (1)); its slope is the
+// slope of some pair of points, a vertex of the dual arrangement (Sections
+// 3.2-3.3), so scanning every pair slope is exact (Algorithm 1, Section 3.4.1).
+//
+// The paper materialises all vertices and fully sorts n dual intercepts per
+// vertex. Here the per-vertex work is a count instead of a sort:
+//
+//   prep      one block: finiteness, centring, FP32 copy, seed pairs.
+//   recheck   one block per entry: FP64 intercepts z = fma(-theta, x, y), a
+//             bitonic sort in LDS and the narrowest-window scan. Runs first on
+//             the seed pairs to give an FP64 width bound W, then on the screen
+//             survivors.
+//   screen    the hot path. Each wavefront takes an anchor point i and 64
+//             partners j at a time; lanes hold the points (registers, plus LDS
+//             beyond 4096 points). For a pair's slope it counts in FP32 how many
+//             points lie within W + tau of the anchor's intercept (one FMA and
+//             one compare per point, ballot + scalar popcount per 64 points),
+//             and rejects the pair as soon as h can no longer be reached. Pairs
+//             that pass both this band test and the anchored one-sided tests
+//             go to the FP64 recheck.
+//   finalize  one block: canonical minimum over all rechecked entries.
+//
+// Soundness of the FP32 screen: tau bounds the FP32 error of every anchored
+// residual against exact arithmetic, and W bounds the optimal width from
+// above. The optimal slab has a pair of points at one edge (equioscillation),
+// so that pair's anchored window of width <= W holds h points and passes the
+// test, reaches the FP64 recheck and gives the same bits as the reference.
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <algorithm>
+#include <array>
+#include <vector>
+#include <map>
+#include <mutex>
+#include <string>
+#include <utility>
+
+#include "lms.h"
+
+namespace {
+
+constexpr unsigned kDegenerate = 0xFFFFFFFFu;  // entry code: slope 0, all x equal
+constexpr int kDefaultSeeds = 255;
+constexpr long long kScreenCap = 1ll << 24;     // survivor slots beyond the seeds
+constexpr int kRegChunks = 64;                  // points per lane kept in VGPRs (max)
+
+// Per-solve state in device memory.
+struct __align__(16) Ctx {
+  int n, h, n_pad, n_seeds;
+  int status, all_x_equal, argminx, argmaxx;
+  double cx, cy;      // centre (midrange) used for the FP32 copy
+  double xh, yh;      // bounds on |x - cx| and |y - cy|
+  double xabs, yabs;  // max |x|, max |y| of the raw input
+  unsigned long long wbound;  // FP64 width bound, as bits (monotone atomicMin)
+  unsigned int n_entries;     // seeds + survivors appended so far
+  unsigned int overflow;
+  unsigned int next_item;
+  unsigned int pad;
+  unsigned long long vertical, screened, band_pass, point_evals, dir_evals, forced;
+};
+
+__device__ __forceinline__ unsigned long long mix64(unsigned long long z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// Smallest float >= v (v finite and >= 0 here; +inf stays +inf).
+__device__ __forceinline__ float f32_up(double v) {
+  float f = (float)v;
+  if ((double)f < v) f = nextafterf(f, INFINITY);
+  return f;
+}
+
+__device__ __forceinline__ float lane_f(float v, int c) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), c));
+}
+__device__ __forceinline__ int lane_i(int v, int c) { return __builtin_amdgcn_readlane(v, c); }
+
+// Upper bound on the exact width at slope theta given its FP64 width w:
+// every z carries at most one rounding of |z| <= yabs + |theta| xabs.
+__device__ __forceinline__ double width_bound(double w, double theta, const Ctx& c) {
+  const double zmax = c.yabs + fabs(theta) * c.xabs;
+  return (w + 4.0 * 0x1p-53 * zmax) * (1.0 + 0x1p-50);
+}
+
+// Bound on |d_fp32 - d_exact| for every anchored residual at slope theta
+// (centred FP32 coordinates, FP32 slope, one FMA; see the derivation above
+// the screen kernel).
+__device__ __forceinline__ double tau_bound(double theta, double xh, double yh) {
+  return 0x1p-24 * (6.25 * yh + 8.25 * fabs(theta) * xh);
+}
+
+// ---------------------------------------------------------------- prep
+
+__global__ __launch_bounds__(1024) void k_prep(const double* __restrict__ xy, int n, int h,
+                                               int n_pad, Ctx* ctx, float2* __restrict__ xy32,
+                                               uint2* __restrict__ entries, int n_seeds,
+                                               unsigned long long seed_key) {
+  __shared__ double s_mn[1024], s_mx[1024], s_my[1024], s_My[1024];
+  __shared__ int s_amn[1024], s_amx[1024], s_fin[1024];
+  const int t = threadIdx.x;
+  double mnx = INFINITY, mxx = -INFINITY, mny = INFINITY, mxy = -INFINITY;
+  int amn = INT_MAX, amx = INT_MAX, fin = 1;
+  for (int k = t; k < n; k += blockDim.x) {
+    const double x = xy[2 * k], y = xy[2 * k + 1];
+    if (!isfinite(x) || !isfinite(y)) fin = 0;
+    if (x < mnx) { mnx = x; amn = k; }
+    if (x > mxx) { mxx = x; amx = k; }
+    mny = fmin(mny, y);
+    mxy = fmax(mxy, y);
+  }
+  s_mn[t] = mnx; s_mx[t] = mxx; s_my[t] = mny; s_My[t] = mxy;
+  s_amn[t] = amn; s_amx[t] = amx; s_fin[t] = fin;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (t < s) {
+      const int u = t + s;
+      if (s_mn[u] < s_mn[t] || (s_mn[u] == s_mn[t] && s_amn[u] < s_amn[t])) {
+        s_mn[t] = s_mn[u]; s_amn[t] = s_amn[u];
+      }
+      if (s_mx[u] > s_mx[t] || (s_mx[u] == s_mx[t] && s_amx[u] < s_amx[t])) {
+        s_mx[t] = s_mx[u]; s_amx[t] = s_amx[u];
+      }
+      s_my[t] = fmin(s_my[t], s_my[u]);
+      s_My[t] = fmax(s_My[t], s_My[u]);
+      s_fin[t] &= s_fin[u];
+    }
+    __syncthreads();
+  }
+  const bool finite = s_fin[0] != 0;
+  const double minx = s_mn[0], maxx = s_mx[0], miny = s_my[0], maxy = s_My[0];
+  const double cx = minx + 0.5 * (maxx - minx), cy = miny + 0.5 * (maxy - miny);
+  if (t == 0) {
+    Ctx c;
+    memset(&c, 0, sizeof(c));
+    c.n = n; c.h = h; c.n_pad = n_pad; c.n_seeds = n_seeds;
+    c.status = finite ? LMS_OK : LMS_ERR_NONFINITE;
+    c.all_x_equal = finite && (minx == maxx);
+    c.argminx = s_amn[0]; c.argmaxx = s_amx[0];
+    c.cx = cx; c.cy = cy;
+    c.xh = fmax(fabs(minx - cx), fabs(maxx - cx)) * (1.0 + 0x1p-40);
+    c.yh = fmax(fabs(miny - cy), fabs(maxy - cy)) * (1.0 + 0x1p-40);
+    c.xabs = fmax(fabs(minx), fabs(maxx));
+    c.yabs = fmax(fabs(miny), fabs(maxy));
+    c.wbound = 0x7FF0000000000000ull;  // +inf
+    c.n_entries = (unsigned)n_seeds;
+    *ctx = c;
+  }
+  if (!finite) return;
+  const float qnan = __int_as_float(0x7FC00000);
+  for (int k = t; k < n_pad; k += blockDim.x) {
+    float2 p = make_float2(qnan, qnan);
+    if (k < n) p = make_float2((float)(xy[2 * k] - cx), (float)(xy[2 * k + 1] - cy));
+    xy32[k] = p;
+  }
+  // Seed entries: the extreme-x pair (never vertical unless all x are equal),
+  // then random pairs from a counter-based SplitMix64 stream.
+  for (int e = t; e < n_seeds; e += blockDim.x) {
+    uint2 p;
+    if (e == 0 && minx == maxx) {
+      p = make_uint2(kDegenerate, kDegenerate);
+    } else if (e == 0) {
+      const int a = s_amn[0], b = s_amx[0];
+      p = make_uint2((unsigned)min(a, b), (unsigned)max(a, b));
+    } else {
+      const unsigned long long r = mix64(seed_key + 0x9E3779B97F4A7C15ull * (unsigned long long)(e + 1));
+      const unsigned a = (unsigned)((r >> 32) % (unsigned long long)n);
+      unsigned b = (unsigned)((r & 0xFFFFFFFFull) % (unsigned long long)(n - 1));
+      if (b >= a) ++b;
+      p = make_uint2(min(a, b), max(a, b));
+    }
+    entries[e] = p;
+  }
+}
+
+// ---------------------------------------------------------------- FP64 window
+
+// Narrowest window of h consecutive values of z_k = fma(-theta, x_k, y_k),
+// k < n, computed by the whole block; z is an LDS array of N2 >= n doubles.
+// Same operation sequence as the reference: fma, full sort, subtraction, and
+// the lowest window among equally narrow ones.
+template <int N2, int NT>
+__device__ void window_f64(const double* __restrict__ xy, int n, int h, double theta, double* z,
+                           unsigned long long* s_w, int* s_s, double* width, double* z_lo,
+                           double* z_hi) {
+  const int t = threadIdx.x;
+  for (int k = t; k < N2; k += NT)
+    z[k] = (k < n) ? fma(-theta, xy[2 * k], xy[2 * k + 1]) : INFINITY;
+  if (t == 0) { *s_w = ~0ull; *s_s = INT_MAX; }
+  __syncthreads();
+  for (int k = 2; k <= N2; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int q = t; q < N2 / 2; q += NT) {
+        const int a = 2 * q - (q & (j - 1));
+        const int b = a + j;
+        const double va = z[a], vb = z[b];
+        const bool up = (a & k) == 0;
+        if ((va > vb) == up) { z[a] = vb; z[b] = va; }
+      }
+      __syncthreads();
+    }
+  }
+  double bw = INFINITY;
+  int bs = INT_MAX;
+  for (int s = t; s + h <= n; s += NT) {
+    const double w = z[s + h - 1] - z[s];
+    if (w < bw) { bw = w; bs = s; }
+  }
+  const unsigned long long bwb = (unsigned long long)__double_as_longlong(bw);
+  atomicMin(s_w, bwb);
+  __syncthreads();
+  if (bs != INT_MAX && bwb == *s_w) atomicMin(s_s, bs);
+  __syncthreads();
+  // No window compares below +inf only if the slope or the data overflow to
+  // NaN; report NaN and read window 0, which always exists.
+  const int s = (*s_s == INT_MAX) ? 0 : *s_s;
+  *width = (*s_s == INT_MAX) ? NAN : __longlong_as_double((long long)*s_w);
+  *z_lo = z[s];
+  *z_hi = z[s + h - 1];
+  __syncthreads();
+}
+
+// One block per entry [begin, min(n_entries, cap)): re-evaluates the pair's
+// slope in FP64. With update_bound, also lowers the width bound.
+template <int N2, int NT>
+__global__ __launch_bounds__(NT) void k_recheck(const double* __restrict__ xy, Ctx* ctx,
+                                                const uint2* __restrict__ entries,
+                                                double4* __restrict__ res, int begin, int cap,
+                                                int update_bound) {
+  __shared__ double z[N2];
+  __shared__ unsigned long long s_w;
+  __shared__ int s_s;
+  const Ctx c = *ctx;
+  if (c.status < 0) return;
+  const unsigned end = min(c.n_entries, (unsigned)cap);
+  for (unsigned e = begin + blockIdx.x; e < end; e += gridDim.x) {
+    const uint2 p = entries[e];
+    double theta = 0.0;
+    if (p.x != kDegenerate) {
+      const double xl = xy[2 * p.x], xr = xy[2 * p.y];
+      if (xl == xr) {
+        if (threadIdx.x == 0) res[e] = make_double4(INFINITY, NAN, NAN, NAN);
+        continue;
+      }
+      theta = (xy[2 * p.y + 1] - xy[2 * p.x + 1]) / (xr - xl);
+    }
+    double w, lo, hi;
+    window_f64<N2, NT>(xy, c.n, c.h, theta, z, &s_w, &s_s, &w, &lo, &hi);
+    if (threadIdx.x == 0) {
+      res[e] = make_double4(w, theta, lo, hi);
+      if (update_bound)
+        atomicMin(&ctx->wbound,
+                  (unsigned long long)__double_as_longlong(width_bound(w, theta, c)));
+    }
+  }
+}
+
+// F(theta) at arbitrary slopes (seed slopes and lms_eval_slopes).
+template <int N2, int NT>
+__global__ __launch_bounds__(NT) void k_eval_slopes(const double* __restrict__ xy, int n, int h,
+                                                    const double* __restrict__ theta, int m,
+                                                    double* __restrict__ out, Ctx* ctx) {
+  __shared__ double z[N2];
+  __shared__ unsigned long long s_w;
+  __shared__ int s_s;
+  if (ctx) {
+    if (ctx->status < 0) return;
+  }
+  for (int e = blockIdx.x; e < m; e += gridDim.x) {
+    const double th = theta[e];
+    double w, lo, hi;
+    window_f64<N2, NT>(xy, n, h, th, z, &s_w, &s_s, &w, &lo, &hi);
+    if (threadIdx.x == 0) {
+      if (out) { out[3 * e] = w; out[3 * e + 1] = lo; out[3 * e + 2] = hi; }
+      if (ctx && isfinite(th))
+        atomicMin(&ctx->wbound, (unsigned long long)__double_as_longlong(width_bound(w, th, *ctx)));
+    }
+  }
+}
+
+// ---------------------------------------------------------------- screen
+//
+// Error bound tau. With u = 2^-24, centred coordinates a_k = x_k - cx (exact),
+// |x32_k - a_k| <= u|a_k| (1 + 2^-29) and the same for y. For a pair (i, j)
+// at exact slope theta the anchored residual is d_k = (y_k - y_i) -
+// theta (x_k - x_i). The kernel evaluates either
+//   (registers) d = fl(fma(-theta32, fl(x32_k - x32_i), fl(y32_k - y32_i))), or
+//   (LDS)       d = fl(fl(fma(-theta32, x32_k, y32_k)) - fl(fma(-theta32, x32_i, y32_i))),
+// with |theta32 - theta| <= u|theta| (1 + 2^-28). Summing the input, shift,
+// slope and FMA roundings gives, for both forms and to first order,
+//   |d - d_k| <= u (6 Yh + 8 |theta| Xh),
+// where Xh, Yh bound |x - cx| and |y - cy|. tau_bound adds a 4 % margin for the
+// higher-order terms. If the exact anchored window [0, W] (or [-W, 0]) holds h
+// points, their FP32 residuals lie in [-tau, W + tau] (or [-W - tau, tau]).
+
+template <int R, bool LDS_PART>
+__device__ __forceinline__ int test_pair(const float (&X)[R], const float (&Y)[R],
+                                         const float2* __restrict__ lds, int nq, float nth,
+                                         float thr, float ta, float nc, int h,
+                                         unsigned long long& evals, unsigned long long& devals,
+                                         unsigned& band) {
+  const int lane = threadIdx.x & 63;
+  const int total = R + (LDS_PART ? nq : 0);  // chunks of 64 points
+  int hits = 0;
+  // Band test: points with |d| <= W + tau.
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const float d = fmaf(nth, X[r], Y[r]);
+    hits += __popcll(__ballot(fabsf(d) <= thr));
+    if ((r & 7) == 7 && r + 1 < total) {
+      if (hits + 64 * (total - r - 1) < h) { evals += 64ull * (r + 1); return 0; }
+    }
+  }
+  if (LDS_PART) {
+    for (int q = 0; q < nq; ++q) {
+      const float2 p = lds[q * 64 + lane];
+      const float d = fmaf(nth, p.x, p.y) + nc;
+      hits += __popcll(__ballot(fabsf(d) <= thr));
+      if ((q & 7) == 7 && q + 1 < nq) {
+        if (hits + 64 * (nq - q - 1) < h) { evals += 64ull * (R + q + 1); return 0; }
+      }
+    }
+  }
+  evals += 64ull * total;
+  if (hits < h) return 0;
+  ++band;
+  // One-sided tests: the window must start or end at the anchor. The slope is
+  // passed through an opaque copy so that the compiler recomputes the
+  // residuals instead of keeping all R of them live from the band test.
+  asm volatile("" : "+v"(nth));
+  int up = 0, dn = 0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const float d = fmaf(nth, X[r], Y[r]);
+    up += __popcll(__ballot(d >= -ta && d <= thr));
+    dn += __popcll(__ballot(d <= ta && d >= -thr));
+    if ((r & 7) == 7 && r + 1 < total) {
+      const int rem = 64 * (total - r - 1);
+      if (up + rem < h && dn + rem < h) { devals += 64ull * (r + 1); return 0; }
+    }
+  }
+  if (LDS_PART) {
+    for (int q = 0; q < nq; ++q) {
+      const float2 p = lds[q * 64 + lane];
+      const float d = fmaf(nth, p.x, p.y) + nc;
+      up += __popcll(__ballot(d >= -ta && d <= thr));
+      dn += __popcll(__ballot(d <= ta && d >= -thr));
+    }
+  }
+  devals += 64ull * total;
+  return (up >= h || dn >= h) ? 1 : 0;
+}
+
+__device__ __forceinline__ void append_entry(Ctx* ctx, uint2* entries, int cap, unsigned lo,
+                                             unsigned hi) {
+  const unsigned idx = atomicAdd(&ctx->n_entries, 1u);
+  if (idx < (unsigned)cap) entries[idx] = make_uint2(lo, hi);
+  else atomicOr(&ctx->overflow, 1u);
+}
+
+// Work item = (anchor i, block of G*64 partner offsets). Partners are
+// j = (i + o) mod n for o = 1..P(i): every unordered pair appears once.
+template <int R, bool LDS_PART>
+__global__ __launch_bounds__(LDS_PART ? 768 : 256, 3) void k_screen(
+    const double* __restrict__ xy, const float2* __restrict__ xy32, Ctx* ctx,
+    uint2* __restrict__ entries, int cap, int G, int ipa, int n_items, int nq) {
+  extern __shared__ float2 lds[];
+  const Ctx c = *ctx;
+  if (c.status != LMS_OK || c.all_x_equal) return;
+  const int n = c.n, h = c.h, lane = threadIdx.x & 63;
+  if (LDS_PART) {
+    for (int k = threadIdx.x; k < nq * 64; k += blockDim.x) lds[k] = xy32[64 * R + k];
+    __syncthreads();
+  }
+  const double W = __longlong_as_double((long long)c.wbound);
+  const int half = n >> 1;
+  unsigned long long n_vert = 0, n_scr = 0, n_evals = 0, n_devals = 0, n_forced = 0;
+  unsigned n_band = 0;
+  for (;;) {
+    int item = 0;
+    if (lane == 0) item = (int)atomicAdd(&ctx->next_item, 1u);
+    item = __shfl(item, 0);
+    if (item >= n_items) break;
+    const int i = item / ipa, blk = item - (item / ipa) * ipa;
+    const float2 pi = xy32[i];
+    // Reload the points for every item: an opaque base pointer keeps the
+    // compiler from hoisting the loads and holding a second register copy.
+    const float2* src = xy32;
+    asm volatile("" : "+s"(src));
+    float X[R], Y[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const float2 p = src[lane + 64 * r];
+      X[r] = p.x - pi.x;
+      Y[r] = p.y - pi.y;
+    }
+    const int P = (n & 1) ? half : (i < half ? half : half - 1);
+    for (int g = 0; g < G; ++g) {
+      const int o = 1 + (blk * G + g) * 64 + lane;
+      const bool valid = o <= P;
+      int j = i + (valid ? o : 1);
+      if (j >= n) j -= n;
+      const int lo = min(i, j), hi = max(i, j);
+      const double xl = xy[2 * lo], yl = xy[2 * lo + 1];
+      const double xr = xy[2 * hi], yr = xy[2 * hi + 1];
+      const bool vert = valid && (xl == xr);
+      const double th = (yr - yl) / (xr - xl);
+      const double tau = tau_bound(th, c.xh, c.yh);
+      const bool force = valid && !vert && !(fabs(th) < 1e30 && tau < 1e30);
+      const bool test = valid && !vert && !force;
+      const float th32 = test ? (float)th : 0.0f;
+      const float thr = test ? f32_up(W + tau) : 0.0f;
+      const float ta = test ? f32_up(tau) : 0.0f;
+      const float nc = test ? -fmaf(-th32, pi.x, pi.y) : 0.0f;
+      n_vert += __popcll(__ballot(vert));
+      n_forced += __popcll(__ballot(force));
+      if (force) append_entry(ctx, entries, cap, (unsigned)lo, (unsigned)hi);
+      unsigned long long m = __ballot(test);
+      n_scr += __popcll(m);
+      while (m) {
+        const int cl = __ffsll((long long)m) - 1;
+        m &= m - 1;
+        const float nth = -lane_f(th32, cl);
+        const int keep = test_pair<R, LDS_PART>(X, Y, lds, nq, nth, lane_f(thr, cl),
+                                                lane_f(ta, cl), lane_f(nc, cl), h, n_evals,
+                                                n_devals, n_band);
+        if (keep && lane == 0)
+          append_entry(ctx, entries, cap, (unsigned)lane_i(lo, cl), (unsigned)lane_i(hi, cl));
+      }
+    }
+  }
+  if (lane == 0) {
+    atomicAdd(&ctx->vertical, n_vert);
+    atomicAdd(&ctx->screened, n_scr);
+    atomicAdd(&ctx->band_pass, (unsigned long long)n_band);
+    atomicAdd(&ctx->point_evals, n_evals);
+    atomicAdd(&ctx->dir_evals, n_devals);
+    atomicAdd(&ctx->forced, n_forced);
+  }
+}
+
+// Verdicts for explicit pairs (lms_screen_pairs): one wavefront per pair,
+// same test as the screen kernel.
+template <int R, bool LDS_PART>
+__global__ __launch_bounds__(LDS_PART ? 768 : 256) void k_screen_pairs(
+    const double* __restrict__ xy, const float2* __restrict__ xy32, const Ctx* ctx, double W,
+    const int* __restrict__ pairs, int m, int* __restrict__ verdict, int nq) {
+  extern __shared__ float2 lds[];
+  const Ctx c = *ctx;
+  if (c.status < 0) return;
+  const int lane = threadIdx.x & 63;
+  if (LDS_PART) {
+    for (int k = threadIdx.x; k < nq * 64; k += blockDim.x) lds[k] = xy32[64 * R + k];
+    __syncthreads();
+  }
+  const int wpb = blockDim.x / 64;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+  for (int t = blockIdx.x * wpb + wave; t < m; t += gridDim.x * wpb) {
+    const int a = pairs[2 * t], b = pairs[2 * t + 1];
+    if (a < 0 || b < 0 || a >= c.n || b >= c.n) {
+      if (lane == 0) verdict[t] = -1;
+      continue;
+    }
+    const int lo = min(a, b), hi = max(a, b);
+    const int i = a;  // anchor on the first member as given
+    const double xl = xy[2 * lo], yl = xy[2 * lo + 1], xr = xy[2 * hi], yr = xy[2 * hi + 1];
+    if (xl == xr) {
+      if (lane == 0) verdict[t] = 2;
+      continue;
+    }
+    const double th = (yr - yl) / (xr - xl);
+    const double tau = tau_bound(th, c.xh, c.yh);
+    if (!(fabs(th) < 1e30 && tau < 1e30)) {
+      if (lane == 0) verdict[t] = 1;
+      continue;
+    }
+    const float2 pi = xy32[i];
+    float X[R], Y[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const float2 p = xy32[lane + 64 * r];
+      X[r] = p.x - pi.x;
+      Y[r] = p.y - pi.y;
+    }
+    const float th32 = (float)th;
+    unsigned long long ev = 0, dev = 0;
+    unsigned bd = 0;
+    // per-pair scalars in SGPRs, as in the screen kernel
+    const int keep = test_pair<R, LDS_PART>(
+        X, Y, lds, nq, lane_f(-th32, 0), lane_f(f32_up(W + tau), 0), lane_f(f32_up(tau), 0),
+        lane_f(-fmaf(-th32, pi.x, pi.y), 0), c.h, ev, dev, bd);
+    if (lane == 0) verdict[t] = keep;
+  }
+}
+
+// ---------------------------------------------------------------- finalize
+
+struct Best {
+  double w, th, lo, hi;
+  unsigned a, b;
+};
+
+__device__ __forceinline__ bool better(const Best& p, const Best& q) {
+  if (p.w != q.w) return p.w < q.w;
+  if (p.th != q.th) return p.th < q.th;
+  if (p.lo != q.lo) return p.lo < q.lo;
+  if (p.a != q.a) return p.a < q.a;
+  return p.b < q.b;
+}
+
+__global__ __launch_bounds__(1024) void k_finalize(Ctx* ctx, const uint2* __restrict__ entries,
+                                                   const double4* __restrict__ res, int cap,
+                                                   lms_result* out) {
+  __shared__ Best sb[1024];
+  const Ctx c = *ctx;
+  const int t = threadIdx.x;
+  Best b = {INFINITY, INFINITY, INFINITY, INFINITY, 0xFFFFFFFFu, 0xFFFFFFFFu};
+  const unsigned end = c.status < 0 ? 0u : min(c.n_entries, (unsigned)cap);
+  for (unsigned e = t; e < end; e += blockDim.x) {
+    const double4 r = res[e];
+    if (!(r.x <= INFINITY) || r.x == INFINITY) continue;  // vertical or NaN
+    const uint2 p = entries[e];
+    const Best q = {r.x, r.y, r.z, r.w, p.x, p.y};
+    if (better(q, b)) b = q;
+  }
+  sb[t] = b;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (t < s && better(sb[t + s], sb[t])) sb[t] = sb[t + s];
+    __syncthreads();
+  }
+  if (t != 0) return;
+  b = sb[0];
+  lms_result o;
+  memset(&o, 0, sizeof(o));
+  o.h = c.h;
+  const unsigned long long pairs = (unsigned long long)c.n * (unsigned long long)(c.n - 1) / 2;
+  int st = c.status;
+  if (st >= 0 && c.overflow) st = LMS_ERR_CAPACITY;
+  if (st >= 0 && c.all_x_equal) st = LMS_OK_DEGENERATE;
+  if (st >= 0 && !(b.w < INFINITY)) st = LMS_ERR_DEVICE;
+  o.status = st;
+  if (st < 0) {
+    o.theta1 = o.theta2 = o.half_width = o.width = o.z_lo = o.z_hi = NAN;
+    o.pair_i = o.pair_j = -1;
+  } else {
+    o.theta1 = b.th;
+    o.theta2 = 0.5 * (b.lo + b.hi);
+    o.width = b.w;
+    o.half_width = 0.5 * b.w;
+    o.z_lo = b.lo;
+    o.z_hi = b.hi;
+    o.pair_i = b.a == kDegenerate ? -1 : (int)b.a;
+    o.pair_j = b.b == kDegenerate ? -1 : (int)b.b;
+  }
+  o.vertical = c.all_x_equal ? pairs : c.vertical;
+  o.candidates = pairs - o.vertical;
+  o.survivors = c.n_entries > (unsigned)c.n_seeds ? c.n_entries - (unsigned)c.n_seeds : 0u;
+  o.point_evals = c.point_evals;
+  o.dir_evals = c.dir_evals;
+  o.band_pass = c.band_pass;
+  *out = o;
+}
+
+// ---------------------------------------------------------------- host side
+
+thread_local std::string g_err;
+
+lms_status fail(lms_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+struct Workspace {
+  void* base = nullptr;
+  size_t bytes = 0;
+};
+
+std::mutex g_mu;
+std::map<std::pair<int, void*>, Workspace> g_ws;
+int g_num_cu = 0;
+
+// Stage timing (lms_profile_begin / lms_profile_end).
+bool g_prof_on = false;
+std::vector<std::array<hipEvent_t, LMS_NSTAGES + 1>> g_prof_events;
+
+struct StageEvents {
+  std::array<hipEvent_t, LMS_NSTAGES + 1> ev{};
+  bool on = false;
+  hipStream_t s = nullptr;
+  int next = 0;
+  void start(hipStream_t stream) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    on = g_prof_on;
+    s = stream;
+    if (!on) return;
+    for (auto& e : ev)
+      if (hipEventCreate(&e) != hipSuccess) { on = false; return; }
+    mark();
+  }
+  void mark() {
+    if (on && next <= LMS_NSTAGES) (void)hipEventRecord(ev[next++], s);
+  }
+  void finish() {
+    if (!on) return;
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (next == LMS_NSTAGES + 1) g_prof_events.push_back(ev);
+    else for (auto& e : ev) (void)hipEventDestroy(e);
+  }
+};
+
+struct Layout {
+  size_t ctx, xy32, entries, res, total;
+};
+
+Layout layout(int n_pad, long long cap) {
+  auto up = [](size_t v) { return (v + 255) & ~size_t(255); };
+  Layout L;
+  L.ctx = 0;
+  L.xy32 = up(sizeof(Ctx));
+  L.entries = L.xy32 + up((size_t)n_pad * sizeof(float2));
+  L.res = L.entries + up((size_t)cap * sizeof(uint2));
+  L.total = L.res + up((size_t)cap * sizeof(double4));
+  return L;
+}
+
+lms_status get_workspace(void* stream, size_t bytes, char** base) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(LMS_ERR_DEVICE, "hipGetDevice failed");
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (g_num_cu == 0) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess)
+      return fail(LMS_ERR_DEVICE, "hipGetDeviceProperties failed");
+    g_num_cu = prop.multiProcessorCount;
+  }
+  Workspace& w = g_ws[{dev, stream}];
+  if (w.bytes < bytes) {
+    if (w.base) {
+      // the old buffer may still be in use by work queued on this stream
+      if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess)
+        return fail(LMS_ERR_DEVICE, "hipStreamSynchronize failed");
+      (void)hipFree(w.base);
+      w.base = nullptr;
+      w.bytes = 0;
+    }
+    if (hipMalloc(&w.base, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(LMS_ERR_NOMEM, "hipMalloc of the workspace failed");
+    }
+    w.bytes = bytes;
+  }
+  *base = (char*)w.base;
+  return LMS_OK;
+}
+
+int next_pow2(int v) {
+  int p = 64;
+  while (p < v) p <<= 1;
+  return p;
+}
+
+// Points per lane kept in VGPRs for the screen: the smallest supported count
+// covering n, or the maximum with the rest in LDS.
+int pick_R(int n) {
+  static const int Rs[] = {1, 2, 4, 8, 16, 24, 32, 48, 64};
+  for (int r : Rs)
+    if (64 * r >= n) return r;
+  return kRegChunks;
+}
+
+template <int N2>
+void launch_recheck_n2(hipStream_t s, int grid, const double* xy, Ctx* ctx, const uint2* e,
+                       double4* res, int begin, int cap, int upd) {
+  constexpr int NT = N2 >= 2048 ? 1024 : 256;
+  hipLaunchKernelGGL((k_recheck<N2, NT>), dim3(grid), dim3(NT), 0, s, xy, ctx, e, res, begin, cap,
+                     upd);
+}
+
+void launch_recheck(hipStream_t s, int n, int grid, const double* xy, Ctx* ctx, const uint2* e,
+                    double4* res, int begin, int cap, int upd) {
+  switch (next_pow2(n)) {
+    case 64: launch_recheck_n2<64>(s, grid, xy, ctx, e, res, begin, cap, upd); break;
+    case 128: launch_recheck_n2<128>(s, grid, xy, ctx, e, res, begin, cap, upd); break;
+    case 256: launch_recheck_n2<256>(s, grid, xy, ctx, e, res, begin, cap, upd); break;
+    case 512: launch_recheck_n2<512>(s, grid, xy, ctx, e, res, begin, cap, upd); break;
+    case 1024: launch_recheck_n2<1024>(s, grid, xy, ctx, e, res, begin, cap, upd); break;
+    case 2048: launch_recheck_n2<2048>(s, grid, xy, ctx, e, res, begin, cap, upd); break;
+    case 4096: launch_recheck_n2<4096>(s, grid, xy, ctx, e, res, begin, cap, upd); break;
+    case 8192: launch_recheck_n2<8192>(s, grid, xy, ctx, e, res, begin, cap, upd); break;
+    default: launch_recheck_n2<16384>(s, grid, xy, ctx, e, res, begin, cap, upd); break;
+  }
+}
+
+template <int N2>
+void launch_eval_n2(hipStream_t s, int grid, const double* xy, int n, int h, const double* th,
+                    int m, double* out, Ctx* ctx) {
+  constexpr int NT = N2 >= 2048 ? 1024 : 256;
+  hipLaunchKernelGGL((k_eval_slopes<N2, NT>), dim3(grid), dim3(NT), 0, s, xy, n, h, th, m, out,
+                     ctx);
+}
+
+void launch_eval(hipStream_t s, int grid, const double* xy, int n, int h, const double* th, int m,
+                 double* out, Ctx* ctx) {
+  switch (next_pow2(n)) {
+    case 64: launch_eval_n2<64>(s, grid, xy, n, h, th, m, out, ctx); break;
+    case 128: launch_eval_n2<128>(s, grid, xy, n, h, th, m, out, ctx); break;
+    case 256: launch_eval_n2<256>(s, grid, xy, n, h, th, m, out, ctx); break;
+    case 512: launch_eval_n2<512>(s, grid, xy, n, h, th, m, out, ctx); break;
+    case 1024: launch_eval_n2<1024>(s, grid, xy, n, h, th, m, out, ctx); break;
+    case 2048: launch_eval_n2<2048>(s, grid, xy, n, h, th, m, out, ctx); break;
+    case 4096: launch_eval_n2<4096>(s, grid, xy, n, h, th, m, out, ctx); break;
+    case 8192: launch_eval_n2<8192>(s, grid, xy, n, h, th, m, out, ctx); break;
+    default: launch_eval_n2<16384>(s, grid, xy, n, h, th, m, out, ctx); break;
+  }
+}
+
+template <int R, bool L>
+hipError_t launch_screen_rl(hipStream_t s, int grid, const double* xy, const float2* xy32,
+                            Ctx* ctx, uint2* e, int cap, int G, int ipa, int n_items, int nq) {
+  const int nt = L ? 768 : 256;
+  const size_t shm = L ? (size_t)nq * 64 * sizeof(float2) : 0;
+  if (L) {
+    (void)hipFuncSetAttribute((const void*)k_screen<R, L>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    (void)hipGetLastError();
+  }
+  hipLaunchKernelGGL((k_screen<R, L>), dim3(grid), dim3(nt), shm, s, xy, xy32, ctx, e, cap, G,
+                     ipa, n_items, nq);
+  return hipGetLastError();
+}
+
+hipError_t launch_screen(hipStream_t s, int R, bool L, int grid, const double* xy,
+                         const float2* xy32, Ctx* ctx, uint2* e, int cap, int G, int ipa,
+                         int n_items, int nq) {
+  if (L) return launch_screen_rl<64, true>(s, grid, xy, xy32, ctx, e, cap, G, ipa, n_items, nq);
+  switch (R) {
+    case 1: return launch_screen_rl<1, false>(s, grid, xy, xy32, ctx, e, cap, G, ipa, n_items, nq);
+    case 2: return launch_screen_rl<2, false>(s, grid, xy, xy32, ctx, e, cap, G, ipa, n_items, nq);
+    case 4: return launch_screen_rl<4, false>(s, grid, xy, xy32, ctx, e, cap, G, ipa, n_items, nq);
+    case 8: return launch_screen_rl<8, false>(s, grid, xy, xy32, ctx, e, cap, G, ipa, n_items, nq);
+    case 16: return launch_screen_rl<16, false>(s, grid, xy, xy32, ctx, e, cap, G, ipa, n_items, nq);
+    case 24: return launch_screen_rl<24, false>(s, grid, xy, xy32, ctx, e, cap, G, ipa, n_items, nq);
+    case 32: return launch_screen_rl<32, false>(s, grid, xy, xy32, ctx, e, cap, G, ipa, n_items, nq);
+    case 48: return launch_screen_rl<48, false>(s, grid, xy, xy32, ctx, e, cap, G, ipa, n_items, nq);
+    default: return launch_screen_rl<64, false>(s, grid, xy, xy32, ctx, e, cap, G, ipa, n_items, nq);
+  }
+}
+
+template <int R, bool L>
+hipError_t launch_pairs_rl(hipStream_t s, const double* xy, const float2* xy32, const Ctx* ctx,
+                           double W, const int* pairs, int m, int* verdict, int nq) {
+  const int nt = L ? 768 : 256;
+  const size_t shm = L ? (size_t)nq * 64 * sizeof(float2) : 0;
+  if (L) {
+    (void)hipFuncSetAttribute((const void*)k_screen_pairs<R, L>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    (void)hipGetLastError();
+  }
+  const int wpb = nt / 64;
+  const int grid = std::max(1, std::min(4096, (m + wpb - 1) / wpb));
+  hipLaunchKernelGGL((k_screen_pairs<R, L>), dim3(grid), dim3(nt), shm, s, xy, xy32, ctx, W,
+                     pairs, m, verdict, nq);
+  return hipGetLastError();
+}
+
+hipError_t launch_pairs(hipStream_t s, int R, bool L, const double* xy, const float2* xy32,
+                        const Ctx* ctx, double W, const int* pairs, int m, int* verdict, int nq) {
+  if (L) return launch_pairs_rl<64, true>(s, xy, xy32, ctx, W, pairs, m, verdict, nq);
+  switch (R) {
+    case 1: return launch_pairs_rl<1, false>(s, xy, xy32, ctx, W, pairs, m, verdict, nq);
+    case 2: return launch_pairs_rl<2, false>(s, xy, xy32, ctx, W, pairs, m, verdict, nq);
+    case 4: return launch_pairs_rl<4, false>(s, xy, xy32, ctx, W, pairs, m, verdict, nq);
+    case 8: return launch_pairs_rl<8, false>(s, xy, xy32, ctx, W, pairs, m, verdict, nq);
+    case 16: return launch_pairs_rl<16, false>(s, xy, xy32, ctx, W, pairs, m, verdict, nq);
+    case 24: return launch_pairs_rl<24, false>(s, xy, xy32, ctx, W, pairs, m, verdict, nq);
+    case 32: return launch_pairs_rl<32, false>(s, xy, xy32, ctx, W, pairs, m, verdict, nq);
+    case 48: return launch_pairs_rl<48, false>(s, xy, xy32, ctx, W, pairs, m, verdict, nq);
+    default: return launch_pairs_rl<64, false>(s, xy, xy32, ctx, W, pairs, m, verdict, nq);
+  }
+}
+
+struct Plan {
+  int n, h, R, nq, n_pad, n_seeds;
+  bool lds;
+  long long cap;
+};
+
+lms_status make_plan(const void* d_xy, int64_t n, int64_t h, Plan* p) {
+  if (!d_xy) return fail(LMS_ERR_ARG, "null point pointer");
+  if (n < 2 || n > LMS_MAX_N)
+    return fail(LMS_ERR_ARG, "n must be in [2, " + std::to_string(LMS_MAX_N) + "]");
+  if (h == 0) h = n / 2 + 1;
+  if (h < 2 || h > n) return fail(LMS_ERR_ARG, "h must be in [2, n]");
+  p->n = (int)n;
+  p->h = (int)h;
+  p->R = pick_R((int)n);
+  p->lds = 64 * p->R < n;
+  p->nq = p->lds ? (int)((n - 64 * p->R + 63) / 64) : 0;
+  p->n_pad = 64 * (p->R + p->nq);
+  return LMS_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- C ABI
+
+extern "C" {
+
+const char* lms_status_str(int s) {
+  switch (s) {
+    case LMS_OK: return "ok";
+    case LMS_OK_DEGENERATE: return "ok (all x equal: slope set to 0)";
+    case LMS_ERR_ARG: return "invalid argument";
+    case LMS_ERR_NONFINITE: return "non-finite coordinate";
+    case LMS_ERR_DEVICE: return "HIP device error";
+    case LMS_ERR_NOMEM: return "out of device memory";
+    case LMS_ERR_CAPACITY: return "survivor list overflow";
+    default: return "unknown status";
+  }
+}
+
+const char* lms_last_error(void) { return g_err.c_str(); }
+
+lms_status lms_solve(const double* d_xy, int64_t n, int64_t h, lms_result* d_out,
+                     const lms_options* opt, void* stream) {
+  g_err.clear();
+  Plan p;
+  lms_status st = make_plan(d_xy, n, h, &p);
+  if (st != LMS_OK) return st;
+  if (!d_out) return fail(LMS_ERR_ARG, "null result pointer");
+  int seeds = kDefaultSeeds;
+  unsigned flags = 0;
+  const double* d_seed_theta = nullptr;
+  int64_t n_seed_theta = 0;
+  if (opt) {
+    if (opt->struct_size < sizeof(lms_options)) return fail(LMS_ERR_ARG, "bad options size");
+    flags = opt->flags;
+    if (opt->seed_pairs < 0) return fail(LMS_ERR_ARG, "seed_pairs must be >= 0");
+    seeds = opt->seed_pairs;
+    d_seed_theta = opt->d_seed_theta;
+    n_seed_theta = opt->n_seed_theta;
+    if (n_seed_theta < 0 || (n_seed_theta > 0 && !d_seed_theta) || n_seed_theta > (1 << 24))
+      return fail(LMS_ERR_ARG, "bad seed slope array");
+  }
+  const long long pairs = (long long)p.n * (p.n - 1) / 2;
+  const bool no_prune = (flags & LMS_F_NO_PRUNE) != 0;
+  if (no_prune && pairs > kScreenCap)
+    return fail(LMS_ERR_ARG, "LMS_F_NO_PRUNE supports at most 2^24 pairs");
+  p.n_seeds = 1 + seeds;
+  const long long screen_cap = std::min(pairs, kScreenCap);
+  p.cap = p.n_seeds + screen_cap;
+  if (p.cap > INT_MAX) return fail(LMS_ERR_ARG, "too many seeds");
+  const Layout L = layout(p.n_pad, p.cap);
+  char* base = nullptr;
+  st = get_workspace(stream, L.total, &base);
+  if (st != LMS_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  Ctx* ctx = (Ctx*)(base + L.ctx);
+  float2* xy32 = (float2*)(base + L.xy32);
+  uint2* entries = (uint2*)(base + L.entries);
+  double4* res = (double4*)(base + L.res);
+  const int cu = g_num_cu > 0 ? g_num_cu : 256;
+
+  StageEvents prof;
+  prof.start(s);
+  hipLaunchKernelGGL(k_prep, dim3(1), dim3(1024), 0, s, d_xy, p.n, p.h, p.n_pad, ctx, xy32,
+                     entries, p.n_seeds, 0x5EEDull + (unsigned long long)p.n * 0x100000001ull);
+  prof.mark();
+  // Seeds: exact FP64 widths of a few pair slopes set the screen's bound.
+  // Without pruning the bound stays +inf and the screen keeps every pair
+  // whose anchored window can hold h points at all.
+  launch_recheck(s, p.n, std::min(p.n_seeds, 4 * cu), d_xy, ctx, entries, res, 0, (int)p.cap,
+                 no_prune ? 0 : 1);
+  if (n_seed_theta > 0 && !no_prune)
+    launch_eval(s, (int)std::min<int64_t>(n_seed_theta, 4 * cu), d_xy, p.n, p.h, d_seed_theta,
+                (int)n_seed_theta, nullptr, ctx);
+  prof.mark();
+  {
+    const int Pmax = p.n / 2;
+    const int batches = (Pmax + 63) / 64;
+    const int G = std::min(4, std::max(1, batches));
+    const int ipa = (batches + G - 1) / G;
+    const long long n_items = (long long)p.n * ipa;
+    const int per_block = p.lds ? 12 : 4;
+    const long long grid_needed = (n_items + per_block - 1) / per_block;
+    const int grid = (int)std::max<long long>(1, std::min<long long>(grid_needed, (long long)cu * (p.lds ? 1 : 3)));
+    hipError_t err = launch_screen(s, p.R, p.lds, grid, d_xy, xy32, ctx, entries, (int)p.cap, G,
+                                   ipa, (int)n_items, p.nq);
+    if (err != hipSuccess) {
+      prof.finish();
+      return fail(LMS_ERR_DEVICE, std::string("screen launch: ") + hipGetErrorString(err));
+    }
+  }
+  prof.mark();
+  launch_recheck(s, p.n, 4 * cu, d_xy, ctx, entries, res, p.n_seeds, (int)p.cap, 0);
+  prof.mark();
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, s, ctx, entries, res, (int)p.cap, d_out);
+  prof.mark();
+  prof.finish();
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return fail(LMS_ERR_DEVICE, std::string("launch: ") + hipGetErrorString(err));
+  return LMS_OK;
+}
+
+lms_status lms_solve_host(const double* xy, int64_t n, int64_t h, lms_result* out,
+                          const lms_options* opt) {
+  g_err.clear();
+  if (!xy || !out) return fail(LMS_ERR_ARG, "null pointer");
+  if (n < 2 || n > LMS_MAX_N) return fail(LMS_ERR_ARG, "n out of range");
+  if (opt && opt->n_seed_theta > 0) return fail(LMS_ERR_ARG, "device seed slopes need lms_solve");
+  hipStream_t s;
+  if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess)
+    return fail(LMS_ERR_DEVICE, "hipStreamCreate failed");
+  double* d_xy = nullptr;
+  lms_result* d_out = nullptr;
+  lms_status st = LMS_OK;
+  if (hipMalloc(&d_xy, (size_t)n * 2 * sizeof(double)) != hipSuccess ||
+      hipMalloc(&d_out, sizeof(lms_result)) != hipSuccess) {
+    st = fail(LMS_ERR_NOMEM, "hipMalloc failed");
+  }
+  if (st == LMS_OK &&
+      hipMemcpyAsync(d_xy, xy, (size_t)n * 2 * sizeof(double), hipMemcpyHostToDevice, s) != hipSuccess)
+    st = fail(LMS_ERR_DEVICE, "hipMemcpy failed");
+  if (st == LMS_OK) st = lms_solve(d_xy, n, h, d_out, opt, s);
+  if (st == LMS_OK &&
+      (hipMemcpyAsync(out, d_out, sizeof(lms_result), hipMemcpyDeviceToHost, s) != hipSuccess ||
+       hipStreamSynchronize(s) != hipSuccess))
+    st = fail(LMS_ERR_DEVICE, "result copy failed");
+  if (st == LMS_OK && out->status < 0) st = (lms_status)out->status;
+  (void)hipStreamSynchronize(s);
+  {
+    // the workspace is keyed by this temporary stream: drop it
+    std::lock_guard<std::mutex> lk(g_mu);
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    auto it = g_ws.find({dev, (void*)s});
+    if (it != g_ws.end()) {
+      (void)hipFree(it->second.base);
+      g_ws.erase(it);
+    }
+  }
+  if (d_xy) (void)hipFree(d_xy);
+  if (d_out) (void)hipFree(d_out);
+  (void)hipStreamDestroy(s);
+  return st;
+}
+
+lms_status lms_eval_slopes(const double* d_xy, int64_t n, int64_t h, const double* d_theta,
+                           int64_t m, double* d_out, void* stream) {
+  g_err.clear();
+  Plan p;
+  lms_status st = make_plan(d_xy, n, h, &p);
+  if (st != LMS_OK) return st;
+  if (m < 0 || m > INT_MAX || (m > 0 && (!d_theta || !d_out)))
+    return fail(LMS_ERR_ARG, "bad slope array");
+  if (m == 0) return LMS_OK;
+  if (g_num_cu == 0) {
+    char* b;
+    st = get_workspace(stream, 256, &b);
+    if (st != LMS_OK) return st;
+  }
+  launch_eval((hipStream_t)stream, (int)std::min<int64_t>(m, 8 * g_num_cu), d_xy, p.n, p.h,
+              d_theta, (int)m, d_out, nullptr);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return fail(LMS_ERR_DEVICE, hipGetErrorString(err));
+  return LMS_OK;
+}
+
+lms_status lms_screen_pairs(const double* d_xy, int64_t n, int64_t h, double W,
+                            const int32_t* d_pairs, int64_t m, int32_t* d_verdict, void* stream) {
+  g_err.clear();
+  Plan p;
+  lms_status st = make_plan(d_xy, n, h, &p);
+  if (st != LMS_OK) return st;
+  if (m < 0 || m > INT_MAX || (m > 0 && (!d_pairs || !d_verdict)))
+    return fail(LMS_ERR_ARG, "bad pair array");
+  if (!(W >= 0.0)) return fail(LMS_ERR_ARG, "W must be >= 0");
+  if (m == 0) return LMS_OK;
+  p.n_seeds = 1;
+  p.cap = 1;
+  const Layout L = layout(p.n_pad, p.cap);
+  char* base = nullptr;
+  st = get_workspace(stream, L.total, &base);
+  if (st != LMS_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  Ctx* ctx = (Ctx*)(base + L.ctx);
+  float2* xy32 = (float2*)(base + L.xy32);
+  uint2* entries = (uint2*)(base + L.entries);
+  hipLaunchKernelGGL(k_prep, dim3(1), dim3(1024), 0, s, d_xy, p.n, p.h, p.n_pad, ctx, xy32,
+                     entries, 1, 0ull);
+  hipError_t err = launch_pairs(s, p.R, p.lds, d_xy, xy32, ctx, W, d_pairs, (int)m, d_verdict, p.nq);
+  if (err != hipSuccess) return fail(LMS_ERR_DEVICE, hipGetErrorString(err));
+  return LMS_OK;
+}
+
+void lms_profile_begin(void) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  for (auto& ev : g_prof_events)
+    for (auto& e : ev) (void)hipEventDestroy(e);
+  g_prof_events.clear();
+  g_prof_on = true;
+}
+
+int64_t lms_profile_end(double* ms) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_prof_on = false;
+  double sum[LMS_NSTAGES] = {0};
+  int64_t count = 0;
+  int64_t st = 0;
+  for (auto& ev : g_prof_events) {
+    if (st == 0 && hipEventSynchronize(ev[LMS_NSTAGES]) != hipSuccess) st = LMS_ERR_DEVICE;
+    for (int k = 0; st == 0 && k < LMS_NSTAGES; ++k) {
+      float t = 0.f;
+      if (hipEventElapsedTime(&t, ev[k], ev[k + 1]) != hipSuccess) st = LMS_ERR_DEVICE;
+      sum[k] += t;
+    }
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    ++count;
+  }
+  g_prof_events.clear();
+  if (ms)
+    for (int k = 0; k < LMS_NSTAGES; ++k) ms[k] = sum[k];
+  return st != 0 ? st : count;
+}
+
+void lms_shutdown(void) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  for (auto& kv : g_ws)
+    if (kv.second.base) (void)hipFree(kv.second.base);
+  g_ws.clear();
+}
+
+}  // extern "C"

@@ -1,0 +1,77 @@
+"""C-ABI checks that need no GPU: the library loads, exports every entry point
+declared in include/*.h, and rejects bad arguments on the host before any
+device work."""
+import ctypes
+import glob
+import os
+import re
+
+import pytest
+
+import paper_1510_01041_amd as lms
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        src = open(h).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", "", src)
+        for m in re.finditer(r"\b(lms_\w+)\s*\(", src):
+            names.add(m.group(1))
+    return sorted(names)
+
+
+def test_headers_declare_entry_points():
+    names = declared_functions()
+    for want in ("lms_solve", "lms_solve_host", "lms_eval_slopes", "lms_screen_pairs",
+                 "lms_status_str", "lms_last_error", "lms_shutdown"):
+        assert want in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = lms.load()
+    missing = [n for n in declared_functions() if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_status_strings():
+    assert lms.status_str(0) == "ok"
+    assert "non-finite" in lms.status_str(-2)
+    assert lms.status_str(12345) == "unknown status"
+
+
+def _solve_raw(ptr, n, h, out, opt=None):
+    L = lms.load()
+    o = opt if opt is not None else lms._options()
+    return L.lms_solve(ptr, n, h, out, ctypes.byref(o), None)
+
+
+def test_argument_errors_are_synchronous():
+    """Bad arguments return LMS_ERR_ARG from the host check, with a message."""
+    fake = 0x1000  # never dereferenced: validation fails first
+    assert _solve_raw(None, 10, 0, fake) == lms.LMS_ERR_ARG
+    assert _solve_raw(fake, 1, 0, fake) == lms.LMS_ERR_ARG
+    assert "n must be" in lms.last_error()
+    assert _solve_raw(fake, lms.MAX_N + 1, 0, fake) == lms.LMS_ERR_ARG
+    assert _solve_raw(fake, 10, 1, fake) == lms.LMS_ERR_ARG
+    assert _solve_raw(fake, 10, 11, fake) == lms.LMS_ERR_ARG
+    assert "h must be" in lms.last_error()
+    assert _solve_raw(fake, 10, 0, None) == lms.LMS_ERR_ARG
+    bad = lms._options()
+    bad.struct_size = 4
+    assert _solve_raw(fake, 10, 0, fake, bad) == lms.LMS_ERR_ARG
+    neg = lms._options(seed_pairs=-1)
+    assert _solve_raw(fake, 10, 0, fake, neg) == lms.LMS_ERR_ARG
+    L = lms.load()
+    assert L.lms_eval_slopes(fake, 10, 0, None, 5, fake, None) == lms.LMS_ERR_ARG
+    assert L.lms_screen_pairs(fake, 10, 0, -1.0, fake, 3, fake, None) == lms.LMS_ERR_ARG
+    assert L.lms_screen_pairs(fake, 10, 0, float("nan"), fake, 3, fake, None) == lms.LMS_ERR_ARG
+
+
+def test_binding_rejects_non_cuda_input():
+    import torch
+    with pytest.raises(ValueError):
+        lms.solve(torch.zeros((10, 2), dtype=torch.float64))

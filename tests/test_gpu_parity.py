@@ -1,0 +1,195 @@
+"""Parity of the HIP path with the CPU oracle, through the C ABI.
+
+Floating-point bar: the slab width must match the oracle's within 1e-9
+relative (zero only as exact zero). The FP64 re-evaluation repeats the
+oracle's operation sequence, so in practice widths, slopes and windows match
+bit for bit; tests assert bitwise equality where the minimiser is unique.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from workloads import gen
+from workloads.gen import Stream, default_h, degenerate_int, planted
+
+pytestmark = pytest.mark.gpu
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "oracle_results.json")
+REL = 1e-9
+
+
+def close(a, b):
+    return abs(a - b) <= REL * max(abs(a), abs(b)) or a == b
+
+
+def dev(xy):
+    return torch.from_numpy(np.ascontiguousarray(xy)).to("cuda:0")
+
+
+def check_against_oracle(gpu, orc, xy, h=0, bitwise=True, **kw):
+    r = gpu.solve(dev(xy), h, **kw)
+    o = orc.solve(xy, h=h)
+    tag = f"n={len(xy)} h={h or default_h(len(xy))}"
+    print(tag, "gpu", r.width, r.theta1, "oracle", o.width, o.theta1, flush=True)
+    assert r.status == o.status, tag
+    assert close(r.width, o.width), (tag, r.width, o.width)
+    if bitwise:
+        assert (r.width, r.theta1, r.z_lo, r.z_hi, r.theta2) == \
+               (o.width, o.theta1, o.z_lo, o.z_hi, o.theta2), tag
+    # the returned line holds h points within its half-width (oracle's check)
+    hth = orc.hth_abs_residual(xy, r.theta1, r.theta2, h)
+    scale = np.abs(xy).max() * (1 + abs(r.theta1))
+    assert abs(hth - r.half_width) <= 1e-9 * max(r.half_width, 1e-300) + 4e-16 * scale, tag
+    assert r.vertical == o.vertical and r.candidates == o.candidates, tag
+    return r, o
+
+
+def test_c1_matches_stored_oracle(gpu):
+    gold = json.load(open(GOLD))
+    for s in (101, 102, 103):
+        g = gold[f"c1/{s}"]
+        r = gpu.solve(dev(gen.make("c1", s)))
+        print("c1", s, r, flush=True)
+        assert r.status == 0
+        assert r.width == float.fromhex(g["width"])
+        assert r.theta1 == float.fromhex(g["theta1"])
+        assert r.theta2 == float.fromhex(g["theta2"])
+        assert r.z_lo == float.fromhex(g["z_lo"]) and r.z_hi == float.fromhex(g["z_hi"])
+        assert r.candidates == g["candidates"]
+
+
+@pytest.mark.parametrize("n", [2, 3, 4, 5, 17, 63, 64, 65, 100, 127, 129, 255, 257, 500,
+                               1000, 1023, 1025, 2047, 3000])
+def test_ragged_sizes_planted(gpu, orc, n):
+    check_against_oracle(gpu, orc, planted(n, 0.4, 5000 + n))
+
+
+@pytest.mark.parametrize("n", [5, 64, 200, 777])
+def test_degenerate_integer_data(gpu, orc, n):
+    """Integer coordinates: shared x, coincident points, exact width ties."""
+    check_against_oracle(gpu, orc, degenerate_int(n, 6000 + n))
+    st = Stream(n, 7)
+    tiny = st.integers(2 * n, 0, 5).reshape(n, 2).astype(np.float64)
+    if len(np.unique(tiny[:, 0])) > 1:
+        check_against_oracle(gpu, orc, tiny)
+
+
+@pytest.mark.parametrize("n,h", [(50, 2), (50, 3), (50, 49), (50, 50), (301, 151), (301, 260),
+                                 (1000, 700), (1000, 2)])
+def test_general_h(gpu, orc, n, h):
+    check_against_oracle(gpu, orc, planted(n, 0.3, 7000 + n + h), h=h)
+
+
+def test_all_x_equal(gpu, orc):
+    for n in (2, 3, 40, 1000):
+        y = Stream(n, 8).uniform(n, -3, 3)
+        xy = np.stack([np.full(n, -2.5), y], 1)
+        r, o = check_against_oracle(gpu, orc, xy)
+        assert r.status == 1 and r.theta1 == 0.0 and r.pair_i == -1
+
+
+def test_collinear_majority_exact_zero(gpu, orc):
+    st = Stream(21, 210)
+    for n in (9, 100, 1001):
+        h = default_h(n)
+        xs = st.permutation(8 * n)[:h].astype(np.float64) - 4 * n
+        on = np.stack([xs, -2.0 * xs + 11.0], 1)
+        off = st.integers(2 * (n - h), -5000, 5000).reshape(-1, 2).astype(np.float64)
+        xy = np.concatenate([on, off])[st.permutation(n)]
+        r, _ = check_against_oracle(gpu, orc, xy)
+        assert r.width == 0.0 and r.theta1 == -2.0 and r.theta2 == 11.0
+
+
+def test_nonfinite_input(gpu):
+    xy = planted(100, 0.3, 1)
+    for v in (np.nan, np.inf, -np.inf):
+        bad = xy.copy()
+        bad[37, 0] = v
+        r = gpu.solve(dev(bad))
+        assert r.status == gpu.LMS_ERR_NONFINITE and np.isnan(r.width)
+
+
+def test_eval_slopes_bitwise(gpu, orc):
+    """F(theta) of the FP64 kernel equals the oracle's bit for bit."""
+    for n in (5, 100, 4096, 16384):
+        xy = planted(n, 0.45, 8000 + n)
+        th = np.concatenate([Stream(n, 9).uniform(200, -3, 3), [0.0, 0.7, -1e6, 1e-300]])
+        out = gpu.eval_slopes(dev(xy), torch.from_numpy(th)).cpu().numpy()
+        for t in range(0, len(th), 7 if n >= 4096 else 1):
+            w, lo, hi = orc.window(xy, th[t])
+            assert (out[t, 0], out[t, 1], out[t, 2]) == (w, lo, hi), (n, th[t])
+
+
+def test_screen_is_sound_on_every_pair(gpu, orc):
+    """No pair whose exact anchored window fits in W is rejected (C1, all pairs)."""
+    xy = gen.make("c1", 101)
+    n = len(xy)
+    o = orc.solve(xy)
+    W = o.width * (1 + 1e-12)
+    ii, jj = np.triu_indices(n, 1)
+    pairs = np.stack([ii, jj], 1)
+    v = gpu.screen_pairs(dev(xy), torch.from_numpy(pairs), W).cpu().numpy()
+    kept = int((v == 1).sum())
+    print("kept", kept, "of", len(pairs), flush=True)
+    assert kept < len(pairs) // 20  # the screen prunes
+    need = []
+    for t in range(len(pairs)):
+        up, dn = orc.anchored(xy, int(ii[t]), int(jj[t]))
+        if min(up, dn) <= W:
+            need.append(t)
+    assert need, "the optimum's pair must have an anchored window <= W"
+    assert all(v[t] == 1 for t in need)
+    # loose bound: still sound, keeps more
+    v2 = gpu.screen_pairs(dev(xy), torch.from_numpy(pairs), 3 * o.width).cpu().numpy()
+    assert np.all(v2[v == 1] == 1) and (v2 == 1).sum() >= kept
+
+
+def test_no_prune_gives_same_answer(gpu):
+    for xy in (gen.make("c1", 102), degenerate_int(300, 31)):
+        a = gpu.solve(dev(xy))
+        b = gpu.solve(dev(xy), no_prune=True)
+        c = gpu.solve(dev(xy), seed_pairs=0)
+        assert (a.width, a.theta1, a.z_lo) == (b.width, b.theta1, b.z_lo) == \
+               (c.width, c.theta1, c.z_lo)
+        assert b.survivors >= a.survivors
+
+
+def test_seed_slopes_do_not_change_result(gpu):
+    xy = gen.make("c1", 103)
+    base = gpu.solve(dev(xy))
+    for th in ([0.7], [0.0, 5.0, -3.0], [base.theta1]):
+        r = gpu.solve(dev(xy), seed_theta=torch.tensor(th, dtype=torch.float64, device="cuda:0"))
+        assert (r.width, r.theta1, r.z_lo) == (base.width, base.theta1, base.z_lo)
+
+
+def test_determinism_and_permutation(gpu):
+    xy = gen.make("c2", 202)[:2000]
+    rs = [gpu.solve(dev(xy)) for _ in range(5)]
+    assert all((r.width, r.theta1, r.z_lo, r.pair_i, r.pair_j) ==
+               (rs[0].width, rs[0].theta1, rs[0].z_lo, rs[0].pair_i, rs[0].pair_j) for r in rs)
+    perm = Stream(4, 40).permutation(len(xy))
+    p = gpu.solve(dev(xy[perm]))
+    assert (p.width, p.theta1, p.z_lo) == (rs[0].width, rs[0].theta1, rs[0].z_lo)
+
+
+def test_solve_host_matches_device(gpu):
+    xy = planted(333, 0.4, 12)
+    a = gpu.solve(dev(xy))
+    b = gpu.solve_host(xy)
+    assert (a.width, a.theta1, a.z_lo) == (b.width, b.theta1, b.z_lo)
+
+
+def test_streams_are_independent(gpu):
+    xs = [planted(500, 0.4, 100 + k) for k in range(3)]
+    streams = [torch.cuda.Stream() for _ in xs]
+    outs = []
+    for xy, s in zip(xs, streams):
+        with torch.cuda.stream(s):
+            d = dev(xy)
+            outs.append(gpu.solve_async(d, stream=s))
+    torch.cuda.synchronize()
+    for xy, o in zip(xs, outs):
+        assert gpu.parse(o).width == gpu.solve(dev(xy)).width
