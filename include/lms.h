@@ -78,7 +78,9 @@ typedef struct lms_options {
   uint32_t flags;       /* LMS_F_* */
   int32_t seed_pairs;   /* random pair slopes evaluated exactly before the screen
                            to set the initial width bound (default 255; >= 0) */
-  int32_t reserved;
+  int32_t tile_regs;    /* 0 = automatic. Otherwise the number of 64-point chunks of
+                           the screen kept in registers (1, 16, 32 or 64); the other
+                           points stream from LDS. */
   const double* d_seed_theta; /* optional device array of extra seed slopes (any
                                  real values; they only tighten the initial bound) */
   int64_t n_seed_theta;       /* length of d_seed_theta */

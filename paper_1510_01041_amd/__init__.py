@@ -45,7 +45,7 @@ assert ctypes.sizeof(_Result) == RESULT_BYTES
 
 class _Options(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("flags", ctypes.c_uint32),
-                ("seed_pairs", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("seed_pairs", ctypes.c_int32), ("tile_regs", ctypes.c_int32),
                 ("d_seed_theta", ctypes.c_void_p), ("n_seed_theta", ctypes.c_int64)]
 
 
@@ -132,10 +132,11 @@ def _stream(stream) -> int:
     return s.cuda_stream
 
 
-def _options(flags=0, seed_pairs=None, seed_theta: torch.Tensor | None = None):
+def _options(flags=0, seed_pairs=None, seed_theta: torch.Tensor | None = None, tile_regs=0):
     o = _Options()
     o.struct_size = ctypes.sizeof(_Options)
     o.flags = flags
+    o.tile_regs = int(tile_regs)
     o.seed_pairs = 255 if seed_pairs is None else int(seed_pairs)
     if seed_theta is not None:
         if not (seed_theta.is_cuda and seed_theta.dtype == torch.float64 and seed_theta.dim() == 1
@@ -155,12 +156,13 @@ def parse(raw: torch.Tensor) -> LmsResult:
 
 def solve_async(xy: torch.Tensor, h: int = 0, out: torch.Tensor | None = None, *,
                 no_prune: bool = False, seed_pairs: int | None = None,
-                seed_theta: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+                seed_theta: torch.Tensor | None = None, tile_regs: int = 0,
+                stream=None) -> torch.Tensor:
     """Enqueue one exact LMS solve; returns the device uint8[112] result buffer."""
     xy = _points(xy)
     if out is None:
         out = torch.empty(RESULT_BYTES, dtype=torch.uint8, device=xy.device)
-    opt = _options(LMS_F_NO_PRUNE if no_prune else 0, seed_pairs, seed_theta)
+    opt = _options(LMS_F_NO_PRUNE if no_prune else 0, seed_pairs, seed_theta, tile_regs)
     st = load().lms_solve(xy.data_ptr(), xy.shape[0], h, out.data_ptr(), ctypes.byref(opt),
                           _stream(stream))
     _check(st)

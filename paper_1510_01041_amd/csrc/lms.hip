@@ -302,62 +302,67 @@ __global__ __launch_bounds__(NT) void k_eval_slopes(const double* __restrict__ x
 // higher-order terms. If the exact anchored window [0, W] (or [-W, 0]) holds h
 // points, their FP32 residuals lie in [-tau, W + tau] (or [-W - tau, tau]).
 
+// Screen test of one pair (uniform across the wavefront).
+//  Band test: B = #{|d| <= thr}, thr = W + tau. A pair whose anchored window
+//  of width <= W holds h points has B >= h; misses beyond 64*chunks - h reject
+//  it at once.
+//  Split test: with N = #{-thr <= d < -ta} and P = #{ta < d <= thr}, the
+//  one-sided counts are up = B - N and dn = B - P, so the pair survives iff
+//  N <= B - h or P <= B - h. Both counts only grow, so the pair is rejected as
+//  soon as both exceed B - h, usually within a few chunks.
+// Outcome of one pair's test: keep flag and the 64-point chunks evaluated by
+// the band and split passes (-1 split chunks: the band test rejected).
+struct PairTest {
+  int keep, band_chunks, split_chunks;
+};
+
 template <int R, bool LDS_PART>
-__device__ __forceinline__ int test_pair(const float (&X)[R], const float (&Y)[R],
-                                         const float2* __restrict__ lds, int nq, float nth,
-                                         float thr, float ta, float nc, int h,
-                                         unsigned long long& evals, unsigned long long& devals,
-                                         unsigned& band) {
+__device__ __forceinline__ PairTest test_pair(const float (&X)[R], const float (&Y)[R],
+                                              const float2* __restrict__ lds, int nq, float nth,
+                                              float thr, float ta, float nc, int h) {
   const int lane = threadIdx.x & 63;
-  const int total = R + (LDS_PART ? nq : 0);  // chunks of 64 points
-  int hits = 0;
-  // Band test: points with |d| <= W + tau.
+  const int total = R + (LDS_PART ? nq : 0);  // chunks of 64 points (padding never hits)
+  // misses allowed before the pair is certainly rejected
+  const int budget = 64 * total - h;
+  int miss = 0;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const float d = fmaf(nth, X[r], Y[r]);
-    hits += __popcll(__ballot(fabsf(d) <= thr));
-    if ((r & 7) == 7 && r + 1 < total) {
-      if (hits + 64 * (total - r - 1) < h) { evals += 64ull * (r + 1); return 0; }
+    miss += __popcll(__ballot(!(fabsf(d) <= thr)));
+    if ((r & 7) == 7 || r == R - 1) {
+      if (miss > budget) return {0, r + 1, -1};
     }
   }
   if (LDS_PART) {
     for (int q = 0; q < nq; ++q) {
       const float2 p = lds[q * 64 + lane];
       const float d = fmaf(nth, p.x, p.y) + nc;
-      hits += __popcll(__ballot(fabsf(d) <= thr));
-      if ((q & 7) == 7 && q + 1 < nq) {
-        if (hits + 64 * (nq - q - 1) < h) { evals += 64ull * (R + q + 1); return 0; }
-      }
+      miss += __popcll(__ballot(!(fabsf(d) <= thr)));
+      if (((q & 7) == 7 || q == nq - 1) && miss > budget) return {0, R + q + 1, -1};
     }
   }
-  evals += 64ull * total;
-  if (hits < h) return 0;
-  ++band;
-  // One-sided tests: the window must start or end at the anchor. The slope is
-  // passed through an opaque copy so that the compiler recomputes the
+  const int slack = budget - miss;  // B - h >= 0
+  // The slope goes through an opaque copy so that the compiler recomputes the
   // residuals instead of keeping all R of them live from the band test.
   asm volatile("" : "+v"(nth));
-  int up = 0, dn = 0;
+  int below = 0, above = 0;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const float d = fmaf(nth, X[r], Y[r]);
-    up += __popcll(__ballot(d >= -ta && d <= thr));
-    dn += __popcll(__ballot(d <= ta && d >= -thr));
-    if ((r & 7) == 7 && r + 1 < total) {
-      const int rem = 64 * (total - r - 1);
-      if (up + rem < h && dn + rem < h) { devals += 64ull * (r + 1); return 0; }
-    }
+    above += __popcll(__ballot(d > ta && d <= thr));
+    below += __popcll(__ballot(d < -ta && d >= -thr));
+    if (above > slack && below > slack) return {0, total, r + 1};
   }
   if (LDS_PART) {
     for (int q = 0; q < nq; ++q) {
       const float2 p = lds[q * 64 + lane];
       const float d = fmaf(nth, p.x, p.y) + nc;
-      up += __popcll(__ballot(d >= -ta && d <= thr));
-      dn += __popcll(__ballot(d <= ta && d >= -thr));
+      above += __popcll(__ballot(d > ta && d <= thr));
+      below += __popcll(__ballot(d < -ta && d >= -thr));
+      if (above > slack && below > slack) return {0, total, R + q + 1};
     }
   }
-  devals += 64ull * total;
-  return (up >= h || dn >= h) ? 1 : 0;
+  return {1, total, total};
 }
 
 __device__ __forceinline__ void append_entry(Ctx* ctx, uint2* entries, int cap, unsigned lo,
@@ -369,8 +374,8 @@ __device__ __forceinline__ void append_entry(Ctx* ctx, uint2* entries, int cap, 
 
 // Work item = (anchor i, block of G*64 partner offsets). Partners are
 // j = (i + o) mod n for o = 1..P(i): every unordered pair appears once.
-template <int R, bool LDS_PART>
-__global__ __launch_bounds__(LDS_PART ? 768 : 256, 3) void k_screen(
+template <int R, bool LDS_PART, int NT>
+__global__ __launch_bounds__(NT, 3) void k_screen(
     const double* __restrict__ xy, const float2* __restrict__ xy32, Ctx* ctx,
     uint2* __restrict__ entries, int cap, int G, int ipa, int n_items, int nq) {
   extern __shared__ float2 lds[];
@@ -430,9 +435,14 @@ __global__ __launch_bounds__(LDS_PART ? 768 : 256, 3) void k_screen(
         const int cl = __ffsll((long long)m) - 1;
         m &= m - 1;
         const float nth = -lane_f(th32, cl);
-        const int keep = test_pair<R, LDS_PART>(X, Y, lds, nq, nth, lane_f(thr, cl),
-                                                lane_f(ta, cl), lane_f(nc, cl), h, n_evals,
-                                                n_devals, n_band);
+        const PairTest pt = test_pair<R, LDS_PART>(X, Y, lds, nq, nth, lane_f(thr, cl),
+                                                   lane_f(ta, cl), lane_f(nc, cl), h);
+        n_evals += (unsigned)pt.band_chunks;
+        if (pt.split_chunks >= 0) {
+          ++n_band;
+          n_devals += (unsigned)pt.split_chunks;
+        }
+        const int keep = pt.keep;
         if (keep && lane == 0)
           append_entry(ctx, entries, cap, (unsigned)lane_i(lo, cl), (unsigned)lane_i(hi, cl));
       }
@@ -442,16 +452,16 @@ __global__ __launch_bounds__(LDS_PART ? 768 : 256, 3) void k_screen(
     atomicAdd(&ctx->vertical, n_vert);
     atomicAdd(&ctx->screened, n_scr);
     atomicAdd(&ctx->band_pass, (unsigned long long)n_band);
-    atomicAdd(&ctx->point_evals, n_evals);
-    atomicAdd(&ctx->dir_evals, n_devals);
+    atomicAdd(&ctx->point_evals, 64ull * n_evals);
+    atomicAdd(&ctx->dir_evals, 64ull * n_devals);
     atomicAdd(&ctx->forced, n_forced);
   }
 }
 
 // Verdicts for explicit pairs (lms_screen_pairs): one wavefront per pair,
 // same test as the screen kernel.
-template <int R, bool LDS_PART>
-__global__ __launch_bounds__(LDS_PART ? 768 : 256) void k_screen_pairs(
+template <int R, bool LDS_PART, int NT>
+__global__ __launch_bounds__(NT) void k_screen_pairs(
     const double* __restrict__ xy, const float2* __restrict__ xy32, const Ctx* ctx, double W,
     const int* __restrict__ pairs, int m, int* __restrict__ verdict, int nq) {
   extern __shared__ float2 lds[];
@@ -492,13 +502,11 @@ __global__ __launch_bounds__(LDS_PART ? 768 : 256) void k_screen_pairs(
       Y[r] = p.y - pi.y;
     }
     const float th32 = (float)th;
-    unsigned long long ev = 0, dev = 0;
-    unsigned bd = 0;
     // per-pair scalars in SGPRs, as in the screen kernel
-    const int keep = test_pair<R, LDS_PART>(
+    const PairTest pt = test_pair<R, LDS_PART>(
         X, Y, lds, nq, lane_f(-th32, 0), lane_f(f32_up(W + tau), 0), lane_f(f32_up(tau), 0),
-        lane_f(-fmaf(-th32, pi.x, pi.y), 0), c.h, ev, dev, bd);
-    if (lane == 0) verdict[t] = keep;
+        lane_f(-fmaf(-th32, pi.x, pi.y), 0), c.h);
+    if (lane == 0) verdict[t] = pt.keep;
   }
 }
 
@@ -724,69 +732,100 @@ void launch_eval(hipStream_t s, int grid, const double* xy, int n, int h, const 
   }
 }
 
+// Threads per block of the screen: 256 when all points sit in registers;
+// with the LDS part one block per CU shares the LDS copy, so it is as large
+// as the register budget allows.
 template <int R, bool L>
-hipError_t launch_screen_rl(hipStream_t s, int grid, const double* xy, const float2* xy32,
-                            Ctx* ctx, uint2* e, int cap, int G, int ipa, int n_items, int nq) {
-  const int nt = L ? 768 : 256;
+constexpr int screen_threads() {
+  return !L ? 256 : (R == 64 ? 768 : 1024);
+}
+
+template <int R, bool L>
+hipError_t launch_screen_rl(hipStream_t s, int cu, const double* xy, const float2* xy32, Ctx* ctx,
+                            uint2* e, int cap, int G, int ipa, int n_items, int nq) {
+  constexpr int nt = screen_threads<R, L>();
   const size_t shm = L ? (size_t)nq * 64 * sizeof(float2) : 0;
   if (L) {
-    (void)hipFuncSetAttribute((const void*)k_screen<R, L>,
+    (void)hipFuncSetAttribute((const void*)k_screen<R, L, nt>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     (void)hipGetLastError();
   }
-  hipLaunchKernelGGL((k_screen<R, L>), dim3(grid), dim3(nt), shm, s, xy, xy32, ctx, e, cap, G,
+  const long long per_block = nt / 64;
+  const long long need = (n_items + per_block - 1) / per_block;
+  const int grid = (int)std::max<long long>(1, std::min<long long>(need, (long long)cu * (L ? 2 : 3)));
+  hipLaunchKernelGGL((k_screen<R, L, nt>), dim3(grid), dim3(nt), shm, s, xy, xy32, ctx, e, cap, G,
                      ipa, n_items, nq);
   return hipGetLastError();
 }
 
-hipError_t launch_screen(hipStream_t s, int R, bool L, int grid, const double* xy,
+hipError_t launch_screen(hipStream_t s, int R, bool L, int cu, const double* xy,
                          const float2* xy32, Ctx* ctx, uint2* e, int cap, int G, int ipa,
                          int n_items, int nq) {
-  if (L) return launch_screen_rl<64, true>(s, grid, xy, xy32, ctx, e, cap, G, ipa, n_items, nq);
-  switch (R) {
-    case 1: return launch_screen_rl<1, false>(s, grid, xy, xy32, ctx, e, cap, G, ipa, n_items, nq);
-    case 2: return launch_screen_rl<2, false>(s, grid, xy, xy32, ctx, e, cap, G, ipa, n_items, nq);
-    case 4: return launch_screen_rl<4, false>(s, grid, xy, xy32, ctx, e, cap, G, ipa, n_items, nq);
-    case 8: return launch_screen_rl<8, false>(s, grid, xy, xy32, ctx, e, cap, G, ipa, n_items, nq);
-    case 16: return launch_screen_rl<16, false>(s, grid, xy, xy32, ctx, e, cap, G, ipa, n_items, nq);
-    case 24: return launch_screen_rl<24, false>(s, grid, xy, xy32, ctx, e, cap, G, ipa, n_items, nq);
-    case 32: return launch_screen_rl<32, false>(s, grid, xy, xy32, ctx, e, cap, G, ipa, n_items, nq);
-    case 48: return launch_screen_rl<48, false>(s, grid, xy, xy32, ctx, e, cap, G, ipa, n_items, nq);
-    default: return launch_screen_rl<64, false>(s, grid, xy, xy32, ctx, e, cap, G, ipa, n_items, nq);
+#define LMS_SCREEN_CASE(RR, LL) \
+  return launch_screen_rl<RR, LL>(s, cu, xy, xy32, ctx, e, cap, G, ipa, n_items, nq)
+  if (L) {
+    switch (R) {
+      case 1: LMS_SCREEN_CASE(1, true);
+      case 16: LMS_SCREEN_CASE(16, true);
+      case 32: LMS_SCREEN_CASE(32, true);
+      default: LMS_SCREEN_CASE(64, true);
+    }
   }
+  switch (R) {
+    case 1: LMS_SCREEN_CASE(1, false);
+    case 2: LMS_SCREEN_CASE(2, false);
+    case 4: LMS_SCREEN_CASE(4, false);
+    case 8: LMS_SCREEN_CASE(8, false);
+    case 16: LMS_SCREEN_CASE(16, false);
+    case 24: LMS_SCREEN_CASE(24, false);
+    case 32: LMS_SCREEN_CASE(32, false);
+    case 48: LMS_SCREEN_CASE(48, false);
+    default: LMS_SCREEN_CASE(64, false);
+  }
+#undef LMS_SCREEN_CASE
 }
 
 template <int R, bool L>
 hipError_t launch_pairs_rl(hipStream_t s, const double* xy, const float2* xy32, const Ctx* ctx,
                            double W, const int* pairs, int m, int* verdict, int nq) {
-  const int nt = L ? 768 : 256;
+  constexpr int nt = screen_threads<R, L>();
   const size_t shm = L ? (size_t)nq * 64 * sizeof(float2) : 0;
   if (L) {
-    (void)hipFuncSetAttribute((const void*)k_screen_pairs<R, L>,
+    (void)hipFuncSetAttribute((const void*)k_screen_pairs<R, L, nt>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     (void)hipGetLastError();
   }
   const int wpb = nt / 64;
   const int grid = std::max(1, std::min(4096, (m + wpb - 1) / wpb));
-  hipLaunchKernelGGL((k_screen_pairs<R, L>), dim3(grid), dim3(nt), shm, s, xy, xy32, ctx, W,
+  hipLaunchKernelGGL((k_screen_pairs<R, L, nt>), dim3(grid), dim3(nt), shm, s, xy, xy32, ctx, W,
                      pairs, m, verdict, nq);
   return hipGetLastError();
 }
 
 hipError_t launch_pairs(hipStream_t s, int R, bool L, const double* xy, const float2* xy32,
                         const Ctx* ctx, double W, const int* pairs, int m, int* verdict, int nq) {
-  if (L) return launch_pairs_rl<64, true>(s, xy, xy32, ctx, W, pairs, m, verdict, nq);
-  switch (R) {
-    case 1: return launch_pairs_rl<1, false>(s, xy, xy32, ctx, W, pairs, m, verdict, nq);
-    case 2: return launch_pairs_rl<2, false>(s, xy, xy32, ctx, W, pairs, m, verdict, nq);
-    case 4: return launch_pairs_rl<4, false>(s, xy, xy32, ctx, W, pairs, m, verdict, nq);
-    case 8: return launch_pairs_rl<8, false>(s, xy, xy32, ctx, W, pairs, m, verdict, nq);
-    case 16: return launch_pairs_rl<16, false>(s, xy, xy32, ctx, W, pairs, m, verdict, nq);
-    case 24: return launch_pairs_rl<24, false>(s, xy, xy32, ctx, W, pairs, m, verdict, nq);
-    case 32: return launch_pairs_rl<32, false>(s, xy, xy32, ctx, W, pairs, m, verdict, nq);
-    case 48: return launch_pairs_rl<48, false>(s, xy, xy32, ctx, W, pairs, m, verdict, nq);
-    default: return launch_pairs_rl<64, false>(s, xy, xy32, ctx, W, pairs, m, verdict, nq);
+#define LMS_PAIRS_CASE(RR, LL) \
+  return launch_pairs_rl<RR, LL>(s, xy, xy32, ctx, W, pairs, m, verdict, nq)
+  if (L) {
+    switch (R) {
+      case 1: LMS_PAIRS_CASE(1, true);
+      case 16: LMS_PAIRS_CASE(16, true);
+      case 32: LMS_PAIRS_CASE(32, true);
+      default: LMS_PAIRS_CASE(64, true);
+    }
   }
+  switch (R) {
+    case 1: LMS_PAIRS_CASE(1, false);
+    case 2: LMS_PAIRS_CASE(2, false);
+    case 4: LMS_PAIRS_CASE(4, false);
+    case 8: LMS_PAIRS_CASE(8, false);
+    case 16: LMS_PAIRS_CASE(16, false);
+    case 24: LMS_PAIRS_CASE(24, false);
+    case 32: LMS_PAIRS_CASE(32, false);
+    case 48: LMS_PAIRS_CASE(48, false);
+    default: LMS_PAIRS_CASE(64, false);
+  }
+#undef LMS_PAIRS_CASE
 }
 
 struct Plan {
@@ -795,7 +834,7 @@ struct Plan {
   long long cap;
 };
 
-lms_status make_plan(const void* d_xy, int64_t n, int64_t h, Plan* p) {
+lms_status make_plan(const void* d_xy, int64_t n, int64_t h, Plan* p, int tile_regs = 0) {
   if (!d_xy) return fail(LMS_ERR_ARG, "null point pointer");
   if (n < 2 || n > LMS_MAX_N)
     return fail(LMS_ERR_ARG, "n must be in [2, " + std::to_string(LMS_MAX_N) + "]");
@@ -804,7 +843,15 @@ lms_status make_plan(const void* d_xy, int64_t n, int64_t h, Plan* p) {
   p->n = (int)n;
   p->h = (int)h;
   p->R = pick_R((int)n);
+  if (tile_regs < 0 || tile_regs > kRegChunks)
+    return fail(LMS_ERR_ARG, "tile_regs must be in [0, 64]");
+  if (tile_regs > 0 && tile_regs < p->R) {
+    // fewer register chunks than the points need: the rest streams from LDS
+    p->R = tile_regs >= 64 ? 64 : tile_regs >= 32 ? 32 : tile_regs >= 16 ? 16 : 1;
+  }
   p->lds = 64 * p->R < n;
+  if (p->lds && p->R != 1 && p->R != 16 && p->R != 32 && p->R != 64)
+    return fail(LMS_ERR_ARG, "unsupported register tile");
   p->nq = p->lds ? (int)((n - 64 * p->R + 63) / 64) : 0;
   p->n_pad = 64 * (p->R + p->nq);
   return LMS_OK;
@@ -834,8 +881,9 @@ const char* lms_last_error(void) { return g_err.c_str(); }
 lms_status lms_solve(const double* d_xy, int64_t n, int64_t h, lms_result* d_out,
                      const lms_options* opt, void* stream) {
   g_err.clear();
+  if (opt && opt->struct_size < sizeof(lms_options)) return fail(LMS_ERR_ARG, "bad options size");
   Plan p;
-  lms_status st = make_plan(d_xy, n, h, &p);
+  lms_status st = make_plan(d_xy, n, h, &p, opt ? opt->tile_regs : 0);
   if (st != LMS_OK) return st;
   if (!d_out) return fail(LMS_ERR_ARG, "null result pointer");
   int seeds = kDefaultSeeds;
@@ -891,10 +939,7 @@ lms_status lms_solve(const double* d_xy, int64_t n, int64_t h, lms_result* d_out
     const int G = std::min(4, std::max(1, batches));
     const int ipa = (batches + G - 1) / G;
     const long long n_items = (long long)p.n * ipa;
-    const int per_block = p.lds ? 12 : 4;
-    const long long grid_needed = (n_items + per_block - 1) / per_block;
-    const int grid = (int)std::max<long long>(1, std::min<long long>(grid_needed, (long long)cu * (p.lds ? 1 : 3)));
-    hipError_t err = launch_screen(s, p.R, p.lds, grid, d_xy, xy32, ctx, entries, (int)p.cap, G,
+    hipError_t err = launch_screen(s, p.R, p.lds, cu, d_xy, xy32, ctx, entries, (int)p.cap, G,
                                    ipa, (int)n_items, p.nq);
     if (err != hipSuccess) {
       prof.finish();

@@ -193,3 +193,92 @@ def test_streams_are_independent(gpu):
     torch.cuda.synchronize()
     for xy, o in zip(xs, outs):
         assert gpu.parse(o).width == gpu.solve(dev(xy)).width
+
+
+@pytest.mark.parametrize("n,tile", [(100, 1), (1000, 1), (1500, 16), (3000, 1), (3000, 16),
+                                    (3000, 32)])
+def test_lds_tiles_match_oracle(gpu, orc, n, tile):
+    """Screen variants that stream part of the points from LDS, at sizes the
+    oracle finishes quickly (forced with tile_regs)."""
+    check_against_oracle(gpu, orc, planted(n, 0.45, 9000 + n + tile), tile_regs=tile)
+    if n <= 1000:
+        check_against_oracle(gpu, orc, degenerate_int(n, 9100 + n), tile_regs=tile)
+
+
+def test_c2_matches_stored_oracle(gpu):
+    gold = json.load(open(GOLD))
+    keys = [k for k in gold if k.startswith("c2/")]
+    assert keys, "no stored n=4096 oracle results"
+    for k in keys:
+        g = gold[k]
+        r = gpu.solve(dev(gen.make("c2", int(k.split("/")[1]))))
+        print(k, r, flush=True)
+        assert r.status == 0
+        assert close(r.width, float.fromhex(g["width"]))
+        assert r.width == float.fromhex(g["width"]) and r.theta1 == float.fromhex(g["theta1"])
+        assert r.z_lo == float.fromhex(g["z_lo"]) and r.z_hi == float.fromhex(g["z_hi"])
+
+
+def test_degenerate_4096_matches_stored_oracle(gpu):
+    gold = json.load(open(GOLD))
+    g = gold.get("degenerate_int_4096/302")
+    if g is None:
+        pytest.skip("stored result not written yet")
+    r = gpu.solve(dev(degenerate_int(4096, 302)))
+    assert r.status == 0 and r.vertical == g["vertical"]
+    assert r.width == float.fromhex(g["width"]) and r.theta1 == float.fromhex(g["theta1"])
+
+
+def full_size_properties(gpu, orc, xy, r, n_sample=3000):
+    """Checks that hold at any size: the oracle re-evaluates the returned slope
+    and gets the same window bit for bit, the line holds h points within its
+    half-width, and no sampled pair slope has a narrower window."""
+    w, lo, hi = orc.window(xy, r.theta1)
+    assert (w, lo, hi) == (r.width, r.z_lo, r.z_hi)
+    hth = orc.hth_abs_residual(xy, r.theta1, r.theta2)
+    assert abs(hth - r.half_width) <= 1e-9 * r.half_width + 1e-12
+    st = Stream(len(xy), 77)
+    a = st.integers(n_sample, 0, len(xy) - 1)
+    b = st.integers(n_sample, 0, len(xy) - 2)
+    b = b + (b >= a)
+    _, ws, _, _ = orc.eval_pairs(xy, np.stack([a, b], 1), nthreads=0)
+    assert np.nanmin(ws) >= r.width
+
+
+@pytest.mark.parametrize("n", [4097, 4500])
+def test_register_and_lds_variants_agree(gpu, orc, n):
+    """Above 4096 points the screen streams from LDS; every register tile must
+    give the same bits, and the oracle certifies the result."""
+    xy = planted(n, 0.45, 9500 + n)
+    rs = [gpu.solve(dev(xy), tile_regs=t) for t in (0, 32, 16, 1)]
+    for r in rs:
+        print(n, r, flush=True)
+        assert (r.width, r.theta1, r.z_lo, r.z_hi) == \
+               (rs[0].width, rs[0].theta1, rs[0].z_lo, rs[0].z_hi)
+    full_size_properties(gpu, orc, xy, rs[0], 1000)
+
+
+@pytest.mark.parametrize("name", ["c3a", "c3b"])
+def test_full_size_16384(gpu, orc, name):
+    """n = 16384 (planted, and integer with duplicated x): certificate, sampled
+    pairs, the vertical-pair count, and agreement between register tiles."""
+    xy = gen.make(name)
+    r = gpu.solve(dev(xy))
+    print(name, r, flush=True)
+    assert r.status == 0
+    _, counts = np.unique(xy[:, 0], return_counts=True)
+    assert r.vertical == int((counts * (counts - 1) // 2).sum())
+    full_size_properties(gpu, orc, xy, r)
+    r32 = gpu.solve(dev(xy), tile_regs=32)
+    assert (r32.width, r32.theta1, r32.z_lo) == (r.width, r.theta1, r.z_lo)
+
+
+def test_full_size_equivariance(gpu):
+    """y -> 2y + 3x - 5 on the integer n = 16384 set is exact in FP64: the
+    width doubles and the slope maps to 2*theta1 + 3 (minimiser permitting)."""
+    xy = gen.make("c3b")
+    r = gpu.solve(dev(xy))
+    t = xy.copy()
+    t[:, 1] = 2.0 * t[:, 1] + 3.0 * t[:, 0] - 5.0
+    q = gpu.solve(dev(t))
+    assert close(q.width, 2.0 * r.width)
