@@ -70,6 +70,9 @@ typedef struct lms_result {
 } lms_result;
 
 /* Flags for lms_options.flags */
+#define LMS_F_GRAPH 2u    /* lms_solve_batched: capture the pipeline in a hipGraph on the
+                             first call and replay it on later calls with the same
+                             pointers, batch shape and stream */
 #define LMS_F_NO_PRUNE 1u /* no width bound: the screen keeps every pair whose anchored
                              window can hold h points at all (slow; for tests) */
 
@@ -94,6 +97,25 @@ typedef struct lms_options {
  * canonical minimiser, ordered by (width, theta1, z_lo). */
 lms_status lms_solve(const double* d_xy, int64_t n, int64_t h, lms_result* d_out,
                      const lms_options* opt, void* stream);
+
+/* Exact LMS lines of B independent point sets in one pass (Section 5 applies
+ * one LMS per Hough peak; this is that many-small-problems form).
+ * d_xy: device, all points, n_b x 2 FP64 interleaved per problem.
+ * d_offsets: device, B+1 int64: problem b holds points [d_offsets[b],
+ *   d_offsets[b+1]), each 2 <= n_b <= LMS_BATCH_MAX_N (a smaller problem gets
+ *   status LMS_ERR_ARG in its own result; the others are solved).
+ * h_offsets: the same offsets in host memory, or NULL (the library then copies
+ *   them, which synchronises the stream). The work plan is built from them
+ *   and cached per (pointers, stream, offsets).
+ * d_h: device, B int32 values of h, or NULL for floor(n_b/2)+1 each.
+ * d_out: device, B results. opt->seed_pairs is per problem (default 31).
+ * With LMS_F_GRAPH the kernels are captured in a hipGraph on the first call
+ * and replayed afterwards; the inputs may change between calls, the pointers
+ * and offsets may not (otherwise the plan and graph are rebuilt). */
+#define LMS_BATCH_MAX_N 4096
+lms_status lms_solve_batched(const double* d_xy, const int64_t* d_offsets,
+                             const int64_t* h_offsets, int64_t B, const int32_t* d_h,
+                             lms_result* d_out, const lms_options* opt, void* stream);
 
 /* Synchronous convenience: host input, host output. Copies the points to the
  * device, solves on a library-owned stream and copies the result back. */

@@ -25,6 +25,8 @@ LIB_PATH = os.path.join(_HERE, "liblms.so")
 LMS_OK, LMS_OK_DEGENERATE = 0, 1
 LMS_ERR_ARG, LMS_ERR_NONFINITE, LMS_ERR_DEVICE, LMS_ERR_NOMEM, LMS_ERR_CAPACITY = -1, -2, -3, -4, -5
 LMS_F_NO_PRUNE = 1
+LMS_F_GRAPH = 2
+BATCH_MAX_N = 4096
 MAX_N = 16384
 RESULT_BYTES = 112
 
@@ -89,6 +91,8 @@ def load():
     L.lms_solve.restype = i32
     L.lms_solve_host.argtypes = [vp, i64, i64, ctypes.POINTER(_Result), ctypes.POINTER(_Options)]
     L.lms_solve_host.restype = i32
+    L.lms_solve_batched.argtypes = [vp, vp, vp, i64, vp, vp, ctypes.POINTER(_Options), vp]
+    L.lms_solve_batched.restype = i32
     L.lms_eval_slopes.argtypes = [vp, i64, i64, vp, i64, vp, vp]
     L.lms_eval_slopes.restype = i32
     L.lms_screen_pairs.argtypes = [vp, i64, i64, ctypes.c_double, vp, i64, vp, vp]
@@ -172,6 +176,66 @@ def solve_async(xy: torch.Tensor, h: int = 0, out: torch.Tensor | None = None, *
 def solve(xy: torch.Tensor, h: int = 0, **kw) -> LmsResult:
     """Exact LMS line of an (n, 2) CUDA float64 point tensor (synchronises)."""
     return parse(solve_async(xy, h, **kw))
+
+
+RESULT_DTYPE = None
+
+
+def _result_dtype():
+    import numpy as np
+    global RESULT_DTYPE
+    if RESULT_DTYPE is None:
+        RESULT_DTYPE = np.dtype([(f, "f8" if t is ctypes.c_double else
+                                  "i4" if t is ctypes.c_int32 else "u8")
+                                 for f, t in _Result._fields_])
+        assert RESULT_DTYPE.itemsize == RESULT_BYTES
+    return RESULT_DTYPE
+
+
+def parse_batch(raw: torch.Tensor):
+    """Decode B results (device or host uint8[B, 112]) into a numpy record array."""
+    import numpy as np
+    a = raw.detach().to("cpu").contiguous().numpy()
+    return np.frombuffer(a.tobytes(), dtype=_result_dtype()).view(np.recarray)
+
+
+def solve_batched_async(xy: torch.Tensor, offsets, h: torch.Tensor | None = None,
+                        out: torch.Tensor | None = None, *, graph: bool = False,
+                        seed_pairs: int | None = None, stream=None) -> torch.Tensor:
+    """Enqueue exact LMS fits of B point sets; problem b is xy[offsets[b]:offsets[b+1]].
+
+    offsets: B+1 int64 (host array or tensor; a device copy is made if needed).
+    h: optional CUDA int32 tensor of B values. graph=True captures the kernels in
+    a hipGraph on the first call and replays it on later calls with the same
+    buffers. Returns the device uint8[B, 112] result buffer."""
+    import numpy as np
+    xy = _points(xy)
+    if isinstance(offsets, torch.Tensor):
+        off_h = offsets.detach().to("cpu", torch.int64).contiguous().numpy()
+        off_d = offsets if (offsets.is_cuda and offsets.dtype == torch.int64
+                            and offsets.is_contiguous()) else \
+            torch.from_numpy(off_h).to(xy.device)
+    else:
+        off_h = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+        off_d = torch.from_numpy(off_h).to(xy.device)
+    B = off_h.shape[0] - 1
+    if out is None:
+        out = torch.empty((B, RESULT_BYTES), dtype=torch.uint8, device=xy.device)
+    if h is not None and not (h.is_cuda and h.dtype == torch.int32 and h.numel() == B):
+        raise ValueError("h must be a CUDA int32 tensor with B values")
+    opt = _options(LMS_F_GRAPH if graph else 0, 31 if seed_pairs is None else seed_pairs)
+    st = load().lms_solve_batched(xy.data_ptr(), off_d.data_ptr(), off_h.ctypes.data, B,
+                                  None if h is None else h.data_ptr(), out.data_ptr(),
+                                  ctypes.byref(opt), _stream(stream))
+    _check(st)
+    # keep the device offsets alive while the work is queued
+    out._lms_offsets = off_d
+    return out
+
+
+def solve_batched(xy: torch.Tensor, offsets, h=None, **kw):
+    """Exact LMS fits of B point sets (synchronises); a numpy record array."""
+    return parse_batch(solve_batched_async(xy, offsets, h, **kw))
 
 
 def solve_host(xy, h: int = 0) -> LmsResult:

@@ -12,7 +12,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = os.path.join(HERE, "csrc", "lms.hip")
+SRCS = [os.path.join(HERE, "csrc", f) for f in ("lms.hip", "lms_batched.hip", "lms_host.cpp")]
 LIB = os.path.join(HERE, "liblms.so")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -27,7 +27,7 @@ FLAGS = [
 
 
 def build(verbose: bool = False, extra=()) -> str:
-    cmd = [HIPCC, *FLAGS, *extra, "-o", LIB + ".tmp", SRC]
+    cmd = [HIPCC, *FLAGS, *extra, "-o", LIB + ".tmp", *SRCS]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

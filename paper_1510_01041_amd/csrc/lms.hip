@@ -44,10 +44,13 @@
 #include <utility>
 
 #include "lms.h"
+#include "lms_device.h"
+#include "lms_host.h"
 
 namespace {
 
-constexpr unsigned kDegenerate = 0xFFFFFFFFu;  // entry code: slope 0, all x equal
+using namespace lms_dev;
+using lms_host::fail;
 constexpr int kDefaultSeeds = 255;
 constexpr long long kScreenCap = 1ll << 24;     // survivor slots beyond the seeds
 constexpr int kRegChunks = 64;                  // points per lane kept in VGPRs (max)
@@ -66,38 +69,6 @@ struct __align__(16) Ctx {
   unsigned int pad;
   unsigned long long vertical, screened, band_pass, point_evals, dir_evals, forced;
 };
-
-__device__ __forceinline__ unsigned long long mix64(unsigned long long z) {
-  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-  return z ^ (z >> 31);
-}
-
-// Smallest float >= v (v finite and >= 0 here; +inf stays +inf).
-__device__ __forceinline__ float f32_up(double v) {
-  float f = (float)v;
-  if ((double)f < v) f = nextafterf(f, INFINITY);
-  return f;
-}
-
-__device__ __forceinline__ float lane_f(float v, int c) {
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), c));
-}
-__device__ __forceinline__ int lane_i(int v, int c) { return __builtin_amdgcn_readlane(v, c); }
-
-// Upper bound on the exact width at slope theta given its FP64 width w:
-// every z carries at most one rounding of |z| <= yabs + |theta| xabs.
-__device__ __forceinline__ double width_bound(double w, double theta, const Ctx& c) {
-  const double zmax = c.yabs + fabs(theta) * c.xabs;
-  return (w + 4.0 * 0x1p-53 * zmax) * (1.0 + 0x1p-50);
-}
-
-// Bound on |d_fp32 - d_exact| for every anchored residual at slope theta
-// (centred FP32 coordinates, FP32 slope, one FMA; see the derivation above
-// the screen kernel).
-__device__ __forceinline__ double tau_bound(double theta, double xh, double yh) {
-  return 0x1p-24 * (6.25 * yh + 8.25 * fabs(theta) * xh);
-}
 
 // ---------------------------------------------------------------- prep
 
@@ -184,51 +155,6 @@ __global__ __launch_bounds__(1024) void k_prep(const double* __restrict__ xy, in
 
 // ---------------------------------------------------------------- FP64 window
 
-// Narrowest window of h consecutive values of z_k = fma(-theta, x_k, y_k),
-// k < n, computed by the whole block; z is an LDS array of N2 >= n doubles.
-// Same operation sequence as the reference: fma, full sort, subtraction, and
-// the lowest window among equally narrow ones.
-template <int N2, int NT>
-__device__ void window_f64(const double* __restrict__ xy, int n, int h, double theta, double* z,
-                           unsigned long long* s_w, int* s_s, double* width, double* z_lo,
-                           double* z_hi) {
-  const int t = threadIdx.x;
-  for (int k = t; k < N2; k += NT)
-    z[k] = (k < n) ? fma(-theta, xy[2 * k], xy[2 * k + 1]) : INFINITY;
-  if (t == 0) { *s_w = ~0ull; *s_s = INT_MAX; }
-  __syncthreads();
-  for (int k = 2; k <= N2; k <<= 1) {
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int q = t; q < N2 / 2; q += NT) {
-        const int a = 2 * q - (q & (j - 1));
-        const int b = a + j;
-        const double va = z[a], vb = z[b];
-        const bool up = (a & k) == 0;
-        if ((va > vb) == up) { z[a] = vb; z[b] = va; }
-      }
-      __syncthreads();
-    }
-  }
-  double bw = INFINITY;
-  int bs = INT_MAX;
-  for (int s = t; s + h <= n; s += NT) {
-    const double w = z[s + h - 1] - z[s];
-    if (w < bw) { bw = w; bs = s; }
-  }
-  const unsigned long long bwb = (unsigned long long)__double_as_longlong(bw);
-  atomicMin(s_w, bwb);
-  __syncthreads();
-  if (bs != INT_MAX && bwb == *s_w) atomicMin(s_s, bs);
-  __syncthreads();
-  // No window compares below +inf only if the slope or the data overflow to
-  // NaN; report NaN and read window 0, which always exists.
-  const int s = (*s_s == INT_MAX) ? 0 : *s_s;
-  *width = (*s_s == INT_MAX) ? NAN : __longlong_as_double((long long)*s_w);
-  *z_lo = z[s];
-  *z_hi = z[s + h - 1];
-  __syncthreads();
-}
-
 // One block per entry [begin, min(n_entries, cap)): re-evaluates the pair's
 // slope in FP64. With update_bound, also lowers the width bound.
 template <int N2, int NT>
@@ -259,7 +185,7 @@ __global__ __launch_bounds__(NT) void k_recheck(const double* __restrict__ xy, C
       res[e] = make_double4(w, theta, lo, hi);
       if (update_bound)
         atomicMin(&ctx->wbound,
-                  (unsigned long long)__double_as_longlong(width_bound(w, theta, c)));
+                  (unsigned long long)__double_as_longlong(width_bound(w, theta, c.xabs, c.yabs)));
     }
   }
 }
@@ -282,89 +208,13 @@ __global__ __launch_bounds__(NT) void k_eval_slopes(const double* __restrict__ x
     if (threadIdx.x == 0) {
       if (out) { out[3 * e] = w; out[3 * e + 1] = lo; out[3 * e + 2] = hi; }
       if (ctx && isfinite(th))
-        atomicMin(&ctx->wbound, (unsigned long long)__double_as_longlong(width_bound(w, th, *ctx)));
+        atomicMin(&ctx->wbound, (unsigned long long)__double_as_longlong(width_bound(w, th, ctx->xabs, ctx->yabs)));
     }
   }
 }
 
 // ---------------------------------------------------------------- screen
 //
-// Error bound tau. With u = 2^-24, centred coordinates a_k = x_k - cx (exact),
-// |x32_k - a_k| <= u|a_k| (1 + 2^-29) and the same for y. For a pair (i, j)
-// at exact slope theta the anchored residual is d_k = (y_k - y_i) -
-// theta (x_k - x_i). The kernel evaluates either
-//   (registers) d = fl(fma(-theta32, fl(x32_k - x32_i), fl(y32_k - y32_i))), or
-//   (LDS)       d = fl(fl(fma(-theta32, x32_k, y32_k)) - fl(fma(-theta32, x32_i, y32_i))),
-// with |theta32 - theta| <= u|theta| (1 + 2^-28). Summing the input, shift,
-// slope and FMA roundings gives, for both forms and to first order,
-//   |d - d_k| <= u (6 Yh + 8 |theta| Xh),
-// where Xh, Yh bound |x - cx| and |y - cy|. tau_bound adds a 4 % margin for the
-// higher-order terms. If the exact anchored window [0, W] (or [-W, 0]) holds h
-// points, their FP32 residuals lie in [-tau, W + tau] (or [-W - tau, tau]).
-
-// Screen test of one pair (uniform across the wavefront).
-//  Band test: B = #{|d| <= thr}, thr = W + tau. A pair whose anchored window
-//  of width <= W holds h points has B >= h; misses beyond 64*chunks - h reject
-//  it at once.
-//  Split test: with N = #{-thr <= d < -ta} and P = #{ta < d <= thr}, the
-//  one-sided counts are up = B - N and dn = B - P, so the pair survives iff
-//  N <= B - h or P <= B - h. Both counts only grow, so the pair is rejected as
-//  soon as both exceed B - h, usually within a few chunks.
-// Outcome of one pair's test: keep flag and the 64-point chunks evaluated by
-// the band and split passes (-1 split chunks: the band test rejected).
-struct PairTest {
-  int keep, band_chunks, split_chunks;
-};
-
-template <int R, bool LDS_PART>
-__device__ __forceinline__ PairTest test_pair(const float (&X)[R], const float (&Y)[R],
-                                              const float2* __restrict__ lds, int nq, float nth,
-                                              float thr, float ta, float nc, int h) {
-  const int lane = threadIdx.x & 63;
-  const int total = R + (LDS_PART ? nq : 0);  // chunks of 64 points (padding never hits)
-  // misses allowed before the pair is certainly rejected
-  const int budget = 64 * total - h;
-  int miss = 0;
-#pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const float d = fmaf(nth, X[r], Y[r]);
-    miss += __popcll(__ballot(!(fabsf(d) <= thr)));
-    if ((r & 7) == 7 || r == R - 1) {
-      if (miss > budget) return {0, r + 1, -1};
-    }
-  }
-  if (LDS_PART) {
-    for (int q = 0; q < nq; ++q) {
-      const float2 p = lds[q * 64 + lane];
-      const float d = fmaf(nth, p.x, p.y) + nc;
-      miss += __popcll(__ballot(!(fabsf(d) <= thr)));
-      if (((q & 7) == 7 || q == nq - 1) && miss > budget) return {0, R + q + 1, -1};
-    }
-  }
-  const int slack = budget - miss;  // B - h >= 0
-  // The slope goes through an opaque copy so that the compiler recomputes the
-  // residuals instead of keeping all R of them live from the band test.
-  asm volatile("" : "+v"(nth));
-  int below = 0, above = 0;
-#pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const float d = fmaf(nth, X[r], Y[r]);
-    above += __popcll(__ballot(d > ta && d <= thr));
-    below += __popcll(__ballot(d < -ta && d >= -thr));
-    if (above > slack && below > slack) return {0, total, r + 1};
-  }
-  if (LDS_PART) {
-    for (int q = 0; q < nq; ++q) {
-      const float2 p = lds[q * 64 + lane];
-      const float d = fmaf(nth, p.x, p.y) + nc;
-      above += __popcll(__ballot(d > ta && d <= thr));
-      below += __popcll(__ballot(d < -ta && d >= -thr));
-      if (above > slack && below > slack) return {0, total, R + q + 1};
-    }
-  }
-  return {1, total, total};
-}
-
 __device__ __forceinline__ void append_entry(Ctx* ctx, uint2* entries, int cap, unsigned lo,
                                              unsigned hi) {
   const unsigned idx = atomicAdd(&ctx->n_entries, 1u);
@@ -512,19 +362,6 @@ __global__ __launch_bounds__(NT) void k_screen_pairs(
 
 // ---------------------------------------------------------------- finalize
 
-struct Best {
-  double w, th, lo, hi;
-  unsigned a, b;
-};
-
-__device__ __forceinline__ bool better(const Best& p, const Best& q) {
-  if (p.w != q.w) return p.w < q.w;
-  if (p.th != q.th) return p.th < q.th;
-  if (p.lo != q.lo) return p.lo < q.lo;
-  if (p.a != q.a) return p.a < q.a;
-  return p.b < q.b;
-}
-
 __global__ __launch_bounds__(1024) void k_finalize(Ctx* ctx, const uint2* __restrict__ entries,
                                                    const double4* __restrict__ res, int cap,
                                                    lms_result* out) {
@@ -581,51 +418,6 @@ __global__ __launch_bounds__(1024) void k_finalize(Ctx* ctx, const uint2* __rest
 
 // ---------------------------------------------------------------- host side
 
-thread_local std::string g_err;
-
-lms_status fail(lms_status s, const std::string& msg) {
-  g_err = msg;
-  return s;
-}
-
-struct Workspace {
-  void* base = nullptr;
-  size_t bytes = 0;
-};
-
-std::mutex g_mu;
-std::map<std::pair<int, void*>, Workspace> g_ws;
-int g_num_cu = 0;
-
-// Stage timing (lms_profile_begin / lms_profile_end).
-bool g_prof_on = false;
-std::vector<std::array<hipEvent_t, LMS_NSTAGES + 1>> g_prof_events;
-
-struct StageEvents {
-  std::array<hipEvent_t, LMS_NSTAGES + 1> ev{};
-  bool on = false;
-  hipStream_t s = nullptr;
-  int next = 0;
-  void start(hipStream_t stream) {
-    std::lock_guard<std::mutex> lk(g_mu);
-    on = g_prof_on;
-    s = stream;
-    if (!on) return;
-    for (auto& e : ev)
-      if (hipEventCreate(&e) != hipSuccess) { on = false; return; }
-    mark();
-  }
-  void mark() {
-    if (on && next <= LMS_NSTAGES) (void)hipEventRecord(ev[next++], s);
-  }
-  void finish() {
-    if (!on) return;
-    std::lock_guard<std::mutex> lk(g_mu);
-    if (next == LMS_NSTAGES + 1) g_prof_events.push_back(ev);
-    else for (auto& e : ev) (void)hipEventDestroy(e);
-  }
-};
-
 struct Layout {
   size_t ctx, xy32, entries, res, total;
 };
@@ -639,36 +431,6 @@ Layout layout(int n_pad, long long cap) {
   L.res = L.entries + up((size_t)cap * sizeof(uint2));
   L.total = L.res + up((size_t)cap * sizeof(double4));
   return L;
-}
-
-lms_status get_workspace(void* stream, size_t bytes, char** base) {
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return fail(LMS_ERR_DEVICE, "hipGetDevice failed");
-  std::lock_guard<std::mutex> lk(g_mu);
-  if (g_num_cu == 0) {
-    hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, dev) != hipSuccess)
-      return fail(LMS_ERR_DEVICE, "hipGetDeviceProperties failed");
-    g_num_cu = prop.multiProcessorCount;
-  }
-  Workspace& w = g_ws[{dev, stream}];
-  if (w.bytes < bytes) {
-    if (w.base) {
-      // the old buffer may still be in use by work queued on this stream
-      if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess)
-        return fail(LMS_ERR_DEVICE, "hipStreamSynchronize failed");
-      (void)hipFree(w.base);
-      w.base = nullptr;
-      w.bytes = 0;
-    }
-    if (hipMalloc(&w.base, bytes) != hipSuccess) {
-      (void)hipGetLastError();
-      return fail(LMS_ERR_NOMEM, "hipMalloc of the workspace failed");
-    }
-    w.bytes = bytes;
-  }
-  *base = (char*)w.base;
-  return LMS_OK;
 }
 
 int next_pow2(int v) {
@@ -876,11 +638,11 @@ const char* lms_status_str(int s) {
   }
 }
 
-const char* lms_last_error(void) { return g_err.c_str(); }
+const char* lms_last_error(void) { return lms_host::last_error(); }
 
 lms_status lms_solve(const double* d_xy, int64_t n, int64_t h, lms_result* d_out,
                      const lms_options* opt, void* stream) {
-  g_err.clear();
+  lms_host::clear_error();
   if (opt && opt->struct_size < sizeof(lms_options)) return fail(LMS_ERR_ARG, "bad options size");
   Plan p;
   lms_status st = make_plan(d_xy, n, h, &p, opt ? opt->tile_regs : 0);
@@ -910,16 +672,16 @@ lms_status lms_solve(const double* d_xy, int64_t n, int64_t h, lms_result* d_out
   if (p.cap > INT_MAX) return fail(LMS_ERR_ARG, "too many seeds");
   const Layout L = layout(p.n_pad, p.cap);
   char* base = nullptr;
-  st = get_workspace(stream, L.total, &base);
+  st = lms_host::get_workspace(0, stream, L.total, &base);
   if (st != LMS_OK) return st;
   hipStream_t s = (hipStream_t)stream;
   Ctx* ctx = (Ctx*)(base + L.ctx);
   float2* xy32 = (float2*)(base + L.xy32);
   uint2* entries = (uint2*)(base + L.entries);
   double4* res = (double4*)(base + L.res);
-  const int cu = g_num_cu > 0 ? g_num_cu : 256;
+  const int cu = lms_host::num_cu();
 
-  StageEvents prof;
+  lms_host::StageEvents prof;
   prof.start(s);
   hipLaunchKernelGGL(k_prep, dim3(1), dim3(1024), 0, s, d_xy, p.n, p.h, p.n_pad, ctx, xy32,
                      entries, p.n_seeds, 0x5EEDull + (unsigned long long)p.n * 0x100000001ull);
@@ -959,7 +721,7 @@ lms_status lms_solve(const double* d_xy, int64_t n, int64_t h, lms_result* d_out
 
 lms_status lms_solve_host(const double* xy, int64_t n, int64_t h, lms_result* out,
                           const lms_options* opt) {
-  g_err.clear();
+  lms_host::clear_error();
   if (!xy || !out) return fail(LMS_ERR_ARG, "null pointer");
   if (n < 2 || n > LMS_MAX_N) return fail(LMS_ERR_ARG, "n out of range");
   if (opt && opt->n_seed_theta > 0) return fail(LMS_ERR_ARG, "device seed slopes need lms_solve");
@@ -983,17 +745,7 @@ lms_status lms_solve_host(const double* xy, int64_t n, int64_t h, lms_result* ou
     st = fail(LMS_ERR_DEVICE, "result copy failed");
   if (st == LMS_OK && out->status < 0) st = (lms_status)out->status;
   (void)hipStreamSynchronize(s);
-  {
-    // the workspace is keyed by this temporary stream: drop it
-    std::lock_guard<std::mutex> lk(g_mu);
-    int dev = 0;
-    (void)hipGetDevice(&dev);
-    auto it = g_ws.find({dev, (void*)s});
-    if (it != g_ws.end()) {
-      (void)hipFree(it->second.base);
-      g_ws.erase(it);
-    }
-  }
+  lms_host::free_workspace(0, (void*)s);  // keyed by this temporary stream
   if (d_xy) (void)hipFree(d_xy);
   if (d_out) (void)hipFree(d_out);
   (void)hipStreamDestroy(s);
@@ -1002,19 +754,14 @@ lms_status lms_solve_host(const double* xy, int64_t n, int64_t h, lms_result* ou
 
 lms_status lms_eval_slopes(const double* d_xy, int64_t n, int64_t h, const double* d_theta,
                            int64_t m, double* d_out, void* stream) {
-  g_err.clear();
+  lms_host::clear_error();
   Plan p;
   lms_status st = make_plan(d_xy, n, h, &p);
   if (st != LMS_OK) return st;
   if (m < 0 || m > INT_MAX || (m > 0 && (!d_theta || !d_out)))
     return fail(LMS_ERR_ARG, "bad slope array");
   if (m == 0) return LMS_OK;
-  if (g_num_cu == 0) {
-    char* b;
-    st = get_workspace(stream, 256, &b);
-    if (st != LMS_OK) return st;
-  }
-  launch_eval((hipStream_t)stream, (int)std::min<int64_t>(m, 8 * g_num_cu), d_xy, p.n, p.h,
+  launch_eval((hipStream_t)stream, (int)std::min<int64_t>(m, 8 * lms_host::num_cu()), d_xy, p.n, p.h,
               d_theta, (int)m, d_out, nullptr);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return fail(LMS_ERR_DEVICE, hipGetErrorString(err));
@@ -1023,7 +770,7 @@ lms_status lms_eval_slopes(const double* d_xy, int64_t n, int64_t h, const doubl
 
 lms_status lms_screen_pairs(const double* d_xy, int64_t n, int64_t h, double W,
                             const int32_t* d_pairs, int64_t m, int32_t* d_verdict, void* stream) {
-  g_err.clear();
+  lms_host::clear_error();
   Plan p;
   lms_status st = make_plan(d_xy, n, h, &p);
   if (st != LMS_OK) return st;
@@ -1035,7 +782,7 @@ lms_status lms_screen_pairs(const double* d_xy, int64_t n, int64_t h, double W,
   p.cap = 1;
   const Layout L = layout(p.n_pad, p.cap);
   char* base = nullptr;
-  st = get_workspace(stream, L.total, &base);
+  st = lms_host::get_workspace(0, stream, L.total, &base);
   if (st != LMS_OK) return st;
   hipStream_t s = (hipStream_t)stream;
   Ctx* ctx = (Ctx*)(base + L.ctx);
@@ -1048,41 +795,13 @@ lms_status lms_screen_pairs(const double* d_xy, int64_t n, int64_t h, double W,
   return LMS_OK;
 }
 
-void lms_profile_begin(void) {
-  std::lock_guard<std::mutex> lk(g_mu);
-  for (auto& ev : g_prof_events)
-    for (auto& e : ev) (void)hipEventDestroy(e);
-  g_prof_events.clear();
-  g_prof_on = true;
-}
+void lms_profile_begin(void) { lms_host::profile_begin(); }
 
-int64_t lms_profile_end(double* ms) {
-  std::lock_guard<std::mutex> lk(g_mu);
-  g_prof_on = false;
-  double sum[LMS_NSTAGES] = {0};
-  int64_t count = 0;
-  int64_t st = 0;
-  for (auto& ev : g_prof_events) {
-    if (st == 0 && hipEventSynchronize(ev[LMS_NSTAGES]) != hipSuccess) st = LMS_ERR_DEVICE;
-    for (int k = 0; st == 0 && k < LMS_NSTAGES; ++k) {
-      float t = 0.f;
-      if (hipEventElapsedTime(&t, ev[k], ev[k + 1]) != hipSuccess) st = LMS_ERR_DEVICE;
-      sum[k] += t;
-    }
-    for (auto& e : ev) (void)hipEventDestroy(e);
-    ++count;
-  }
-  g_prof_events.clear();
-  if (ms)
-    for (int k = 0; k < LMS_NSTAGES; ++k) ms[k] = sum[k];
-  return st != 0 ? st : count;
-}
+int64_t lms_profile_end(double* ms) { return lms_host::profile_end(ms); }
 
 void lms_shutdown(void) {
-  std::lock_guard<std::mutex> lk(g_mu);
-  for (auto& kv : g_ws)
-    if (kv.second.base) (void)hipFree(kv.second.base);
-  g_ws.clear();
+  lms_host::release_batches();
+  lms_host::free_workspaces();
 }
 
 }  // extern "C"

@@ -1,0 +1,680 @@
+// Batched exact LMS: many independent point sets in one pass of persistent
+// kernels, optionally captured in a hipGraph.
+//
+// Motivation: the paper follows a coarse Hough transform with one LMS fit
+// per accumulator peak, on the points that voted for it (Section 5). That is
+// many small, uneven problems. Launching one solve per problem leaves the GPU
+// idle between tiny kernels. Here every stage covers all problems at once:
+//
+//   k_bprep     one block per problem: n, h, finiteness, centring, the padded
+//               FP32 copy, seed pairs.
+//   k_bwindow   FP64 windows of the seed pairs (per-problem width bound W_b),
+//               later of the screen survivors.
+//   k_bscreen   persistent wavefronts over work items (problem, anchor), the
+//               same band and split tests as the single-problem screen, with
+//               the number of 64-point chunks of each problem as a runtime
+//               bound. One launch per register class (up to 512, 1024 and
+//               4096 points).
+//   k_bselect   canonical minimum per problem, (width, theta, z_lo, pair), in
+//               three passes of order-preserving u64 atomicMin over the
+//               entries.
+//   k_bfinal    one lms_result per problem.
+//
+// Every counter and key is initialised by a kernel (no memset nodes), so the
+// whole sequence replays from a captured graph.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <numeric>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "lms.h"
+#include "lms_device.h"
+#include "lms_host.h"
+
+namespace {
+
+using namespace lms_dev;
+using lms_host::fail;
+
+constexpr int kBatchMaxN = 4096;
+constexpr int kClassChunks[3] = {8, 16, 64};  // register classes: n <= 512, 1024, 4096
+constexpr long long kBatchScreenCap = 1ll << 24;
+
+// Per-problem state in device memory.
+struct __align__(16) PMeta {
+  int off, n, h, pad_off;
+  int R, status, all_x_equal, pad;
+  double xh, yh, xabs, yabs;
+  unsigned long long wbound;
+  unsigned long long best_w, best_th, best_lo, best_pair;
+  double best_hi;
+  unsigned long long vertical, survivors, evals, dir_evals, band_pass;
+};
+
+struct __align__(16) BState {
+  unsigned n_entries, overflow;
+  unsigned next_item[3];
+  unsigned pad[3];
+};
+
+// Entry: problem id and the pair packed as lo | hi << 16 (n <= 4096).
+__device__ __forceinline__ unsigned pack_pair(unsigned lo, unsigned hi) { return lo | (hi << 16); }
+constexpr unsigned kInvalidPair = 0xFFFFFFFEu;
+
+__device__ __forceinline__ double key_to_double(unsigned long long k) {
+  const unsigned long long b = (k >> 63) ? (k & 0x7FFFFFFFFFFFFFFFull) : ~k;
+  return __longlong_as_double((long long)b);
+}
+
+// ---------------------------------------------------------------- prep
+
+__global__ __launch_bounds__(256) void k_bprep(const double* __restrict__ xy,
+                                               const int64_t* __restrict__ offsets,
+                                               const int* __restrict__ d_h, int B,
+                                               const int* __restrict__ pad_off,
+                                               const int* __restrict__ chunks, PMeta* meta,
+                                               float2* __restrict__ xy32, uint2* __restrict__ entries,
+                                               int S, BState* state, unsigned long long seed_key) {
+  __shared__ double s_mn[256], s_mx[256], s_my[256], s_My[256];
+  __shared__ int s_amn[256], s_amx[256], s_fin[256];
+  const int b = blockIdx.x, t = threadIdx.x;
+  if (b == 0 && t == 0) {
+    BState st;
+    memset(&st, 0, sizeof(st));
+    st.n_entries = (unsigned)B * (unsigned)S;
+    *state = st;
+  }
+  const int off = (int)offsets[b];
+  const int n = (int)(offsets[b + 1] - offsets[b]);
+  const int h = d_h ? d_h[b] : n / 2 + 1;
+  double mnx = INFINITY, mxx = -INFINITY, mny = INFINITY, mxy = -INFINITY;
+  int amn = INT_MAX, amx = INT_MAX, fin = 1;
+  for (int k = t; k < n; k += blockDim.x) {
+    const double x = xy[2 * (off + k)], y = xy[2 * (off + k) + 1];
+    if (!isfinite(x) || !isfinite(y)) fin = 0;
+    if (x < mnx) { mnx = x; amn = k; }
+    if (x > mxx) { mxx = x; amx = k; }
+    mny = fmin(mny, y);
+    mxy = fmax(mxy, y);
+  }
+  s_mn[t] = mnx; s_mx[t] = mxx; s_my[t] = mny; s_My[t] = mxy;
+  s_amn[t] = amn; s_amx[t] = amx; s_fin[t] = fin;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (t < s) {
+      const int u = t + s;
+      if (s_mn[u] < s_mn[t] || (s_mn[u] == s_mn[t] && s_amn[u] < s_amn[t])) {
+        s_mn[t] = s_mn[u]; s_amn[t] = s_amn[u];
+      }
+      if (s_mx[u] > s_mx[t] || (s_mx[u] == s_mx[t] && s_amx[u] < s_amx[t])) {
+        s_mx[t] = s_mx[u]; s_amx[t] = s_amx[u];
+      }
+      s_my[t] = fmin(s_my[t], s_my[u]);
+      s_My[t] = fmax(s_My[t], s_My[u]);
+      s_fin[t] &= s_fin[u];
+    }
+    __syncthreads();
+  }
+  const double minx = s_mn[0], maxx = s_mx[0], miny = s_my[0], maxy = s_My[0];
+  int status = LMS_OK;
+  if (n < 2 || n > kBatchMaxN || h < 2 || h > n) status = LMS_ERR_ARG;
+  else if (!s_fin[0]) status = LMS_ERR_NONFINITE;
+  const bool ok = status == LMS_OK;
+  const double cx = minx + 0.5 * (maxx - minx), cy = miny + 0.5 * (maxy - miny);
+  const int R = chunks[b];
+  if (t == 0) {
+    PMeta m;
+    memset(&m, 0, sizeof(m));
+    m.off = off; m.n = n; m.h = h; m.pad_off = pad_off[b]; m.R = R;
+    m.status = status;
+    m.all_x_equal = ok && (minx == maxx);
+    if (ok) {
+      m.xh = fmax(fabs(minx - cx), fabs(maxx - cx)) * (1.0 + 0x1p-40);
+      m.yh = fmax(fabs(miny - cy), fabs(maxy - cy)) * (1.0 + 0x1p-40);
+      m.xabs = fmax(fabs(minx), fabs(maxx));
+      m.yabs = fmax(fabs(miny), fabs(maxy));
+    }
+    m.wbound = 0x7FF0000000000000ull;
+    m.best_w = m.best_th = m.best_lo = m.best_pair = ~0ull;
+    meta[b] = m;
+  }
+  const float qnan = __int_as_float(0x7FC00000);
+  const int po = pad_off[b];
+  for (int k = t; k < 64 * R; k += blockDim.x) {
+    float2 p = make_float2(qnan, qnan);
+    if (ok && k < n)
+      p = make_float2((float)(xy[2 * (off + k)] - cx), (float)(xy[2 * (off + k) + 1] - cy));
+    xy32[po + k] = p;
+  }
+  for (int e = t; e < S; e += blockDim.x) {
+    unsigned code = kInvalidPair;
+    if (ok && e == 0) {
+      code = (minx == maxx) ? kDegenerate
+                            : pack_pair((unsigned)min(s_amn[0], s_amx[0]),
+                                        (unsigned)max(s_amn[0], s_amx[0]));
+    } else if (ok && minx != maxx) {
+      const unsigned long long r =
+          mix64(seed_key + 0x9E3779B97F4A7C15ull * ((unsigned long long)b * 4096u + e + 1));
+      const unsigned a = (unsigned)((r >> 32) % (unsigned long long)n);
+      unsigned c = (unsigned)((r & 0xFFFFFFFFull) % (unsigned long long)(n - 1));
+      if (c >= a) ++c;
+      code = pack_pair(min(a, c), max(a, c));
+    }
+    entries[(size_t)b * S + e] = make_uint2((unsigned)b, code);
+  }
+}
+
+// ---------------------------------------------------------------- FP64 windows
+
+// FP64 window of each entry in [begin, end): pair slope, fma intercepts, a
+// bitonic sort of next_pow2(n_b) values in LDS, narrowest window. Lowers the
+// problem's best width key, and with update_bound also its screen bound.
+template <int NMAX, int NT>
+__global__ __launch_bounds__(NT) void k_bwindow(const double* __restrict__ xy, PMeta* meta,
+                                                const uint2* __restrict__ entries,
+                                                double4* __restrict__ res, int begin,
+                                                const BState* state, int fixed_end, int cap,
+                                                int update_bound) {
+  __shared__ double z[NMAX];
+  __shared__ unsigned long long s_w;
+  __shared__ int s_s;
+  const unsigned end = fixed_end >= 0 ? (unsigned)fixed_end : min(state->n_entries, (unsigned)cap);
+  for (unsigned e = begin + blockIdx.x; e < end; e += gridDim.x) {
+    const uint2 en = entries[e];
+    const PMeta m = meta[en.x];
+    if (m.status != LMS_OK || en.y == kInvalidPair) {
+      if (threadIdx.x == 0) res[e] = make_double4(INFINITY, NAN, NAN, NAN);
+      continue;
+    }
+    double theta = 0.0;
+    if (en.y != kDegenerate) {
+      const int lo = m.off + (int)(en.y & 0xFFFFu), hi = m.off + (int)(en.y >> 16);
+      const double xl = xy[2 * lo], xr = xy[2 * hi];
+      if (xl == xr) {
+        if (threadIdx.x == 0) res[e] = make_double4(INFINITY, NAN, NAN, NAN);
+        continue;
+      }
+      theta = (xy[2 * hi + 1] - xy[2 * lo + 1]) / (xr - xl);
+    }
+    int n2 = 64;
+    while (n2 < m.n) n2 <<= 1;
+    double w, lo, hi;
+    window_f64_rt<NMAX, NT>(xy + 2 * m.off, m.n, m.h, n2, theta, z, &s_w, &s_s, &w, &lo, &hi);
+    if (threadIdx.x == 0) {
+      res[e] = make_double4(w, theta, lo, hi);
+      if (w == w) atomicMin(&meta[en.x].best_w, (unsigned long long)__double_as_longlong(w));
+      if (update_bound && w == w)
+        atomicMin(&meta[en.x].wbound, (unsigned long long)__double_as_longlong(
+                                          width_bound(w, theta, m.xabs, m.yabs)));
+    }
+  }
+}
+
+// ---------------------------------------------------------------- screen
+
+// Work item = (problem, anchor i): all partners j = (i + o) mod n, o = 1..P(i),
+// in batches of 64. Items of one register class are numbered problem by
+// problem in the order `order` (largest problems first); item_begin[p] is
+// the first item of the p-th problem in that order.
+template <int RMAX>
+__global__ __launch_bounds__(256, 3) void k_bscreen(
+    const double* __restrict__ xy, const float2* __restrict__ xy32, PMeta* meta,
+    const int* __restrict__ order, const int* __restrict__ item_begin, int n_probs, int n_items,
+    uint2* __restrict__ entries, int cap, BState* state, int cls) {
+  const int lane = threadIdx.x & 63;
+  for (;;) {
+    int item = 0;
+    if (lane == 0) item = (int)atomicAdd(&state->next_item[cls], 1u);
+    item = __shfl(item, 0);
+    if (item >= n_items) break;
+    // p = last problem with item_begin[p] <= item
+    int lo_p = 0, hi_p = n_probs - 1;
+    while (lo_p < hi_p) {
+      const int mid = (lo_p + hi_p + 1) >> 1;
+      if (item_begin[mid] <= item) lo_p = mid;
+      else hi_p = mid - 1;
+    }
+    const int b = __builtin_amdgcn_readfirstlane(order[lo_p]);
+    const int i = item - item_begin[lo_p];
+    const PMeta m = meta[b];
+    if (m.status != LMS_OK || m.all_x_equal) continue;
+    // per-problem scalars, made explicitly wave-uniform (SGPRs)
+    const int n = __builtin_amdgcn_readfirstlane(m.n);
+    const int h = __builtin_amdgcn_readfirstlane(m.h);
+    const int Rb = __builtin_amdgcn_readfirstlane(m.R);
+    const int poff = __builtin_amdgcn_readfirstlane(m.pad_off);
+    const int goff = __builtin_amdgcn_readfirstlane(m.off);
+    const float2* pts = xy32 + poff;
+    const float2 pi = pts[i];
+    const float2* src = pts;
+    asm volatile("" : "+s"(src));
+    float X[RMAX], Y[RMAX];
+#pragma unroll
+    for (int r = 0; r < RMAX; ++r) {
+      if (r < Rb) {
+        const float2 p = src[lane + 64 * r];
+        X[r] = p.x - pi.x;
+        Y[r] = p.y - pi.y;
+      }
+    }
+    const int half = n >> 1;
+    const int P = (n & 1) ? half : (i < half ? half : half - 1);
+    const double* gxy = xy + 2 * goff;
+    const double W = __longlong_as_double((long long)m.wbound);
+    unsigned long long n_vert = 0, n_evals = 0, n_devals = 0, n_band = 0, n_keep = 0;
+    for (int o0 = 1; o0 <= P; o0 += 64) {
+      const int o = o0 + lane;
+      const bool valid = o <= P;
+      int j = i + (valid ? o : 1);
+      if (j >= n) j -= n;
+      const int lo = min(i, j), hi = max(i, j);
+      const double xl = gxy[2 * lo], yl = gxy[2 * lo + 1];
+      const double xr = gxy[2 * hi], yr = gxy[2 * hi + 1];
+      const bool vert = valid && (xl == xr);
+      const double th = (yr - yl) / (xr - xl);
+      const double tau = tau_bound(th, m.xh, m.yh);
+      const bool force = valid && !vert && !(fabs(th) < 1e30 && tau < 1e30);
+      const bool test = valid && !vert && !force;
+      const float th32 = test ? (float)th : 0.0f;
+      const float thr = test ? f32_up(W + tau) : 0.0f;
+      const float ta = test ? f32_up(tau) : 0.0f;
+      n_vert += __popcll(__ballot(vert));
+      if (force) {
+        const unsigned idx = atomicAdd(&state->n_entries, 1u);
+        if (idx < (unsigned)cap) entries[idx] = make_uint2((unsigned)b, pack_pair(lo, hi));
+        else atomicOr(&state->overflow, 1u);
+        atomicAdd(&meta[b].survivors, 1ull);
+      }
+      unsigned long long msk = __ballot(test);
+      while (msk) {
+        const int cl = __ffsll((long long)msk) - 1;
+        msk &= msk - 1;
+        const PairTest pt = test_pair_rt<RMAX>(X, Y, Rb, -lane_f(th32, cl), lane_f(thr, cl),
+                                               lane_f(ta, cl), h);
+        n_evals += (unsigned)pt.band_chunks;
+        if (pt.split_chunks >= 0) {
+          ++n_band;
+          n_devals += (unsigned)pt.split_chunks;
+        }
+        if (pt.keep) {
+          ++n_keep;
+          if (lane == 0) {
+            const unsigned idx = atomicAdd(&state->n_entries, 1u);
+            if (idx < (unsigned)cap)
+              entries[idx] = make_uint2((unsigned)b, pack_pair((unsigned)lane_i(lo, cl),
+                                                              (unsigned)lane_i(hi, cl)));
+            else
+              atomicOr(&state->overflow, 1u);
+          }
+        }
+      }
+    }
+    if (lane == 0) {
+      if (n_vert) atomicAdd(&meta[b].vertical, n_vert);
+      if (n_keep) atomicAdd(&meta[b].survivors, n_keep);
+      atomicAdd(&meta[b].evals, 64ull * n_evals);
+      if (n_band) {
+        atomicAdd(&meta[b].band_pass, n_band);
+        atomicAdd(&meta[b].dir_evals, 64ull * n_devals);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- selection
+
+// pass 1: slope key among the narrowest; pass 2: z_lo key; pass 3: pair key
+// and the window's upper end.
+__global__ __launch_bounds__(256) void k_bselect(const uint2* __restrict__ entries,
+                                                 const double4* __restrict__ res, PMeta* meta,
+                                                 const BState* state, int cap, int pass) {
+  const unsigned end = min(state->n_entries, (unsigned)cap);
+  for (unsigned e = blockIdx.x * blockDim.x + threadIdx.x; e < end; e += gridDim.x * blockDim.x) {
+    const double4 r = res[e];
+    if (!(r.x < INFINITY)) continue;
+    const uint2 en = entries[e];
+    PMeta* m = &meta[en.x];
+    if ((unsigned long long)__double_as_longlong(r.x) != m->best_w) continue;
+    const unsigned long long kth = order_key(r.y);
+    if (pass == 1) { atomicMin(&m->best_th, kth); continue; }
+    if (kth != m->best_th) continue;
+    const unsigned long long klo = order_key(r.z);
+    if (pass == 2) { atomicMin(&m->best_lo, klo); continue; }
+    if (klo != m->best_lo) continue;
+    const unsigned long long kp =
+        en.y == kDegenerate ? ~0ull - 1
+                            : ((unsigned long long)(en.y & 0xFFFFu) << 32) | (en.y >> 16);
+    atomicMin(&m->best_pair, kp);
+    m->best_hi = r.w;  // equal slope => identical sorted intercepts => same window
+  }
+}
+
+__global__ __launch_bounds__(256) void k_bfinal(const PMeta* __restrict__ meta, int B,
+                                                const BState* state, lms_result* out) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  const PMeta m = meta[b];
+  lms_result o;
+  memset(&o, 0, sizeof(o));
+  o.h = m.h;
+  int st = m.status;
+  if (st >= 0 && state->overflow) st = LMS_ERR_CAPACITY;
+  if (st >= 0 && m.best_w == ~0ull) st = LMS_ERR_DEVICE;
+  if (st >= 0 && m.all_x_equal) st = LMS_OK_DEGENERATE;
+  o.status = st;
+  const unsigned long long pairs =
+      m.n >= 2 ? (unsigned long long)m.n * (unsigned long long)(m.n - 1) / 2 : 0;
+  if (st < 0) {
+    o.theta1 = o.theta2 = o.half_width = o.width = o.z_lo = o.z_hi = NAN;
+    o.pair_i = o.pair_j = -1;
+  } else {
+    o.width = __longlong_as_double((long long)m.best_w);
+    o.half_width = 0.5 * o.width;
+    o.theta1 = key_to_double(m.best_th);
+    o.z_lo = key_to_double(m.best_lo);
+    o.z_hi = m.best_hi;
+    o.theta2 = 0.5 * (o.z_lo + o.z_hi);
+    if (m.best_pair >= ~0ull - 1) {
+      o.pair_i = o.pair_j = -1;
+    } else {
+      o.pair_i = (int)(m.best_pair >> 32);
+      o.pair_j = (int)(m.best_pair & 0xFFFFFFFFull);
+    }
+  }
+  o.vertical = m.all_x_equal ? pairs : m.vertical;
+  o.candidates = pairs - o.vertical;
+  o.survivors = m.survivors;
+  o.point_evals = m.evals;
+  o.dir_evals = m.dir_evals;
+  o.band_pass = m.band_pass;
+  out[b] = o;
+}
+
+// ---------------------------------------------------------------- host side
+
+// Host-side plan of a batch: per-problem padding and register class, and the
+// work order of each class. Cached by the content of the offsets.
+struct BPlan {
+  int B = 0, S = 0, max_n = 0;
+  long long pad_total = 0, pairs = 0, cap = 0;
+  int n_probs[3] = {0, 0, 0};
+  int n_items[3] = {0, 0, 0};
+  // device arrays inside the workspace
+  size_t o_meta = 0, o_state = 0, o_pad = 0, o_chunks = 0, o_order = 0, o_ibeg = 0, o_xy32 = 0,
+         o_entries = 0, o_res = 0, total = 0;
+  size_t order_off[3] = {0, 0, 0}, ibeg_off[3] = {0, 0, 0};
+  std::vector<int> h_pad, h_chunks, h_order, h_ibeg;
+};
+
+size_t up256(size_t v) { return (v + 255) & ~size_t(255); }
+
+lms_status plan_batch(const int64_t* h_off, int B, int S, BPlan* P) {
+  P->B = B;
+  P->S = S;
+  P->h_pad.assign(B, 0);
+  P->h_chunks.assign(B, 1);
+  std::vector<std::vector<int>> cls(3);
+  long long pad = 0;
+  for (int b = 0; b < B; ++b) {
+    const long long n = h_off[b + 1] - h_off[b];
+    if (n < 0) return fail(LMS_ERR_ARG, "offsets must be non-decreasing");
+    if (n > kBatchMaxN)
+      return fail(LMS_ERR_ARG, "batched problems hold at most 4096 points; use lms_solve");
+    const int R = (int)std::max<long long>(1, (n + 63) / 64);
+    P->h_chunks[b] = R;
+    P->h_pad[b] = (int)pad;
+    pad += 64ll * R;
+    P->max_n = std::max<int>(P->max_n, (int)n);
+    P->pairs += n * (n - 1) / 2;
+    if (n >= 2) cls[R <= kClassChunks[0] ? 0 : R <= kClassChunks[1] ? 1 : 2].push_back(b);
+  }
+  if (h_off[0] < 0) return fail(LMS_ERR_ARG, "offsets must be >= 0");
+  P->pad_total = pad;
+  P->h_order.clear();
+  P->h_ibeg.clear();
+  for (int c = 0; c < 3; ++c) {
+    auto& v = cls[c];
+    // largest problems first: the tail of the persistent loop is small items
+    std::stable_sort(v.begin(), v.end(), [&](int a, int b) {
+      return (h_off[a + 1] - h_off[a]) > (h_off[b + 1] - h_off[b]);
+    });
+    P->order_off[c] = P->h_order.size();
+    P->ibeg_off[c] = P->h_ibeg.size();
+    long long items = 0;
+    for (int b : v) {
+      P->h_order.push_back(b);
+      P->h_ibeg.push_back((int)items);
+      items += h_off[b + 1] - h_off[b];
+    }
+    if (items > INT_MAX) return fail(LMS_ERR_ARG, "batch too large");
+    P->h_ibeg.push_back((int)items);
+    P->n_probs[c] = (int)v.size();
+    P->n_items[c] = (int)items;
+  }
+  const long long seeds = (long long)B * S;
+  P->cap = seeds + std::min<long long>(P->pairs, kBatchScreenCap);
+  if (P->cap > INT_MAX) return fail(LMS_ERR_ARG, "batch too large");
+  size_t o = 0;
+  P->o_state = o; o += up256(sizeof(BState));
+  P->o_meta = o; o += up256((size_t)B * sizeof(PMeta));
+  P->o_pad = o; o += up256((size_t)B * sizeof(int));
+  P->o_chunks = o; o += up256((size_t)B * sizeof(int));
+  P->o_order = o; o += up256(P->h_order.size() * sizeof(int) + 4);
+  P->o_ibeg = o; o += up256(P->h_ibeg.size() * sizeof(int) + 4);
+  P->o_xy32 = o; o += up256((size_t)pad * sizeof(float2));
+  P->o_entries = o; o += up256((size_t)P->cap * sizeof(uint2));
+  P->o_res = o; o += up256((size_t)P->cap * sizeof(double4));
+  P->total = o;
+  return LMS_OK;
+}
+
+template <int NMAX>
+void launch_bwindow(hipStream_t s, int grid, const double* xy, PMeta* meta, const uint2* e,
+                    double4* res, int begin, const BState* st, int fixed_end, int cap, int upd) {
+  constexpr int NT = NMAX >= 2048 ? 512 : (NMAX >= 512 ? 256 : 128);
+  hipLaunchKernelGGL((k_bwindow<NMAX, NT>), dim3(grid), dim3(NT), 0, s, xy, meta, e, res, begin,
+                     st, fixed_end, cap, upd);
+}
+
+void launch_bwindow_n(hipStream_t s, int max_n, int grid, const double* xy, PMeta* meta,
+                      const uint2* e, double4* res, int begin, const BState* st, int fixed_end,
+                      int cap, int upd) {
+  if (max_n <= 256) launch_bwindow<256>(s, grid, xy, meta, e, res, begin, st, fixed_end, cap, upd);
+  else if (max_n <= 512) launch_bwindow<512>(s, grid, xy, meta, e, res, begin, st, fixed_end, cap, upd);
+  else if (max_n <= 1024) launch_bwindow<1024>(s, grid, xy, meta, e, res, begin, st, fixed_end, cap, upd);
+  else launch_bwindow<4096>(s, grid, xy, meta, e, res, begin, st, fixed_end, cap, upd);
+}
+
+struct BatchKey {
+  const void* xy;
+  const void* off;
+  const void* h;
+  const void* out;
+  void* stream;
+  int B, S;
+  bool operator<(const BatchKey& o) const {
+    return std::tie(xy, off, h, out, stream, B, S) <
+           std::tie(o.xy, o.off, o.h, o.out, o.stream, o.B, o.S);
+  }
+};
+
+// A plan with its own device buffer (plan arrays, state, FP32 copy, entries)
+// and, once captured, its graph.
+struct BatchCache {
+  std::vector<int64_t> offsets;  // the offsets the plan was made for
+  BPlan plan;
+  char* base = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  void release() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (base) (void)hipFree(base);
+    exec = nullptr;
+    graph = nullptr;
+    base = nullptr;
+  }
+};
+
+std::mutex g_bmu;
+std::map<BatchKey, BatchCache> g_batches;
+
+// Enqueues the whole batched pipeline on s (capturable: kernels only).
+lms_status enqueue_batch(const BPlan& P, char* base, const double* d_xy, const int64_t* d_off,
+                         const int32_t* d_h, lms_result* d_out, hipStream_t s,
+                         lms_host::StageEvents* prof) {
+  PMeta* meta = (PMeta*)(base + P.o_meta);
+  BState* state = (BState*)(base + P.o_state);
+  const int* pad = (const int*)(base + P.o_pad);
+  const int* chunks = (const int*)(base + P.o_chunks);
+  const int* order = (const int*)(base + P.o_order);
+  const int* ibeg = (const int*)(base + P.o_ibeg);
+  float2* xy32 = (float2*)(base + P.o_xy32);
+  uint2* entries = (uint2*)(base + P.o_entries);
+  double4* res = (double4*)(base + P.o_res);
+  const int cu = lms_host::num_cu();
+  const int cap = (int)P.cap;
+  const int seeds = P.B * P.S;
+  hipLaunchKernelGGL(k_bprep, dim3(P.B), dim3(256), 0, s, d_xy, d_off, d_h, P.B, pad, chunks,
+                     meta, xy32, entries, P.S, state, 0xBA7C4ull);
+  if (prof) prof->mark();
+  launch_bwindow_n(s, P.max_n, std::min(seeds, 16 * cu), d_xy, meta, entries, res, 0, state,
+                   seeds, cap, 1);
+  if (prof) prof->mark();
+  for (int c = 0; c < 3; ++c) {
+    if (P.n_items[c] == 0) continue;
+    const int* ord = order + P.order_off[c];
+    const int* ib = ibeg + P.ibeg_off[c];
+    const int grid = std::max(1, std::min((P.n_items[c] + 3) / 4, 3 * cu));
+    switch (c) {
+      case 0:
+        hipLaunchKernelGGL((k_bscreen<8>), dim3(grid), dim3(256), 0, s, d_xy, xy32, meta, ord, ib,
+                           P.n_probs[c], P.n_items[c], entries, cap, state, c);
+        break;
+      case 1:
+        hipLaunchKernelGGL((k_bscreen<16>), dim3(grid), dim3(256), 0, s, d_xy, xy32, meta, ord, ib,
+                           P.n_probs[c], P.n_items[c], entries, cap, state, c);
+        break;
+      default:
+        hipLaunchKernelGGL((k_bscreen<64>), dim3(grid), dim3(256), 0, s, d_xy, xy32, meta, ord, ib,
+                           P.n_probs[c], P.n_items[c], entries, cap, state, c);
+        break;
+    }
+  }
+  if (prof) prof->mark();
+  launch_bwindow_n(s, P.max_n, 16 * cu, d_xy, meta, entries, res, seeds, state, -1, cap, 0);
+  if (prof) prof->mark();
+  for (int pass = 1; pass <= 3; ++pass)
+    hipLaunchKernelGGL(k_bselect, dim3(4 * cu), dim3(256), 0, s, entries, res, meta, state, cap,
+                       pass);
+  hipLaunchKernelGGL(k_bfinal, dim3((P.B + 255) / 256), dim3(256), 0, s, meta, P.B, state, d_out);
+  if (prof) prof->mark();
+  const hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return fail(LMS_ERR_DEVICE, std::string("launch: ") + hipGetErrorString(err));
+  return LMS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lms_status lms_solve_batched(const double* d_xy, const int64_t* d_offsets,
+                             const int64_t* h_offsets, int64_t B, const int32_t* d_h,
+                             lms_result* d_out, const lms_options* opt, void* stream) {
+  lms_host::clear_error();
+  if (!d_xy || !d_offsets || !d_out) return fail(LMS_ERR_ARG, "null pointer");
+  if (B < 1 || B > (1 << 24)) return fail(LMS_ERR_ARG, "B must be in [1, 2^24]");
+  if (opt && opt->struct_size < sizeof(lms_options)) return fail(LMS_ERR_ARG, "bad options size");
+  unsigned flags = opt ? opt->flags : 0u;
+  int S = 1 + (opt && opt->seed_pairs >= 0 ? std::min(opt->seed_pairs, 1 << 16) : 31);
+  if (opt && opt->seed_pairs < 0) return fail(LMS_ERR_ARG, "seed_pairs must be >= 0");
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<int64_t> off((size_t)B + 1);
+  if (h_offsets) {
+    std::memcpy(off.data(), h_offsets, off.size() * sizeof(int64_t));
+  } else {
+    if (hipMemcpyAsync(off.data(), d_offsets, off.size() * sizeof(int64_t), hipMemcpyDeviceToHost,
+                       s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return fail(LMS_ERR_DEVICE, "copying the offsets to the host failed");
+  }
+  const BatchKey key{d_xy, d_offsets, d_h, d_out, stream, (int)B, S};
+  std::lock_guard<std::mutex> lk(g_bmu);
+  BatchCache& bc = g_batches[key];
+  const bool same = bc.plan.B == (int)B && bc.offsets == off;
+  if (!same) {
+    // work queued with the old plan may still use its buffer
+    if (bc.base && hipStreamSynchronize(s) != hipSuccess)
+      return fail(LMS_ERR_DEVICE, "hipStreamSynchronize failed");
+    bc.release();
+    BPlan P;
+    lms_status st = plan_batch(off.data(), (int)B, S, &P);
+    if (st != LMS_OK) { g_batches.erase(key); return st; }
+    char* base = nullptr;
+    if (hipMalloc(&base, P.total) != hipSuccess) {
+      (void)hipGetLastError();
+      g_batches.erase(key);
+      return fail(LMS_ERR_NOMEM, "hipMalloc of the batch buffer failed");
+    }
+    // plan arrays: staged once, synchronously, outside any graph
+    if (hipMemcpy(base + P.o_pad, P.h_pad.data(), P.h_pad.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(base + P.o_chunks, P.h_chunks.data(), P.h_chunks.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+        (!P.h_order.empty() && hipMemcpy(base + P.o_order, P.h_order.data(), P.h_order.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess) ||
+        hipMemcpy(base + P.o_ibeg, P.h_ibeg.data(), P.h_ibeg.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess) {
+      (void)hipFree(base);
+      g_batches.erase(key);
+      return fail(LMS_ERR_DEVICE, "uploading the batch plan failed");
+    }
+    bc.offsets = off;
+    bc.plan = std::move(P);
+    bc.base = base;
+  }
+  if (flags & LMS_F_GRAPH) {
+    if (!bc.exec) {
+      if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return fail(LMS_ERR_DEVICE, "hipStreamBeginCapture failed");
+      const lms_status st = enqueue_batch(bc.plan, bc.base, d_xy, d_offsets, d_h, d_out, s, nullptr);
+      hipGraph_t g = nullptr;
+      const hipError_t e = hipStreamEndCapture(s, &g);
+      if (st != LMS_OK) { if (g) (void)hipGraphDestroy(g); return st; }
+      if (e != hipSuccess || !g) return fail(LMS_ERR_DEVICE, "hipStreamEndCapture failed");
+      if (hipGraphInstantiate(&bc.exec, g, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return fail(LMS_ERR_DEVICE, "hipGraphInstantiate failed");
+      }
+      bc.graph = g;
+    }
+    lms_host::StageEvents prof;
+    prof.start(s);
+    if (hipGraphLaunch(bc.exec, s) != hipSuccess) return fail(LMS_ERR_DEVICE, "hipGraphLaunch failed");
+    for (int k = 0; k < LMS_NSTAGES; ++k) prof.mark();  // the whole graph is stage 0
+    prof.finish();
+    return LMS_OK;
+  }
+  lms_host::StageEvents prof;
+  prof.start(s);
+  const lms_status st = enqueue_batch(bc.plan, bc.base, d_xy, d_offsets, d_h, d_out, s, &prof);
+  prof.finish();
+  return st;
+}
+
+}  // extern "C"
+
+namespace lms_host {
+
+void release_batches() {
+  std::lock_guard<std::mutex> lk(g_bmu);
+  for (auto& kv : g_batches) kv.second.release();
+  g_batches.clear();
+}
+
+}  // namespace lms_host

@@ -1,0 +1,236 @@
+// Device-side building blocks shared by the single-problem and batched LMS
+// kernels (gfx950). See lms.hip for the method and the pipeline.
+#ifndef LMS_DEVICE_H
+#define LMS_DEVICE_H
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cmath>
+
+namespace lms_dev {
+
+constexpr unsigned kDegenerate = 0xFFFFFFFFu;  // entry code: slope 0, all x equal
+
+__device__ __forceinline__ unsigned long long mix64(unsigned long long z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// Smallest float >= v (v finite and >= 0 here; +inf stays +inf).
+__device__ __forceinline__ float f32_up(double v) {
+  float f = (float)v;
+  if ((double)f < v) f = nextafterf(f, INFINITY);
+  return f;
+}
+
+__device__ __forceinline__ float lane_f(float v, int c) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), c));
+}
+__device__ __forceinline__ int lane_i(int v, int c) { return __builtin_amdgcn_readlane(v, c); }
+
+// Upper bound on the exact width at slope theta given its FP64 width w:
+// every z carries at most one rounding of |z| <= yabs + |theta| xabs.
+__device__ __forceinline__ double width_bound(double w, double theta, double xabs,
+                                              double yabs) {
+  const double zmax = yabs + fabs(theta) * xabs;
+  return (w + 4.0 * 0x1p-53 * zmax) * (1.0 + 0x1p-50);
+}
+
+// Bound on |d_fp32 - d_exact| for every anchored residual at slope theta
+// (centred FP32 coordinates, FP32 slope, one FMA; see the derivation above
+// the screen kernel).
+__device__ __forceinline__ double tau_bound(double theta, double xh, double yh) {
+  return 0x1p-24 * (6.25 * yh + 8.25 * fabs(theta) * xh);
+}
+
+// Order-preserving map of a non-NaN double to u64 (for atomicMin keys).
+__device__ __forceinline__ unsigned long long order_key(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+
+// ---------------------------------------------------------------- FP64 window
+
+// Narrowest window of h consecutive values of z_k = fma(-theta, x_k, y_k),
+// k < n, computed by the whole block; z is an LDS array of N2 >= n doubles.
+// Same operation sequence as the reference: fma, full sort, subtraction, and
+// the lowest window among equally narrow ones.
+template <int NMAX, int NT>
+__device__ void window_f64_rt(const double* __restrict__ xy, int n, int h, int n2, double theta,
+                              double* z, unsigned long long* s_w, int* s_s, double* width,
+                              double* z_lo, double* z_hi) {
+  const int t = threadIdx.x;
+  for (int k = t; k < n2; k += NT)
+    z[k] = (k < n) ? fma(-theta, xy[2 * k], xy[2 * k + 1]) : INFINITY;
+  if (t == 0) { *s_w = ~0ull; *s_s = INT_MAX; }
+  __syncthreads();
+  for (int k = 2; k <= n2; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int q = t; q < n2 / 2; q += NT) {
+        const int a = 2 * q - (q & (j - 1));
+        const int b = a + j;
+        const double va = z[a], vb = z[b];
+        const bool up = (a & k) == 0;
+        if ((va > vb) == up) { z[a] = vb; z[b] = va; }
+      }
+      __syncthreads();
+    }
+  }
+  double bw = INFINITY;
+  int bs = INT_MAX;
+  for (int s = t; s + h <= n; s += NT) {
+    const double w = z[s + h - 1] - z[s];
+    if (w < bw) { bw = w; bs = s; }
+  }
+  const unsigned long long bwb = (unsigned long long)__double_as_longlong(bw);
+  atomicMin(s_w, bwb);
+  __syncthreads();
+  if (bs != INT_MAX && bwb == *s_w) atomicMin(s_s, bs);
+  __syncthreads();
+  // No window compares below +inf only if the slope or the data overflow to
+  // NaN; report NaN and read window 0, which always exists.
+  const int s = (*s_s == INT_MAX) ? 0 : *s_s;
+  *width = (*s_s == INT_MAX) ? NAN : __longlong_as_double((long long)*s_w);
+  *z_lo = z[s];
+  *z_hi = z[s + h - 1];
+  __syncthreads();
+}
+
+// Narrowest window of h consecutive values of z_k = fma(-theta, x_k, y_k),
+// k < n, computed by the whole block; z is an LDS array of N2 >= n doubles.
+// Same operation sequence as the reference: fma, full sort, subtraction, and
+// the lowest window among equally narrow ones.
+template <int N2, int NT>
+__device__ __forceinline__ void window_f64(const double* __restrict__ xy, int n, int h,
+                                           double theta, double* z, unsigned long long* s_w,
+                                           int* s_s, double* width, double* z_lo, double* z_hi) {
+  window_f64_rt<N2, NT>(xy, n, h, N2, theta, z, s_w, s_s, width, z_lo, z_hi);
+}
+
+// ---------------------------------------------------------------- FP32 screen
+
+// Error bound tau. With u = 2^-24, centred coordinates a_k = x_k - cx (exact),
+// |x32_k - a_k| <= u|a_k| (1 + 2^-29) and the same for y. For a pair (i, j)
+// at exact slope theta the anchored residual is d_k = (y_k - y_i) -
+// theta (x_k - x_i). The kernel evaluates either
+//   (registers) d = fl(fma(-theta32, fl(x32_k - x32_i), fl(y32_k - y32_i))), or
+//   (LDS)       d = fl(fl(fma(-theta32, x32_k, y32_k)) - fl(fma(-theta32, x32_i, y32_i))),
+// with |theta32 - theta| <= u|theta| (1 + 2^-28). Summing the input, shift,
+// slope and FMA roundings gives, for both forms and to first order,
+//   |d - d_k| <= u (6 Yh + 8 |theta| Xh),
+// where Xh, Yh bound |x - cx| and |y - cy|. tau_bound adds a 4 % margin for the
+// higher-order terms. If the exact anchored window [0, W] (or [-W, 0]) holds h
+// points, their FP32 residuals lie in [-tau, W + tau] (or [-W - tau, tau]).
+
+// Screen test of one pair (uniform across the wavefront).
+//  Band test: B = #{|d| <= thr}, thr = W + tau. A pair whose anchored window
+//  of width <= W holds h points has B >= h; misses beyond 64*chunks - h reject
+//  it at once.
+//  Split test: with N = #{-thr <= d < -ta} and P = #{ta < d <= thr}, the
+//  one-sided counts are up = B - N and dn = B - P, so the pair survives iff
+//  N <= B - h or P <= B - h. Both counts only grow, so the pair is rejected as
+//  soon as both exceed B - h, usually within a few chunks.
+// Outcome of one pair's test: keep flag and the 64-point chunks evaluated by
+// the band and split passes (-1 split chunks: the band test rejected).
+struct PairTest {
+  int keep, band_chunks, split_chunks;
+};
+
+template <int R, bool LDS_PART>
+__device__ __forceinline__ PairTest test_pair(const float (&X)[R], const float (&Y)[R],
+                                              const float2* __restrict__ lds, int nq, float nth,
+                                              float thr, float ta, float nc, int h) {
+  const int lane = threadIdx.x & 63;
+  const int total = R + (LDS_PART ? nq : 0);  // chunks of 64 points (padding never hits)
+  // misses allowed before the pair is certainly rejected
+  const int budget = 64 * total - h;
+  int miss = 0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const float d = fmaf(nth, X[r], Y[r]);
+    miss += __popcll(__ballot(!(fabsf(d) <= thr)));
+    if ((r & 7) == 7 || r == R - 1) {
+      if (miss > budget) return {0, r + 1, -1};
+    }
+  }
+  if (LDS_PART) {
+    for (int q = 0; q < nq; ++q) {
+      const float2 p = lds[q * 64 + lane];
+      const float d = fmaf(nth, p.x, p.y) + nc;
+      miss += __popcll(__ballot(!(fabsf(d) <= thr)));
+      if (((q & 7) == 7 || q == nq - 1) && miss > budget) return {0, R + q + 1, -1};
+    }
+  }
+  const int slack = budget - miss;  // B - h >= 0
+  // The slope goes through an opaque copy so that the compiler recomputes the
+  // residuals instead of keeping all R of them live from the band test.
+  asm volatile("" : "+v"(nth));
+  int below = 0, above = 0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const float d = fmaf(nth, X[r], Y[r]);
+    above += __popcll(__ballot(d > ta && d <= thr));
+    below += __popcll(__ballot(d < -ta && d >= -thr));
+    if (above > slack && below > slack) return {0, total, r + 1};
+  }
+  if (LDS_PART) {
+    for (int q = 0; q < nq; ++q) {
+      const float2 p = lds[q * 64 + lane];
+      const float d = fmaf(nth, p.x, p.y) + nc;
+      above += __popcll(__ballot(d > ta && d <= thr));
+      below += __popcll(__ballot(d < -ta && d >= -thr));
+      if (above > slack && below > slack) return {0, total, R + q + 1};
+    }
+  }
+  return {1, total, total};
+}
+
+// test_pair for points held in registers only, with the number of 64-point
+// chunks Rb <= RMAX known at run time (batched problems of different sizes).
+template <int RMAX>
+__device__ __forceinline__ PairTest test_pair_rt(const float (&X)[RMAX], const float (&Y)[RMAX],
+                                                 int Rb, float nth, float thr, float ta, int h) {
+  const int budget = 64 * Rb - h;
+  int miss = 0;
+#pragma unroll
+  for (int r = 0; r < RMAX; ++r) {
+    if (r < Rb) {
+      const float d = fmaf(nth, X[r], Y[r]);
+      miss += __popcll(__ballot(!(fabsf(d) <= thr)));
+      if (((r & 7) == 7 || r == Rb - 1) && miss > budget) return {0, r + 1, -1};
+    }
+  }
+  const int slack = budget - miss;
+  asm volatile("" : "+v"(nth));
+  int below = 0, above = 0;
+#pragma unroll
+  for (int r = 0; r < RMAX; ++r) {
+    if (r < Rb) {
+      const float d = fmaf(nth, X[r], Y[r]);
+      above += __popcll(__ballot(d > ta && d <= thr));
+      below += __popcll(__ballot(d < -ta && d >= -thr));
+      if (above > slack && below > slack) return {0, Rb, r + 1};
+    }
+  }
+  return {1, Rb, Rb};
+}
+
+// ---------------------------------------------------------------- canonical order
+
+struct Best {
+  double w, th, lo, hi;
+  unsigned a, b;
+};
+
+__device__ __forceinline__ bool better(const Best& p, const Best& q) {
+  if (p.w != q.w) return p.w < q.w;
+  if (p.th != q.th) return p.th < q.th;
+  if (p.lo != q.lo) return p.lo < q.lo;
+  if (p.a != q.a) return p.a < q.a;
+  return p.b < q.b;
+}
+
+}  // namespace lms_dev
+
+#endif

@@ -1,0 +1,148 @@
+// Host-side utilities shared by the C-ABI entry points (see lms_host.h).
+#include "lms_host.h"
+
+#include <map>
+#include <tuple>
+#include <vector>
+
+namespace lms_host {
+namespace {
+
+thread_local std::string g_err;
+
+struct Workspace {
+  void* base = nullptr;
+  size_t bytes = 0;
+};
+
+std::mutex g_mu;
+std::map<std::tuple<int, void*, int>, Workspace> g_ws;
+int g_num_cu = 0;
+bool g_prof_on = false;
+std::vector<std::array<hipEvent_t, LMS_NSTAGES + 1>> g_prof_events;
+
+}  // namespace
+
+lms_status fail(lms_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+void clear_error() { g_err.clear(); }
+
+const char* last_error() { return g_err.c_str(); }
+
+int num_cu() {
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (g_num_cu == 0) {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+      g_num_cu = prop.multiProcessorCount;
+    else
+      return 256;
+  }
+  return g_num_cu;
+}
+
+lms_status get_workspace(int tag, void* stream, size_t bytes, char** base) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(LMS_ERR_DEVICE, "hipGetDevice failed");
+  (void)num_cu();
+  std::lock_guard<std::mutex> lk(g_mu);
+  Workspace& w = g_ws[{dev, stream, tag}];
+  if (w.bytes < bytes) {
+    if (w.base) {
+      if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess)
+        return fail(LMS_ERR_DEVICE, "hipStreamSynchronize failed");
+      (void)hipFree(w.base);
+      w.base = nullptr;
+      w.bytes = 0;
+    }
+    if (hipMalloc(&w.base, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(LMS_ERR_NOMEM, "hipMalloc of the workspace failed");
+    }
+    w.bytes = bytes;
+  }
+  *base = (char*)w.base;
+  return LMS_OK;
+}
+
+void free_workspace(int tag, void* stream) {
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_ws.find({dev, stream, tag});
+  if (it != g_ws.end()) {
+    (void)hipFree(it->second.base);
+    g_ws.erase(it);
+  }
+}
+
+void free_workspaces() {
+  std::lock_guard<std::mutex> lk(g_mu);
+  for (auto& kv : g_ws)
+    if (kv.second.base) (void)hipFree(kv.second.base);
+  g_ws.clear();
+}
+
+void StageEvents::start(hipStream_t stream) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  on = g_prof_on;
+  s = stream;
+  if (!on) return;
+  for (auto& e : ev)
+    if (hipEventCreate(&e) != hipSuccess) {
+      on = false;
+      return;
+    }
+  if (on && next <= LMS_NSTAGES) (void)hipEventRecord(ev[next++], s);
+}
+
+void StageEvents::mark() {
+  if (on && next <= LMS_NSTAGES) (void)hipEventRecord(ev[next++], s);
+}
+
+void StageEvents::finish() {
+  if (!on) return;
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (next == LMS_NSTAGES + 1) {
+    g_prof_events.push_back(ev);
+  } else {
+    for (auto& e : ev) (void)hipEventDestroy(e);
+  }
+  on = false;
+}
+
+void profile_begin() {
+  std::lock_guard<std::mutex> lk(g_mu);
+  for (auto& ev : g_prof_events)
+    for (auto& e : ev) (void)hipEventDestroy(e);
+  g_prof_events.clear();
+  g_prof_on = true;
+}
+
+int64_t profile_end(double* ms) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_prof_on = false;
+  double sum[LMS_NSTAGES] = {0};
+  int64_t count = 0;
+  int64_t st = 0;
+  for (auto& ev : g_prof_events) {
+    if (st == 0 && hipEventSynchronize(ev[LMS_NSTAGES]) != hipSuccess) st = LMS_ERR_DEVICE;
+    for (int k = 0; st == 0 && k < LMS_NSTAGES; ++k) {
+      float t = 0.f;
+      if (hipEventElapsedTime(&t, ev[k], ev[k + 1]) != hipSuccess) st = LMS_ERR_DEVICE;
+      sum[k] += t;
+    }
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    ++count;
+  }
+  g_prof_events.clear();
+  if (ms)
+    for (int k = 0; k < LMS_NSTAGES; ++k) ms[k] = sum[k];
+  return st != 0 ? st : count;
+}
+
+}  // namespace lms_host

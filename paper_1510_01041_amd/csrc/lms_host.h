@@ -1,0 +1,48 @@
+// Host-side utilities shared by the C-ABI entry points: error reporting,
+// per-(device, stream) workspaces, and HIP-event stage timing.
+#ifndef LMS_HOST_H
+#define LMS_HOST_H
+#include <hip/hip_runtime.h>
+
+#include <array>
+#include <mutex>
+#include <string>
+
+#include "lms.h"
+
+namespace lms_host {
+
+// Records msg as this thread's last error and returns s.
+lms_status fail(lms_status s, const std::string& msg);
+void clear_error();
+const char* last_error();
+
+// A device buffer of at least `bytes` owned by the library, one per
+// (device, stream, tag). Growing it first synchronises the stream, since
+// queued work may still use the old buffer. Freed by free_workspaces().
+lms_status get_workspace(int tag, void* stream, size_t bytes, char** base);
+void free_workspaces();
+void free_workspace(int tag, void* stream);
+
+// Frees the cached batch plans, buffers and graphs (lms_batched.hip).
+void release_batches();
+
+// Compute units of the current device (queried once).
+int num_cu();
+
+// HIP events around the stages of one solve, kept while profiling is on.
+struct StageEvents {
+  std::array<hipEvent_t, LMS_NSTAGES + 1> ev{};
+  bool on = false;
+  hipStream_t s = nullptr;
+  int next = 0;
+  void start(hipStream_t stream);
+  void mark();
+  void finish();
+};
+void profile_begin();
+int64_t profile_end(double* ms);
+
+}  // namespace lms_host
+
+#endif

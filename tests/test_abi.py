@@ -75,3 +75,22 @@ def test_binding_rejects_non_cuda_input():
     import torch
     with pytest.raises(ValueError):
         lms.solve(torch.zeros((10, 2), dtype=torch.float64))
+
+
+def test_batched_argument_errors():
+    L = lms.load()
+    import numpy as np
+    fake = 0x1000
+    opt = lms._options()
+    off = np.array([0, 10, 20], dtype=np.int64)
+    assert L.lms_solve_batched(fake, fake, off.ctypes.data, 0, None, fake, ctypes.byref(opt),
+                               None) == lms.LMS_ERR_ARG
+    assert L.lms_solve_batched(None, fake, off.ctypes.data, 2, None, fake, ctypes.byref(opt),
+                               None) == lms.LMS_ERR_ARG
+    big = np.array([0, 5000], dtype=np.int64)
+    assert L.lms_solve_batched(fake, fake, big.ctypes.data, 1, None, fake, ctypes.byref(opt),
+                               None) == lms.LMS_ERR_ARG
+    assert "4096" in lms.last_error()
+    dec = np.array([0, 10, 5], dtype=np.int64)
+    assert L.lms_solve_batched(fake, fake, dec.ctypes.data, 2, None, fake, ctypes.byref(opt),
+                               None) == lms.LMS_ERR_ARG

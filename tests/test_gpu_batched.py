@@ -1,0 +1,129 @@
+"""Batched solves (many uneven point sets in one pass) against the oracle and
+against one solve per problem, including hipGraph replays."""
+import numpy as np
+import pytest
+import torch
+
+from workloads import gen
+from workloads.gen import Stream, planted
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def key(r):
+    return (float(r.width), float(r.theta1), float(r.z_lo), float(r.z_hi), float(r.theta2))
+
+
+def check_tied(orc, p, r, h=0):
+    """Integer data has exact width ties between different slopes; the oracle's
+    FP64 rounding may prefer either. Check the width to 1e-9 relative and
+    certify the GPU's line: the oracle's window at its slope is the same
+    window, bit for bit, and holds h points within its half-width."""
+    o = orc.solve(p, h=h)
+    assert r.status == o.status
+    assert abs(r.width - o.width) <= 1e-9 * max(r.width, o.width) or r.width == o.width
+    w, lo, hi = orc.window(p, float(r.theta1), h=h)
+    assert (w, lo, hi) == (r.width, r.z_lo, r.z_hi)
+    assert r.vertical == o.vertical and r.candidates == o.candidates
+    return o
+
+
+def test_hough_patches_match_oracle(gpu, orc):
+    xy, off = gen.hough_patches(40, 11)
+    res = gpu.solve_batched(dev(xy), off)
+    for b in range(len(off) - 1):
+        assert res[b].status == 0
+        check_tied(orc, xy[off[b]:off[b + 1]], res[b])
+
+
+def test_batched_equals_single_solves(gpu):
+    xy, off = gen.hough_patches(300, 12)
+    d = dev(xy)
+    res = gpu.solve_batched(d, off)
+    for b in range(0, 300, 7):
+        one = gpu.solve(d[off[b]:off[b + 1]].contiguous())
+        assert key(res[b]) == (one.width, one.theta1, one.z_lo, one.z_hi, one.theta2), b
+
+
+def test_mixed_sizes_all_classes(gpu, orc):
+    """Problems in every register class (<= 512, <= 1024, <= 4096 points)."""
+    sizes = [2, 3, 33, 64, 65, 511, 512, 513, 1024, 1025, 2000]
+    parts = [planted(n, 0.4, 300 + n) for n in sizes]
+    off = np.concatenate([[0], np.cumsum([len(p) for p in parts])]).astype(np.int64)
+    res = gpu.solve_batched(dev(np.concatenate(parts)), off)
+    for b, p in enumerate(parts):
+        if len(p) <= 1025:
+            o = orc.solve(p)
+            assert key(res[b]) == (o.width, o.theta1, o.z_lo, o.z_hi, o.theta2), len(p)
+        else:
+            one = gpu.solve(dev(p))
+            assert key(res[b]) == (one.width, one.theta1, one.z_lo, one.z_hi, one.theta2)
+
+
+def test_invalid_and_degenerate_problems(gpu, orc):
+    parts = [planted(50, 0.3, 1), np.zeros((1, 2)), np.stack([np.full(9, 3.0), np.arange(9.0)], 1),
+             planted(70, 0.3, 2)]
+    bad = planted(20, 0.3, 3)
+    bad[4, 1] = np.inf
+    parts.append(bad)
+    off = np.concatenate([[0], np.cumsum([len(p) for p in parts])]).astype(np.int64)
+    res = gpu.solve_batched(dev(np.concatenate(parts)), off)
+    assert res[1].status == gpu.LMS_ERR_ARG
+    assert res[2].status == 1 and res[2].theta1 == 0.0
+    assert res[4].status == gpu.LMS_ERR_NONFINITE
+    for b in (0, 2, 3):
+        o = orc.solve(parts[b])
+        assert key(res[b]) == (o.width, o.theta1, o.z_lo, o.z_hi, o.theta2)
+
+
+def test_custom_h(gpu, orc):
+    xy, off = gen.hough_patches(30, 13)
+    n = np.diff(off)
+    h = np.maximum(2, (n * 3) // 4).astype(np.int32)
+    res = gpu.solve_batched(dev(xy), off, h=torch.from_numpy(h).to("cuda:0"))
+    for b in range(30):
+        check_tied(orc, xy[off[b]:off[b + 1]], res[b], h=int(h[b]))
+        assert res[b].h == h[b]
+
+
+def test_graph_replays_match_eager(gpu):
+    """Several replays, with eager work and synchronisation in between, and new
+    point values between replays (same offsets): every replay equals eager."""
+    xy, off = gen.hough_patches(200, 14)
+    d = dev(xy)
+    eager = gpu.solve_batched(d, off)
+    out = torch.empty((200, gpu.RESULT_BYTES), dtype=torch.uint8, device="cuda:0")
+    for rep in range(3):
+        gpu.solve_batched_async(d, off, out=out, graph=True)
+        torch.cuda.synchronize()
+        g = gpu.parse_batch(out)
+        assert all(key(g[b]) == key(eager[b]) for b in range(200)), rep
+        _ = (d * 2).sum().item()  # unrelated eager work between replays
+    # new values in the same buffer: the replay sees them
+    xy2 = xy.copy()
+    xy2[:, 1] = 63.0 - xy2[:, 1]
+    d.copy_(dev(xy2))
+    gpu.solve_batched_async(d, off, out=out, graph=True)
+    torch.cuda.synchronize()
+    g = gpu.parse_batch(out)
+    eager2 = gpu.solve_batched(dev(xy2), off)
+    assert all(key(g[b]) == key(eager2[b]) for b in range(200))
+
+
+def test_full_c4_sample(gpu, orc):
+    """The full 20,000-patch workload: a sample checked against single solves
+    and against the oracle."""
+    xy, off = gen.make("c4")
+    d = dev(xy)
+    res = gpu.solve_batched(d, off, graph=True)
+    assert np.all(res.status == 0)
+    st = Stream(15, 150)
+    for b in st.integers(60, 0, len(off) - 2):
+        one = gpu.solve(d[off[b]:off[b + 1]].contiguous())
+        assert key(res[b]) == (one.width, one.theta1, one.z_lo, one.z_hi, one.theta2), b
+    for b in st.integers(6, 0, len(off) - 2):
+        check_tied(orc, xy[off[b]:off[b + 1]], res[b])
