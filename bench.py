@@ -170,9 +170,62 @@ def main():
         "result": {"half_width": r.half_width, "theta1": r.theta1, "theta2": r.theta2,
                    "parity": parity},
     }
+    line["learned_vs_plain"] = seeding_comparison(lms, d, r, max(3, args.steps // 5))
     if args.cpu_seconds > 0:
         line["cpu_baseline"] = cpu_baseline(xy, args.cpu_seconds)
     print(json.dumps(line), flush=True)
+
+
+def seeding_comparison(lms, d, ref, steps):
+    """Time the same solve under different initial width bounds.
+
+    plain: 255 random pair slopes (the default). learned: the seed network's
+    slope only, with network inference inside the timed region. Also reported:
+    the network slope plus the random pairs, no seed at all (only the extreme-x
+    pair), and a control of 63 random pairs. Every variant must return the
+    same line."""
+    import numpy as np
+    import torch
+    from paper_1510_01041_amd import seednet
+
+    wpath = os.path.join(ROOT, "paper_1510_01041_amd", "seednet_weights.npy")
+    net = seednet.SeedNet.load_weights(wpath) if os.path.exists(wpath) else None
+    off = np.array([0, d.shape[0]], dtype=np.int64)
+    out = torch.empty(lms.RESULT_BYTES, dtype=torch.uint8, device=d.device)
+
+    def run(kind):
+        def once():
+            if kind == "plain":
+                lms.solve_async(d, 0, out)
+            elif kind == "no_seed":
+                lms.solve_async(d, 0, out, seed_pairs=0)
+            elif kind == "control63":
+                lms.solve_async(d, 0, out, seed_pairs=63)
+            else:
+                th = net.predict_slopes(d, off)
+                lms.solve_async(d, 0, out, seed_pairs=0 if kind == "learned" else None,
+                                seed_theta=th)
+        once()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            once()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        r = lms.parse(out)
+        return {"ms": ms, "survivors": r.survivors, "band_pass": r.band_pass,
+                "band_evals_per_pair": r.point_evals / max(r.candidates, 1),
+                "same_result": (r.width, r.theta1, r.z_lo) == (ref.width, ref.theta1, ref.z_lo)}
+
+    kinds = ["plain", "no_seed", "control63"] + (["learned", "learned+pairs"] if net else [])
+    res = {k: run(k) for k in kinds}
+    res["mismatches"] = sum(not v["same_result"] for v in res.values() if isinstance(v, dict))
+    if net:
+        res["speedup_learned_vs_plain"] = res["plain"]["ms"] / res["learned"]["ms"]
+        res["speedup_learned_vs_no_seed"] = res["no_seed"]["ms"] / res["learned"]["ms"]
+    else:
+        res["note"] = "no trained seed network weights found"
+    return res
 
 
 def bench_batched(args):

@@ -152,6 +152,43 @@ lms_status lms_screen_pairs(const double* d_xy, int64_t n, int64_t h, double W,
 void lms_profile_begin(void);
 int64_t lms_profile_end(double* ms);
 
+/* ---- Learned seed slope (a proposal for the initial width bound) ----
+ * A small point-set network: per point 2 -> 64 -> 64 (ReLU), max-pool over
+ * the points, head 64 -> 64 -> 2 (ReLU between), with BF16 weights (rounded
+ * from FP32 masters) and FP32 accumulation. It predicts (cos 2phi, sin 2phi)
+ * of the LMS line's angle phi in each set's normalised frame. Its slope only
+ * seeds lms_solve through lms_options.d_seed_theta; since F(theta) >= the
+ * optimum for every theta (Eq. (1)), the result stays exact for any
+ * prediction. Parameters: LMS_NET_PARAMS FP32 values, packed
+ * W1[64][2] b1[64] W2[64][64] b2[64] W3[64][64] b3[64] W4[2][64] b4[2].
+ * Sets are CSR like lms_solve_batched (d_offsets, B+1 int64). */
+#define LMS_NET_PARAMS 8642
+
+/* Per set: midrange centre and half-range scale of x and y (1 for a zero
+ * range). Writes d_pts (float2 per point, in [-1,1]^2) and d_scale
+ * (B x 4 FP64: cx, cy, sx, sy). */
+lms_status lms_net_prepare(const double* d_xy, const int64_t* d_offsets, int64_t B, float* d_pts,
+                           double* d_scale, void* stream);
+/* Forward pass: d_out (B x 2 FP32) and, if d_g is not NULL, the pooled
+ * features (B x 64 FP32) that lms_net_backward needs. */
+lms_status lms_net_forward(const float* d_params, const float* d_pts, const int64_t* d_offsets,
+                           int64_t B, float* d_out, float* d_g, void* stream);
+/* Gradient of the mean over sets of 0.5 ||out - target||^2 (targets B x 2).
+ * The max-pool routes each channel's gradient to the first point attaining
+ * the maximum; the BF16 roundings pass gradients straight through.
+ * d_grad_set: B x LMS_NET_PARAMS scratch; d_grad: LMS_NET_PARAMS, the sum
+ * over sets in set order; d_loss: B per-set contributions to the mean loss. */
+lms_status lms_net_backward(const float* d_params, const float* d_pts, const int64_t* d_offsets,
+                            int64_t B, const float* d_target, const float* d_out,
+                            const float* d_g, float* d_grad_set, float* d_grad, float* d_loss,
+                            void* stream);
+/* One bias-corrected Adam step (step >= 1) on the FP32 masters. */
+lms_status lms_net_adam(float* d_params, float* d_m, float* d_v, const float* d_grad, int64_t step,
+                        float lr, float beta1, float beta2, float eps, void* stream);
+/* Seed slopes in the original frames: tan(atan2(out1, out0)/2) * sy / sx. */
+lms_status lms_net_slopes(const float* d_out, const double* d_scale, int64_t B, double* d_theta,
+                          void* stream);
+
 const char* lms_status_str(int status);
 /* Message for the last failing call on this thread ("" if none). */
 const char* lms_last_error(void);

@@ -13,8 +13,8 @@
 //   k_bscreen   persistent wavefronts over work items (problem, anchor), the
 //               same band and split tests as the single-problem screen, with
 //               the number of 64-point chunks of each problem as a runtime
-//               bound. One launch per register class (up to 512, 1024 and
-//               4096 points).
+//               bound. One launch per register class (up to 512, 1024, 2048
+//               and 4096 points).
 //   k_bselect   canonical minimum per problem, (width, theta, z_lo, pair), in
 //               three passes of order-preserving u64 atomicMin over the
 //               entries.
@@ -46,7 +46,8 @@ using namespace lms_dev;
 using lms_host::fail;
 
 constexpr int kBatchMaxN = 4096;
-constexpr int kClassChunks[3] = {8, 16, 64};  // register classes: n <= 512, 1024, 4096
+constexpr int kClasses = 4;
+constexpr int kClassChunks[kClasses] = {8, 16, 32, 64};  // n <= 512, 1024, 2048, 4096
 constexpr long long kBatchScreenCap = 1ll << 24;
 
 // Per-problem state in device memory.
@@ -62,8 +63,8 @@ struct __align__(16) PMeta {
 
 struct __align__(16) BState {
   unsigned n_entries, overflow;
-  unsigned next_item[3];
-  unsigned pad[3];
+  unsigned next_item[kClasses];
+  unsigned pad[2];
 };
 
 // Entry: problem id and the pair packed as lo | hi << 16 (n <= 4096).
@@ -406,12 +407,12 @@ __global__ __launch_bounds__(256) void k_bfinal(const PMeta* __restrict__ meta, 
 struct BPlan {
   int B = 0, S = 0, max_n = 0;
   long long pad_total = 0, pairs = 0, cap = 0;
-  int n_probs[3] = {0, 0, 0};
-  int n_items[3] = {0, 0, 0};
+  int n_probs[kClasses] = {};
+  int n_items[kClasses] = {};
   // device arrays inside the workspace
   size_t o_meta = 0, o_state = 0, o_pad = 0, o_chunks = 0, o_order = 0, o_ibeg = 0, o_xy32 = 0,
          o_entries = 0, o_res = 0, total = 0;
-  size_t order_off[3] = {0, 0, 0}, ibeg_off[3] = {0, 0, 0};
+  size_t order_off[kClasses] = {}, ibeg_off[kClasses] = {};
   std::vector<int> h_pad, h_chunks, h_order, h_ibeg;
 };
 
@@ -422,7 +423,7 @@ lms_status plan_batch(const int64_t* h_off, int B, int S, BPlan* P) {
   P->S = S;
   P->h_pad.assign(B, 0);
   P->h_chunks.assign(B, 1);
-  std::vector<std::vector<int>> cls(3);
+  std::vector<std::vector<int>> cls(kClasses);
   long long pad = 0;
   for (int b = 0; b < B; ++b) {
     const long long n = h_off[b + 1] - h_off[b];
@@ -435,13 +436,17 @@ lms_status plan_batch(const int64_t* h_off, int B, int S, BPlan* P) {
     pad += 64ll * R;
     P->max_n = std::max<int>(P->max_n, (int)n);
     P->pairs += n * (n - 1) / 2;
-    if (n >= 2) cls[R <= kClassChunks[0] ? 0 : R <= kClassChunks[1] ? 1 : 2].push_back(b);
+    if (n >= 2) {
+      int c = 0;
+      while (R > kClassChunks[c]) ++c;
+      cls[c].push_back(b);
+    }
   }
   if (h_off[0] < 0) return fail(LMS_ERR_ARG, "offsets must be >= 0");
   P->pad_total = pad;
   P->h_order.clear();
   P->h_ibeg.clear();
-  for (int c = 0; c < 3; ++c) {
+  for (int c = 0; c < kClasses; ++c) {
     auto& v = cls[c];
     // largest problems first: the tail of the persistent loop is small items
     std::stable_sort(v.begin(), v.end(), [&](int a, int b) {
@@ -550,7 +555,7 @@ lms_status enqueue_batch(const BPlan& P, char* base, const double* d_xy, const i
   launch_bwindow_n(s, P.max_n, std::min(seeds, 16 * cu), d_xy, meta, entries, res, 0, state,
                    seeds, cap, 1);
   if (prof) prof->mark();
-  for (int c = 0; c < 3; ++c) {
+  for (int c = 0; c < kClasses; ++c) {
     if (P.n_items[c] == 0) continue;
     const int* ord = order + P.order_off[c];
     const int* ib = ibeg + P.ibeg_off[c];
@@ -562,6 +567,10 @@ lms_status enqueue_batch(const BPlan& P, char* base, const double* d_xy, const i
         break;
       case 1:
         hipLaunchKernelGGL((k_bscreen<16>), dim3(grid), dim3(256), 0, s, d_xy, xy32, meta, ord, ib,
+                           P.n_probs[c], P.n_items[c], entries, cap, state, c);
+        break;
+      case 2:
+        hipLaunchKernelGGL((k_bscreen<32>), dim3(grid), dim3(256), 0, s, d_xy, xy32, meta, ord, ib,
                            P.n_probs[c], P.n_items[c], entries, cap, state, c);
         break;
       default:
@@ -640,11 +649,19 @@ lms_status lms_solve_batched(const double* d_xy, const int64_t* d_offsets,
   }
   if (flags & LMS_F_GRAPH) {
     if (!bc.exec) {
-      if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess)
+      // Capture on a private stream (the legacy null stream cannot be
+      // captured); the graph is then launched on the caller's stream.
+      hipStream_t cs = nullptr;
+      if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess)
+        return fail(LMS_ERR_DEVICE, "hipStreamCreate failed");
+      if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        (void)hipStreamDestroy(cs);
         return fail(LMS_ERR_DEVICE, "hipStreamBeginCapture failed");
-      const lms_status st = enqueue_batch(bc.plan, bc.base, d_xy, d_offsets, d_h, d_out, s, nullptr);
+      }
+      const lms_status st = enqueue_batch(bc.plan, bc.base, d_xy, d_offsets, d_h, d_out, cs, nullptr);
       hipGraph_t g = nullptr;
-      const hipError_t e = hipStreamEndCapture(s, &g);
+      const hipError_t e = hipStreamEndCapture(cs, &g);
+      (void)hipStreamDestroy(cs);
       if (st != LMS_OK) { if (g) (void)hipGraphDestroy(g); return st; }
       if (e != hipSuccess || !g) return fail(LMS_ERR_DEVICE, "hipStreamEndCapture failed");
       if (hipGraphInstantiate(&bc.exec, g, nullptr, nullptr, 0) != hipSuccess) {

@@ -1,0 +1,406 @@
+// Point-set network that proposes a seed slope for the exact search.
+//
+// Not part of the paper's method: a proposal can only tighten the screen's
+// initial width bound, because F(theta) >= the optimal width for every theta
+// (Eq. (1)). The exhaustive search stays exact whatever the network says.
+//
+// Architecture, for one set of points in a [-1, 1]^2 frame:
+//   h1 = relu(W1 p + b1) (64) -> BF16
+//   h2 = relu(W2 h1 + b2) (64), W2 . h1 by v_dot2 BF16 pairs into FP32
+//   g = max over points of h2 (64)
+//   h3 = relu(W3 g + b3) (64);  out = W4 h3 + b4 (2) ~ (cos 2phi, sin 2phi)
+// Weights are BF16 roundings (ties to even) of FP32 masters, taken at load.
+// Parameters are packed FP32 in the order W1 b1 W2 b2 W3 b3 W4 b4 (row-major,
+// W[out][in]).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstdint>
+#include <string>
+
+#include "lms.h"
+#include "lms_host.h"
+
+namespace {
+
+using lms_host::fail;
+
+constexpr int H = 64;
+constexpr int OFF_W1 = 0, OFF_B1 = OFF_W1 + H * 2, OFF_W2 = OFF_B1 + H, OFF_B2 = OFF_W2 + H * H,
+              OFF_W3 = OFF_B2 + H, OFF_B3 = OFF_W3 + H * H, OFF_W4 = OFF_B3 + H,
+              OFF_B4 = OFF_W4 + 2 * H, N_PARAMS = OFF_B4 + 2;
+static_assert(N_PARAMS == LMS_NET_PARAMS, "parameter count");
+
+constexpr int NT = 256;
+
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+// FP32 -> BF16 bits, round to nearest, ties to even.
+__device__ __forceinline__ unsigned bf16_bits(float f) {
+  const unsigned u = __float_as_uint(f);
+  return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
+}
+__device__ __forceinline__ float bf16_round(float f) { return __uint_as_float(bf16_bits(f) << 16); }
+__device__ __forceinline__ unsigned pack2(float a, float b) {
+  return bf16_bits(a) | (bf16_bits(b) << 16);
+}
+__device__ __forceinline__ float dot2(unsigned w, unsigned x, float acc) {
+  return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2, w),
+                                         __builtin_bit_cast(bf16x2, x), acc, false);
+}
+
+// Weights of the point MLP in LDS: W1/b1/b2 as FP32 (W1 rounded), W2 as BF16
+// pairs: s_w2[c][k/2] = (W2[c][k], W2[c][k+1]).
+struct PointMLP {
+  float w1[H * 2], b1[H], b2[H];
+  unsigned w2[H * H / 2];
+};
+
+__device__ void load_point_mlp(const float* __restrict__ P, PointMLP& s) {
+  for (int i = threadIdx.x; i < H * 2; i += blockDim.x) s.w1[i] = bf16_round(P[OFF_W1 + i]);
+  for (int i = threadIdx.x; i < H; i += blockDim.x) {
+    s.b1[i] = P[OFF_B1 + i];
+    s.b2[i] = P[OFF_B2 + i];
+  }
+  for (int i = threadIdx.x; i < H * H / 2; i += blockDim.x)
+    s.w2[i] = pack2(P[OFF_W2 + 2 * i], P[OFF_W2 + 2 * i + 1]);
+  __syncthreads();
+}
+
+// Layer 1 of one point, packed as BF16 pairs.
+__device__ __forceinline__ void layer1(const PointMLP& s, float x, float y, unsigned (&h1)[H / 2]) {
+#pragma unroll
+  for (int k = 0; k < H / 2; ++k) {
+    const float a = fmaxf(fmaf(s.w1[4 * k + 1], y, fmaf(s.w1[4 * k], x, s.b1[2 * k])), 0.0f);
+    const float b = fmaxf(fmaf(s.w1[4 * k + 3], y, fmaf(s.w1[4 * k + 2], x, s.b1[2 * k + 1])), 0.0f);
+    h1[k] = pack2(a, b);
+  }
+}
+
+// Pre-activation of layer 2, channel c.
+__device__ __forceinline__ float layer2(const PointMLP& s, const unsigned (&h1)[H / 2], int c) {
+  float acc = s.b2[c];
+#pragma unroll
+  for (int k = 0; k < H / 2; ++k) acc = dot2(s.w2[c * (H / 2) + k], h1[k], acc);
+  return acc;
+}
+
+__device__ __forceinline__ float wave_max(float v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ __forceinline__ int wave_min_i(int v) {
+  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+  return v;
+}
+
+// ---------------------------------------------------------------- kernels
+
+// Midrange centre and half-range scale per set; FP32 points in [-1, 1]^2.
+__global__ __launch_bounds__(NT) void k_net_prepare(const double* __restrict__ xy,
+                                                    const int64_t* __restrict__ off,
+                                                    float2* __restrict__ pts,
+                                                    double* __restrict__ scale) {
+  __shared__ double s[4][NT];
+  const int b = blockIdx.x, t = threadIdx.x;
+  const int64_t o = off[b], n = off[b + 1] - off[b];
+  double mnx = INFINITY, mxx = -INFINITY, mny = INFINITY, mxy = -INFINITY;
+  for (int64_t k = t; k < n; k += NT) {
+    const double x = xy[2 * (o + k)], y = xy[2 * (o + k) + 1];
+    mnx = fmin(mnx, x); mxx = fmax(mxx, x); mny = fmin(mny, y); mxy = fmax(mxy, y);
+  }
+  s[0][t] = mnx; s[1][t] = mxx; s[2][t] = mny; s[3][t] = mxy;
+  __syncthreads();
+  for (int w = NT / 2; w > 0; w >>= 1) {
+    if (t < w) {
+      s[0][t] = fmin(s[0][t], s[0][t + w]);
+      s[1][t] = fmax(s[1][t], s[1][t + w]);
+      s[2][t] = fmin(s[2][t], s[2][t + w]);
+      s[3][t] = fmax(s[3][t], s[3][t + w]);
+    }
+    __syncthreads();
+  }
+  const double cx = s[0][0] + 0.5 * (s[1][0] - s[0][0]), cy = s[2][0] + 0.5 * (s[3][0] - s[2][0]);
+  double sx = fmax(fabs(s[0][0] - cx), fabs(s[1][0] - cx));
+  double sy = fmax(fabs(s[2][0] - cy), fabs(s[3][0] - cy));
+  if (!(sx > 0)) sx = 1.0;
+  if (!(sy > 0)) sy = 1.0;
+  if (t == 0) {
+    scale[4 * b] = cx; scale[4 * b + 1] = cy; scale[4 * b + 2] = sx; scale[4 * b + 3] = sy;
+  }
+  for (int64_t k = t; k < n; k += NT)
+    pts[o + k] = make_float2((float)((xy[2 * (o + k)] - cx) / sx),
+                             (float)((xy[2 * (o + k) + 1] - cy) / sy));
+}
+
+// Max-pooled point features g (B x 64) and the head's output (B x 2).
+__global__ __launch_bounds__(NT) void k_net_forward(const float* __restrict__ P,
+                                                    const float2* __restrict__ pts,
+                                                    const int64_t* __restrict__ off,
+                                                    float* __restrict__ out, float* __restrict__ g_out) {
+  __shared__ PointMLP s;
+  __shared__ float s_max[NT / 64][H];
+  __shared__ float s_g[H], s_h3[H];
+  load_point_mlp(P, s);
+  const int b = blockIdx.x, t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int64_t o = off[b], n = off[b + 1] - off[b];
+  float run[H];
+#pragma unroll
+  for (int c = 0; c < H; ++c) run[c] = 0.0f;  // h2 >= 0 after relu
+  for (int64_t k = t; k < n; k += NT) {
+    // keep the weights in LDS: without this the compiler hoists all 2048 W2
+    // loads out of the point loop and spills them
+    asm volatile("" ::: "memory");
+    const float2 p = pts[o + k];
+    unsigned h1[H / 2];
+    layer1(s, p.x, p.y, h1);
+#pragma unroll
+    for (int c = 0; c < H; ++c) run[c] = fmaxf(run[c], fmaxf(layer2(s, h1, c), 0.0f));
+  }
+#pragma unroll
+  for (int c = 0; c < H; ++c) {
+    const float m = wave_max(run[c]);
+    if (lane == 0) s_max[wv][c] = m;
+  }
+  __syncthreads();
+  if (t < H) {
+    float m = s_max[0][t];
+    for (int w = 1; w < NT / 64; ++w) m = fmaxf(m, s_max[w][t]);
+    s_g[t] = m;
+    if (g_out) g_out[(size_t)b * H + t] = m;
+  }
+  __syncthreads();
+  if (t < H) {
+    float a = P[OFF_B3 + t];
+    for (int k = 0; k < H; ++k) a = fmaf(bf16_round(P[OFF_W3 + t * H + k]), s_g[k], a);
+    s_h3[t] = fmaxf(a, 0.0f);
+  }
+  __syncthreads();
+  if (t < 2) {
+    float a = P[OFF_B4 + t];
+    for (int k = 0; k < H; ++k) a = fmaf(bf16_round(P[OFF_W4 + t * H + k]), s_h3[k], a);
+    out[2 * b + t] = a;
+  }
+}
+
+// Gradient of the mean loss 0.5 ||out - target||^2 / B for each set, written
+// per set (B x N_PARAMS) so that the sum over sets has a fixed order.
+__global__ __launch_bounds__(NT) void k_net_backward(const float* __restrict__ P,
+                                                     const float2* __restrict__ pts,
+                                                     const int64_t* __restrict__ off, int B,
+                                                     const float* __restrict__ target,
+                                                     const float* __restrict__ out,
+                                                     const float* __restrict__ g_in,
+                                                     float* __restrict__ grad_set,
+                                                     float* __restrict__ loss_set) {
+  __shared__ PointMLP s;
+  __shared__ float s_g[H], s_z3[H], s_dz3[H], s_dg[H], s_dz2[H];
+  __shared__ float s_dout[2];
+  __shared__ int s_arg[NT / 64][H];
+  __shared__ int s_argf[H];
+  load_point_mlp(P, s);
+  const int b = blockIdx.x, t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int64_t o = off[b], n = off[b + 1] - off[b];
+  float* G = grad_set + (size_t)b * N_PARAMS;
+  if (t < H) s_g[t] = g_in[(size_t)b * H + t];
+  if (t < 2) {
+    const float d = out[2 * b + t] - target[2 * b + t];
+    s_dout[t] = d / (float)B;
+  }
+  __syncthreads();
+  if (t == 0) loss_set[b] = 0.5f * (s_dout[0] * s_dout[0] + s_dout[1] * s_dout[1]) * (float)B;
+  // head
+  if (t < H) {
+    float a = P[OFF_B3 + t];
+    for (int k = 0; k < H; ++k) a = fmaf(bf16_round(P[OFF_W3 + t * H + k]), s_g[k], a);
+    s_z3[t] = a;
+  }
+  __syncthreads();
+  if (t < H) {
+    const float h3 = fmaxf(s_z3[t], 0.0f);
+    const float w40 = bf16_round(P[OFF_W4 + t]), w41 = bf16_round(P[OFF_W4 + H + t]);
+    G[OFF_W4 + t] = s_dout[0] * h3;
+    G[OFF_W4 + H + t] = s_dout[1] * h3;
+    const float dh3 = w40 * s_dout[0] + w41 * s_dout[1];
+    s_dz3[t] = s_z3[t] > 0.0f ? dh3 : 0.0f;
+  }
+  if (t < 2) G[OFF_B4 + t] = s_dout[t];
+  __syncthreads();
+  if (t < H) {
+    G[OFF_B3 + t] = s_dz3[t];
+    for (int k = 0; k < H; ++k) G[OFF_W3 + t * H + k] = s_dz3[t] * s_g[k];
+    float dg = 0.0f;
+    for (int c = 0; c < H; ++c) dg = fmaf(bf16_round(P[OFF_W3 + c * H + t]), s_dz3[c], dg);
+    s_dg[t] = dg;
+  }
+  // first point attaining each channel's maximum (same arithmetic as forward)
+  int first[H];
+#pragma unroll
+  for (int c = 0; c < H; ++c) first[c] = INT_MAX;
+  for (int64_t k = t; k < n; k += NT) {
+    asm volatile("" ::: "memory");
+    const float2 p = pts[o + k];
+    unsigned h1[H / 2];
+    layer1(s, p.x, p.y, h1);
+#pragma unroll
+    for (int c = 0; c < H; ++c)
+      if (first[c] == INT_MAX && fmaxf(layer2(s, h1, c), 0.0f) == s_g[c]) first[c] = (int)k;
+  }
+#pragma unroll
+  for (int c = 0; c < H; ++c) {
+    const int m = wave_min_i(first[c]);
+    if (lane == 0) s_arg[wv][c] = m;
+  }
+  __syncthreads();
+  if (t < H) {
+    int m = s_arg[0][t];
+    for (int w = 1; w < NT / 64; ++w) m = min(m, s_arg[w][t]);
+    if (m == INT_MAX) m = 0;  // empty set: nothing to route (dz2 is then 0 or n is 0)
+    s_argf[t] = m;
+    // dz2 at that point; zero if the channel was inactive everywhere
+    unsigned h1[H / 2];
+    float z2 = 0.0f;
+    if (n > 0) {
+      const float2 p = pts[o + m];
+      layer1(s, p.x, p.y, h1);
+      z2 = layer2(s, h1, t);
+    } else {
+      for (int k = 0; k < H / 2; ++k) h1[k] = 0u;
+    }
+    s_dz2[t] = z2 > 0.0f ? s_dg[t] : 0.0f;
+    G[OFF_B2 + t] = s_dz2[t];
+    // dW2 row t = dz2_t * bf16(h1(arg_t))
+    for (int k = 0; k < H / 2; ++k) {
+      G[OFF_W2 + t * H + 2 * k] = s_dz2[t] * __uint_as_float(h1[k] << 16);
+      G[OFF_W2 + t * H + 2 * k + 1] = s_dz2[t] * __uint_as_float(h1[k] & 0xFFFF0000u);
+    }
+  }
+  __syncthreads();
+  // layer 1: thread t = hidden unit k; sum over channels c of W2[c][k] dz2_c at point arg_c
+  if (t < H) {
+    const int k = t;
+    const float w1x = s.w1[2 * k], w1y = s.w1[2 * k + 1], b1 = s.b1[k];
+    float gw0 = 0.0f, gw1 = 0.0f, gb = 0.0f;
+    for (int c = 0; c < H; ++c) {
+      const float dz2 = s_dz2[c];
+      if (dz2 == 0.0f) continue;
+      const float2 p = pts[o + s_argf[c]];
+      const float z1 = fmaf(w1y, p.y, fmaf(w1x, p.x, b1));
+      if (!(z1 > 0.0f)) continue;
+      const unsigned wp = s.w2[c * (H / 2) + k / 2];
+      const float w2 = __uint_as_float((k & 1) ? (wp & 0xFFFF0000u) : (wp << 16));
+      const float d = w2 * dz2;
+      gw0 = fmaf(d, p.x, gw0);
+      gw1 = fmaf(d, p.y, gw1);
+      gb += d;
+    }
+    G[OFF_W1 + 2 * k] = gw0;
+    G[OFF_W1 + 2 * k + 1] = gw1;
+    G[OFF_B1 + k] = gb;
+  }
+}
+
+// Sum of the per-set gradients, in set order.
+__global__ __launch_bounds__(NT) void k_net_reduce(const float* __restrict__ grad_set, int B,
+                                                   float* __restrict__ grad) {
+  const int i = blockIdx.x * NT + threadIdx.x;
+  if (i >= N_PARAMS) return;
+  float a = 0.0f;
+  for (int b = 0; b < B; ++b) a += grad_set[(size_t)b * N_PARAMS + i];
+  grad[i] = a;
+}
+
+// Adam (Kingma & Ba), bias-corrected, on the FP32 masters.
+__global__ __launch_bounds__(NT) void k_net_adam(float* __restrict__ P, float* __restrict__ m,
+                                                 float* __restrict__ v,
+                                                 const float* __restrict__ grad, float lr,
+                                                 float beta1, float beta2, float eps, float c1,
+                                                 float c2) {
+  const int i = blockIdx.x * NT + threadIdx.x;
+  if (i >= N_PARAMS) return;
+  const float gr = grad[i];
+  const float mi = beta1 * m[i] + (1.0f - beta1) * gr;
+  const float vi = beta2 * v[i] + (1.0f - beta2) * gr * gr;
+  m[i] = mi;
+  v[i] = vi;
+  P[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// Slope in the original frame from (cos 2phi, sin 2phi) in the normalised one.
+__global__ void k_net_slopes(const float* __restrict__ out, const double* __restrict__ scale,
+                             int B, double* __restrict__ theta) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  const double phi = 0.5 * atan2((double)out[2 * b + 1], (double)out[2 * b]);
+  theta[b] = tan(phi) * scale[4 * b + 3] / scale[4 * b + 2];
+}
+
+lms_status check(const char* what) {
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(LMS_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+  return LMS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lms_status lms_net_prepare(const double* d_xy, const int64_t* d_offsets, int64_t B, float* d_pts,
+                           double* d_scale, void* stream) {
+  lms_host::clear_error();
+  if (!d_xy || !d_offsets || !d_pts || !d_scale || B < 1 || B > INT_MAX)
+    return fail(LMS_ERR_ARG, "bad arguments");
+  hipLaunchKernelGGL(k_net_prepare, dim3((unsigned)B), dim3(NT), 0, (hipStream_t)stream, d_xy,
+                     d_offsets, (float2*)d_pts, d_scale);
+  return check("k_net_prepare");
+}
+
+lms_status lms_net_forward(const float* d_params, const float* d_pts, const int64_t* d_offsets,
+                           int64_t B, float* d_out, float* d_g, void* stream) {
+  lms_host::clear_error();
+  if (!d_params || !d_pts || !d_offsets || !d_out || B < 1 || B > INT_MAX)
+    return fail(LMS_ERR_ARG, "bad arguments");
+  hipLaunchKernelGGL(k_net_forward, dim3((unsigned)B), dim3(NT), 0, (hipStream_t)stream, d_params,
+                     (const float2*)d_pts, d_offsets, d_out, d_g);
+  return check("k_net_forward");
+}
+
+lms_status lms_net_backward(const float* d_params, const float* d_pts, const int64_t* d_offsets,
+                            int64_t B, const float* d_target, const float* d_out,
+                            const float* d_g, float* d_grad_set, float* d_grad, float* d_loss,
+                            void* stream) {
+  lms_host::clear_error();
+  if (!d_params || !d_pts || !d_offsets || !d_target || !d_out || !d_g || !d_grad_set ||
+      !d_grad || !d_loss || B < 1 || B > INT_MAX)
+    return fail(LMS_ERR_ARG, "bad arguments");
+  hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_net_backward, dim3((unsigned)B), dim3(NT), 0, s, d_params,
+                     (const float2*)d_pts, d_offsets, (int)B, d_target, d_out, d_g, d_grad_set,
+                     d_loss);
+  hipLaunchKernelGGL(k_net_reduce, dim3((N_PARAMS + NT - 1) / NT), dim3(NT), 0, s, d_grad_set,
+                     (int)B, d_grad);
+  return check("k_net_backward");
+}
+
+lms_status lms_net_adam(float* d_params, float* d_m, float* d_v, const float* d_grad, int64_t step,
+                        float lr, float beta1, float beta2, float eps, void* stream) {
+  lms_host::clear_error();
+  if (!d_params || !d_m || !d_v || !d_grad || step < 1) return fail(LMS_ERR_ARG, "bad arguments");
+  const float c1 = 1.0f - powf(beta1, (float)step), c2 = 1.0f - powf(beta2, (float)step);
+  hipLaunchKernelGGL(k_net_adam, dim3((N_PARAMS + NT - 1) / NT), dim3(NT), 0, (hipStream_t)stream,
+                     d_params, d_m, d_v, d_grad, lr, beta1, beta2, eps, c1, c2);
+  return check("k_net_adam");
+}
+
+lms_status lms_net_slopes(const float* d_out, const double* d_scale, int64_t B, double* d_theta,
+                          void* stream) {
+  lms_host::clear_error();
+  if (!d_out || !d_scale || !d_theta || B < 1 || B > INT_MAX) return fail(LMS_ERR_ARG, "bad arguments");
+  hipLaunchKernelGGL(k_net_slopes, dim3((unsigned)((B + 255) / 256)), dim3(256), 0,
+                     (hipStream_t)stream, d_out, d_scale, (int)B, d_theta);
+  return check("k_net_slopes");
+}
+
+}  // extern "C"

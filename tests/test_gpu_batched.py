@@ -50,8 +50,8 @@ def test_batched_equals_single_solves(gpu):
 
 
 def test_mixed_sizes_all_classes(gpu, orc):
-    """Problems in every register class (<= 512, <= 1024, <= 4096 points)."""
-    sizes = [2, 3, 33, 64, 65, 511, 512, 513, 1024, 1025, 2000]
+    """Problems in every register class (<= 512, 1024, 2048, 4096 points)."""
+    sizes = [2, 3, 33, 64, 65, 511, 512, 513, 1024, 1025, 2000, 2048, 2049, 3000]
     parts = [planted(n, 0.4, 300 + n) for n in sizes]
     off = np.concatenate([[0], np.cumsum([len(p) for p in parts])]).astype(np.int64)
     res = gpu.solve_batched(dev(np.concatenate(parts)), off)

@@ -1,0 +1,101 @@
+"""The point-set network's GPU kernels against the FP64 reference in
+oracle/net.py (same BF16 rounding points), and the seed's effect on the
+exact search."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import net as ref
+from workloads import gen
+from workloads.gen import Stream
+
+pytestmark = pytest.mark.gpu
+
+
+def batch(seed, B=6, n=300):
+    xy, off = gen.rotated_line(B, n, seed)
+    return xy, off
+
+
+def test_forward_and_gradient_match_reference(gpu):
+    from paper_1510_01041_amd import seednet
+    params = ref.init_params(11)
+    st = Stream(12, 120)
+    for k in params:
+        if k.startswith("b"):
+            params[k] = st.uniform(params[k].size, -0.2, 0.2).reshape(params[k].shape)
+    # FP32 masters, as the GPU holds them
+    p32 = {k: np.asarray(v, dtype=np.float32).astype(np.float64) for k, v in params.items()}
+    xy, off = batch(13)
+    B = len(off) - 1
+    targets = st.uniform(2 * B, -1, 1).reshape(B, 2)
+    net = seednet.SeedNet(seednet.pack(p32))
+    pts, scale, doff = net.prepare(torch.from_numpy(xy).cuda(), off)
+    grad, loss, out = net.gradient(pts, doff, torch.from_numpy(targets))
+    pts_h = pts.cpu().numpy().astype(np.float64)
+    sets = [pts_h[off[b]:off[b + 1]] for b in range(B)]
+    # the prepared frame matches the reference normalisation (FP32 rounding)
+    for b in range(B):
+        r, c, s = ref.normalise(xy[off[b]:off[b + 1]])
+        assert np.max(np.abs(r - sets[b])) < 1e-6
+        assert np.allclose(scale[b].cpu().numpy(), [c[0], c[1], s[0], s[1]], rtol=0, atol=0)
+    rl, rg, rout = ref.loss_and_grad(p32, sets, targets)
+    assert np.allclose(out.cpu().numpy(), rout, rtol=1e-4, atol=1e-5)
+    assert abs(float(loss.sum()) - rl) <= 1e-4 * max(rl, 1e-6)
+    g = grad.cpu().numpy()
+    gref = seednet.pack(rg)
+    scale_g = np.abs(gref).max()
+    assert np.max(np.abs(g - gref)) <= 1e-3 * scale_g, np.max(np.abs(g - gref)) / scale_g
+    for k, shp in seednet.LAYOUT:
+        a = seednet.unpack(g)[k]
+        assert np.linalg.norm(a - rg[k]) <= 1e-3 * max(np.linalg.norm(rg[k]), 1e-6 * scale_g), k
+
+
+def test_adam_step(gpu):
+    from paper_1510_01041_amd import seednet
+    net = seednet.SeedNet(seed=3)
+    p0 = net.P.cpu().numpy().astype(np.float64)
+    g = Stream(5, 50).uniform(seednet.N_PARAMS, -1, 1).astype(np.float32)
+    gd = torch.from_numpy(g).cuda()
+    net.adam(gd, lr=0.01)
+    net.adam(gd, lr=0.01)
+    m = v = np.zeros_like(p0)
+    p = p0.copy()
+    for t in (1, 2):
+        m = 0.9 * m + 0.1 * g
+        v = 0.999 * v + 0.001 * g.astype(np.float64) ** 2
+        p = p - 0.01 * (m / (1 - 0.9 ** t)) / (np.sqrt(v / (1 - 0.999 ** t)) + 1e-8)
+    assert np.allclose(net.P.cpu().numpy(), p, rtol=1e-5, atol=1e-6)
+
+
+def test_slope_decoding(gpu):
+    from paper_1510_01041_amd import seednet
+    net = seednet.SeedNet(seed=4)
+    xy, off = batch(14, B=5, n=200)
+    th = net.predict_slopes(torch.from_numpy(xy).cuda(), off).cpu().numpy()
+    pts, scale, doff = net.prepare(torch.from_numpy(xy).cuda(), off)
+    out, _ = net.forward(pts, doff)
+    o = out.cpu().numpy().astype(np.float64)
+    sc = scale.cpu().numpy()
+    want = np.tan(0.5 * np.arctan2(o[:, 1], o[:, 0])) * sc[:, 3] / sc[:, 2]
+    assert np.allclose(th, want, rtol=1e-9)
+
+
+def test_training_reduces_loss(gpu):
+    from paper_1510_01041_amd import seednet, train_seednet
+    net, hist = train_seednet.train(n_sets=512, n=256, epochs=6, batch=64, lr=3e-3, seed=21,
+                                    chunk=256, log=print)
+    assert hist["loss"][-1] < 0.7 * hist["loss"][0], hist["loss"]
+
+
+def test_seed_slope_keeps_result_exact(gpu):
+    """Whatever the network predicts, the search result is unchanged."""
+    from paper_1510_01041_amd import seednet
+    net = seednet.SeedNet(seed=9)  # untrained: arbitrary slopes
+    for name, s in (("c1", 101), ("c1", 102)):
+        xy = gen.make(name, s)
+        d = torch.from_numpy(xy).cuda()
+        th = net.predict_slopes(d, np.array([0, len(xy)]))
+        a = gpu.solve(d)
+        b = gpu.solve(d, seed_pairs=0, seed_theta=th)
+        assert (a.width, a.theta1, a.z_lo) == (b.width, b.theta1, b.z_lo)

@@ -257,6 +257,59 @@ def hough_patches(B: int, seed: int, n_lo: int = 32, n_hi: int = 512,
     return np.ascontiguousarray(xy), offsets
 
 
+def rotated_line(count: int, n: int, seed: int, f_lo: float = 0.0, f_hi: float = 0.45):
+    """count sets of n points around a line at a random angle (training data).
+
+    Per set: outlier fraction f ~ U[f_lo, f_hi]; round(f n) outliers uniform in
+    [-10,10]x[-20,20]; the other points c + t (cos phi, sin phi) +
+    e (-sin phi, cos phi) with phi ~ U[-pi/2, pi/2), c ~ U([-2,2]^2),
+    t ~ U(-10,10), e ~ N(0, 0.05^2). Returns (xy (count*n, 2), offsets).
+    """
+    st = Stream(seed, 6)
+    f = st.uniform(count, f_lo, f_hi)
+    n_out = np.round(f * n).astype(np.int64)
+    # direction with cos phi >= 0: uniform angle on [-pi/2, pi/2)
+    dx = np.empty(count)
+    dy = np.empty(count)
+    have = 0
+    while have < count:
+        need = count - have
+        t = int(need * 1.35) + 16
+        u = st.uniform(t, -1.0, 1.0)
+        v = st.uniform(t, -1.0, 1.0)
+        r2 = u * u + v * v
+        ok = (r2 > 1e-6) & (r2 < 1.0)
+        u, v, r2 = u[ok], v[ok], r2[ok]
+        r = np.sqrt(r2)
+        u, v = u / r, v / r
+        flip = u < 0.0
+        u = np.where(flip, -u, u)
+        v = np.where(flip, -v, v)
+        take = min(need, len(u))
+        dx[have:have + take] = u[:take]
+        dy[have:have + take] = v[:take]
+        have += take
+    c = st.uniform(2 * count, -2.0, 2.0).reshape(count, 2)
+    N = count * n
+    pid = np.repeat(np.arange(count), n)
+    k = np.tile(np.arange(n), count)
+    is_out = k < n_out[pid]
+    t = st.uniform(N, -10.0, 10.0)
+    e = 0.05 * st.normal(N)
+    x = c[pid, 0] + t * dx[pid] - e * dy[pid]
+    y = c[pid, 1] + t * dy[pid] + e * dx[pid]
+    ox = st.uniform(N, -10.0, 10.0)
+    oy = st.uniform(N, -20.0, 20.0)
+    x = np.where(is_out, ox, x)
+    y = np.where(is_out, oy, y)
+    order = np.lexsort((st.u64(N), pid))
+    xy = np.empty((N, 2), dtype=np.float64)
+    xy[:, 0] = x[order]
+    xy[:, 1] = y[order]
+    offsets = np.arange(count + 1, dtype=np.int64) * n
+    return np.ascontiguousarray(xy), offsets
+
+
 # --------------------------------------------------------------------------
 # Named workloads
 # --------------------------------------------------------------------------
