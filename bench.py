@@ -40,6 +40,10 @@ def parse_args():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3a", "c3b", "c4"])
     ap.add_argument("--seed", type=int, default=None)
+    ap.add_argument("--tile-regs", type=int, default=0,
+                    help="64-point chunks of the screen kept in registers (0 = automatic)")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the seeding comparison")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target wall time of the CPU-oracle sample (0 = skip)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -114,7 +118,7 @@ def main():
     out = torch.empty(lms.RESULT_BYTES, dtype=torch.uint8, device=dev)
 
     for _ in range(args.warmup):
-        lms.solve_async(d, 0, out)
+        lms.solve_async(d, 0, out, tile_regs=args.tile_regs)
     torch.cuda.synchronize()
     first = lms.parse(out)
     if first.status < 0:
@@ -124,7 +128,7 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        lms.solve_async(d, 0, out)
+        lms.solve_async(d, 0, out, tile_regs=args.tile_regs)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     n_prof, stage_ms = lms.profile_end()
@@ -156,7 +160,7 @@ def main():
             f"planted line y=0.7x+2+N(0,0.05^2), n={n}, {cfg.get('f_out', 0):.0%} uniform "
             f"outliers" if cfg["kind"] == "planted" else
             f"integer points in [0,1023]^2, n={n}, 30% duplicated x"),
-            "n": n, "h": h, "pairs": pairs, "seed": seed},
+            "n": n, "h": h, "pairs": pairs, "seed": seed, "tile_regs": args.tile_regs},
         "solves_per_sec": 1e3 / ms_step,
         "stages_ms_per_solve": {k: v / max(n_prof, 1) for k, v in stage_ms.items()},
         "roofline": {"bound": "alu", "kernel": "k_screen", "achieved": achieved / 1e12,
@@ -170,7 +174,8 @@ def main():
         "result": {"half_width": r.half_width, "theta1": r.theta1, "theta2": r.theta2,
                    "parity": parity},
     }
-    line["learned_vs_plain"] = seeding_comparison(lms, d, r, max(3, args.steps // 5))
+    if not args.no_compare:
+        line["learned_vs_plain"] = seeding_comparison(lms, d, r, max(3, args.steps // 5))
     if args.cpu_seconds > 0:
         line["cpu_baseline"] = cpu_baseline(xy, args.cpu_seconds)
     print(json.dumps(line), flush=True)

@@ -80,14 +80,26 @@ typedef struct lms_options {
   uint32_t struct_size; /* sizeof(lms_options) */
   uint32_t flags;       /* LMS_F_* */
   int32_t seed_pairs;   /* random pair slopes evaluated exactly before the screen
-                           to set the initial width bound (default 255; >= 0) */
-  int32_t tile_regs;    /* 0 = automatic. Otherwise the number of 64-point chunks of
-                           the screen kept in registers (1, 16, 32 or 64); the other
+                           to set the initial width bound; -1 = automatic (the tuned
+                           value, else 255 for lms_solve and 31 per problem for
+                           lms_solve_batched) */
+  int32_t tile_regs;    /* 0 = automatic (tuned, else all points in registers up to
+                           4096). Otherwise the number of 64-point chunks of the
+                           screen kept in registers (1, 16, 32 or 64); the other
                            points stream from LDS. */
   const double* d_seed_theta; /* optional device array of extra seed slopes (any
                                  real values; they only tighten the initial bound) */
   int64_t n_seed_theta;       /* length of d_seed_theta */
+  int32_t tile_batches; /* 0 = automatic; otherwise 64-partner batches per work item
+                           of the screen (1..64) */
+  int32_t reserved;
 } lms_options;
+
+/* Tile choice found by the autotuner for one size class. */
+typedef struct lms_tuning {
+  int32_t tile_regs, tile_batches, seed_pairs, reserved;
+  double ms; /* median time of one solve (or one batched pass) with this choice */
+} lms_tuning;
 
 /* Exact LMS line of one point set (Eq. (1); Algorithm 1's exhaustive search
  * over pair slopes).
@@ -116,6 +128,22 @@ lms_status lms_solve(const double* d_xy, int64_t n, int64_t h, lms_result* d_out
 lms_status lms_solve_batched(const double* d_xy, const int64_t* d_offsets,
                              const int64_t* h_offsets, int64_t B, const int32_t* d_h,
                              lms_result* d_out, const lms_options* opt, void* stream);
+
+/* Autotuner. Times lms_solve on the caller's point set (device memory) for
+ * the candidate tiles (register chunks vs LDS streaming, partner batches per
+ * work item) with HIP events on `stream`, `reps` runs each, and keeps the
+ * fastest for the size class next_pow2(n) of this device. Later lms_solve
+ * calls with automatic tiles use it. If the environment variable
+ * LMS_TUNE_FILE names a file, the table is read from it at the first use and
+ * written back after each tuning. Synchronises the stream. */
+lms_status lms_autotune(const double* d_xy, int64_t n, int64_t h, int32_t reps, void* stream,
+                        lms_tuning* out);
+/* The same for lms_solve_batched: tunes the seed pairs per problem on the
+ * caller's batch (the arguments are those of lms_solve_batched), for the
+ * batch's size class (next_pow2 of its largest problem). */
+lms_status lms_autotune_batched(const double* d_xy, const int64_t* d_offsets,
+                                const int64_t* h_offsets, int64_t B, const int32_t* d_h,
+                                lms_result* d_out, int32_t reps, void* stream, lms_tuning* out);
 
 /* Synchronous convenience: host input, host output. Copies the points to the
  * device, solves on a library-owned stream and copies the result back. */

@@ -48,7 +48,14 @@ assert ctypes.sizeof(_Result) == RESULT_BYTES
 class _Options(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("flags", ctypes.c_uint32),
                 ("seed_pairs", ctypes.c_int32), ("tile_regs", ctypes.c_int32),
-                ("d_seed_theta", ctypes.c_void_p), ("n_seed_theta", ctypes.c_int64)]
+                ("d_seed_theta", ctypes.c_void_p), ("n_seed_theta", ctypes.c_int64),
+                ("tile_batches", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class _Tuning(ctypes.Structure):
+    _fields_ = [("tile_regs", ctypes.c_int32), ("tile_batches", ctypes.c_int32),
+                ("seed_pairs", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("ms", ctypes.c_double)]
 
 
 @dataclass
@@ -93,6 +100,11 @@ def load():
     L.lms_solve_host.restype = i32
     L.lms_solve_batched.argtypes = [vp, vp, vp, i64, vp, vp, ctypes.POINTER(_Options), vp]
     L.lms_solve_batched.restype = i32
+    L.lms_autotune.argtypes = [vp, i64, i64, ctypes.c_int32, vp, ctypes.POINTER(_Tuning)]
+    L.lms_autotune.restype = i32
+    L.lms_autotune_batched.argtypes = [vp, vp, vp, i64, vp, vp, ctypes.c_int32, vp,
+                                       ctypes.POINTER(_Tuning)]
+    L.lms_autotune_batched.restype = i32
     L.lms_eval_slopes.argtypes = [vp, i64, i64, vp, i64, vp, vp]
     L.lms_eval_slopes.restype = i32
     L.lms_screen_pairs.argtypes = [vp, i64, i64, ctypes.c_double, vp, i64, vp, vp]
@@ -136,12 +148,14 @@ def _stream(stream) -> int:
     return s.cuda_stream
 
 
-def _options(flags=0, seed_pairs=None, seed_theta: torch.Tensor | None = None, tile_regs=0):
+def _options(flags=0, seed_pairs=None, seed_theta: torch.Tensor | None = None, tile_regs=0,
+             tile_batches=0):
     o = _Options()
     o.struct_size = ctypes.sizeof(_Options)
     o.flags = flags
     o.tile_regs = int(tile_regs)
-    o.seed_pairs = 255 if seed_pairs is None else int(seed_pairs)
+    o.tile_batches = int(tile_batches)
+    o.seed_pairs = -1 if seed_pairs is None else int(seed_pairs)
     if seed_theta is not None:
         if not (seed_theta.is_cuda and seed_theta.dtype == torch.float64 and seed_theta.dim() == 1
                 and seed_theta.is_contiguous()):
@@ -161,12 +175,13 @@ def parse(raw: torch.Tensor) -> LmsResult:
 def solve_async(xy: torch.Tensor, h: int = 0, out: torch.Tensor | None = None, *,
                 no_prune: bool = False, seed_pairs: int | None = None,
                 seed_theta: torch.Tensor | None = None, tile_regs: int = 0,
-                stream=None) -> torch.Tensor:
+                tile_batches: int = 0, stream=None) -> torch.Tensor:
     """Enqueue one exact LMS solve; returns the device uint8[112] result buffer."""
     xy = _points(xy)
     if out is None:
         out = torch.empty(RESULT_BYTES, dtype=torch.uint8, device=xy.device)
-    opt = _options(LMS_F_NO_PRUNE if no_prune else 0, seed_pairs, seed_theta, tile_regs)
+    opt = _options(LMS_F_NO_PRUNE if no_prune else 0, seed_pairs, seed_theta, tile_regs,
+                   tile_batches)
     st = load().lms_solve(xy.data_ptr(), xy.shape[0], h, out.data_ptr(), ctypes.byref(opt),
                           _stream(stream))
     _check(st)
@@ -223,7 +238,7 @@ def solve_batched_async(xy: torch.Tensor, offsets, h: torch.Tensor | None = None
         out = torch.empty((B, RESULT_BYTES), dtype=torch.uint8, device=xy.device)
     if h is not None and not (h.is_cuda and h.dtype == torch.int32 and h.numel() == B):
         raise ValueError("h must be a CUDA int32 tensor with B values")
-    opt = _options(LMS_F_GRAPH if graph else 0, 31 if seed_pairs is None else seed_pairs)
+    opt = _options(LMS_F_GRAPH if graph else 0, seed_pairs)
     st = load().lms_solve_batched(xy.data_ptr(), off_d.data_ptr(), off_h.ctypes.data, B,
                                   None if h is None else h.data_ptr(), out.data_ptr(),
                                   ctypes.byref(opt), _stream(stream))
@@ -231,6 +246,32 @@ def solve_batched_async(xy: torch.Tensor, offsets, h: torch.Tensor | None = None
     # keep the device offsets alive while the work is queued
     out._lms_offsets = off_d
     return out
+
+
+def autotune(xy: torch.Tensor, h: int = 0, reps: int = 3, stream=None) -> dict:
+    """Time the screen tiles on this point set and keep the fastest for its
+    size class (used by later solves with automatic tiles)."""
+    xy = _points(xy)
+    t = _Tuning()
+    _check(load().lms_autotune(xy.data_ptr(), xy.shape[0], h, reps, _stream(stream),
+                               ctypes.byref(t)))
+    return {f: getattr(t, f) for f, _ in _Tuning._fields_}
+
+
+def autotune_batched(xy: torch.Tensor, offsets, h=None, reps: int = 3, stream=None) -> dict:
+    """Tune the seed pairs per problem of lms_solve_batched on this batch."""
+    import numpy as np
+    xy = _points(xy)
+    off_h = np.ascontiguousarray(np.asarray(offsets.cpu() if isinstance(offsets, torch.Tensor)
+                                            else offsets, dtype=np.int64))
+    off_d = torch.from_numpy(off_h).to(xy.device)
+    B = off_h.shape[0] - 1
+    out = torch.empty((B, RESULT_BYTES), dtype=torch.uint8, device=xy.device)
+    t = _Tuning()
+    _check(load().lms_autotune_batched(xy.data_ptr(), off_d.data_ptr(), off_h.ctypes.data, B,
+                                       None if h is None else h.data_ptr(), out.data_ptr(), reps,
+                                       _stream(stream), ctypes.byref(t)))
+    return {f: getattr(t, f) for f, _ in _Tuning._fields_}
 
 
 def solve_batched(xy: torch.Tensor, offsets, h=None, **kw):

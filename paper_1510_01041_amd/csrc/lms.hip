@@ -54,6 +54,7 @@ using lms_host::fail;
 constexpr int kDefaultSeeds = 255;
 constexpr long long kScreenCap = 1ll << 24;     // survivor slots beyond the seeds
 constexpr int kRegChunks = 64;                  // points per lane kept in VGPRs (max)
+constexpr int kPathSingle = 0;                  // tuning-table key of lms_solve
 
 // Per-solve state in device memory.
 struct __align__(16) Ctx {
@@ -644,19 +645,27 @@ lms_status lms_solve(const double* d_xy, int64_t n, int64_t h, lms_result* d_out
                      const lms_options* opt, void* stream) {
   lms_host::clear_error();
   if (opt && opt->struct_size < sizeof(lms_options)) return fail(LMS_ERR_ARG, "bad options size");
+  // automatic tiles and seeds: the autotuned choice for this size class, if any
+  lms_tuning tuned{0, 0, -1, 0, 0.0};
+  const bool have_tuned = n >= 2 && n <= LMS_MAX_N &&
+                          lms_host::get_tuning(kPathSingle, lms_host::size_class((int)n), &tuned);
+  int tile_regs = opt ? opt->tile_regs : 0;
+  int tile_batches = opt ? opt->tile_batches : 0;
+  if (have_tuned && tile_regs == 0) tile_regs = tuned.tile_regs;
+  if (have_tuned && tile_batches == 0) tile_batches = tuned.tile_batches;
+  if (tile_batches < 0 || tile_batches > 64) return fail(LMS_ERR_ARG, "tile_batches must be in [0, 64]");
   Plan p;
-  lms_status st = make_plan(d_xy, n, h, &p, opt ? opt->tile_regs : 0);
+  lms_status st = make_plan(d_xy, n, h, &p, tile_regs);
   if (st != LMS_OK) return st;
   if (!d_out) return fail(LMS_ERR_ARG, "null result pointer");
-  int seeds = kDefaultSeeds;
+  int seeds = (have_tuned && tuned.seed_pairs >= 0) ? tuned.seed_pairs : kDefaultSeeds;
   unsigned flags = 0;
   const double* d_seed_theta = nullptr;
   int64_t n_seed_theta = 0;
   if (opt) {
-    if (opt->struct_size < sizeof(lms_options)) return fail(LMS_ERR_ARG, "bad options size");
     flags = opt->flags;
-    if (opt->seed_pairs < 0) return fail(LMS_ERR_ARG, "seed_pairs must be >= 0");
-    seeds = opt->seed_pairs;
+    if (opt->seed_pairs < -1) return fail(LMS_ERR_ARG, "seed_pairs must be >= -1");
+    if (opt->seed_pairs >= 0) seeds = opt->seed_pairs;
     d_seed_theta = opt->d_seed_theta;
     n_seed_theta = opt->n_seed_theta;
     if (n_seed_theta < 0 || (n_seed_theta > 0 && !d_seed_theta) || n_seed_theta > (1 << 24))
@@ -698,7 +707,7 @@ lms_status lms_solve(const double* d_xy, int64_t n, int64_t h, lms_result* d_out
   {
     const int Pmax = p.n / 2;
     const int batches = (Pmax + 63) / 64;
-    const int G = std::min(4, std::max(1, batches));
+    const int G = std::min(tile_batches > 0 ? tile_batches : 4, std::max(1, batches));
     const int ipa = (batches + G - 1) / G;
     const long long n_items = (long long)p.n * ipa;
     hipError_t err = launch_screen(s, p.R, p.lds, cu, d_xy, xy32, ctx, entries, (int)p.cap, G,
@@ -716,6 +725,60 @@ lms_status lms_solve(const double* d_xy, int64_t n, int64_t h, lms_result* d_out
   prof.finish();
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return fail(LMS_ERR_DEVICE, std::string("launch: ") + hipGetErrorString(err));
+  return LMS_OK;
+}
+
+lms_status lms_autotune(const double* d_xy, int64_t n, int64_t h, int32_t reps, void* stream,
+                        lms_tuning* out) {
+  lms_host::clear_error();
+  if (!d_xy || n < 2 || n > LMS_MAX_N || reps < 1 || reps > 100)
+    return fail(LMS_ERR_ARG, "bad arguments");
+  hipStream_t s = (hipStream_t)stream;
+  lms_result* d_res = nullptr;
+  if (hipMalloc(&d_res, sizeof(lms_result)) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(LMS_ERR_NOMEM, "hipMalloc failed");
+  }
+  hipEvent_t e0, e1;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  const int auto_R = pick_R((int)n);
+  static const int kRegs[] = {0, 32, 16, 1};
+  static const int kBatches[] = {1, 2, 4, 8};
+  lms_tuning best{0, 0, kDefaultSeeds, 0, 1e30};
+  lms_status st = LMS_OK;
+  for (int r : kRegs) {
+    if (r != 0 && r >= auto_R) continue;  // only fewer register chunks than automatic
+    for (int g : kBatches) {
+      lms_options o;
+      std::memset(&o, 0, sizeof(o));
+      o.struct_size = sizeof(o);
+      o.seed_pairs = kDefaultSeeds;
+      o.tile_regs = r == 0 ? 64 : r;
+      o.tile_batches = g;
+      st = lms_solve(d_xy, n, h, d_res, &o, stream);  // warm-up, also sizes the workspace
+      if (st != LMS_OK) break;
+      std::vector<float> t(reps);
+      for (int k = 0; k < reps && st == LMS_OK; ++k) {
+        (void)hipEventRecord(e0, s);
+        st = lms_solve(d_xy, n, h, d_res, &o, stream);
+        (void)hipEventRecord(e1, s);
+        if (hipEventSynchronize(e1) != hipSuccess) st = fail(LMS_ERR_DEVICE, "event failed");
+        (void)hipEventElapsedTime(&t[k], e0, e1);
+      }
+      if (st != LMS_OK) break;
+      std::sort(t.begin(), t.end());
+      const double ms = t[reps / 2];
+      if (ms < best.ms) best = {o.tile_regs, g, kDefaultSeeds, 0, ms};
+    }
+    if (st != LMS_OK) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(d_res);
+  if (st != LMS_OK) return st;
+  lms_host::set_tuning(kPathSingle, lms_host::size_class((int)n), best);
+  if (out) *out = best;
   return LMS_OK;
 }
 

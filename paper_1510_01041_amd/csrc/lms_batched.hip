@@ -49,6 +49,8 @@ constexpr int kBatchMaxN = 4096;
 constexpr int kClasses = 4;
 constexpr int kClassChunks[kClasses] = {8, 16, 32, 64};  // n <= 512, 1024, 2048, 4096
 constexpr long long kBatchScreenCap = 1ll << 24;
+constexpr int kBatchSeeds = 31;   // default random seed pairs per problem
+constexpr int kPathBatched = 1;   // tuning-table key of lms_solve_batched
 
 // Per-problem state in device memory.
 struct __align__(16) PMeta {
@@ -604,8 +606,7 @@ lms_status lms_solve_batched(const double* d_xy, const int64_t* d_offsets,
   if (B < 1 || B > (1 << 24)) return fail(LMS_ERR_ARG, "B must be in [1, 2^24]");
   if (opt && opt->struct_size < sizeof(lms_options)) return fail(LMS_ERR_ARG, "bad options size");
   unsigned flags = opt ? opt->flags : 0u;
-  int S = 1 + (opt && opt->seed_pairs >= 0 ? std::min(opt->seed_pairs, 1 << 16) : 31);
-  if (opt && opt->seed_pairs < 0) return fail(LMS_ERR_ARG, "seed_pairs must be >= 0");
+  if (opt && opt->seed_pairs < -1) return fail(LMS_ERR_ARG, "seed_pairs must be >= -1");
   hipStream_t s = (hipStream_t)stream;
   std::vector<int64_t> off((size_t)B + 1);
   if (h_offsets) {
@@ -616,6 +617,19 @@ lms_status lms_solve_batched(const double* d_xy, const int64_t* d_offsets,
         hipStreamSynchronize(s) != hipSuccess)
       return fail(LMS_ERR_DEVICE, "copying the offsets to the host failed");
   }
+  int seed_pairs = kBatchSeeds;
+  if (opt && opt->seed_pairs >= 0) {
+    seed_pairs = std::min(opt->seed_pairs, 1 << 16);
+  } else {
+    long long mx = 0;
+    for (int64_t b = 0; b < B; ++b) mx = std::max<long long>(mx, off[b + 1] - off[b]);
+    lms_tuning t;
+    if (mx <= kBatchMaxN &&
+        lms_host::get_tuning(kPathBatched, lms_host::size_class((int)std::max(2ll, mx)), &t) &&
+        t.seed_pairs >= 0)
+      seed_pairs = t.seed_pairs;
+  }
+  const int S = 1 + seed_pairs;
   const BatchKey key{d_xy, d_offsets, d_h, d_out, stream, (int)B, S};
   std::lock_guard<std::mutex> lk(g_bmu);
   BatchCache& bc = g_batches[key];
@@ -682,6 +696,48 @@ lms_status lms_solve_batched(const double* d_xy, const int64_t* d_offsets,
   const lms_status st = enqueue_batch(bc.plan, bc.base, d_xy, d_offsets, d_h, d_out, s, &prof);
   prof.finish();
   return st;
+}
+
+lms_status lms_autotune_batched(const double* d_xy, const int64_t* d_offsets,
+                                const int64_t* h_offsets, int64_t B, const int32_t* d_h,
+                                lms_result* d_out, int32_t reps, void* stream, lms_tuning* out) {
+  lms_host::clear_error();
+  if (!h_offsets || B < 1 || reps < 1 || reps > 100) return fail(LMS_ERR_ARG, "bad arguments");
+  long long mx = 0;
+  for (int64_t b = 0; b < B; ++b) mx = std::max<long long>(mx, h_offsets[b + 1] - h_offsets[b]);
+  if (mx > kBatchMaxN) return fail(LMS_ERR_ARG, "problems hold at most 4096 points");
+  hipStream_t s = (hipStream_t)stream;
+  hipEvent_t e0, e1;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  static const int kSeeds[] = {7, 15, 31, 63};
+  lms_tuning best{0, 0, kBatchSeeds, 0, 1e30};
+  lms_status st = LMS_OK;
+  for (int sp : kSeeds) {
+    lms_options o;
+    std::memset(&o, 0, sizeof(o));
+    o.struct_size = sizeof(o);
+    o.seed_pairs = sp;
+    st = lms_solve_batched(d_xy, d_offsets, h_offsets, B, d_h, d_out, &o, stream);
+    if (st != LMS_OK) break;
+    std::vector<float> t(reps);
+    for (int k = 0; k < reps && st == LMS_OK; ++k) {
+      (void)hipEventRecord(e0, s);
+      st = lms_solve_batched(d_xy, d_offsets, h_offsets, B, d_h, d_out, &o, stream);
+      (void)hipEventRecord(e1, s);
+      if (hipEventSynchronize(e1) != hipSuccess) st = fail(LMS_ERR_DEVICE, "event failed");
+      (void)hipEventElapsedTime(&t[k], e0, e1);
+    }
+    if (st != LMS_OK) break;
+    std::sort(t.begin(), t.end());
+    if (t[reps / 2] < best.ms) best = {0, 0, sp, 0, t[reps / 2]};
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != LMS_OK) return st;
+  lms_host::set_tuning(kPathBatched, lms_host::size_class((int)std::max(2ll, mx)), best);
+  if (out) *out = best;
+  return LMS_OK;
 }
 
 }  // extern "C"

@@ -1,6 +1,9 @@
 // Host-side utilities shared by the C-ABI entry points (see lms_host.h).
 #include "lms_host.h"
 
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
 #include <map>
 #include <tuple>
 #include <vector>
@@ -21,7 +24,85 @@ int g_num_cu = 0;
 bool g_prof_on = false;
 std::vector<std::array<hipEvent_t, LMS_NSTAGES + 1>> g_prof_events;
 
+// tuning table: key (arch, path, size class)
+std::map<std::tuple<std::string, int, int>, lms_tuning> g_tune;
+bool g_tune_loaded = false;
+
+std::string arch_name() {
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+    return "unknown";
+  std::string a = prop.gcnArchName;
+  const size_t c = a.find(':');
+  return c == std::string::npos ? a : a.substr(0, c);
+}
+
+// One entry per line: arch path class tile_regs tile_batches seed_pairs ms
+// (a JSON array of arrays, so that other tools can read it).
+void load_tuning_locked() {
+  g_tune_loaded = true;
+  const char* path = std::getenv("LMS_TUNE_FILE");
+  if (!path) return;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return;
+  char arch[64];
+  int p, c, r, b, sp;
+  double ms;
+  int ch;
+  while ((ch = std::fgetc(f)) != EOF) {
+    if (ch != '[') continue;
+    if (std::fscanf(f, " \"%63[^\"]\" , %d , %d , %d , %d , %d , %lf ]", arch, &p, &c, &r, &b,
+                    &sp, &ms) == 7) {
+      lms_tuning t{r, b, sp, 0, ms};
+      g_tune[{arch, p, c}] = t;
+    }
+  }
+  std::fclose(f);
+}
+
+void save_tuning_locked() {
+  const char* path = std::getenv("LMS_TUNE_FILE");
+  if (!path) return;
+  FILE* f = std::fopen(path, "w");
+  if (!f) return;
+  std::fprintf(f, "[\n");
+  size_t k = 0;
+  for (auto& kv : g_tune) {
+    std::fprintf(f, " [\"%s\", %d, %d, %d, %d, %d, %.6f]%s\n", std::get<0>(kv.first).c_str(),
+                 std::get<1>(kv.first), std::get<2>(kv.first), kv.second.tile_regs,
+                 kv.second.tile_batches, kv.second.seed_pairs, kv.second.ms,
+                 ++k < g_tune.size() ? "," : "");
+  }
+  std::fprintf(f, "]\n");
+  std::fclose(f);
+}
+
 }  // namespace
+
+int size_class(int n) {
+  int p = 64;
+  while (p < n) p <<= 1;
+  return p;
+}
+
+bool get_tuning(int path, int cls, lms_tuning* t) {
+  const std::string a = arch_name();
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (!g_tune_loaded) load_tuning_locked();
+  auto it = g_tune.find({a, path, cls});
+  if (it == g_tune.end()) return false;
+  *t = it->second;
+  return true;
+}
+
+void set_tuning(int path, int cls, const lms_tuning& t) {
+  const std::string a = arch_name();
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (!g_tune_loaded) load_tuning_locked();
+  g_tune[{a, path, cls}] = t;
+  save_tuning_locked();
+}
 
 lms_status fail(lms_status s, const std::string& msg) {
   g_err = msg;

@@ -27,6 +27,12 @@ void free_workspace(int tag, void* stream);
 // Frees the cached batch plans, buffers and graphs (lms_batched.hip).
 void release_batches();
 
+// Autotuned tile choices per (device architecture, path, size class),
+// optionally persisted as JSON in the file named by LMS_TUNE_FILE.
+bool get_tuning(int path, int size_class, lms_tuning* t);
+void set_tuning(int path, int size_class, const lms_tuning& t);
+int size_class(int n);  // next power of two >= n (>= 64)
+
 // Compute units of the current device (queried once).
 int num_cu();
 

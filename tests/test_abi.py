@@ -63,7 +63,7 @@ def test_argument_errors_are_synchronous():
     bad = lms._options()
     bad.struct_size = 4
     assert _solve_raw(fake, 10, 0, fake, bad) == lms.LMS_ERR_ARG
-    neg = lms._options(seed_pairs=-1)
+    neg = lms._options(seed_pairs=-2)
     assert _solve_raw(fake, 10, 0, fake, neg) == lms.LMS_ERR_ARG
     L = lms.load()
     assert L.lms_eval_slopes(fake, 10, 0, None, 5, fake, None) == lms.LMS_ERR_ARG
@@ -94,3 +94,15 @@ def test_batched_argument_errors():
     dec = np.array([0, 10, 5], dtype=np.int64)
     assert L.lms_solve_batched(fake, fake, dec.ctypes.data, 2, None, fake, ctypes.byref(opt),
                                None) == lms.LMS_ERR_ARG
+
+
+def test_tile_and_tuning_argument_errors():
+    L = lms.load()
+    fake = 0x1000
+    bad = lms._options(tile_regs=65)
+    assert _solve_raw(fake, 100, 0, fake, bad) == lms.LMS_ERR_ARG
+    bad = lms._options(tile_batches=65)
+    assert _solve_raw(fake, 100, 0, fake, bad) == lms.LMS_ERR_ARG
+    t = lms._Tuning()
+    assert L.lms_autotune(None, 100, 0, 3, None, ctypes.byref(t)) == lms.LMS_ERR_ARG
+    assert L.lms_autotune(fake, 100, 0, 0, None, ctypes.byref(t)) == lms.LMS_ERR_ARG
