@@ -83,8 +83,9 @@ def cpu_baseline(xy, target_s):
 def main():
     args = parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the pair range would be split across GPUs; see DESIGN.md).", file=sys.stderr)
+        print("bench.py measures one GPU only: there is no multi-GPU path (one problem "
+              "would shard by anchor range, each GPU screening its share against the same "
+              "width bound).", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -185,10 +186,14 @@ def seeding_comparison(lms, d, ref, steps):
     """Time the same solve under different initial width bounds.
 
     plain: 255 random pair slopes (the default). learned: the seed network's
-    slope only, with network inference inside the timed region. Also reported:
-    the network slope plus the random pairs, no seed at all (only the extreme-x
-    pair), and a control of 63 random pairs. Every variant must return the
-    same line."""
+    slope, then two rounds of 63 pairs drawn from the narrowest window found
+    (from the network's line, then from the best of those pairs), with network
+    inference inside the timed region. Also reported: the network slope alone,
+    the learned seeds plus the random pairs, no seed at all (only the
+    extreme-x pair), 63 random pairs, and the exact LMS slope itself (the
+    tightest bound any seed can give). Every variant must return the same
+    line. pruned: the fraction of candidate slopes that the band test rejects
+    early."""
     import numpy as np
     import torch
     from paper_1510_01041_amd import seednet
@@ -197,6 +202,7 @@ def seeding_comparison(lms, d, ref, steps):
     net = seednet.SeedNet.load_weights(wpath) if os.path.exists(wpath) else None
     off = np.array([0, d.shape[0]], dtype=np.int64)
     out = torch.empty(lms.RESULT_BYTES, dtype=torch.uint8, device=d.device)
+    exact = torch.tensor([ref.theta1], dtype=torch.float64, device=d.device)
 
     def run(kind):
         def once():
@@ -206,10 +212,13 @@ def seeding_comparison(lms, d, ref, steps):
                 lms.solve_async(d, 0, out, seed_pairs=0)
             elif kind == "control63":
                 lms.solve_async(d, 0, out, seed_pairs=63)
+            elif kind == "exact_slope":
+                lms.solve_async(d, 0, out, seed_pairs=0, seed_theta=exact)
             else:
                 th = net.predict_slopes(d, off)
-                lms.solve_async(d, 0, out, seed_pairs=0 if kind == "learned" else None,
-                                seed_theta=th)
+                lms.solve_async(d, 0, out, seed_pairs=None if kind == "learned+pairs" else 0,
+                                seed_theta=th,
+                                window_pairs=0 if kind == "learned_slope_only" else 63)
         once()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -219,13 +228,18 @@ def seeding_comparison(lms, d, ref, steps):
         ms = (time.perf_counter() - t0) * 1e3 / steps
         r = lms.parse(out)
         return {"ms": ms, "survivors": r.survivors, "band_pass": r.band_pass,
+                "pruned": 1.0 - r.band_pass / max(r.candidates, 1),
                 "band_evals_per_pair": r.point_evals / max(r.candidates, 1),
                 "same_result": (r.width, r.theta1, r.z_lo) == (ref.width, ref.theta1, ref.z_lo)}
 
-    kinds = ["plain", "no_seed", "control63"] + (["learned", "learned+pairs"] if net else [])
+    kinds = ["plain", "no_seed", "control63", "exact_slope"]
+    if net:
+        kinds += ["learned", "learned_slope_only", "learned+pairs"]
     res = {k: run(k) for k in kinds}
     res["mismatches"] = sum(not v["same_result"] for v in res.values() if isinstance(v, dict))
     if net:
+        th = float(net.predict_slopes(d, off)[0])
+        res["learned_angle_error_deg"] = abs(np.degrees(np.arctan(th) - np.arctan(ref.theta1)))
         res["speedup_learned_vs_plain"] = res["plain"]["ms"] / res["learned"]["ms"]
         res["speedup_learned_vs_no_seed"] = res["no_seed"]["ms"] / res["learned"]["ms"]
     else:

@@ -50,7 +50,7 @@ typedef enum {
   LMS_ERR_CAPACITY = -5   /* more screen survivors than the workspace holds */
 } lms_status;
 
-/* Result of one solve. 112 bytes, written to device memory by lms_solve.
+/* Result of one solve. 128 bytes, written to device memory by lms_solve.
  * On a negative status the FP64 fields are NaN. */
 typedef struct lms_result {
   double theta1;     /* slope of the LMS line (a pair slope; 0 if degenerate) */
@@ -67,6 +67,9 @@ typedef struct lms_result {
   uint64_t point_evals;   /* FP32 residuals of the band test (FMA + one compare each) */
   uint64_t dir_evals;     /* FP32 residuals of the one-sided tests (FMA + four compares) */
   uint64_t band_pass;     /* pairs that passed the band test */
+  uint64_t bin_pass;      /* pairs the slope-bin screen passed to the FP32 test
+                             (lms_solve; 0 where that screen did not run) */
+  uint64_t reserved;
 } lms_result;
 
 /* Flags for lms_options.flags */
@@ -92,12 +95,23 @@ typedef struct lms_options {
   int64_t n_seed_theta;       /* length of d_seed_theta */
   int32_t tile_batches; /* 0 = automatic; otherwise 64-partner batches per work item
                            of the screen (1..64) */
+  int32_t window_pairs; /* lms_solve with device seed slopes: 0, or the number of
+                           pairs (<= 65536) drawn among the points of the narrowest
+                           seed slope's window and evaluated exactly as further
+                           seeds; a second round draws as many from the narrowest
+                           window of the first round's pairs. A slope near the LMS
+                           line puts mostly inliers in its window, so these pairs
+                           give a tight bound. Ignored by lms_solve_batched. */
+  int32_t bins_log2;    /* lms_solve: slope bins per anchor of the first screen,
+                           2^bins_log2 (11..15; raised to at least n); 0 = automatic
+                           (tuned, else about 2n); -1 = no slope-bin screen (every
+                           pair goes through the FP32 test) */
   int32_t reserved;
 } lms_options;
 
 /* Tile choice found by the autotuner for one size class. */
 typedef struct lms_tuning {
-  int32_t tile_regs, tile_batches, seed_pairs, reserved;
+  int32_t tile_regs, tile_batches, seed_pairs, bins_log2;
   double ms; /* median time of one solve (or one batched pass) with this choice */
 } lms_tuning;
 

@@ -28,7 +28,7 @@ LMS_F_NO_PRUNE = 1
 LMS_F_GRAPH = 2
 BATCH_MAX_N = 4096
 MAX_N = 16384
-RESULT_BYTES = 112
+RESULT_BYTES = 128
 
 
 class _Result(ctypes.Structure):
@@ -39,7 +39,8 @@ class _Result(ctypes.Structure):
                 ("status", ctypes.c_int32), ("h", ctypes.c_int32),
                 ("candidates", ctypes.c_uint64), ("vertical", ctypes.c_uint64),
                 ("survivors", ctypes.c_uint64), ("point_evals", ctypes.c_uint64),
-                ("dir_evals", ctypes.c_uint64), ("band_pass", ctypes.c_uint64)]
+                ("dir_evals", ctypes.c_uint64), ("band_pass", ctypes.c_uint64),
+                ("bin_pass", ctypes.c_uint64), ("reserved", ctypes.c_uint64)]
 
 
 assert ctypes.sizeof(_Result) == RESULT_BYTES
@@ -49,12 +50,13 @@ class _Options(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("flags", ctypes.c_uint32),
                 ("seed_pairs", ctypes.c_int32), ("tile_regs", ctypes.c_int32),
                 ("d_seed_theta", ctypes.c_void_p), ("n_seed_theta", ctypes.c_int64),
-                ("tile_batches", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("tile_batches", ctypes.c_int32), ("window_pairs", ctypes.c_int32),
+                ("bins_log2", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class _Tuning(ctypes.Structure):
     _fields_ = [("tile_regs", ctypes.c_int32), ("tile_batches", ctypes.c_int32),
-                ("seed_pairs", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("seed_pairs", ctypes.c_int32), ("bins_log2", ctypes.c_int32),
                 ("ms", ctypes.c_double)]
 
 
@@ -149,12 +151,14 @@ def _stream(stream) -> int:
 
 
 def _options(flags=0, seed_pairs=None, seed_theta: torch.Tensor | None = None, tile_regs=0,
-             tile_batches=0):
+             tile_batches=0, window_pairs=0, bins_log2=0):
     o = _Options()
     o.struct_size = ctypes.sizeof(_Options)
     o.flags = flags
     o.tile_regs = int(tile_regs)
     o.tile_batches = int(tile_batches)
+    o.window_pairs = int(window_pairs)
+    o.bins_log2 = int(bins_log2)
     o.seed_pairs = -1 if seed_pairs is None else int(seed_pairs)
     if seed_theta is not None:
         if not (seed_theta.is_cuda and seed_theta.dtype == torch.float64 and seed_theta.dim() == 1
@@ -166,7 +170,7 @@ def _options(flags=0, seed_pairs=None, seed_theta: torch.Tensor | None = None, t
 
 
 def parse(raw: torch.Tensor) -> LmsResult:
-    """Decode a 112-byte lms_result (device or host uint8 tensor)."""
+    """Decode a 128-byte lms_result (device or host uint8 tensor)."""
     b = bytes(raw.detach().to("cpu").numpy().tobytes())
     r = _Result.from_buffer_copy(b)
     return LmsResult(**{f: getattr(r, f) for f, _ in _Result._fields_})
@@ -175,13 +179,19 @@ def parse(raw: torch.Tensor) -> LmsResult:
 def solve_async(xy: torch.Tensor, h: int = 0, out: torch.Tensor | None = None, *,
                 no_prune: bool = False, seed_pairs: int | None = None,
                 seed_theta: torch.Tensor | None = None, tile_regs: int = 0,
-                tile_batches: int = 0, stream=None) -> torch.Tensor:
-    """Enqueue one exact LMS solve; returns the device uint8[112] result buffer."""
+                tile_batches: int = 0, window_pairs: int = 0, bins_log2: int = 0,
+                stream=None) -> torch.Tensor:
+    """Enqueue one exact LMS solve; returns the device uint8[128] result buffer.
+
+    seed_theta: optional CUDA float64 slopes whose exact widths seed the bound;
+    window_pairs: with seed_theta, pairs drawn from the best seed line's window
+    (two rounds) as further seeds. bins_log2: slope bins per anchor of the
+    first screen (0 automatic, -1 off)."""
     xy = _points(xy)
     if out is None:
         out = torch.empty(RESULT_BYTES, dtype=torch.uint8, device=xy.device)
     opt = _options(LMS_F_NO_PRUNE if no_prune else 0, seed_pairs, seed_theta, tile_regs,
-                   tile_batches)
+                   tile_batches, window_pairs, bins_log2)
     st = load().lms_solve(xy.data_ptr(), xy.shape[0], h, out.data_ptr(), ctypes.byref(opt),
                           _stream(stream))
     _check(st)
@@ -208,7 +218,7 @@ def _result_dtype():
 
 
 def parse_batch(raw: torch.Tensor):
-    """Decode B results (device or host uint8[B, 112]) into a numpy record array."""
+    """Decode B results (device or host uint8[B, 128]) into a numpy record array."""
     import numpy as np
     a = raw.detach().to("cpu").contiguous().numpy()
     return np.frombuffer(a.tobytes(), dtype=_result_dtype()).view(np.recarray)
@@ -222,7 +232,7 @@ def solve_batched_async(xy: torch.Tensor, offsets, h: torch.Tensor | None = None
     offsets: B+1 int64 (host array or tensor; a device copy is made if needed).
     h: optional CUDA int32 tensor of B values. graph=True captures the kernels in
     a hipGraph on the first call and replays it on later calls with the same
-    buffers. Returns the device uint8[B, 112] result buffer."""
+    buffers. Returns the device uint8[B, 128] result buffer."""
     import numpy as np
     xy = _points(xy)
     if isinstance(offsets, torch.Tensor):

@@ -66,9 +66,13 @@ struct __align__(16) Ctx {
   unsigned long long wbound;  // FP64 width bound, as bits (monotone atomicMin)
   unsigned int n_entries;     // seeds + survivors appended so far
   unsigned int overflow;
-  unsigned int next_item;
+  unsigned int next_item;     // work counter of the exhaustive screen
+  unsigned int n_cands;       // pairs passed by the slope-bin screen
+  unsigned int cand_overflow;
+  unsigned int next_anchor;   // work counter of the slope-bin screen
+  unsigned int next_block;    // work counter of the FP32 test of the listed pairs
   unsigned int pad;
-  unsigned long long vertical, screened, band_pass, point_evals, dir_evals, forced;
+  unsigned long long vertical, screened, band_pass, point_evals, dir_evals, forced, bin_pass;
 };
 
 // ---------------------------------------------------------------- prep
@@ -76,7 +80,7 @@ struct __align__(16) Ctx {
 __global__ __launch_bounds__(1024) void k_prep(const double* __restrict__ xy, int n, int h,
                                                int n_pad, Ctx* ctx, float2* __restrict__ xy32,
                                                uint2* __restrict__ entries, int n_seeds,
-                                               unsigned long long seed_key) {
+                                               int n_random, unsigned long long seed_key) {
   __shared__ double s_mn[1024], s_mx[1024], s_my[1024], s_My[1024];
   __shared__ int s_amn[1024], s_amx[1024], s_fin[1024];
   const int t = threadIdx.x;
@@ -135,12 +139,13 @@ __global__ __launch_bounds__(1024) void k_prep(const double* __restrict__ xy, in
     xy32[k] = p;
   }
   // Seed entries: the extreme-x pair (never vertical unless all x are equal),
-  // then random pairs from a counter-based SplitMix64 stream.
+  // then n_random random pairs from a counter-based SplitMix64 stream. Slots
+  // past those (window pairs, written later) start as the extreme-x pair.
   for (int e = t; e < n_seeds; e += blockDim.x) {
     uint2 p;
-    if (e == 0 && minx == maxx) {
+    if ((e == 0 || e > n_random) && minx == maxx) {
       p = make_uint2(kDegenerate, kDegenerate);
-    } else if (e == 0) {
+    } else if (e == 0 || e > n_random) {
       const int a = s_amn[0], b = s_amx[0];
       p = make_uint2((unsigned)min(a, b), (unsigned)max(a, b));
     } else {
@@ -195,7 +200,8 @@ __global__ __launch_bounds__(NT) void k_recheck(const double* __restrict__ xy, C
 template <int N2, int NT>
 __global__ __launch_bounds__(NT) void k_eval_slopes(const double* __restrict__ xy, int n, int h,
                                                     const double* __restrict__ theta, int m,
-                                                    double* __restrict__ out, Ctx* ctx) {
+                                                    double* __restrict__ out, Ctx* ctx,
+                                                    double4* __restrict__ rec) {
   __shared__ double z[N2];
   __shared__ unsigned long long s_w;
   __shared__ int s_s;
@@ -208,9 +214,69 @@ __global__ __launch_bounds__(NT) void k_eval_slopes(const double* __restrict__ x
     window_f64<N2, NT>(xy, n, h, th, z, &s_w, &s_s, &w, &lo, &hi);
     if (threadIdx.x == 0) {
       if (out) { out[3 * e] = w; out[3 * e + 1] = lo; out[3 * e + 2] = hi; }
+      if (rec) rec[e] = make_double4(w, th, lo, hi);
       if (ctx && isfinite(th))
         atomicMin(&ctx->wbound, (unsigned long long)__double_as_longlong(width_bound(w, th, ctx->xabs, ctx->yabs)));
     }
+  }
+}
+
+// ---------------------------------------------------------------- window pairs
+
+// Seed pairs from a candidate line: of m candidate windows (width, theta,
+// z_lo, z_hi), take the narrowest, list the points whose FP64 intercept
+// fma(-theta, x, y) lies in it (its h points, plus any tied at its ends) in
+// index order, and draw `count` pairs among them into entries [first,
+// first + count). When the line is close to the LMS line, most of those
+// points are inliers, and a pair of them has a slope near the optimum, so
+// its exact width tightens the bound far more than a random pair's.
+constexpr int kWinNT = 1024;
+__global__ __launch_bounds__(kWinNT) void k_window_pairs(const double* __restrict__ xy,
+                                                         const Ctx* ctx,
+                                                         const double4* __restrict__ cand, int m,
+                                                         uint2* __restrict__ entries, int first,
+                                                         int count, unsigned long long key) {
+  __shared__ int list[LMS_MAX_N];
+  __shared__ int s_wave[kWinNT / 64];
+  __shared__ int s_best;
+  const Ctx c = *ctx;
+  if (c.status != LMS_OK || c.all_x_equal) return;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  if (t == 0) {
+    int b = -1;
+    for (int k = 0; k < m; ++k)
+      if (cand[k].x < INFINITY && (b < 0 || cand[k].x < cand[b].x)) b = k;
+    s_best = b;
+  }
+  __syncthreads();
+  const int b = s_best;
+  if (b < 0) return;  // no finite window: the slots keep the extreme-x pair
+  const double4 w = cand[b];
+  int total = 0;
+  for (int base = 0; base < c.n; base += kWinNT) {
+    const int k = base + t;
+    bool in = false;
+    if (k < c.n) {
+      const double z = fma(-w.y, xy[2 * k], xy[2 * k + 1]);
+      in = z >= w.z && z <= w.w;
+    }
+    const unsigned long long mk = __ballot(in);
+    if (lane == 0) s_wave[wave] = __popcll(mk);
+    __syncthreads();
+    int before = total;
+    for (int v = 0; v < wave; ++v) before += s_wave[v];
+    if (in) list[before + __popcll(mk & ((1ull << lane) - 1ull))] = k;
+    for (int v = 0; v < kWinNT / 64; ++v) total += s_wave[v];
+    __syncthreads();
+  }
+  if (total < 2) return;
+  for (int e = t; e < count; e += kWinNT) {
+    const unsigned long long r = mix64(key + 0x9E3779B97F4A7C15ull * (unsigned long long)(e + 1));
+    const int a = (int)((r >> 32) % (unsigned long long)total);
+    int d = (int)((r & 0xFFFFFFFFull) % (unsigned long long)(total - 1));
+    if (d >= a) ++d;
+    const unsigned u = (unsigned)list[a], v = (unsigned)list[d];
+    entries[first + e] = make_uint2(min(u, v), max(u, v));
   }
 }
 
@@ -225,13 +291,16 @@ __device__ __forceinline__ void append_entry(Ctx* ctx, uint2* entries, int cap, 
 
 // Work item = (anchor i, block of G*64 partner offsets). Partners are
 // j = (i + o) mod n for o = 1..P(i): every unordered pair appears once.
+// fallback = 1: runs only if the slope-bin screen's list overflowed, which
+// then has already counted and listed the vertical and forced pairs.
 template <int R, bool LDS_PART, int NT>
 __global__ __launch_bounds__(NT, 3) void k_screen(
     const double* __restrict__ xy, const float2* __restrict__ xy32, Ctx* ctx,
-    uint2* __restrict__ entries, int cap, int G, int ipa, int n_items, int nq) {
+    uint2* __restrict__ entries, int cap, int G, int ipa, int n_items, int nq, int fallback) {
   extern __shared__ float2 lds[];
   const Ctx c = *ctx;
   if (c.status != LMS_OK || c.all_x_equal) return;
+  if (fallback && !c.cand_overflow) return;
   const int n = c.n, h = c.h, lane = threadIdx.x & 63;
   if (LDS_PART) {
     for (int k = threadIdx.x; k < nq * 64; k += blockDim.x) lds[k] = xy32[64 * R + k];
@@ -277,11 +346,34 @@ __global__ __launch_bounds__(NT, 3) void k_screen(
       const float thr = test ? f32_up(W + tau) : 0.0f;
       const float ta = test ? f32_up(tau) : 0.0f;
       const float nc = test ? -fmaf(-th32, pi.x, pi.y) : 0.0f;
-      n_vert += __popcll(__ballot(vert));
-      n_forced += __popcll(__ballot(force));
-      if (force) append_entry(ctx, entries, cap, (unsigned)lo, (unsigned)hi);
       unsigned long long m = __ballot(test);
-      n_scr += __popcll(m);
+      if (!fallback) {
+        n_vert += __popcll(__ballot(vert));
+        n_forced += __popcll(__ballot(force));
+        if (force) append_entry(ctx, entries, cap, (unsigned)lo, (unsigned)hi);
+        n_scr += __popcll(m);
+      }
+      // With the LDS part, two candidates at a time while at least two remain:
+      // each LDS read then serves both. (Registers only, the pairing's extra
+      // scalar registers cost more than the overlap gains.)
+      while (LDS_PART && (m & (m - 1))) {
+        const int ca = __ffsll((long long)m) - 1;
+        m &= m - 1;
+        const int cb = __ffsll((long long)m) - 1;
+        m &= m - 1;
+        const PairTest2 pt = test_pair2<R, LDS_PART>(
+            X, Y, lds, nq, -lane_f(th32, ca), lane_f(thr, ca), lane_f(ta, ca), lane_f(nc, ca),
+            -lane_f(th32, cb), lane_f(thr, cb), lane_f(ta, cb), lane_f(nc, cb), h);
+        n_evals += (unsigned)(pt.a.band_chunks + pt.b.band_chunks);
+        n_band += (pt.a.split_chunks >= 0) + (pt.b.split_chunks >= 0);
+        n_devals += (unsigned)(max(pt.a.split_chunks, 0) + max(pt.b.split_chunks, 0));
+        if (lane == 0) {
+          if (pt.a.keep)
+            append_entry(ctx, entries, cap, (unsigned)lane_i(lo, ca), (unsigned)lane_i(hi, ca));
+          if (pt.b.keep)
+            append_entry(ctx, entries, cap, (unsigned)lane_i(lo, cb), (unsigned)lane_i(hi, cb));
+        }
+      }
       while (m) {
         const int cl = __ffsll((long long)m) - 1;
         m &= m - 1;
@@ -306,6 +398,283 @@ __global__ __launch_bounds__(NT, 3) void k_screen(
     atomicAdd(&ctx->point_evals, 64ull * n_evals);
     atomicAdd(&ctx->dir_evals, 64ull * n_devals);
     atomicAdd(&ctx->forced, n_forced);
+  }
+}
+
+// ---------------------------------------------------------------- slope-bin screen
+//
+// Anchor i, point k, Dx = x_k - x_i, Dy = y_k - y_i (exact reals). The anchored
+// residual d_k(theta) = Dy - theta Dx lies in the upper window [0, W] for theta
+// in one closed interval and in the lower window [-W, 0] for theta in the
+// adjacent one; both end at the slope of (i, k). The pair (i, j) has window
+// counts U = #{k : 0 <= d_k <= W} and D = #{k : -W <= d_k <= 0} at its slope,
+// and the optimal pair, with the optimal slab's boundary through both its
+// points (Section 3.3), has U >= h or D >= h for every W >= the optimal width.
+// Per anchor the kernel adds every point's two intervals to a difference
+// array of NB slope bins in LDS (bins uniform in u = theta / (1 + |theta|)),
+// takes its prefix sum, and reads the bounds on U and D of each partner from
+// the bin of its slope. Each interval is widened by a rigorous bound on its
+// FP64 rounding and by two bins (rounding of the bin map and of the partner's
+// slope), so a bin's count is never below the exact count of any slope in
+// it. Pairs whose bound reaches h are listed for the FP32 test.
+
+__device__ __forceinline__ double umap(double t) {
+  return fabs(t) < 1e300 ? t / (1.0 + fabs(t)) : copysign(1.0, t);
+}
+
+template <int NB>
+__device__ __forceinline__ int ubin(double t) {
+  const int b = (int)floor((umap(t) + 1.0) * (0.5 * NB));
+  return b < 0 ? 0 : (b > NB - 1 ? NB - 1 : b);
+}
+
+// Bins covering [a, b] widened by two on each side; a NaN end (an interval
+// whose rounding bound overflowed) opens that side fully.
+template <int NB>
+__device__ __forceinline__ int2 bin_range(double a, double b) {
+  const int lo = (a == a) ? ubin<NB>(a) - 2 : 0;
+  const int hi = (b == b) ? ubin<NB>(b) + 2 : NB - 1;
+  return make_int2(lo < 0 ? 0 : lo, hi > NB - 1 ? NB - 1 : hi);
+}
+
+// Prefix sums use one padding word per S = NB / NT bins so that each thread's
+// S consecutive bins sit in distinct banks across a wavefront.
+template <int NB, int NT>
+__device__ __forceinline__ int bin_addr(int b) {
+  return b + b / (NB / NT);
+}
+
+template <int NB, int NT>
+__global__ __launch_bounds__(NT) void k_bins(const double* __restrict__ xy, Ctx* ctx,
+                                             uint2* __restrict__ cands, int cand_cap,
+                                             uint2* __restrict__ entries, int cap) {
+  constexpr int S = NB / NT;  // bins per thread in the prefix sum
+  static_assert(S >= 1 && (NB % NT) == 0, "bins must be a multiple of the block");
+  __shared__ unsigned bins[NB + NB / S];
+  // partner offsets o - 1 that pass; P(i) <= n / 2 <= NB / 2 as NB >= n
+  __shared__ unsigned short list[NB / 2 < LMS_MAX_N / 2 ? NB / 2 : LMS_MAX_N / 2];
+  __shared__ unsigned s_part[NT / 64];
+  __shared__ unsigned s_all, s_cnt, s_base;
+  __shared__ int s_anchor;
+  const Ctx c = *ctx;
+  if (c.status != LMS_OK || c.all_x_equal) return;
+  const int n = c.n, h = c.h, t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const double W = __longlong_as_double((long long)c.wbound);
+  const double lim = W * (1.0 + 0x1p-50);
+  const int half = n >> 1;
+  unsigned long long n_vert = 0, n_scr = 0, n_forced = 0, n_pass = 0;
+  for (;;) {
+    __syncthreads();  // the previous anchor's queries are done with the bins
+    if (t == 0) {
+      s_anchor = (int)atomicAdd(&ctx->next_anchor, 1u);
+      s_all = 0;
+      s_cnt = 0;
+    }
+    for (int b = t; b < NB + NB / S; b += NT) bins[b] = 0u;
+    __syncthreads();
+    const int i = s_anchor;
+    if (i >= n) break;
+    const double xi = xy[2 * i], yi = xy[2 * i + 1];
+    // 1. intervals of every point (packed counts: U in the low, D in the high half)
+    unsigned all = 0;
+    for (int k = t; k < n; k += NT) {
+      const double dx = xy[2 * k] - xi, dy = xy[2 * k + 1] - yi;
+      if (dx == 0.0) {  // same x as the anchor: in a window at every slope or at none
+        all += (dy >= 0.0 && dy <= lim ? 1u : 0u) + (dy <= 0.0 && dy >= -lim ? 65536u : 0u);
+        continue;
+      }
+      // end e = (Dy + c) / Dx for c = -W, 0, W; |e - e_exact| <= 2^-51 (|Dy| + |Dy + c|) / |Dx|
+      const double adx = fabs(dx), ady = fabs(dy);
+      const double nm = dy - W, np = dy + W;
+      const double e0 = nm / dx, e1 = dy / dx, e2 = np / dx;
+      const double r0 = 0x1p-51 * ((ady + fabs(nm)) / adx);
+      const double r1 = 0x1p-51 * ((ady + ady) / adx);
+      const double r2 = 0x1p-51 * ((ady + fabs(np)) / adx);
+      int2 bu, bd;
+      if (dx > 0.0) {
+        bu = bin_range<NB>(e0 - r0, e1 + r1);
+        bd = bin_range<NB>(e1 - r1, e2 + r2);
+      } else {
+        bu = bin_range<NB>(e1 - r1, e0 + r0);
+        bd = bin_range<NB>(e2 - r2, e1 + r1);
+      }
+      atomicAdd(&bins[bin_addr<NB, NT>(bu.x)], 1u);
+      if (bu.y + 1 < NB) atomicAdd(&bins[bin_addr<NB, NT>(bu.y + 1)], 0xFFFFFFFFu);
+      atomicAdd(&bins[bin_addr<NB, NT>(bd.x)], 65536u);
+      if (bd.y + 1 < NB) atomicAdd(&bins[bin_addr<NB, NT>(bd.y + 1)], 0xFFFF0000u);
+    }
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) all += __shfl_xor(all, m);
+    if (lane == 0) atomicAdd(&s_all, all);
+    __syncthreads();
+    // 2. prefix sum of the difference array (modular: the true sums are < 2^31)
+    {
+      unsigned v[S];
+      unsigned run = 0;
+#pragma unroll
+      for (int r = 0; r < S; ++r) {
+        run += bins[t * (S + 1) + r];
+        v[r] = run;
+      }
+      unsigned x = run;  // inclusive scan of the thread totals within the wavefront
+#pragma unroll
+      for (int m = 1; m < 64; m <<= 1) {
+        const unsigned y = __shfl_up(x, m);
+        if (lane >= m) x += y;
+      }
+      if (lane == 63) s_part[wave] = x;
+      __syncthreads();
+      unsigned off = x - run;
+      for (int w = 0; w < wave; ++w) off += s_part[w];
+#pragma unroll
+      for (int r = 0; r < S; ++r) bins[t * (S + 1) + r] = v[r] + off;
+    }
+    __syncthreads();
+    // 3. partners: j = (i + o) mod n, o = 1..P(i)
+    const unsigned pall = s_all;
+    const int P = (n & 1) ? half : (i < half ? half : half - 1);
+    for (int o0 = 1; o0 <= P; o0 += NT) {
+      const int o = o0 + t;
+      const bool valid = o <= P;
+      int j = i + (valid ? o : 1);
+      if (j >= n) j -= n;
+      const int lo = min(i, j), hi = max(i, j);
+      const double xl = xy[2 * lo], yl = xy[2 * lo + 1];
+      const double xr = xy[2 * hi], yr = xy[2 * hi + 1];
+      const bool vert = valid && (xl == xr);
+      const double th = (yr - yl) / (xr - xl);
+      const double tau = tau_bound(th, c.xh, c.yh);
+      const bool force = valid && !vert && !(fabs(th) < 1e30 && tau < 1e30);
+      const bool test = valid && !vert && !force;
+      bool pass = false;
+      if (test) {
+        const unsigned pb = bins[bin_addr<NB, NT>(ubin<NB>(th))];
+        pass = (int)((pb & 0xFFFFu) + (pall & 0xFFFFu)) >= h ||
+               (int)((pb >> 16) + (pall >> 16)) >= h;
+      }
+      const unsigned long long mv = __ballot(vert), mf = __ballot(force),
+                               mt = __ballot(test), mp = __ballot(pass);
+      if (lane == 0) {
+        n_vert += __popcll(mv);
+        n_forced += __popcll(mf);
+        n_scr += __popcll(mt);
+        n_pass += __popcll(mp);
+      }
+      if (force) append_entry(ctx, entries, cap, (unsigned)lo, (unsigned)hi);
+      if (mp) {
+        unsigned base = 0;
+        if (lane == 0) base = atomicAdd(&s_cnt, (unsigned)__popcll(mp));
+        base = __shfl(base, 0);
+        if (pass) list[base + __popcll(mp & ((1ull << lane) - 1ull))] = (unsigned short)(o - 1);
+      }
+    }
+    __syncthreads();
+    // 4. the anchor's passes, as one contiguous block of the list
+    const unsigned cnt = s_cnt;
+    if (cnt) {
+      if (t == 0) s_base = atomicAdd(&ctx->n_cands, cnt);
+      __syncthreads();
+      const unsigned base = s_base;
+      for (unsigned q = t; q < cnt; q += NT) {
+        int j = i + 1 + (int)list[q];
+        if (j >= n) j -= n;
+        if (base + q < (unsigned)cand_cap) cands[base + q] = make_uint2((unsigned)i, (unsigned)j);
+        else atomicOr(&ctx->cand_overflow, 1u);
+      }
+    }
+  }
+  if (lane == 0) {
+    atomicAdd(&ctx->vertical, n_vert);
+    atomicAdd(&ctx->screened, n_scr);
+    atomicAdd(&ctx->forced, n_forced);
+    atomicAdd(&ctx->bin_pass, n_pass);
+  }
+}
+
+// FP32 test of the listed pairs: a wavefront takes 64 consecutive list
+// entries, loads the points shifted by each distinct anchor among them, and
+// runs the band and split tests of the exhaustive screen on every pair.
+template <int R, bool LDS_PART, int NT>
+__global__ __launch_bounds__(NT, 3) void k_screen_list(
+    const double* __restrict__ xy, const float2* __restrict__ xy32, Ctx* ctx,
+    const uint2* __restrict__ cands, int cand_cap, uint2* __restrict__ entries, int cap, int nq) {
+  extern __shared__ float2 lds[];
+  const Ctx c = *ctx;
+  if (c.status != LMS_OK || c.all_x_equal || c.cand_overflow) return;
+  const int h = c.h, lane = threadIdx.x & 63;
+  if (LDS_PART) {
+    for (int k = threadIdx.x; k < nq * 64; k += blockDim.x) lds[k] = xy32[64 * R + k];
+    __syncthreads();
+  }
+  const unsigned total = min(c.n_cands, (unsigned)cand_cap);
+  const unsigned n_blocks = (total + 63u) / 64u;
+  const double W = __longlong_as_double((long long)c.wbound);
+  unsigned long long n_evals = 0, n_devals = 0;
+  unsigned n_band = 0;
+  int loaded = -1;
+  float X[R], Y[R];
+  float2 pi = make_float2(0.0f, 0.0f);
+#pragma unroll
+  for (int r = 0; r < R; ++r) X[r] = Y[r] = 0.0f;
+  for (;;) {
+    unsigned blk = 0;
+    if (lane == 0) blk = atomicAdd(&ctx->next_block, 1u);
+    blk = __shfl(blk, 0);
+    if (blk >= n_blocks) break;
+    const unsigned e = blk * 64u + (unsigned)lane;
+    const bool valid = e < total;
+    const uint2 cd = valid ? cands[e] : make_uint2(0u, 0u);
+    const int ai = (int)cd.x, aj = (int)cd.y;
+    unsigned long long todo = __ballot(valid);
+    while (todo) {
+      const int l0 = __ffsll((long long)todo) - 1;
+      const int a = lane_i(ai, l0);
+      const unsigned long long mine = __ballot(valid && ai == a) & todo;
+      todo &= ~mine;
+      if (a != loaded) {
+        pi = xy32[a];
+        const float2* src = xy32;
+        asm volatile("" : "+s"(src));
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const float2 p = src[lane + 64 * r];
+          X[r] = p.x - pi.x;
+          Y[r] = p.y - pi.y;
+        }
+        loaded = a;
+      }
+      const bool me = (mine >> lane) & 1ull;
+      const int j = me ? aj : (a == 0 ? 1 : 0);
+      const int lo = min(a, j), hi = max(a, j);
+      const double xl = xy[2 * lo], yl = xy[2 * lo + 1];
+      const double xr = xy[2 * hi], yr = xy[2 * hi + 1];
+      const double th = (yr - yl) / (xr - xl);
+      const double tau = tau_bound(th, c.xh, c.yh);
+      const float th32 = me ? (float)th : 0.0f;
+      const float thr = me ? f32_up(W + tau) : 0.0f;
+      const float ta = me ? f32_up(tau) : 0.0f;
+      const float nc = me ? -fmaf(-th32, pi.x, pi.y) : 0.0f;
+      unsigned long long m = mine;
+      while (m) {
+        const int cl = __ffsll((long long)m) - 1;
+        m &= m - 1;
+        const PairTest pt = test_pair<R, LDS_PART>(X, Y, lds, nq, -lane_f(th32, cl),
+                                                   lane_f(thr, cl), lane_f(ta, cl),
+                                                   lane_f(nc, cl), h);
+        n_evals += (unsigned)pt.band_chunks;
+        if (pt.split_chunks >= 0) {
+          ++n_band;
+          n_devals += (unsigned)pt.split_chunks;
+        }
+        if (pt.keep && lane == 0)
+          append_entry(ctx, entries, cap, (unsigned)lane_i(lo, cl), (unsigned)lane_i(hi, cl));
+      }
+    }
+  }
+  if (lane == 0) {
+    atomicAdd(&ctx->band_pass, (unsigned long long)n_band);
+    atomicAdd(&ctx->point_evals, 64ull * n_evals);
+    atomicAdd(&ctx->dir_evals, 64ull * n_devals);
   }
 }
 
@@ -414,23 +783,28 @@ __global__ __launch_bounds__(1024) void k_finalize(Ctx* ctx, const uint2* __rest
   o.point_evals = c.point_evals;
   o.dir_evals = c.dir_evals;
   o.band_pass = c.band_pass;
+  o.bin_pass = c.bin_pass;
   *out = o;
 }
 
 // ---------------------------------------------------------------- host side
 
 struct Layout {
-  size_t ctx, xy32, entries, res, total;
+  size_t ctx, xy32, entries, res, rec, cands, total;
 };
 
-Layout layout(int n_pad, long long cap) {
+// n_rec: windows of the device seed slopes (kept only for window pairs);
+// cand_cap: list of the slope-bin screen's passes
+Layout layout(int n_pad, long long cap, long long n_rec = 0, long long cand_cap = 0) {
   auto up = [](size_t v) { return (v + 255) & ~size_t(255); };
   Layout L;
   L.ctx = 0;
   L.xy32 = up(sizeof(Ctx));
   L.entries = L.xy32 + up((size_t)n_pad * sizeof(float2));
   L.res = L.entries + up((size_t)cap * sizeof(uint2));
-  L.total = L.res + up((size_t)cap * sizeof(double4));
+  L.rec = L.res + up((size_t)cap * sizeof(double4));
+  L.cands = L.rec + up((size_t)n_rec * sizeof(double4));
+  L.total = L.cands + up((size_t)cand_cap * sizeof(uint2));
   return L;
 }
 
@@ -474,24 +848,24 @@ void launch_recheck(hipStream_t s, int n, int grid, const double* xy, Ctx* ctx, 
 
 template <int N2>
 void launch_eval_n2(hipStream_t s, int grid, const double* xy, int n, int h, const double* th,
-                    int m, double* out, Ctx* ctx) {
+                    int m, double* out, Ctx* ctx, double4* rec) {
   constexpr int NT = N2 >= 2048 ? 1024 : 256;
   hipLaunchKernelGGL((k_eval_slopes<N2, NT>), dim3(grid), dim3(NT), 0, s, xy, n, h, th, m, out,
-                     ctx);
+                     ctx, rec);
 }
 
 void launch_eval(hipStream_t s, int grid, const double* xy, int n, int h, const double* th, int m,
-                 double* out, Ctx* ctx) {
+                 double* out, Ctx* ctx, double4* rec = nullptr) {
   switch (next_pow2(n)) {
-    case 64: launch_eval_n2<64>(s, grid, xy, n, h, th, m, out, ctx); break;
-    case 128: launch_eval_n2<128>(s, grid, xy, n, h, th, m, out, ctx); break;
-    case 256: launch_eval_n2<256>(s, grid, xy, n, h, th, m, out, ctx); break;
-    case 512: launch_eval_n2<512>(s, grid, xy, n, h, th, m, out, ctx); break;
-    case 1024: launch_eval_n2<1024>(s, grid, xy, n, h, th, m, out, ctx); break;
-    case 2048: launch_eval_n2<2048>(s, grid, xy, n, h, th, m, out, ctx); break;
-    case 4096: launch_eval_n2<4096>(s, grid, xy, n, h, th, m, out, ctx); break;
-    case 8192: launch_eval_n2<8192>(s, grid, xy, n, h, th, m, out, ctx); break;
-    default: launch_eval_n2<16384>(s, grid, xy, n, h, th, m, out, ctx); break;
+    case 64: launch_eval_n2<64>(s, grid, xy, n, h, th, m, out, ctx, rec); break;
+    case 128: launch_eval_n2<128>(s, grid, xy, n, h, th, m, out, ctx, rec); break;
+    case 256: launch_eval_n2<256>(s, grid, xy, n, h, th, m, out, ctx, rec); break;
+    case 512: launch_eval_n2<512>(s, grid, xy, n, h, th, m, out, ctx, rec); break;
+    case 1024: launch_eval_n2<1024>(s, grid, xy, n, h, th, m, out, ctx, rec); break;
+    case 2048: launch_eval_n2<2048>(s, grid, xy, n, h, th, m, out, ctx, rec); break;
+    case 4096: launch_eval_n2<4096>(s, grid, xy, n, h, th, m, out, ctx, rec); break;
+    case 8192: launch_eval_n2<8192>(s, grid, xy, n, h, th, m, out, ctx, rec); break;
+    default: launch_eval_n2<16384>(s, grid, xy, n, h, th, m, out, ctx, rec); break;
   }
 }
 
@@ -505,7 +879,7 @@ constexpr int screen_threads() {
 
 template <int R, bool L>
 hipError_t launch_screen_rl(hipStream_t s, int cu, const double* xy, const float2* xy32, Ctx* ctx,
-                            uint2* e, int cap, int G, int ipa, int n_items, int nq) {
+                            uint2* e, int cap, int G, int ipa, int n_items, int nq, int fb) {
   constexpr int nt = screen_threads<R, L>();
   const size_t shm = L ? (size_t)nq * 64 * sizeof(float2) : 0;
   if (L) {
@@ -515,17 +889,30 @@ hipError_t launch_screen_rl(hipStream_t s, int cu, const double* xy, const float
   }
   const long long per_block = nt / 64;
   const long long need = (n_items + per_block - 1) / per_block;
-  const int grid = (int)std::max<long long>(1, std::min<long long>(need, (long long)cu * (L ? 2 : 3)));
+  // persistent blocks: as many as fit on the chip at once
+  static int resident_regs = 0;  // register-only form: no LDS, so fixed per kernel
+  int resident = L ? 0 : resident_regs;
+  if (resident == 0) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)k_screen<R, L, nt>, nt,
+                                                     shm) != hipSuccess || nb < 1) {
+      (void)hipGetLastError();
+      nb = L ? 1 : 3;
+    }
+    resident = nb;
+    if (!L) resident_regs = nb;
+  }
+  const int grid = (int)std::max<long long>(1, std::min<long long>(need, (long long)cu * resident));
   hipLaunchKernelGGL((k_screen<R, L, nt>), dim3(grid), dim3(nt), shm, s, xy, xy32, ctx, e, cap, G,
-                     ipa, n_items, nq);
+                     ipa, n_items, nq, fb);
   return hipGetLastError();
 }
 
 hipError_t launch_screen(hipStream_t s, int R, bool L, int cu, const double* xy,
                          const float2* xy32, Ctx* ctx, uint2* e, int cap, int G, int ipa,
-                         int n_items, int nq) {
+                         int n_items, int nq, int fb = 0) {
 #define LMS_SCREEN_CASE(RR, LL) \
-  return launch_screen_rl<RR, LL>(s, cu, xy, xy32, ctx, e, cap, G, ipa, n_items, nq)
+  return launch_screen_rl<RR, LL>(s, cu, xy, xy32, ctx, e, cap, G, ipa, n_items, nq, fb)
   if (L) {
     switch (R) {
       case 1: LMS_SCREEN_CASE(1, true);
@@ -591,6 +978,98 @@ hipError_t launch_pairs(hipStream_t s, int R, bool L, const double* xy, const fl
 #undef LMS_PAIRS_CASE
 }
 
+// Slope-bin screen: threads per block for NB bins (the prefix sum holds
+// NB / NT bins per thread in registers).
+template <int NB>
+constexpr int bins_threads() {
+  return NB >= 32768 ? 1024 : (NB >= 16384 ? 512 : 256);
+}
+
+template <int NB>
+hipError_t launch_bins_nb(hipStream_t s, int cu, int n, const double* xy, Ctx* ctx, uint2* cands,
+                          int cand_cap, uint2* e, int cap) {
+  constexpr int nt = bins_threads<NB>();
+  static int resident = 0;
+  if (resident == 0) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)k_bins<NB, nt>, nt, 0) !=
+            hipSuccess || nb < 1) {
+      (void)hipGetLastError();
+      nb = 1;
+    }
+    resident = nb;
+  }
+  const int grid = std::max(1, std::min(n, cu * resident));
+  hipLaunchKernelGGL((k_bins<NB, nt>), dim3(grid), dim3(nt), 0, s, xy, ctx, cands, cand_cap, e,
+                     cap);
+  return hipGetLastError();
+}
+
+hipError_t launch_bins(hipStream_t s, int nb_log2, int cu, int n, const double* xy, Ctx* ctx,
+                       uint2* cands, int cand_cap, uint2* e, int cap) {
+  switch (nb_log2) {
+    case 11: return launch_bins_nb<2048>(s, cu, n, xy, ctx, cands, cand_cap, e, cap);
+    case 12: return launch_bins_nb<4096>(s, cu, n, xy, ctx, cands, cand_cap, e, cap);
+    case 13: return launch_bins_nb<8192>(s, cu, n, xy, ctx, cands, cand_cap, e, cap);
+    case 14: return launch_bins_nb<16384>(s, cu, n, xy, ctx, cands, cand_cap, e, cap);
+    default: return launch_bins_nb<32768>(s, cu, n, xy, ctx, cands, cand_cap, e, cap);
+  }
+}
+
+template <int R, bool L>
+hipError_t launch_list_rl(hipStream_t s, int cu, const double* xy, const float2* xy32, Ctx* ctx,
+                          const uint2* cands, int cand_cap, uint2* e, int cap, int nq) {
+  constexpr int nt = screen_threads<R, L>();
+  const size_t shm = L ? (size_t)nq * 64 * sizeof(float2) : 0;
+  if (L) {
+    (void)hipFuncSetAttribute((const void*)k_screen_list<R, L, nt>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    (void)hipGetLastError();
+  }
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)k_screen_list<R, L, nt>, nt,
+                                                   shm) != hipSuccess || nb < 1) {
+    (void)hipGetLastError();
+    nb = 1;
+  }
+  hipLaunchKernelGGL((k_screen_list<R, L, nt>), dim3(cu * nb), dim3(nt), shm, s, xy, xy32, ctx,
+                     cands, cand_cap, e, cap, nq);
+  return hipGetLastError();
+}
+
+hipError_t launch_list(hipStream_t s, int R, bool L, int cu, const double* xy, const float2* xy32,
+                       Ctx* ctx, const uint2* cands, int cand_cap, uint2* e, int cap, int nq) {
+#define LMS_LIST_CASE(RR, LL) \
+  return launch_list_rl<RR, LL>(s, cu, xy, xy32, ctx, cands, cand_cap, e, cap, nq)
+  if (L) {
+    switch (R) {
+      case 1: LMS_LIST_CASE(1, true);
+      case 16: LMS_LIST_CASE(16, true);
+      case 32: LMS_LIST_CASE(32, true);
+      default: LMS_LIST_CASE(64, true);
+    }
+  }
+  switch (R) {
+    case 1: LMS_LIST_CASE(1, false);
+    case 2: LMS_LIST_CASE(2, false);
+    case 4: LMS_LIST_CASE(4, false);
+    case 8: LMS_LIST_CASE(8, false);
+    case 16: LMS_LIST_CASE(16, false);
+    case 24: LMS_LIST_CASE(24, false);
+    case 32: LMS_LIST_CASE(32, false);
+    case 48: LMS_LIST_CASE(48, false);
+    default: LMS_LIST_CASE(64, false);
+  }
+#undef LMS_LIST_CASE
+}
+
+// Default slope bins per anchor: about 2n, at least 2^11, at most 2^15.
+int default_bins_log2(int n) {
+  int b = 11;
+  while (b < 15 && (1 << b) < 2 * n) ++b;
+  return b;
+}
+
 struct Plan {
   int n, h, R, nq, n_pad, n_seeds;
   bool lds;
@@ -651,9 +1130,13 @@ lms_status lms_solve(const double* d_xy, int64_t n, int64_t h, lms_result* d_out
                           lms_host::get_tuning(kPathSingle, lms_host::size_class((int)n), &tuned);
   int tile_regs = opt ? opt->tile_regs : 0;
   int tile_batches = opt ? opt->tile_batches : 0;
+  int bins_log2 = opt ? opt->bins_log2 : 0;
   if (have_tuned && tile_regs == 0) tile_regs = tuned.tile_regs;
   if (have_tuned && tile_batches == 0) tile_batches = tuned.tile_batches;
+  if (have_tuned && bins_log2 == 0) bins_log2 = tuned.bins_log2;
   if (tile_batches < 0 || tile_batches > 64) return fail(LMS_ERR_ARG, "tile_batches must be in [0, 64]");
+  if (bins_log2 != 0 && bins_log2 != -1 && (bins_log2 < 11 || bins_log2 > 15))
+    return fail(LMS_ERR_ARG, "bins_log2 must be 0, -1 or in [11, 15]");
   Plan p;
   lms_status st = make_plan(d_xy, n, h, &p, tile_regs);
   if (st != LMS_OK) return st;
@@ -662,6 +1145,7 @@ lms_status lms_solve(const double* d_xy, int64_t n, int64_t h, lms_result* d_out
   unsigned flags = 0;
   const double* d_seed_theta = nullptr;
   int64_t n_seed_theta = 0;
+  int window_pairs = 0;
   if (opt) {
     flags = opt->flags;
     if (opt->seed_pairs < -1) return fail(LMS_ERR_ARG, "seed_pairs must be >= -1");
@@ -670,16 +1154,28 @@ lms_status lms_solve(const double* d_xy, int64_t n, int64_t h, lms_result* d_out
     n_seed_theta = opt->n_seed_theta;
     if (n_seed_theta < 0 || (n_seed_theta > 0 && !d_seed_theta) || n_seed_theta > (1 << 24))
       return fail(LMS_ERR_ARG, "bad seed slope array");
+    window_pairs = opt->window_pairs;
+    if (window_pairs < 0 || window_pairs > (1 << 16))
+      return fail(LMS_ERR_ARG, "window_pairs must be in [0, 65536]");
   }
   const long long pairs = (long long)p.n * (p.n - 1) / 2;
   const bool no_prune = (flags & LMS_F_NO_PRUNE) != 0;
   if (no_prune && pairs > kScreenCap)
     return fail(LMS_ERR_ARG, "LMS_F_NO_PRUNE supports at most 2^24 pairs");
-  p.n_seeds = 1 + seeds;
+  // window pairs need a seed line and a bound to tighten
+  if (n_seed_theta == 0 || no_prune) window_pairs = 0;
+  p.n_seeds = 1 + seeds + 2 * window_pairs;
   const long long screen_cap = std::min(pairs, kScreenCap);
   p.cap = p.n_seeds + screen_cap;
   if (p.cap > INT_MAX) return fail(LMS_ERR_ARG, "too many seeds");
-  const Layout L = layout(p.n_pad, p.cap);
+  // slope-bin screen: at least n bins (its per-anchor list holds n / 2 partners)
+  const bool use_bins = bins_log2 != -1;
+  if (use_bins) {
+    if (bins_log2 == 0) bins_log2 = default_bins_log2(p.n);
+    while (bins_log2 < 15 && (1 << bins_log2) < p.n) ++bins_log2;
+  }
+  const long long cand_cap = use_bins ? screen_cap : 0;
+  const Layout L = layout(p.n_pad, p.cap, window_pairs ? n_seed_theta : 0, cand_cap);
   char* base = nullptr;
   st = lms_host::get_workspace(0, stream, L.total, &base);
   if (st != LMS_OK) return st;
@@ -692,26 +1188,57 @@ lms_status lms_solve(const double* d_xy, int64_t n, int64_t h, lms_result* d_out
 
   lms_host::StageEvents prof;
   prof.start(s);
+  const unsigned long long key = 0x5EEDull + (unsigned long long)p.n * 0x100000001ull;
   hipLaunchKernelGGL(k_prep, dim3(1), dim3(1024), 0, s, d_xy, p.n, p.h, p.n_pad, ctx, xy32,
-                     entries, p.n_seeds, 0x5EEDull + (unsigned long long)p.n * 0x100000001ull);
+                     entries, p.n_seeds, seeds, key);
   prof.mark();
-  // Seeds: exact FP64 widths of a few pair slopes set the screen's bound.
-  // Without pruning the bound stays +inf and the screen keeps every pair
-  // whose anchored window can hold h points at all.
-  launch_recheck(s, p.n, std::min(p.n_seeds, 4 * cu), d_xy, ctx, entries, res, 0, (int)p.cap,
-                 no_prune ? 0 : 1);
+  // Seeds: exact FP64 widths of a few slopes set the screen's bound: the
+  // device seed slopes, the extreme-x and random pairs, and with window pairs
+  // two rounds of pairs drawn from the narrowest window found so far. Without
+  // pruning the bound stays +inf and the screen keeps every pair whose
+  // anchored window can hold h points at all.
+  double4* rec = (double4*)(base + L.rec);
   if (n_seed_theta > 0 && !no_prune)
     launch_eval(s, (int)std::min<int64_t>(n_seed_theta, 4 * cu), d_xy, p.n, p.h, d_seed_theta,
-                (int)n_seed_theta, nullptr, ctx);
+                (int)n_seed_theta, nullptr, ctx, window_pairs ? rec : nullptr);
+  const int first_w = 1 + seeds;
+  if (window_pairs)
+    hipLaunchKernelGGL(k_window_pairs, dim3(1), dim3(kWinNT), 0, s, d_xy, ctx, rec,
+                       (int)n_seed_theta, entries, first_w, window_pairs, key ^ 0xA1ull);
+  launch_recheck(s, p.n, std::min(first_w + window_pairs, 4 * cu), d_xy, ctx, entries, res, 0,
+                 first_w + window_pairs, no_prune ? 0 : 1);
+  if (window_pairs) {
+    // second round: from the narrowest window of the first round's pairs
+    hipLaunchKernelGGL(k_window_pairs, dim3(1), dim3(kWinNT), 0, s, d_xy, ctx, res + first_w,
+                       window_pairs, entries, first_w + window_pairs, window_pairs, key ^ 0xA2ull);
+    launch_recheck(s, p.n, std::min(window_pairs, 4 * cu), d_xy, ctx, entries, res,
+                   first_w + window_pairs, p.n_seeds, 1);
+  }
   prof.mark();
   {
+    // Screen. With slope bins: per-anchor bin counts, then the FP32 test of
+    // the pairs they pass, and the exhaustive FP32 screen only if their list
+    // could overflow and did. Without: the exhaustive FP32 screen.
     const int Pmax = p.n / 2;
     const int batches = (Pmax + 63) / 64;
     const int G = std::min(tile_batches > 0 ? tile_batches : 4, std::max(1, batches));
     const int ipa = (batches + G - 1) / G;
     const long long n_items = (long long)p.n * ipa;
-    hipError_t err = launch_screen(s, p.R, p.lds, cu, d_xy, xy32, ctx, entries, (int)p.cap, G,
-                                   ipa, (int)n_items, p.nq);
+    hipError_t err = hipSuccess;
+    if (use_bins) {
+      uint2* cands = (uint2*)(base + L.cands);
+      err = launch_bins(s, bins_log2, cu, p.n, d_xy, ctx, cands, (int)cand_cap, entries,
+                        (int)p.cap);
+      if (err == hipSuccess)
+        err = launch_list(s, p.R, p.lds, cu, d_xy, xy32, ctx, cands, (int)cand_cap, entries,
+                          (int)p.cap, p.nq);
+      if (err == hipSuccess && pairs > cand_cap)
+        err = launch_screen(s, p.R, p.lds, cu, d_xy, xy32, ctx, entries, (int)p.cap, G, ipa,
+                            (int)n_items, p.nq, 1);
+    } else {
+      err = launch_screen(s, p.R, p.lds, cu, d_xy, xy32, ctx, entries, (int)p.cap, G, ipa,
+                          (int)n_items, p.nq);
+    }
     if (err != hipSuccess) {
       prof.finish();
       return fail(LMS_ERR_DEVICE, std::string("screen launch: ") + hipGetErrorString(err));
@@ -852,7 +1379,7 @@ lms_status lms_screen_pairs(const double* d_xy, int64_t n, int64_t h, double W,
   float2* xy32 = (float2*)(base + L.xy32);
   uint2* entries = (uint2*)(base + L.entries);
   hipLaunchKernelGGL(k_prep, dim3(1), dim3(1024), 0, s, d_xy, p.n, p.h, p.n_pad, ctx, xy32,
-                     entries, 1, 0ull);
+                     entries, 1, 0, 0ull);
   hipError_t err = launch_pairs(s, p.R, p.lds, d_xy, xy32, ctx, W, d_pairs, (int)m, d_verdict, p.nq);
   if (err != hipSuccess) return fail(LMS_ERR_DEVICE, hipGetErrorString(err));
   return LMS_OK;

@@ -9,12 +9,14 @@
 //   k_bprep     one block per problem: n, h, finiteness, centring, the padded
 //               FP32 copy, seed pairs.
 //   k_bwindow   FP64 windows of the seed pairs (per-problem width bound W_b),
-//               later of the screen survivors.
+//               later of the screen survivors that k_bmerge_* keep.
 //   k_bscreen   persistent wavefronts over work items (problem, anchor), the
 //               same band and split tests as the single-problem screen, with
 //               the number of 64-point chunks of each problem as a runtime
 //               bound. One launch per register class (up to 512, 1024, 2048
 //               and 4096 points).
+//   k_bmerge_*  survivors of one problem with bit-identical slopes share one
+//               FP64 window: a hash set keeps the smallest pair per slope.
 //   k_bselect   canonical minimum per problem, (width, theta, z_lo, pair), in
 //               three passes of order-preserving u64 atomicMin over the
 //               entries.
@@ -66,8 +68,17 @@ struct __align__(16) PMeta {
 struct __align__(16) BState {
   unsigned n_entries, overflow;
   unsigned next_item[kClasses];
-  unsigned pad[2];
+  unsigned n_reps, pad;
 };
+
+// Slot of the hash set that merges survivors of equal slope: key (slope bits,
+// problem), value the smallest pair key (lo << 16 | hi) seen with that key.
+struct __align__(16) Slot {
+  unsigned long long th;
+  unsigned prob, pair;
+};
+constexpr unsigned kNoSlot = 0xFFFFFFFFu;
+constexpr int kProbes = 64;
 
 // Entry: problem id and the pair packed as lo | hi << 16 (n <= 4096).
 __device__ __forceinline__ unsigned pack_pair(unsigned lo, unsigned hi) { return lo | (hi << 16); }
@@ -186,12 +197,17 @@ __global__ __launch_bounds__(NT) void k_bwindow(const double* __restrict__ xy, P
                                                 const uint2* __restrict__ entries,
                                                 double4* __restrict__ res, int begin,
                                                 const BState* state, int fixed_end, int cap,
-                                                int update_bound) {
+                                                int update_bound,
+                                                const unsigned* __restrict__ reps) {
   __shared__ double z[NMAX];
   __shared__ unsigned long long s_w;
   __shared__ int s_s;
-  const unsigned end = fixed_end >= 0 ? (unsigned)fixed_end : min(state->n_entries, (unsigned)cap);
-  for (unsigned e = begin + blockIdx.x; e < end; e += gridDim.x) {
+  // entries [begin, fixed_end), or the listed representatives
+  const unsigned end = reps ? min(state->n_reps, (unsigned)cap)
+                            : fixed_end >= 0 ? (unsigned)fixed_end
+                                             : min(state->n_entries, (unsigned)cap);
+  for (unsigned k = (reps ? 0u : (unsigned)begin) + blockIdx.x; k < end; k += gridDim.x) {
+    const unsigned e = reps ? reps[k] : k;
     const uint2 en = entries[e];
     const PMeta m = meta[en.x];
     if (m.status != LMS_OK || en.y == kInvalidPair) {
@@ -225,29 +241,22 @@ __global__ __launch_bounds__(NT) void k_bwindow(const double* __restrict__ xy, P
 // ---------------------------------------------------------------- screen
 
 // Work item = (problem, anchor i): all partners j = (i + o) mod n, o = 1..P(i),
-// in batches of 64. Items of one register class are numbered problem by
-// problem in the order `order` (largest problems first); item_begin[p] is
-// the first item of the p-th problem in that order.
+// in batches of 64. items[k] = (problem, anchor) of the k-th item of one
+// register class, numbered problem by problem with the largest problems first.
 template <int RMAX>
 __global__ __launch_bounds__(256, 3) void k_bscreen(
     const double* __restrict__ xy, const float2* __restrict__ xy32, PMeta* meta,
-    const int* __restrict__ order, const int* __restrict__ item_begin, int n_probs, int n_items,
-    uint2* __restrict__ entries, int cap, BState* state, int cls) {
+    const uint2* __restrict__ items, int n_items, uint2* __restrict__ entries, int cap,
+    BState* state, int cls) {
   const int lane = threadIdx.x & 63;
   for (;;) {
     int item = 0;
     if (lane == 0) item = (int)atomicAdd(&state->next_item[cls], 1u);
     item = __shfl(item, 0);
     if (item >= n_items) break;
-    // p = last problem with item_begin[p] <= item
-    int lo_p = 0, hi_p = n_probs - 1;
-    while (lo_p < hi_p) {
-      const int mid = (lo_p + hi_p + 1) >> 1;
-      if (item_begin[mid] <= item) lo_p = mid;
-      else hi_p = mid - 1;
-    }
-    const int b = __builtin_amdgcn_readfirstlane(order[lo_p]);
-    const int i = item - item_begin[lo_p];
+    const uint2 it = items[item];
+    const int b = __builtin_amdgcn_readfirstlane((int)it.x);
+    const int i = __builtin_amdgcn_readfirstlane((int)it.y);
     const PMeta m = meta[b];
     if (m.status != LMS_OK || m.all_x_equal) continue;
     // per-problem scalars, made explicitly wave-uniform (SGPRs)
@@ -291,13 +300,8 @@ __global__ __launch_bounds__(256, 3) void k_bscreen(
       const float thr = test ? f32_up(W + tau) : 0.0f;
       const float ta = test ? f32_up(tau) : 0.0f;
       n_vert += __popcll(__ballot(vert));
-      if (force) {
-        const unsigned idx = atomicAdd(&state->n_entries, 1u);
-        if (idx < (unsigned)cap) entries[idx] = make_uint2((unsigned)b, pack_pair(lo, hi));
-        else atomicOr(&state->overflow, 1u);
-        atomicAdd(&meta[b].survivors, 1ull);
-      }
       unsigned long long msk = __ballot(test);
+      unsigned long long kept = __ballot(force);  // lanes whose pair is appended
       while (msk) {
         const int cl = __ffsll((long long)msk) - 1;
         msk &= msk - 1;
@@ -308,17 +312,26 @@ __global__ __launch_bounds__(256, 3) void k_bscreen(
           ++n_band;
           n_devals += (unsigned)pt.split_chunks;
         }
-        if (pt.keep) {
-          ++n_keep;
-          if (lane == 0) {
-            const unsigned idx = atomicAdd(&state->n_entries, 1u);
-            if (idx < (unsigned)cap)
-              entries[idx] = make_uint2((unsigned)b, pack_pair((unsigned)lane_i(lo, cl),
-                                                              (unsigned)lane_i(hi, cl)));
-            else
-              atomicOr(&state->overflow, 1u);
-          }
+        if (pt.keep) kept |= 1ull << cl;
+      }
+      // one reservation per batch of 64 partners; each kept lane writes its
+      // own entry
+      if (kept) {
+        const unsigned cnt = (unsigned)__popcll(kept);
+        unsigned base = 0;
+        if (lane == 0) {
+          // no reservation once the list is full, so the counter never wraps
+          const unsigned now = __hip_atomic_load(&state->n_entries, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+          base = now >= (unsigned)cap ? (unsigned)cap : atomicAdd(&state->n_entries, cnt);
         }
+        base = __shfl(base, 0);
+        if ((kept >> lane) & 1ull) {
+          const unsigned idx = base + (unsigned)__popcll(kept & ((1ull << lane) - 1ull));
+          if (idx < (unsigned)cap) entries[idx] = make_uint2((unsigned)b, pack_pair(lo, hi));
+          else atomicOr(&state->overflow, 1u);
+        }
+        n_keep += cnt;
       }
     }
     if (lane == 0) {
@@ -330,6 +343,96 @@ __global__ __launch_bounds__(256, 3) void k_bscreen(
         atomicAdd(&meta[b].dir_evals, 64ull * n_devals);
       }
     }
+  }
+}
+
+// ---------------------------------------------------------------- merge of equal slopes
+
+// Survivors of one problem with bit-identical FP64 slopes have identical
+// intercepts z_k = fma(-theta, x_k, y_k), hence the same window, so the
+// canonical order (width, theta, z_lo, pair) among them is decided by the pair
+// alone. Only the smallest pair of each (problem, slope) needs its FP64
+// window; the others are marked as not evaluated. Integer data (pixel
+// coordinates) gives thousands of survivors on a few slopes.
+__global__ __launch_bounds__(256) void k_bmerge_clear(Slot* __restrict__ tab, unsigned size) {
+  for (unsigned k = blockIdx.x * blockDim.x + threadIdx.x; k < size; k += gridDim.x * blockDim.x) {
+    Slot sl;
+    sl.th = ~0ull;
+    sl.prob = kNoSlot;
+    sl.pair = kNoSlot;
+    tab[k] = sl;
+  }
+}
+
+__device__ __forceinline__ unsigned pair_key(unsigned code) {
+  return ((code & 0xFFFFu) << 16) | (code >> 16);  // (lo, hi) in lexicographic order
+}
+
+// Inserts every screen survivor e in [begin, end) into the set and records its
+// slot (kNoSlot: not merged, evaluated on its own).
+__global__ __launch_bounds__(256) void k_bmerge_insert(const double* __restrict__ xy,
+                                                       const PMeta* __restrict__ meta,
+                                                       const uint2* __restrict__ entries,
+                                                       const BState* state, int begin, int cap,
+                                                       Slot* __restrict__ tab, unsigned size,
+                                                       unsigned* __restrict__ slot_of) {
+  const unsigned end = min(state->n_entries, (unsigned)cap);
+  for (unsigned e = begin + blockIdx.x * blockDim.x + threadIdx.x; e < end;
+       e += gridDim.x * blockDim.x) {
+    const uint2 en = entries[e];
+    unsigned slot = kNoSlot;
+    if (en.y != kDegenerate && en.y != kInvalidPair) {
+      const int off = meta[en.x].off;
+      const int lo = off + (int)(en.y & 0xFFFFu), hi = off + (int)(en.y >> 16);
+      const double xl = xy[2 * lo], xr = xy[2 * hi];
+      if (xl != xr) {
+        // the same expression as the window kernel, hence the same bits
+        const double theta = (xy[2 * hi + 1] - xy[2 * lo + 1]) / (xr - xl);
+        const unsigned long long key = (unsigned long long)__double_as_longlong(theta);
+        const unsigned pk = pair_key(en.y);
+        unsigned s = (unsigned)mix64(key ^ (0x9E3779B97F4A7C15ull * (en.x + 1ull))) & (size - 1);
+        for (int q = 0; q < kProbes; ++q, s = (s + 1) & (size - 1)) {
+          const unsigned long long t = atomicCAS(&tab[s].th, ~0ull, key);
+          if (t != ~0ull && t != key) continue;
+          const unsigned pb = atomicCAS(&tab[s].prob, kNoSlot, en.x);
+          if (pb != kNoSlot && pb != en.x) continue;
+          atomicMin(&tab[s].pair, pk);
+          slot = s;
+          break;
+        }
+      }
+    }
+    slot_of[e] = slot;
+  }
+}
+
+// Lists the survivors whose window is evaluated: those not merged and the
+// smallest pair of each slot. The others get an infinite width.
+__global__ __launch_bounds__(256) void k_bmerge_mark(const uint2* __restrict__ entries,
+                                                     BState* state, int begin, int cap,
+                                                     const Slot* __restrict__ tab,
+                                                     const unsigned* __restrict__ slot_of,
+                                                     unsigned* __restrict__ reps,
+                                                     double4* __restrict__ res) {
+  const unsigned end = min(state->n_entries, (unsigned)cap);
+  const int lane = threadIdx.x & 63;
+  const unsigned stride = gridDim.x * blockDim.x;
+  // whole wavefronts step together so that the ballot sees every lane
+  for (unsigned w0 = begin + blockIdx.x * blockDim.x + (threadIdx.x & ~63u); w0 < end;
+       w0 += stride) {
+    const unsigned e = w0 + lane;
+    bool rep = false;
+    if (e < end) {
+      const unsigned s = slot_of[e];
+      rep = s == kNoSlot || tab[s].pair == pair_key(entries[e].y);
+      if (!rep) res[e] = make_double4(INFINITY, NAN, NAN, NAN);
+    }
+    const unsigned long long mask = __ballot(rep);
+    if (!mask) continue;
+    unsigned base = 0;
+    if (lane == 0) base = atomicAdd(&state->n_reps, (unsigned)__popcll(mask));
+    base = __shfl(base, 0);
+    if (rep) reps[base + (unsigned)__popcll(mask & ((1ull << lane) - 1ull))] = e;
   }
 }
 
@@ -412,10 +515,12 @@ struct BPlan {
   int n_probs[kClasses] = {};
   int n_items[kClasses] = {};
   // device arrays inside the workspace
-  size_t o_meta = 0, o_state = 0, o_pad = 0, o_chunks = 0, o_order = 0, o_ibeg = 0, o_xy32 = 0,
-         o_entries = 0, o_res = 0, total = 0;
-  size_t order_off[kClasses] = {}, ibeg_off[kClasses] = {};
-  std::vector<int> h_pad, h_chunks, h_order, h_ibeg;
+  size_t o_meta = 0, o_state = 0, o_pad = 0, o_chunks = 0, o_items = 0, o_xy32 = 0,
+         o_entries = 0, o_res = 0, o_tab = 0, o_slot = 0, o_reps = 0, total = 0;
+  size_t items_off[kClasses] = {};  // first item of each class in the item table
+  unsigned tab_size = 0;            // slots of the equal-slope set (power of two)
+  std::vector<int> h_pad, h_chunks;
+  std::vector<unsigned> h_items;  // (problem, anchor) per work item
 };
 
 size_t up256(size_t v) { return (v + 255) & ~size_t(255); }
@@ -446,24 +551,24 @@ lms_status plan_batch(const int64_t* h_off, int B, int S, BPlan* P) {
   }
   if (h_off[0] < 0) return fail(LMS_ERR_ARG, "offsets must be >= 0");
   P->pad_total = pad;
-  P->h_order.clear();
-  P->h_ibeg.clear();
+  P->h_items.clear();
   for (int c = 0; c < kClasses; ++c) {
     auto& v = cls[c];
     // largest problems first: the tail of the persistent loop is small items
     std::stable_sort(v.begin(), v.end(), [&](int a, int b) {
       return (h_off[a + 1] - h_off[a]) > (h_off[b + 1] - h_off[b]);
     });
-    P->order_off[c] = P->h_order.size();
-    P->ibeg_off[c] = P->h_ibeg.size();
+    P->items_off[c] = P->h_items.size() / 2;
     long long items = 0;
     for (int b : v) {
-      P->h_order.push_back(b);
-      P->h_ibeg.push_back((int)items);
-      items += h_off[b + 1] - h_off[b];
+      const long long n = h_off[b + 1] - h_off[b];
+      for (long long i = 0; i < n; ++i) {
+        P->h_items.push_back((unsigned)b);
+        P->h_items.push_back((unsigned)i);
+      }
+      items += n;
     }
     if (items > INT_MAX) return fail(LMS_ERR_ARG, "batch too large");
-    P->h_ibeg.push_back((int)items);
     P->n_probs[c] = (int)v.size();
     P->n_items[c] = (int)items;
   }
@@ -475,30 +580,38 @@ lms_status plan_batch(const int64_t* h_off, int B, int S, BPlan* P) {
   P->o_meta = o; o += up256((size_t)B * sizeof(PMeta));
   P->o_pad = o; o += up256((size_t)B * sizeof(int));
   P->o_chunks = o; o += up256((size_t)B * sizeof(int));
-  P->o_order = o; o += up256(P->h_order.size() * sizeof(int) + 4);
-  P->o_ibeg = o; o += up256(P->h_ibeg.size() * sizeof(int) + 4);
+  P->o_items = o; o += up256(P->h_items.size() * sizeof(unsigned) + 8);
   P->o_xy32 = o; o += up256((size_t)pad * sizeof(float2));
   P->o_entries = o; o += up256((size_t)P->cap * sizeof(uint2));
   P->o_res = o; o += up256((size_t)P->cap * sizeof(double4));
+  // equal-slope set: at least twice the screen's entry capacity, at most 2^23
+  // slots (128 MiB); survivors that find no slot are evaluated on their own
+  unsigned ts = 256;
+  while (ts < (1u << 23) && (long long)ts < 2 * (P->cap - seeds)) ts <<= 1;
+  P->tab_size = ts;
+  P->o_tab = o; o += up256((size_t)ts * sizeof(Slot));
+  P->o_slot = o; o += up256((size_t)P->cap * sizeof(unsigned));
+  P->o_reps = o; o += up256((size_t)P->cap * sizeof(unsigned));
   P->total = o;
   return LMS_OK;
 }
 
 template <int NMAX>
 void launch_bwindow(hipStream_t s, int grid, const double* xy, PMeta* meta, const uint2* e,
-                    double4* res, int begin, const BState* st, int fixed_end, int cap, int upd) {
+                    double4* res, int begin, const BState* st, int fixed_end, int cap, int upd,
+                    const unsigned* reps) {
   constexpr int NT = NMAX >= 2048 ? 512 : (NMAX >= 512 ? 256 : 128);
   hipLaunchKernelGGL((k_bwindow<NMAX, NT>), dim3(grid), dim3(NT), 0, s, xy, meta, e, res, begin,
-                     st, fixed_end, cap, upd);
+                     st, fixed_end, cap, upd, reps);
 }
 
 void launch_bwindow_n(hipStream_t s, int max_n, int grid, const double* xy, PMeta* meta,
                       const uint2* e, double4* res, int begin, const BState* st, int fixed_end,
-                      int cap, int upd) {
-  if (max_n <= 256) launch_bwindow<256>(s, grid, xy, meta, e, res, begin, st, fixed_end, cap, upd);
-  else if (max_n <= 512) launch_bwindow<512>(s, grid, xy, meta, e, res, begin, st, fixed_end, cap, upd);
-  else if (max_n <= 1024) launch_bwindow<1024>(s, grid, xy, meta, e, res, begin, st, fixed_end, cap, upd);
-  else launch_bwindow<4096>(s, grid, xy, meta, e, res, begin, st, fixed_end, cap, upd);
+                      int cap, int upd, const unsigned* reps) {
+  if (max_n <= 256) launch_bwindow<256>(s, grid, xy, meta, e, res, begin, st, fixed_end, cap, upd, reps);
+  else if (max_n <= 512) launch_bwindow<512>(s, grid, xy, meta, e, res, begin, st, fixed_end, cap, upd, reps);
+  else if (max_n <= 1024) launch_bwindow<1024>(s, grid, xy, meta, e, res, begin, st, fixed_end, cap, upd, reps);
+  else launch_bwindow<4096>(s, grid, xy, meta, e, res, begin, st, fixed_end, cap, upd, reps);
 }
 
 struct BatchKey {
@@ -535,6 +648,24 @@ struct BatchCache {
 std::mutex g_bmu;
 std::map<BatchKey, BatchCache> g_batches;
 
+// Resident 256-thread blocks per CU of the screen kernel of class c.
+int bscreen_blocks_per_cu(int c) {
+  static int cached[kClasses] = {};
+  if (cached[c] == 0) {
+    const void* f = c == 0   ? (const void*)k_bscreen<8>
+                    : c == 1 ? (const void*)k_bscreen<16>
+                    : c == 2 ? (const void*)k_bscreen<32>
+                             : (const void*)k_bscreen<64>;
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, 256, 0) != hipSuccess || nb < 1) {
+      (void)hipGetLastError();
+      nb = 3;
+    }
+    cached[c] = nb;
+  }
+  return cached[c];
+}
+
 // Enqueues the whole batched pipeline on s (capturable: kernels only).
 lms_status enqueue_batch(const BPlan& P, char* base, const double* d_xy, const int64_t* d_off,
                          const int32_t* d_h, lms_result* d_out, hipStream_t s,
@@ -543,8 +674,10 @@ lms_status enqueue_batch(const BPlan& P, char* base, const double* d_xy, const i
   BState* state = (BState*)(base + P.o_state);
   const int* pad = (const int*)(base + P.o_pad);
   const int* chunks = (const int*)(base + P.o_chunks);
-  const int* order = (const int*)(base + P.o_order);
-  const int* ibeg = (const int*)(base + P.o_ibeg);
+  const uint2* items = (const uint2*)(base + P.o_items);
+  Slot* tab = (Slot*)(base + P.o_tab);
+  unsigned* slot_of = (unsigned*)(base + P.o_slot);
+  unsigned* reps = (unsigned*)(base + P.o_reps);
   float2* xy32 = (float2*)(base + P.o_xy32);
   uint2* entries = (uint2*)(base + P.o_entries);
   double4* res = (double4*)(base + P.o_res);
@@ -555,34 +688,40 @@ lms_status enqueue_batch(const BPlan& P, char* base, const double* d_xy, const i
                      meta, xy32, entries, P.S, state, 0xBA7C4ull);
   if (prof) prof->mark();
   launch_bwindow_n(s, P.max_n, std::min(seeds, 16 * cu), d_xy, meta, entries, res, 0, state,
-                   seeds, cap, 1);
+                   seeds, cap, 1, nullptr);
   if (prof) prof->mark();
+  hipLaunchKernelGGL(k_bmerge_clear, dim3(std::min<unsigned>(P.tab_size / 256, 8u * cu)), dim3(256), 0,
+                     s, tab, P.tab_size);
   for (int c = 0; c < kClasses; ++c) {
     if (P.n_items[c] == 0) continue;
-    const int* ord = order + P.order_off[c];
-    const int* ib = ibeg + P.ibeg_off[c];
-    const int grid = std::max(1, std::min((P.n_items[c] + 3) / 4, 3 * cu));
+    const uint2* it = items + P.items_off[c];
+    // persistent blocks: as many as fit on the chip at once
+    const int grid = std::max(1, std::min((P.n_items[c] + 3) / 4, bscreen_blocks_per_cu(c) * cu));
     switch (c) {
       case 0:
-        hipLaunchKernelGGL((k_bscreen<8>), dim3(grid), dim3(256), 0, s, d_xy, xy32, meta, ord, ib,
-                           P.n_probs[c], P.n_items[c], entries, cap, state, c);
+        hipLaunchKernelGGL((k_bscreen<8>), dim3(grid), dim3(256), 0, s, d_xy, xy32, meta, it,
+                           P.n_items[c], entries, cap, state, c);
         break;
       case 1:
-        hipLaunchKernelGGL((k_bscreen<16>), dim3(grid), dim3(256), 0, s, d_xy, xy32, meta, ord, ib,
-                           P.n_probs[c], P.n_items[c], entries, cap, state, c);
+        hipLaunchKernelGGL((k_bscreen<16>), dim3(grid), dim3(256), 0, s, d_xy, xy32, meta, it,
+                           P.n_items[c], entries, cap, state, c);
         break;
       case 2:
-        hipLaunchKernelGGL((k_bscreen<32>), dim3(grid), dim3(256), 0, s, d_xy, xy32, meta, ord, ib,
-                           P.n_probs[c], P.n_items[c], entries, cap, state, c);
+        hipLaunchKernelGGL((k_bscreen<32>), dim3(grid), dim3(256), 0, s, d_xy, xy32, meta, it,
+                           P.n_items[c], entries, cap, state, c);
         break;
       default:
-        hipLaunchKernelGGL((k_bscreen<64>), dim3(grid), dim3(256), 0, s, d_xy, xy32, meta, ord, ib,
-                           P.n_probs[c], P.n_items[c], entries, cap, state, c);
+        hipLaunchKernelGGL((k_bscreen<64>), dim3(grid), dim3(256), 0, s, d_xy, xy32, meta, it,
+                           P.n_items[c], entries, cap, state, c);
         break;
     }
   }
   if (prof) prof->mark();
-  launch_bwindow_n(s, P.max_n, 16 * cu, d_xy, meta, entries, res, seeds, state, -1, cap, 0);
+  hipLaunchKernelGGL(k_bmerge_insert, dim3(16 * cu), dim3(256), 0, s, d_xy, meta, entries, state,
+                     seeds, cap, tab, P.tab_size, slot_of);
+  hipLaunchKernelGGL(k_bmerge_mark, dim3(16 * cu), dim3(256), 0, s, entries, state, seeds, cap,
+                     tab, slot_of, reps, res);
+  launch_bwindow_n(s, P.max_n, 16 * cu, d_xy, meta, entries, res, seeds, state, -1, cap, 0, reps);
   if (prof) prof->mark();
   for (int pass = 1; pass <= 3; ++pass)
     hipLaunchKernelGGL(k_bselect, dim3(4 * cu), dim3(256), 0, s, entries, res, meta, state, cap,
@@ -651,8 +790,7 @@ lms_status lms_solve_batched(const double* d_xy, const int64_t* d_offsets,
     // plan arrays: staged once, synchronously, outside any graph
     if (hipMemcpy(base + P.o_pad, P.h_pad.data(), P.h_pad.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(base + P.o_chunks, P.h_chunks.data(), P.h_chunks.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
-        (!P.h_order.empty() && hipMemcpy(base + P.o_order, P.h_order.data(), P.h_order.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess) ||
-        hipMemcpy(base + P.o_ibeg, P.h_ibeg.data(), P.h_ibeg.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess) {
+        (!P.h_items.empty() && hipMemcpy(base + P.o_items, P.h_items.data(), P.h_items.size() * sizeof(unsigned), hipMemcpyHostToDevice) != hipSuccess)) {
       (void)hipFree(base);
       g_batches.erase(key);
       return fail(LMS_ERR_DEVICE, "uploading the batch plan failed");

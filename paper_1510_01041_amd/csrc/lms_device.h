@@ -186,6 +186,124 @@ __device__ __forceinline__ PairTest test_pair(const float (&X)[R], const float (
   return {1, total, total};
 }
 
+// Rest of one pair's test after its band count over chunks [0, start) came
+// to `miss` (start a multiple of 8 within the register chunks, or a chunk
+// index past them): the remaining band chunks, then the split test. Same
+// checkpoints and outcome as test_pair<R, LDS_PART>.
+template <int R, bool LDS_PART>
+__device__ __forceinline__ PairTest finish_pair(const float (&X)[R], const float (&Y)[R],
+                                                const float2* __restrict__ lds, int nq,
+                                                float nth, float thr, float ta, float nc,
+                                                int start, int miss, int h) {
+  const int lane = threadIdx.x & 63;
+  const int total = R + (LDS_PART ? nq : 0);
+  const int budget = 64 * total - h;
+#pragma unroll
+  for (int b = 0; b < R; b += 8) {
+    if (b >= start) {
+#pragma unroll
+      for (int r = b; r < b + 8 && r < R; ++r) {
+        const float d = fmaf(nth, X[r], Y[r]);
+        miss += __popcll(__ballot(!(fabsf(d) <= thr)));
+      }
+      if (miss > budget) return {0, b + 8 < R ? b + 8 : R, -1};
+    }
+  }
+  if (LDS_PART) {
+    for (int q = start > R ? start - R : 0; q < nq; ++q) {
+      const float2 p = lds[q * 64 + lane];
+      const float d = fmaf(nth, p.x, p.y) + nc;
+      miss += __popcll(__ballot(!(fabsf(d) <= thr)));
+      if (((q & 7) == 7 || q == nq - 1) && miss > budget) return {0, R + q + 1, -1};
+    }
+  }
+  const int slack = budget - miss;
+  asm volatile("" : "+v"(nth));
+  int below = 0, above = 0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const float d = fmaf(nth, X[r], Y[r]);
+    above += __popcll(__ballot(d > ta && d <= thr));
+    below += __popcll(__ballot(d < -ta && d >= -thr));
+    if (above > slack && below > slack) return {0, total, r + 1};
+  }
+  if (LDS_PART) {
+    for (int q = 0; q < nq; ++q) {
+      const float2 p = lds[q * 64 + lane];
+      const float d = fmaf(nth, p.x, p.y) + nc;
+      above += __popcll(__ballot(d > ta && d <= thr));
+      below += __popcll(__ballot(d < -ta && d >= -thr));
+      if (above > slack && below > slack) return {0, total, R + q + 1};
+    }
+  }
+  return {1, total, total};
+}
+
+// Two pairs tested together. Their band counts run in lockstep over the same
+// points (registers, then LDS), so each chunk issues two independent
+// compare-and-count chains and each LDS read serves both; at the first
+// checkpoint where either pair is rejected, each pair still open finishes
+// alone. The outcomes equal two calls of test_pair<R, LDS_PART>.
+struct PairTest2 {
+  PairTest a, b;
+};
+
+template <int R, bool LDS_PART>
+__device__ __forceinline__ PairTest2 test_pair2(const float (&X)[R], const float (&Y)[R],
+                                                const float2* __restrict__ lds, int nq,
+                                                float nth_a, float thr_a, float ta_a, float nc_a,
+                                                float nth_b, float thr_b, float ta_b, float nc_b,
+                                                int h) {
+  const int lane = threadIdx.x & 63;
+  const int total = R + (LDS_PART ? nq : 0);
+  const int budget = 64 * total - h;
+  int ma = 0, mb = 0, e = total;
+  bool open = true;
+#pragma unroll
+  for (int b = 0; b < R; b += 8) {
+#pragma unroll
+    for (int r = b; r < b + 8 && r < R; ++r) {
+      const float da = fmaf(nth_a, X[r], Y[r]);
+      const float db = fmaf(nth_b, X[r], Y[r]);
+      ma += __popcll(__ballot(!(fabsf(da) <= thr_a)));
+      mb += __popcll(__ballot(!(fabsf(db) <= thr_b)));
+    }
+    if (ma > budget || mb > budget) {
+      e = b + 8 < R ? b + 8 : R;
+      open = false;
+      break;
+    }
+  }
+  if (LDS_PART && open) {
+    for (int q = 0; q < nq; ++q) {
+      const float2 p = lds[q * 64 + lane];
+      const float da = fmaf(nth_a, p.x, p.y) + nc_a;
+      const float db = fmaf(nth_b, p.x, p.y) + nc_b;
+      ma += __popcll(__ballot(!(fabsf(da) <= thr_a)));
+      mb += __popcll(__ballot(!(fabsf(db) <= thr_b)));
+      if (((q & 7) == 7 || q == nq - 1) && (ma > budget || mb > budget)) {
+        e = R + q + 1;
+        break;
+      }
+    }
+  }
+  PairTest2 out;
+  out.a = {0, e, -1};
+  out.b = {0, e, -1};
+  // One copy of the single-pair code serves both (k = 0: pair a, 1: pair b).
+#pragma nounroll
+  for (int k = 0; k < 2; ++k) {
+    const int miss = k ? mb : ma;
+    if (miss > budget) continue;
+    const PairTest t = finish_pair<R, LDS_PART>(X, Y, lds, nq, k ? nth_b : nth_a,
+                                                k ? thr_b : thr_a, k ? ta_b : ta_a,
+                                                k ? nc_b : nc_a, e, miss, h);
+    if (k) out.b = t;
+    else out.a = t;
+  }
+  return out;
+}
+
 // test_pair for points held in registers only, with the number of 64-point
 // chunks Rb <= RMAX known at run time (batched problems of different sizes).
 template <int RMAX>

@@ -38,8 +38,8 @@ std::string arch_name() {
   return c == std::string::npos ? a : a.substr(0, c);
 }
 
-// One entry per line: arch path class tile_regs tile_batches seed_pairs ms
-// (a JSON array of arrays, so that other tools can read it).
+// One entry per line: arch path class tile_regs tile_batches seed_pairs
+// bins_log2 ms (a JSON array of arrays, so that other tools can read it).
 void load_tuning_locked() {
   g_tune_loaded = true;
   const char* path = std::getenv("LMS_TUNE_FILE");
@@ -47,14 +47,14 @@ void load_tuning_locked() {
   FILE* f = std::fopen(path, "r");
   if (!f) return;
   char arch[64];
-  int p, c, r, b, sp;
+  int p, c, r, b, sp, bl;
   double ms;
   int ch;
   while ((ch = std::fgetc(f)) != EOF) {
     if (ch != '[') continue;
-    if (std::fscanf(f, " \"%63[^\"]\" , %d , %d , %d , %d , %d , %lf ]", arch, &p, &c, &r, &b,
-                    &sp, &ms) == 7) {
-      lms_tuning t{r, b, sp, 0, ms};
+    if (std::fscanf(f, " \"%63[^\"]\" , %d , %d , %d , %d , %d , %d , %lf ]", arch, &p, &c, &r,
+                    &b, &sp, &bl, &ms) == 8) {
+      lms_tuning t{r, b, sp, bl, ms};
       g_tune[{arch, p, c}] = t;
     }
   }
@@ -69,9 +69,9 @@ void save_tuning_locked() {
   std::fprintf(f, "[\n");
   size_t k = 0;
   for (auto& kv : g_tune) {
-    std::fprintf(f, " [\"%s\", %d, %d, %d, %d, %d, %.6f]%s\n", std::get<0>(kv.first).c_str(),
+    std::fprintf(f, " [\"%s\", %d, %d, %d, %d, %d, %d, %.6f]%s\n", std::get<0>(kv.first).c_str(),
                  std::get<1>(kv.first), std::get<2>(kv.first), kv.second.tile_regs,
-                 kv.second.tile_batches, kv.second.seed_pairs, kv.second.ms,
+                 kv.second.tile_batches, kv.second.seed_pairs, kv.second.bins_log2, kv.second.ms,
                  ++k < g_tune.size() ? "," : "");
   }
   std::fprintf(f, "]\n");

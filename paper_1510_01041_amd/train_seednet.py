@@ -29,6 +29,34 @@ from paper_1510_01041_amd import seednet  # noqa: E402
 from workloads import gen  # noqa: E402
 
 
+def label(d: torch.Tensor, off: np.ndarray, log=print):
+    """Exact LMS slope of every set in one batch (FP64, host array).
+
+    A batch whose survivor list overflows (every set then reports
+    LMS_ERR_CAPACITY) is split in halves and solved again; a single set that
+    still overflows goes to the single-problem solver."""
+    B = off.shape[0] - 1
+    res = lms.solve_batched(d, off)
+    st = np.asarray(res.status)
+    if np.all(st >= 0):
+        return np.asarray(res.theta1, dtype=np.float64)
+    if np.any((st < 0) & (st != lms.LMS_ERR_CAPACITY)):
+        bad = np.unique(st[st < 0]).tolist()
+        raise RuntimeError(f"labelling failed with status {bad}")
+    if B == 1:
+        r = lms.solve(d[int(off[0]):int(off[1])].contiguous())
+        if r.status < 0:
+            raise RuntimeError(f"labelling failed with status {r.status}")
+        return np.array([r.theta1])
+    log(f"survivor list overflow on a batch of {B} sets: splitting it")
+    m = B // 2
+    a = off[:m + 1]
+    b = off[m:]
+    ta = label(d[int(a[0]):int(a[-1])].contiguous(), a - a[0], log)
+    tb = label(d[int(b[0]):int(b[-1])].contiguous(), b - b[0], log)
+    return np.concatenate([ta, tb])
+
+
 def build_dataset(n_sets, n, seed, chunk, net, log=print):
     """Generate, label (exact solver) and normalise n_sets sets of n points."""
     dev = net.device
@@ -40,14 +68,12 @@ def build_dataset(n_sets, n, seed, chunk, net, log=print):
         cn = min(chunk, n_sets - c0)
         xy, off = gen.rotated_line(cn, n, seed * 1000 + c0 // chunk)
         d = torch.from_numpy(xy).to(dev)
-        res = lms.solve_batched(d, off)
-        if np.any(res.status < 0):
-            raise RuntimeError("labelling failed")
+        theta = label(d, np.asarray(off, dtype=np.int64), log)
         pts, scale, _ = net.prepare(d, off)
         pts_all[c0 * n:(c0 + cn) * n] = pts
         sc = scale.cpu().numpy()
-        theta_all[c0:c0 + cn] = res.theta1
-        tgt_all[c0:c0 + cn] = seednet.targets_from_slopes(res.theta1, sc)
+        theta_all[c0:c0 + cn] = theta
+        tgt_all[c0:c0 + cn] = seednet.targets_from_slopes(theta, sc)
         log(f"labelled {c0 + cn}/{n_sets} sets ({time.time() - t0:.1f} s)")
     return pts_all, torch.from_numpy(tgt_all).to(dev), theta_all
 

@@ -103,6 +103,11 @@ def test_tile_and_tuning_argument_errors():
     assert _solve_raw(fake, 100, 0, fake, bad) == lms.LMS_ERR_ARG
     bad = lms._options(tile_batches=65)
     assert _solve_raw(fake, 100, 0, fake, bad) == lms.LMS_ERR_ARG
+    bad = lms._options(window_pairs=-1)
+    assert _solve_raw(fake, 100, 0, fake, bad) == lms.LMS_ERR_ARG
+    assert "window_pairs" in lms.last_error()
+    bad = lms._options(window_pairs=(1 << 16) + 1)
+    assert _solve_raw(fake, 100, 0, fake, bad) == lms.LMS_ERR_ARG
     t = lms._Tuning()
     assert L.lms_autotune(None, 100, 0, 3, None, ctypes.byref(t)) == lms.LMS_ERR_ARG
     assert L.lms_autotune(fake, 100, 0, 0, None, ctypes.byref(t)) == lms.LMS_ERR_ARG

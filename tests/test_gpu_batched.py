@@ -18,6 +18,13 @@ def key(r):
     return (float(r.width), float(r.theta1), float(r.z_lo), float(r.z_hi), float(r.theta2))
 
 
+def check_pair(p, r):
+    """The reported pair is one whose FP64 slope is the result's slope."""
+    i, j = int(r.pair_i), int(r.pair_j)
+    assert 0 <= i < j < len(p), (i, j)
+    assert (p[j, 1] - p[i, 1]) / (p[j, 0] - p[i, 0]) == r.theta1, (i, j)
+
+
 def check_tied(orc, p, r, h=0):
     """Integer data has exact width ties between different slopes; the oracle's
     FP64 rounding may prefer either. Check the width to 1e-9 relative and
@@ -29,6 +36,7 @@ def check_tied(orc, p, r, h=0):
     w, lo, hi = orc.window(p, float(r.theta1), h=h)
     assert (w, lo, hi) == (r.width, r.z_lo, r.z_hi)
     assert r.vertical == o.vertical and r.candidates == o.candidates
+    check_pair(p, r)
     return o
 
 
@@ -47,6 +55,7 @@ def test_batched_equals_single_solves(gpu):
     for b in range(0, 300, 7):
         one = gpu.solve(d[off[b]:off[b + 1]].contiguous())
         assert key(res[b]) == (one.width, one.theta1, one.z_lo, one.z_hi, one.theta2), b
+        check_pair(xy[off[b]:off[b + 1]], res[b])
 
 
 def test_mixed_sizes_all_classes(gpu, orc):
@@ -125,5 +134,6 @@ def test_full_c4_sample(gpu, orc):
     for b in st.integers(60, 0, len(off) - 2):
         one = gpu.solve(d[off[b]:off[b + 1]].contiguous())
         assert key(res[b]) == (one.width, one.theta1, one.z_lo, one.z_hi, one.theta2), b
+        check_pair(xy[off[b]:off[b + 1]], res[b])
     for b in st.integers(6, 0, len(off) - 2):
         check_tied(orc, xy[off[b]:off[b + 1]], res[b])

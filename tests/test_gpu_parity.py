@@ -172,6 +172,61 @@ def test_seed_slopes_do_not_change_result(gpu):
         assert (r.width, r.theta1, r.z_lo) == (base.width, base.theta1, base.z_lo)
 
 
+@pytest.mark.parametrize("n", [300, 2000, 5000])
+def test_window_pairs_do_not_change_result(gpu, orc, n):
+    """Window-pair seeds (drawn from the best seed line's window) only tighten
+    the bound: every seed line, good, poor, absurd or NaN, gives the same
+    exact line, and a good one prunes at least as well as no seed."""
+    xy = planted(n, 0.45, 7000 + n)
+    base = gpu.solve(dev(xy))
+    if n <= 2000:
+        o = orc.solve(xy)
+        assert (base.width, base.theta1, base.z_lo) == (o.width, o.theta1, o.z_lo)
+    none = gpu.solve(dev(xy), seed_pairs=0)
+    for th in ([base.theta1], [base.theta1 + 0.05], [0.7, -2.0], [1e6], [float("nan")]):
+        t = torch.tensor(th, dtype=torch.float64, device="cuda:0")
+        for wp in (1, 63, 1000):
+            r = gpu.solve(dev(xy), seed_pairs=0, seed_theta=t, window_pairs=wp)
+            assert (r.width, r.theta1, r.z_lo, r.z_hi) == \
+                   (base.width, base.theta1, base.z_lo, base.z_hi), (th, wp)
+            if th == [base.theta1] and wp >= 63:
+                assert r.band_pass <= none.band_pass and r.survivors <= none.survivors
+
+
+@pytest.mark.parametrize("n", [2, 3, 5, 64, 65, 300, 1000, 2047, 4096])
+def test_bin_screen_equals_exhaustive(gpu, orc, n):
+    """The slope-bin screen drops only pairs whose exact window counts rule
+    them out: with it, without it (bins_log2=-1) and at every bin count the
+    line is the same, and the bins keep a subset of the FP32 survivors."""
+    for xy in (planted(n, 0.45, 5000 + n), degenerate_int(n, 5100 + n)):
+        ref = gpu.solve(dev(xy), bins_log2=-1)
+        if n <= 1000:
+            o = orc.solve(xy)
+            assert close(ref.width, o.width)
+        for b in (0, 11, 13, 15):
+            r = gpu.solve(dev(xy), bins_log2=b)
+            assert (r.width, r.theta1, r.z_lo, r.z_hi) == \
+                   (ref.width, ref.theta1, ref.z_lo, ref.z_hi), (n, b)
+            assert r.vertical == ref.vertical and r.candidates == ref.candidates
+            assert r.survivors <= ref.survivors
+            assert r.bin_pass <= r.candidates
+    if n == 4096:
+        r = gpu.solve(dev(planted(n, 0.45, 5000 + n)))
+        assert 0 < r.bin_pass < 0.02 * r.candidates, r.bin_pass
+
+
+def test_bin_screen_no_prune_and_seedless(gpu):
+    """With no bound (LMS_F_NO_PRUNE) every pair passes the bins; with only the
+    extreme-x seed the bound is loose. Both give the exact line."""
+    xy = gen.make("c1", 101)
+    base = gpu.solve(dev(xy), bins_log2=-1)
+    a = gpu.solve(dev(xy), no_prune=True)
+    assert a.bin_pass == a.candidates
+    b = gpu.solve(dev(xy), seed_pairs=0)
+    for r in (a, b):
+        assert (r.width, r.theta1, r.z_lo) == (base.width, base.theta1, base.z_lo)
+
+
 def test_determinism_and_permutation(gpu):
     xy = gen.make("c2", 202)[:2000]
     rs = [gpu.solve(dev(xy)) for _ in range(5)]
