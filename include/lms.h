@@ -185,12 +185,13 @@ lms_status lms_screen_pairs(const double* d_xy, int64_t n, int64_t h, double W,
                             void* stream);
 
 /* Stage timing. Between lms_profile_begin() and lms_profile_end(), every
- * lms_solve records HIP events on its own stream around its five stages
- * (prep, seed evaluation, FP32 screen, FP64 recheck, finalize); the events add
- * no synchronisation. lms_profile_end() waits for those events, writes the
- * summed milliseconds per stage to ms[0..LMS_NSTAGES) and returns the number
- * of solves timed (negative status on a HIP error). */
-#define LMS_NSTAGES 5
+ * lms_solve records HIP events on its own stream around its six stages
+ * (prep, seed evaluation, slope-bin screen, FP32 screen, FP64 recheck,
+ * finalize); the events add no synchronisation. lms_profile_end() waits for
+ * those events, writes the summed milliseconds per stage to
+ * ms[0..LMS_NSTAGES) and returns the number of solves timed (negative status
+ * on a HIP error). */
+#define LMS_NSTAGES 6
 void lms_profile_begin(void);
 int64_t lms_profile_end(double* ms);
 

@@ -78,6 +78,8 @@ class LmsResult:
     point_evals: int
     dir_evals: int
     band_pass: int
+    bin_pass: int
+    reserved: int
 
 
 class LmsError(RuntimeError):
@@ -226,7 +228,8 @@ def parse_batch(raw: torch.Tensor):
 
 def solve_batched_async(xy: torch.Tensor, offsets, h: torch.Tensor | None = None,
                         out: torch.Tensor | None = None, *, graph: bool = False,
-                        seed_pairs: int | None = None, stream=None) -> torch.Tensor:
+                        seed_pairs: int | None = None, bins_log2: int = 0,
+                        stream=None) -> torch.Tensor:
     """Enqueue exact LMS fits of B point sets; problem b is xy[offsets[b]:offsets[b+1]].
 
     offsets: B+1 int64 (host array or tensor; a device copy is made if needed).
@@ -248,7 +251,7 @@ def solve_batched_async(xy: torch.Tensor, offsets, h: torch.Tensor | None = None
         out = torch.empty((B, RESULT_BYTES), dtype=torch.uint8, device=xy.device)
     if h is not None and not (h.is_cuda and h.dtype == torch.int32 and h.numel() == B):
         raise ValueError("h must be a CUDA int32 tensor with B values")
-    opt = _options(LMS_F_GRAPH if graph else 0, seed_pairs)
+    opt = _options(LMS_F_GRAPH if graph else 0, seed_pairs, bins_log2=bins_log2)
     st = load().lms_solve_batched(xy.data_ptr(), off_d.data_ptr(), off_h.ctypes.data, B,
                                   None if h is None else h.data_ptr(), out.data_ptr(),
                                   ctypes.byref(opt), _stream(stream))
@@ -325,7 +328,7 @@ def screen_pairs(xy: torch.Tensor, pairs: torch.Tensor, W: float, h: int = 0,
     return out
 
 
-STAGES = ("prep", "seed", "screen", "recheck", "finalize")
+STAGES = ("prep", "seed", "bins", "screen", "recheck", "finalize")
 
 
 def profile_begin():

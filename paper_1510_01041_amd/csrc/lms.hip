@@ -69,11 +69,24 @@ struct __align__(16) Ctx {
   unsigned int next_item;     // work counter of the exhaustive screen
   unsigned int n_cands;       // pairs passed by the slope-bin screen
   unsigned int cand_overflow;
-  unsigned int next_anchor;   // work counter of the slope-bin screen
-  unsigned int next_block;    // work counter of the FP32 test of the listed pairs
-  unsigned int pad;
-  unsigned long long vertical, screened, band_pass, point_evals, dir_evals, forced, bin_pass;
 };
+
+// Search counters, each spread over kSlots addresses (slot = block index mod
+// kSlots) so that the waves of a launch do not all hit one address; k_finalize
+// adds the slots. They live right after the Ctx in the workspace.
+enum { ST_VERT, ST_SCREENED, ST_BAND, ST_EVALS, ST_DEVALS, ST_FORCED, ST_BIN, kStats };
+constexpr int kSlots = 64;
+struct Stats {
+  unsigned long long v[kStats][kSlots];
+};
+constexpr size_t kStatsOffset = (sizeof(Ctx) + 255) & ~size_t(255);
+
+__device__ __forceinline__ void stat_add(Ctx* ctx, int k, unsigned long long v) {
+  if (v) {
+    Stats* st = reinterpret_cast<Stats*>(reinterpret_cast<char*>(ctx) + kStatsOffset);
+    atomicAdd(&st->v[k][blockIdx.x % kSlots], v);
+  }
+}
 
 // ---------------------------------------------------------------- prep
 
@@ -130,6 +143,10 @@ __global__ __launch_bounds__(1024) void k_prep(const double* __restrict__ xy, in
     c.wbound = 0x7FF0000000000000ull;  // +inf
     c.n_entries = (unsigned)n_seeds;
     *ctx = c;
+  }
+  {
+    Stats* st = reinterpret_cast<Stats*>(reinterpret_cast<char*>(ctx) + kStatsOffset);
+    for (int k = t; k < kStats * kSlots; k += blockDim.x) (&st->v[0][0])[k] = 0ull;
   }
   if (!finite) return;
   const float qnan = __int_as_float(0x7FC00000);
@@ -392,12 +409,12 @@ __global__ __launch_bounds__(NT, 3) void k_screen(
     }
   }
   if (lane == 0) {
-    atomicAdd(&ctx->vertical, n_vert);
-    atomicAdd(&ctx->screened, n_scr);
-    atomicAdd(&ctx->band_pass, (unsigned long long)n_band);
-    atomicAdd(&ctx->point_evals, 64ull * n_evals);
-    atomicAdd(&ctx->dir_evals, 64ull * n_devals);
-    atomicAdd(&ctx->forced, n_forced);
+    stat_add(ctx, ST_VERT, n_vert);
+    stat_add(ctx, ST_SCREENED, n_scr);
+    stat_add(ctx, ST_BAND, n_band);
+    stat_add(ctx, ST_EVALS, 64ull * n_evals);
+    stat_add(ctx, ST_DEVALS, 64ull * n_devals);
+    stat_add(ctx, ST_FORCED, n_forced);
   }
 }
 
@@ -418,32 +435,6 @@ __global__ __launch_bounds__(NT, 3) void k_screen(
 // slope), so a bin's count is never below the exact count of any slope in
 // it. Pairs whose bound reaches h are listed for the FP32 test.
 
-__device__ __forceinline__ double umap(double t) {
-  return fabs(t) < 1e300 ? t / (1.0 + fabs(t)) : copysign(1.0, t);
-}
-
-template <int NB>
-__device__ __forceinline__ int ubin(double t) {
-  const int b = (int)floor((umap(t) + 1.0) * (0.5 * NB));
-  return b < 0 ? 0 : (b > NB - 1 ? NB - 1 : b);
-}
-
-// Bins covering [a, b] widened by two on each side; a NaN end (an interval
-// whose rounding bound overflowed) opens that side fully.
-template <int NB>
-__device__ __forceinline__ int2 bin_range(double a, double b) {
-  const int lo = (a == a) ? ubin<NB>(a) - 2 : 0;
-  const int hi = (b == b) ? ubin<NB>(b) + 2 : NB - 1;
-  return make_int2(lo < 0 ? 0 : lo, hi > NB - 1 ? NB - 1 : hi);
-}
-
-// Prefix sums use one padding word per S = NB / NT bins so that each thread's
-// S consecutive bins sit in distinct banks across a wavefront.
-template <int NB, int NT>
-__device__ __forceinline__ int bin_addr(int b) {
-  return b + b / (NB / NT);
-}
-
 template <int NB, int NT>
 __global__ __launch_bounds__(NT) void k_bins(const double* __restrict__ xy, Ctx* ctx,
                                              uint2* __restrict__ cands, int cand_cap,
@@ -453,82 +444,61 @@ __global__ __launch_bounds__(NT) void k_bins(const double* __restrict__ xy, Ctx*
   __shared__ unsigned bins[NB + NB / S];
   // partner offsets o - 1 that pass; P(i) <= n / 2 <= NB / 2 as NB >= n
   __shared__ unsigned short list[NB / 2 < LMS_MAX_N / 2 ? NB / 2 : LMS_MAX_N / 2];
+  // passes of the block's anchors so far, written out together (one
+  // reservation per flush instead of one per anchor)
+  constexpr int PB = 512;
+  __shared__ uint2 pbuf[PB];
   __shared__ unsigned s_part[NT / 64];
-  __shared__ unsigned s_all, s_cnt, s_base;
-  __shared__ int s_anchor;
+  __shared__ unsigned s_all, s_cnt, s_base, s_fill;
   const Ctx c = *ctx;
   if (c.status != LMS_OK || c.all_x_equal) return;
-  const int n = c.n, h = c.h, t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int n = c.n, h = c.h, t = threadIdx.x, lane = t & 63;
   const double W = __longlong_as_double((long long)c.wbound);
   const double lim = W * (1.0 + 0x1p-50);
+  const float sc = bin_scale(c.xh, c.yh);
   const int half = n >> 1;
   unsigned long long n_vert = 0, n_scr = 0, n_forced = 0, n_pass = 0;
-  for (;;) {
+  // reserves cnt list slots (thread 0; the base goes to s_base)
+  auto reserve = [&](unsigned cnt) {
+    const unsigned base = atomicAdd(&ctx->n_cands, cnt);
+    if (base + cnt > (unsigned)cand_cap || base + cnt < base) atomicOr(&ctx->cand_overflow, 1u);
+    s_base = base;
+  };
+  auto flush = [&]() {  // all threads; leaves s_fill = 0
+    __syncthreads();
+    const unsigned fill = s_fill;
+    if (fill) {
+      if (t == 0) reserve(fill);
+      __syncthreads();
+      const unsigned base = s_base;
+      for (unsigned q = t; q < fill; q += NT)
+        if (base + q < (unsigned)cand_cap) cands[base + q] = pbuf[q];
+      __syncthreads();
+      if (t == 0) s_fill = 0;
+      __syncthreads();
+    }
+  };
+  if (t == 0) s_fill = 0;
+  // anchors round-robin over the blocks (no shared counter)
+  for (int i = blockIdx.x; i < n; i += gridDim.x) {
     __syncthreads();  // the previous anchor's queries are done with the bins
     if (t == 0) {
-      s_anchor = (int)atomicAdd(&ctx->next_anchor, 1u);
       s_all = 0;
       s_cnt = 0;
     }
     for (int b = t; b < NB + NB / S; b += NT) bins[b] = 0u;
     __syncthreads();
-    const int i = s_anchor;
-    if (i >= n) break;
     const double xi = xy[2 * i], yi = xy[2 * i + 1];
     // 1. intervals of every point (packed counts: U in the low, D in the high half)
     unsigned all = 0;
-    for (int k = t; k < n; k += NT) {
-      const double dx = xy[2 * k] - xi, dy = xy[2 * k + 1] - yi;
-      if (dx == 0.0) {  // same x as the anchor: in a window at every slope or at none
-        all += (dy >= 0.0 && dy <= lim ? 1u : 0u) + (dy <= 0.0 && dy >= -lim ? 65536u : 0u);
-        continue;
-      }
-      // end e = (Dy + c) / Dx for c = -W, 0, W; |e - e_exact| <= 2^-51 (|Dy| + |Dy + c|) / |Dx|
-      const double adx = fabs(dx), ady = fabs(dy);
-      const double nm = dy - W, np = dy + W;
-      const double e0 = nm / dx, e1 = dy / dx, e2 = np / dx;
-      const double r0 = 0x1p-51 * ((ady + fabs(nm)) / adx);
-      const double r1 = 0x1p-51 * ((ady + ady) / adx);
-      const double r2 = 0x1p-51 * ((ady + fabs(np)) / adx);
-      int2 bu, bd;
-      if (dx > 0.0) {
-        bu = bin_range<NB>(e0 - r0, e1 + r1);
-        bd = bin_range<NB>(e1 - r1, e2 + r2);
-      } else {
-        bu = bin_range<NB>(e1 - r1, e0 + r0);
-        bd = bin_range<NB>(e2 - r2, e1 + r1);
-      }
-      atomicAdd(&bins[bin_addr<NB, NT>(bu.x)], 1u);
-      if (bu.y + 1 < NB) atomicAdd(&bins[bin_addr<NB, NT>(bu.y + 1)], 0xFFFFFFFFu);
-      atomicAdd(&bins[bin_addr<NB, NT>(bd.x)], 65536u);
-      if (bd.y + 1 < NB) atomicAdd(&bins[bin_addr<NB, NT>(bd.y + 1)], 0xFFFF0000u);
-    }
+    for (int k = t; k < n; k += NT)
+      all += add_point_bins<NB, NT>(bins, xy[2 * k] - xi, xy[2 * k + 1] - yi, W, lim, sc);
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1) all += __shfl_xor(all, m);
     if (lane == 0) atomicAdd(&s_all, all);
     __syncthreads();
-    // 2. prefix sum of the difference array (modular: the true sums are < 2^31)
-    {
-      unsigned v[S];
-      unsigned run = 0;
-#pragma unroll
-      for (int r = 0; r < S; ++r) {
-        run += bins[t * (S + 1) + r];
-        v[r] = run;
-      }
-      unsigned x = run;  // inclusive scan of the thread totals within the wavefront
-#pragma unroll
-      for (int m = 1; m < 64; m <<= 1) {
-        const unsigned y = __shfl_up(x, m);
-        if (lane >= m) x += y;
-      }
-      if (lane == 63) s_part[wave] = x;
-      __syncthreads();
-      unsigned off = x - run;
-      for (int w = 0; w < wave; ++w) off += s_part[w];
-#pragma unroll
-      for (int r = 0; r < S; ++r) bins[t * (S + 1) + r] = v[r] + off;
-    }
+    // 2. prefix sum of the difference array
+    scan_bins<NB, NT>(bins, s_part);
     __syncthreads();
     // 3. partners: j = (i + o) mod n, o = 1..P(i)
     const unsigned pall = s_all;
@@ -548,9 +518,7 @@ __global__ __launch_bounds__(NT) void k_bins(const double* __restrict__ xy, Ctx*
       const bool test = valid && !vert && !force;
       bool pass = false;
       if (test) {
-        const unsigned pb = bins[bin_addr<NB, NT>(ubin<NB>(th))];
-        pass = (int)((pb & 0xFFFFu) + (pall & 0xFFFFu)) >= h ||
-               (int)((pb >> 16) + (pall >> 16)) >= h;
+        pass = bins_pass(bins[bin_addr<NB, NT>(ubin<NB>(th, sc))], pall, h);
       }
       const unsigned long long mv = __ballot(vert), mf = __ballot(force),
                                mt = __ballot(test), mp = __ballot(pass);
@@ -569,31 +537,48 @@ __global__ __launch_bounds__(NT) void k_bins(const double* __restrict__ xy, Ctx*
       }
     }
     __syncthreads();
-    // 4. the anchor's passes, as one contiguous block of the list
+    // 4. the anchor's passes: into the block's buffer, or straight out if they
+    //    do not fit in it
     const unsigned cnt = s_cnt;
     if (cnt) {
-      if (t == 0) s_base = atomicAdd(&ctx->n_cands, cnt);
-      __syncthreads();
-      const unsigned base = s_base;
-      for (unsigned q = t; q < cnt; q += NT) {
-        int j = i + 1 + (int)list[q];
-        if (j >= n) j -= n;
-        if (base + q < (unsigned)cand_cap) cands[base + q] = make_uint2((unsigned)i, (unsigned)j);
-        else atomicOr(&ctx->cand_overflow, 1u);
+      if (s_fill + cnt > (unsigned)PB) flush();
+      if (cnt > (unsigned)PB) {
+        if (t == 0) reserve(cnt);
+        __syncthreads();
+        const unsigned base = s_base;
+        for (unsigned q = t; q < cnt; q += NT) {
+          int j = i + 1 + (int)list[q];
+          if (j >= n) j -= n;
+          if (base + q < (unsigned)cand_cap) cands[base + q] = make_uint2((unsigned)i, (unsigned)j);
+        }
+      } else {
+        const unsigned fill = s_fill;
+        for (unsigned q = t; q < cnt; q += NT) {
+          int j = i + 1 + (int)list[q];
+          if (j >= n) j -= n;
+          pbuf[fill + q] = make_uint2((unsigned)i, (unsigned)j);
+        }
+        __syncthreads();
+        if (t == 0) s_fill = fill + cnt;
       }
     }
   }
+  flush();
   if (lane == 0) {
-    atomicAdd(&ctx->vertical, n_vert);
-    atomicAdd(&ctx->screened, n_scr);
-    atomicAdd(&ctx->forced, n_forced);
-    atomicAdd(&ctx->bin_pass, n_pass);
+    stat_add(ctx, ST_VERT, n_vert);
+    stat_add(ctx, ST_SCREENED, n_scr);
+    stat_add(ctx, ST_FORCED, n_forced);
+    stat_add(ctx, ST_BIN, n_pass);
   }
 }
 
-// FP32 test of the listed pairs: a wavefront takes 64 consecutive list
-// entries, loads the points shifted by each distinct anchor among them, and
-// runs the band and split tests of the exhaustive screen on every pair.
+// FP32 test of the listed pairs: a wavefront takes kListBlock consecutive
+// list entries (mostly of one anchor, as the list is written per anchor),
+// loads the points shifted by each distinct anchor among them, and runs the
+// band and split tests of the exhaustive screen on every pair. Each pair
+// costs up to two passes over the points, so blocks are small to spread the
+// pairs over many wavefronts.
+constexpr int kListBlock = 16;
 template <int R, bool LDS_PART, int NT>
 __global__ __launch_bounds__(NT, 3) void k_screen_list(
     const double* __restrict__ xy, const float2* __restrict__ xy32, Ctx* ctx,
@@ -607,7 +592,7 @@ __global__ __launch_bounds__(NT, 3) void k_screen_list(
     __syncthreads();
   }
   const unsigned total = min(c.n_cands, (unsigned)cand_cap);
-  const unsigned n_blocks = (total + 63u) / 64u;
+  const unsigned n_blocks = (total + kListBlock - 1u) / kListBlock;
   const double W = __longlong_as_double((long long)c.wbound);
   unsigned long long n_evals = 0, n_devals = 0;
   unsigned n_band = 0;
@@ -616,13 +601,14 @@ __global__ __launch_bounds__(NT, 3) void k_screen_list(
   float2 pi = make_float2(0.0f, 0.0f);
 #pragma unroll
   for (int r = 0; r < R; ++r) X[r] = Y[r] = 0.0f;
-  for (;;) {
-    unsigned blk = 0;
-    if (lane == 0) blk = atomicAdd(&ctx->next_block, 1u);
-    blk = __shfl(blk, 0);
-    if (blk >= n_blocks) break;
-    const unsigned e = blk * 64u + (unsigned)lane;
-    const bool valid = e < total;
+  // Static round-robin over the blocks: no shared counter, so the waves that
+  // find no work leave at once (a contended counter costs tens of us).
+  const unsigned n_waves = gridDim.x * (blockDim.x / 64u);
+  const unsigned w0 = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x / 64u) +
+                                                     threadIdx.x / 64u);
+  for (unsigned blk = w0; blk < n_blocks; blk += n_waves) {
+    const unsigned e = blk * kListBlock + (unsigned)lane;
+    const bool valid = lane < kListBlock && e < total;
     const uint2 cd = valid ? cands[e] : make_uint2(0u, 0u);
     const int ai = (int)cd.x, aj = (int)cd.y;
     unsigned long long todo = __ballot(valid);
@@ -672,9 +658,9 @@ __global__ __launch_bounds__(NT, 3) void k_screen_list(
     }
   }
   if (lane == 0) {
-    atomicAdd(&ctx->band_pass, (unsigned long long)n_band);
-    atomicAdd(&ctx->point_evals, 64ull * n_evals);
-    atomicAdd(&ctx->dir_evals, 64ull * n_devals);
+    stat_add(ctx, ST_BAND, n_band);
+    stat_add(ctx, ST_EVALS, 64ull * n_evals);
+    stat_add(ctx, ST_DEVALS, 64ull * n_devals);
   }
 }
 
@@ -736,8 +722,15 @@ __global__ __launch_bounds__(1024) void k_finalize(Ctx* ctx, const uint2* __rest
                                                    const double4* __restrict__ res, int cap,
                                                    lms_result* out) {
   __shared__ Best sb[1024];
+  __shared__ unsigned long long s_stat[kStats];
   const Ctx c = *ctx;
   const int t = threadIdx.x;
+  if (t < kStats) {
+    const Stats* st = reinterpret_cast<const Stats*>(reinterpret_cast<char*>(ctx) + kStatsOffset);
+    unsigned long long v = 0;
+    for (int k = 0; k < kSlots; ++k) v += st->v[t][k];
+    s_stat[t] = v;
+  }
   Best b = {INFINITY, INFINITY, INFINITY, INFINITY, 0xFFFFFFFFu, 0xFFFFFFFFu};
   const unsigned end = c.status < 0 ? 0u : min(c.n_entries, (unsigned)cap);
   for (unsigned e = t; e < end; e += blockDim.x) {
@@ -777,13 +770,13 @@ __global__ __launch_bounds__(1024) void k_finalize(Ctx* ctx, const uint2* __rest
     o.pair_i = b.a == kDegenerate ? -1 : (int)b.a;
     o.pair_j = b.b == kDegenerate ? -1 : (int)b.b;
   }
-  o.vertical = c.all_x_equal ? pairs : c.vertical;
+  o.vertical = c.all_x_equal ? pairs : s_stat[ST_VERT];
   o.candidates = pairs - o.vertical;
   o.survivors = c.n_entries > (unsigned)c.n_seeds ? c.n_entries - (unsigned)c.n_seeds : 0u;
-  o.point_evals = c.point_evals;
-  o.dir_evals = c.dir_evals;
-  o.band_pass = c.band_pass;
-  o.bin_pass = c.bin_pass;
+  o.point_evals = s_stat[ST_EVALS];
+  o.dir_evals = s_stat[ST_DEVALS];
+  o.band_pass = s_stat[ST_BAND];
+  o.bin_pass = s_stat[ST_BIN];
   *out = o;
 }
 
@@ -799,7 +792,7 @@ Layout layout(int n_pad, long long cap, long long n_rec = 0, long long cand_cap 
   auto up = [](size_t v) { return (v + 255) & ~size_t(255); };
   Layout L;
   L.ctx = 0;
-  L.xy32 = up(sizeof(Ctx));
+  L.xy32 = up(kStatsOffset + sizeof(Stats));
   L.entries = L.xy32 + up((size_t)n_pad * sizeof(float2));
   L.res = L.entries + up((size_t)cap * sizeof(uint2));
   L.rec = L.res + up((size_t)cap * sizeof(double4));
@@ -1032,7 +1025,11 @@ hipError_t launch_list_rl(hipStream_t s, int cu, const double* xy, const float2*
     (void)hipGetLastError();
     nb = 1;
   }
-  hipLaunchKernelGGL((k_screen_list<R, L, nt>), dim3(cu * nb), dim3(nt), shm, s, xy, xy32, ctx,
+  // persistent blocks, but no more than the list could ever fill
+  const long long most = ((long long)cand_cap + kListBlock - 1) / kListBlock;
+  const long long need = (most + nt / 64 - 1) / (nt / 64);
+  const int grid = (int)std::max<long long>(1, std::min<long long>((long long)cu * nb, need));
+  hipLaunchKernelGGL((k_screen_list<R, L, nt>), dim3(grid), dim3(nt), shm, s, xy, xy32, ctx,
                      cands, cand_cap, e, cap, nq);
   return hipGetLastError();
 }
@@ -1229,6 +1226,7 @@ lms_status lms_solve(const double* d_xy, int64_t n, int64_t h, lms_result* d_out
       uint2* cands = (uint2*)(base + L.cands);
       err = launch_bins(s, bins_log2, cu, p.n, d_xy, ctx, cands, (int)cand_cap, entries,
                         (int)p.cap);
+      prof.mark();
       if (err == hipSuccess)
         err = launch_list(s, p.R, p.lds, cu, d_xy, xy32, ctx, cands, (int)cand_cap, entries,
                           (int)p.cap, p.nq);
@@ -1236,6 +1234,7 @@ lms_status lms_solve(const double* d_xy, int64_t n, int64_t h, lms_result* d_out
         err = launch_screen(s, p.R, p.lds, cu, d_xy, xy32, ctx, entries, (int)p.cap, G, ipa,
                             (int)n_items, p.nq, 1);
     } else {
+      prof.mark();  // no slope-bin stage
       err = launch_screen(s, p.R, p.lds, cu, d_xy, xy32, ctx, entries, (int)p.cap, G, ipa,
                           (int)n_items, p.nq);
     }

@@ -50,7 +50,8 @@ using lms_host::fail;
 constexpr int kBatchMaxN = 4096;
 constexpr int kClasses = 4;
 constexpr int kClassChunks[kClasses] = {8, 16, 32, 64};  // n <= 512, 1024, 2048, 4096
-constexpr long long kBatchScreenCap = 1ll << 24;
+constexpr long long kBatchScreenCap = 1ll << 24;  // FP64 survivor slots
+constexpr long long kBatchCandCap = 1ll << 26;    // slope-bin list slots per class
 constexpr int kBatchSeeds = 31;   // default random seed pairs per problem
 constexpr int kPathBatched = 1;   // tuning-table key of lms_solve_batched
 
@@ -62,13 +63,15 @@ struct __align__(16) PMeta {
   unsigned long long wbound;
   unsigned long long best_w, best_th, best_lo, best_pair;
   double best_hi;
-  unsigned long long vertical, survivors, evals, dir_evals, band_pass;
+  unsigned long long vertical, survivors, evals, dir_evals, band_pass, bin_pass;
 };
 
 struct __align__(16) BState {
   unsigned n_entries, overflow;
   unsigned next_item[kClasses];
-  unsigned n_reps, pad;
+  unsigned n_reps;
+  unsigned cand_overflow;        // bit c: the slope-bin list of class c overflowed
+  unsigned n_cands[kClasses];    // list slots reserved by the slope-bin screen, per class
 };
 
 // Slot of the hash set that merges survivors of equal slope: key (slope bits,
@@ -243,12 +246,15 @@ __global__ __launch_bounds__(NT) void k_bwindow(const double* __restrict__ xy, P
 // Work item = (problem, anchor i): all partners j = (i + o) mod n, o = 1..P(i),
 // in batches of 64. items[k] = (problem, anchor) of the k-th item of one
 // register class, numbered problem by problem with the largest problems first.
+// fallback = 1: runs only if the slope-bin list of this class overflowed,
+// which has then already counted and listed the vertical and forced pairs.
 template <int RMAX>
 __global__ __launch_bounds__(256, 3) void k_bscreen(
     const double* __restrict__ xy, const float2* __restrict__ xy32, PMeta* meta,
     const uint2* __restrict__ items, int n_items, uint2* __restrict__ entries, int cap,
-    BState* state, int cls) {
+    BState* state, int cls, int fallback) {
   const int lane = threadIdx.x & 63;
+  if (fallback && !((state->cand_overflow >> cls) & 1u)) return;
   for (;;) {
     int item = 0;
     if (lane == 0) item = (int)atomicAdd(&state->next_item[cls], 1u);
@@ -299,9 +305,10 @@ __global__ __launch_bounds__(256, 3) void k_bscreen(
       const float th32 = test ? (float)th : 0.0f;
       const float thr = test ? f32_up(W + tau) : 0.0f;
       const float ta = test ? f32_up(tau) : 0.0f;
-      n_vert += __popcll(__ballot(vert));
+      if (!fallback) n_vert += __popcll(__ballot(vert));
       unsigned long long msk = __ballot(test);
-      unsigned long long kept = __ballot(force);  // lanes whose pair is appended
+      // lanes whose pair is appended
+      unsigned long long kept = fallback ? 0ull : __ballot(force);
       while (msk) {
         const int cl = __ffsll((long long)msk) - 1;
         msk &= msk - 1;
@@ -344,6 +351,274 @@ __global__ __launch_bounds__(256, 3) void k_bscreen(
       }
     }
   }
+}
+
+// ---------------------------------------------------------------- slope-bin screen
+
+// One work item (problem b, anchor i) at a time per block, items taken
+// round-robin (no shared counter): the two window intervals of every point of
+// b in NB slope bins (see add_point_bins), their prefix sum, and each
+// partner's bounds on its window counts from the bin of its slope. Passing
+// pairs go to the class's list as (b, i | j << 16); a block reserves list
+// slots kReserve at a time and marks the slots it leaves unused with
+// kNoProblem. Forced slopes go straight to the FP64 entries.
+constexpr unsigned kNoProblem = 0xFFFFFFFFu;
+constexpr unsigned kReserve = 512;
+
+template <int NB, int NT>
+__global__ __launch_bounds__(NT) void k_bbins(const double* __restrict__ xy, PMeta* meta,
+                                              const uint2* __restrict__ items, int n_items,
+                                              uint2* __restrict__ cands, int cand_cap,
+                                              uint2* __restrict__ entries, int cap, BState* state,
+                                              int cls) {
+  constexpr int S = NB / NT;
+  static_assert(S >= 1 && (NB % NT) == 0, "bins must be a multiple of the block");
+  __shared__ unsigned bins[NB + NT];
+  __shared__ unsigned short list[NB / 2];  // partner offsets o - 1 (P <= n / 2 <= NB / 2)
+  __shared__ unsigned s_part[NT / 64 > 0 ? NT / 64 : 1];
+  __shared__ unsigned s_all, s_cnt, s_next, s_end;
+  const int t = threadIdx.x, lane = t & 63;
+  if (t == 0) s_next = s_end = 0;  // reserved list slots [s_next, s_end)
+  for (int item = blockIdx.x; item < n_items; item += gridDim.x) {
+    __syncthreads();  // the previous item's queries are done with the bins
+    if (t == 0) {
+      s_all = 0;
+      s_cnt = 0;
+    }
+    for (int b = t; b < NB + NT; b += NT) bins[b] = 0u;
+    __syncthreads();
+    const uint2 it = items[item];
+    const int b = __builtin_amdgcn_readfirstlane((int)it.x);
+    const int i = __builtin_amdgcn_readfirstlane((int)it.y);
+    const PMeta m = meta[b];
+    if (m.status != LMS_OK || m.all_x_equal) continue;
+    const int n = __builtin_amdgcn_readfirstlane(m.n);
+    const int h = __builtin_amdgcn_readfirstlane(m.h);
+    const double* gxy = xy + 2 * m.off;
+    const double W = __longlong_as_double((long long)m.wbound);
+    const double lim = W * (1.0 + 0x1p-50);
+    const float sc = bin_scale(m.xh, m.yh);
+    const double xi = gxy[2 * i], yi = gxy[2 * i + 1];
+    unsigned all = 0;
+    for (int k = t; k < n; k += NT)
+      all += add_point_bins<NB, NT>(bins, gxy[2 * k] - xi, gxy[2 * k + 1] - yi, W, lim, sc);
+#pragma unroll
+    for (int q = 32; q >= 1; q >>= 1) all += __shfl_xor(all, q);
+    if (lane == 0) atomicAdd(&s_all, all);
+    __syncthreads();
+    scan_bins<NB, NT>(bins, s_part);
+    __syncthreads();
+    const unsigned pall = s_all;
+    const int half = n >> 1;
+    const int P = (n & 1) ? half : (i < half ? half : half - 1);
+    unsigned long long n_vert = 0, n_forced = 0, n_pass = 0;
+    for (int o0 = 1; o0 <= P; o0 += NT) {
+      const int o = o0 + t;
+      const bool valid = o <= P;
+      int j = i + (valid ? o : 1);
+      if (j >= n) j -= n;
+      const int lo = min(i, j), hi = max(i, j);
+      const double xl = gxy[2 * lo], yl = gxy[2 * lo + 1];
+      const double xr = gxy[2 * hi], yr = gxy[2 * hi + 1];
+      const bool vert = valid && (xl == xr);
+      const double th = (yr - yl) / (xr - xl);
+      const double tau = tau_bound(th, m.xh, m.yh);
+      const bool force = valid && !vert && !(fabs(th) < 1e30 && tau < 1e30);
+      const bool test = valid && !vert && !force;
+      const bool pass = test && bins_pass(bins[bin_addr<NB, NT>(ubin<NB>(th, sc))], pall, h);
+      const unsigned long long mv = __ballot(vert), mf = __ballot(force), mp = __ballot(pass);
+      n_vert += __popcll(mv);
+      n_forced += __popcll(mf);
+      n_pass += __popcll(mp);
+      if (mf) {
+        unsigned base = 0;
+        if (lane == 0) {
+          const unsigned now = __hip_atomic_load(&state->n_entries, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+          base = now >= (unsigned)cap ? (unsigned)cap
+                                      : atomicAdd(&state->n_entries, (unsigned)__popcll(mf));
+        }
+        base = __shfl(base, 0);
+        if (force) {
+          const unsigned idx = base + (unsigned)__popcll(mf & ((1ull << lane) - 1ull));
+          if (idx < (unsigned)cap) entries[idx] = make_uint2((unsigned)b, pack_pair(lo, hi));
+          else atomicOr(&state->overflow, 1u);
+        }
+      }
+      if (mp) {
+        unsigned base = 0;
+        if (lane == 0) base = atomicAdd(&s_cnt, (unsigned)__popcll(mp));
+        base = __shfl(base, 0);
+        if (pass) list[base + __popcll(mp & ((1ull << lane) - 1ull))] = (unsigned short)(o - 1);
+      }
+    }
+    if (lane == 0) {
+      if (n_vert) atomicAdd(&meta[b].vertical, n_vert);
+      if (n_forced) atomicAdd(&meta[b].survivors, n_forced);
+      if (n_pass) atomicAdd(&meta[b].bin_pass, n_pass);
+    }
+    __syncthreads();
+    const unsigned cnt = s_cnt;
+    if (cnt) {
+      unsigned first = s_next;
+      if (s_end - first < cnt) {  // not enough reserved: mark the rest unused, reserve more
+        for (unsigned q = first + t; q < s_end; q += NT)
+          cands[q] = make_uint2(kNoProblem, 0u);
+        __syncthreads();
+        if (t == 0) {
+          const unsigned want = cnt > kReserve ? cnt : kReserve;
+          const unsigned now = __hip_atomic_load(&state->n_cands[cls], __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+          const unsigned got = now >= (unsigned)cand_cap ? (unsigned)cand_cap
+                                                         : atomicAdd(&state->n_cands[cls], want);
+          s_next = got;
+          s_end = got >= (unsigned)cand_cap ? got : min(got + want, (unsigned)cand_cap);
+          if (s_end - s_next < cnt) atomicOr(&state->cand_overflow, 1u << cls);
+        }
+        __syncthreads();
+        first = s_next;
+      }
+      const unsigned room = s_end - first;
+      for (unsigned q = t; q < cnt && q < room; q += NT) {
+        int j = i + 1 + (int)list[q];
+        if (j >= n) j -= n;
+        cands[first + q] = make_uint2((unsigned)b, (unsigned)i | ((unsigned)j << 16));
+      }
+      __syncthreads();
+      if (t == 0) s_next = first + min(cnt, room);
+    }
+  }
+  __syncthreads();
+  for (unsigned q = s_next + t; q < s_end; q += NT) cands[q] = make_uint2(kNoProblem, 0u);
+}
+
+// FP32 test of the listed pairs of one register class: a wavefront takes 64
+// consecutive list entries and, for each distinct (problem, anchor) among
+// them, loads that problem's points shifted by the anchor and runs the band
+// and split tests on its pairs.
+constexpr int kBListBlock = 32;
+constexpr unsigned kEntryReserve = 256;
+
+template <int RMAX>
+__global__ __launch_bounds__(256, 3) void k_bscreen_list(
+    const double* __restrict__ xy, const float2* __restrict__ xy32, PMeta* meta,
+    const uint2* __restrict__ cands, int cand_cap, uint2* __restrict__ entries, int cap,
+    BState* state, int cls) {
+  const int lane = threadIdx.x & 63;
+  if ((state->cand_overflow >> cls) & 1u) return;
+  const unsigned total = min(state->n_cands[cls], (unsigned)cand_cap);
+  const unsigned n_blocks = (total + kBListBlock - 1u) / kBListBlock;
+  const unsigned n_waves = gridDim.x * (blockDim.x / 64u);
+  const unsigned w0 = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x / 64u) +
+                                                     threadIdx.x / 64u);
+  // Per-problem counters accumulate while consecutive groups share a problem;
+  // survivor slots are reserved kEntryReserve at a time per wavefront, and
+  // slots left unused are marked kInvalidPair.
+  int cur = -1;
+  unsigned long long a_evals = 0, a_devals = 0, a_band = 0, a_keep = 0;
+  unsigned e_next = 0, e_end = 0;
+  auto flush_counts = [&]() {
+    if (cur >= 0 && lane == 0) {
+      if (a_keep) atomicAdd(&meta[cur].survivors, a_keep);
+      if (a_evals) atomicAdd(&meta[cur].evals, 64ull * a_evals);
+      if (a_band) {
+        atomicAdd(&meta[cur].band_pass, a_band);
+        atomicAdd(&meta[cur].dir_evals, 64ull * a_devals);
+      }
+    }
+    a_evals = a_devals = a_band = a_keep = 0;
+  };
+  for (unsigned blk = w0; blk < n_blocks; blk += n_waves) {
+    const unsigned e = blk * kBListBlock + (unsigned)lane;
+    uint2 cd = make_uint2(0u, 0u);
+    bool valid = false;
+    if (lane < kBListBlock && e < total) {
+      cd = cands[e];
+      valid = cd.x != kNoProblem;
+    }
+    const int cb = (int)cd.x, ci = (int)(cd.y & 0xFFFFu), cj = (int)(cd.y >> 16);
+    unsigned long long todo = __ballot(valid);
+    while (todo) {
+      const int l0 = __ffsll((long long)todo) - 1;
+      const int b = lane_i(cb, l0), i = lane_i(ci, l0);
+      const unsigned long long mine = __ballot(valid && cb == b && ci == i) & todo;
+      todo &= ~mine;
+      const PMeta m = meta[b];
+      const int h = __builtin_amdgcn_readfirstlane(m.h);
+      const int Rb = __builtin_amdgcn_readfirstlane(m.R);
+      const int poff = __builtin_amdgcn_readfirstlane(m.pad_off);
+      const float2* pts = xy32 + poff;
+      const float2 pi = pts[i];
+      const float2* src = pts;
+      asm volatile("" : "+s"(src));
+      float X[RMAX], Y[RMAX];
+#pragma unroll
+      for (int r = 0; r < RMAX; ++r) {
+        if (r < Rb) {
+          const float2 p = src[lane + 64 * r];
+          X[r] = p.x - pi.x;
+          Y[r] = p.y - pi.y;
+        }
+      }
+      const bool me = (mine >> lane) & 1ull;
+      const int j = me ? cj : (i == 0 ? 1 : 0);
+      const int lo = min(i, j), hi = max(i, j);
+      const double* gxy = xy + 2 * m.off;
+      const double xl = gxy[2 * lo], yl = gxy[2 * lo + 1];
+      const double xr = gxy[2 * hi], yr = gxy[2 * hi + 1];
+      const double th = (yr - yl) / (xr - xl);
+      const double tau = tau_bound(th, m.xh, m.yh);
+      const double W = __longlong_as_double((long long)m.wbound);
+      const float th32 = me ? (float)th : 0.0f;
+      const float thr = me ? f32_up(W + tau) : 0.0f;
+      const float ta = me ? f32_up(tau) : 0.0f;
+      if (b != cur) {
+        flush_counts();
+        cur = b;
+      }
+      unsigned long long kept = 0;
+      unsigned long long msk = mine;
+      while (msk) {
+        const int cl = __ffsll((long long)msk) - 1;
+        msk &= msk - 1;
+        const PairTest pt = test_pair_rt<RMAX>(X, Y, Rb, -lane_f(th32, cl), lane_f(thr, cl),
+                                               lane_f(ta, cl), h);
+        a_evals += (unsigned)pt.band_chunks;
+        if (pt.split_chunks >= 0) {
+          ++a_band;
+          a_devals += (unsigned)pt.split_chunks;
+        }
+        if (pt.keep) kept |= 1ull << cl;
+      }
+      if (kept) {
+        const unsigned cnt = (unsigned)__popcll(kept);
+        a_keep += cnt;
+        if (e_end - e_next < cnt) {
+          for (unsigned q = e_next + (unsigned)lane; q < e_end; q += 64u)
+            entries[q] = make_uint2(0u, kInvalidPair);
+          unsigned got = 0;
+          const unsigned want = cnt > kEntryReserve ? cnt : kEntryReserve;
+          if (lane == 0) {
+            const unsigned now = __hip_atomic_load(&state->n_entries, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+            got = now >= (unsigned)cap ? (unsigned)cap : atomicAdd(&state->n_entries, want);
+          }
+          got = __shfl(got, 0);
+          e_next = got;
+          e_end = got >= (unsigned)cap ? got : min(got + want, (unsigned)cap);
+          if (e_end - e_next < cnt && lane == 0) atomicOr(&state->overflow, 1u);
+        }
+        if ((kept >> lane) & 1ull) {
+          const unsigned idx = e_next + (unsigned)__popcll(kept & ((1ull << lane) - 1ull));
+          if (idx < e_end) entries[idx] = make_uint2((unsigned)b, pack_pair(lo, hi));
+        }
+        e_next = min(e_next + cnt, e_end);
+      }
+    }
+  }
+  flush_counts();
+  for (unsigned q = e_next + (unsigned)lane; q < e_end; q += 64u)
+    entries[q] = make_uint2(0u, kInvalidPair);
 }
 
 // ---------------------------------------------------------------- merge of equal slopes
@@ -423,8 +698,9 @@ __global__ __launch_bounds__(256) void k_bmerge_mark(const uint2* __restrict__ e
     const unsigned e = w0 + lane;
     bool rep = false;
     if (e < end) {
+      const unsigned code = entries[e].y;
       const unsigned s = slot_of[e];
-      rep = s == kNoSlot || tab[s].pair == pair_key(entries[e].y);
+      rep = code != kInvalidPair && (s == kNoSlot || tab[s].pair == pair_key(code));
       if (!rep) res[e] = make_double4(INFINITY, NAN, NAN, NAN);
     }
     const unsigned long long mask = __ballot(rep);
@@ -502,6 +778,7 @@ __global__ __launch_bounds__(256) void k_bfinal(const PMeta* __restrict__ meta, 
   o.point_evals = m.evals;
   o.dir_evals = m.dir_evals;
   o.band_pass = m.band_pass;
+  o.bin_pass = m.bin_pass;
   out[b] = o;
 }
 
@@ -514,9 +791,12 @@ struct BPlan {
   long long pad_total = 0, pairs = 0, cap = 0;
   int n_probs[kClasses] = {};
   int n_items[kClasses] = {};
+  long long pairs_c[kClasses] = {};   // pairs per register class
+  long long cand_cap[kClasses] = {};  // slope-bin list slots per class
+  size_t cand_off[kClasses] = {};     // first slot of each class's list
   // device arrays inside the workspace
   size_t o_meta = 0, o_state = 0, o_pad = 0, o_chunks = 0, o_items = 0, o_xy32 = 0,
-         o_entries = 0, o_res = 0, o_tab = 0, o_slot = 0, o_reps = 0, total = 0;
+         o_entries = 0, o_res = 0, o_tab = 0, o_slot = 0, o_reps = 0, o_cands = 0, total = 0;
   size_t items_off[kClasses] = {};  // first item of each class in the item table
   unsigned tab_size = 0;            // slots of the equal-slope set (power of two)
   std::vector<int> h_pad, h_chunks;
@@ -547,6 +827,7 @@ lms_status plan_batch(const int64_t* h_off, int B, int S, BPlan* P) {
       int c = 0;
       while (R > kClassChunks[c]) ++c;
       cls[c].push_back(b);
+      P->pairs_c[c] += n * (n - 1) / 2;
     }
   }
   if (h_off[0] < 0) return fail(LMS_ERR_ARG, "offsets must be >= 0");
@@ -573,7 +854,8 @@ lms_status plan_batch(const int64_t* h_off, int B, int S, BPlan* P) {
     P->n_items[c] = (int)items;
   }
   const long long seeds = (long long)B * S;
-  P->cap = seeds + std::min<long long>(P->pairs, kBatchScreenCap);
+  // slack for the survivor slots each wavefront reserves ahead
+  P->cap = seeds + std::min<long long>(P->pairs, kBatchScreenCap) + (1ll << 20);
   if (P->cap > INT_MAX) return fail(LMS_ERR_ARG, "batch too large");
   size_t o = 0;
   P->o_state = o; o += up256(sizeof(BState));
@@ -592,6 +874,15 @@ lms_status plan_batch(const int64_t* h_off, int B, int S, BPlan* P) {
   P->o_tab = o; o += up256((size_t)ts * sizeof(Slot));
   P->o_slot = o; o += up256((size_t)P->cap * sizeof(unsigned));
   P->o_reps = o; o += up256((size_t)P->cap * sizeof(unsigned));
+  long long cands = 0;
+  for (int c = 0; c < kClasses; ++c) {
+    P->cand_off[c] = (size_t)cands;
+    // slack for the slots each block reserves ahead and may leave unused
+    P->cand_cap[c] = P->pairs_c[c] ? std::min<long long>(P->pairs_c[c] + (1ll << 20), kBatchCandCap)
+                                   : 0;
+    cands += P->cand_cap[c];
+  }
+  P->o_cands = o; o += up256((size_t)cands * sizeof(uint2));
   P->total = o;
   return LMS_OK;
 }
@@ -621,9 +912,10 @@ struct BatchKey {
   const void* out;
   void* stream;
   int B, S;
+  bool bins;
   bool operator<(const BatchKey& o) const {
-    return std::tie(xy, off, h, out, stream, B, S) <
-           std::tie(o.xy, o.off, o.h, o.out, o.stream, o.B, o.S);
+    return std::tie(xy, off, h, out, stream, B, S, bins) <
+           std::tie(o.xy, o.off, o.h, o.out, o.stream, o.B, o.S, o.bins);
   }
 };
 
@@ -666,10 +958,96 @@ int bscreen_blocks_per_cu(int c) {
   return cached[c];
 }
 
+void launch_bscreen(hipStream_t s, int c, int cu, const double* xy, const float2* xy32,
+                    PMeta* meta, const uint2* it, int n_items, uint2* entries, int cap,
+                    BState* state, int fallback) {
+  // persistent blocks: as many as fit on the chip at once
+  const int grid = std::max(1, std::min((n_items + 3) / 4, bscreen_blocks_per_cu(c) * cu));
+  switch (c) {
+    case 0:
+      hipLaunchKernelGGL((k_bscreen<8>), dim3(grid), dim3(256), 0, s, xy, xy32, meta, it, n_items,
+                         entries, cap, state, c, fallback);
+      break;
+    case 1:
+      hipLaunchKernelGGL((k_bscreen<16>), dim3(grid), dim3(256), 0, s, xy, xy32, meta, it, n_items,
+                         entries, cap, state, c, fallback);
+      break;
+    case 2:
+      hipLaunchKernelGGL((k_bscreen<32>), dim3(grid), dim3(256), 0, s, xy, xy32, meta, it, n_items,
+                         entries, cap, state, c, fallback);
+      break;
+    default:
+      hipLaunchKernelGGL((k_bscreen<64>), dim3(grid), dim3(256), 0, s, xy, xy32, meta, it, n_items,
+                         entries, cap, state, c, fallback);
+      break;
+  }
+}
+
+// Slope bins per class: 4096 up to 1024 points (pixel data with many tied
+// slopes needs about 8 bins per point to keep the bounds within a few counts
+// of exact), 8192 above; four wavefronts per item.
+template <int NB, int NT>
+void launch_bbins_nb(hipStream_t s, int c, int cu, const double* xy, PMeta* meta,
+                     const uint2* it, int n_items, uint2* cands, int cand_cap, uint2* entries,
+                     int cap, BState* state) {
+  static int resident = 0;
+  if (resident == 0) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)k_bbins<NB, NT>, NT, 0) !=
+            hipSuccess || nb < 1) {
+      (void)hipGetLastError();
+      nb = 1;
+    }
+    resident = nb;
+  }
+  const int grid = std::max(1, std::min(n_items, resident * cu));
+  hipLaunchKernelGGL((k_bbins<NB, NT>), dim3(grid), dim3(NT), 0, s, xy, meta, it, n_items, cands,
+                     cand_cap, entries, cap, state, c);
+}
+
+void launch_bbins(hipStream_t s, int c, int cu, const double* xy, PMeta* meta, const uint2* it,
+                  int n_items, uint2* cands, int cand_cap, uint2* entries, int cap,
+                  BState* state) {
+  switch (c) {
+    case 0: launch_bbins_nb<4096, 256>(s, c, cu, xy, meta, it, n_items, cands, cand_cap, entries, cap, state); break;
+    case 1: launch_bbins_nb<4096, 256>(s, c, cu, xy, meta, it, n_items, cands, cand_cap, entries, cap, state); break;
+    default: launch_bbins_nb<8192, 256>(s, c, cu, xy, meta, it, n_items, cands, cand_cap, entries, cap, state); break;
+  }
+}
+
+template <int RMAX>
+void launch_bscreen_list_r(hipStream_t s, int c, int cu, const double* xy, const float2* xy32,
+                           PMeta* meta, const uint2* cands, int cand_cap, uint2* entries, int cap,
+                           BState* state) {
+  static int resident = 0;
+  if (resident == 0) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)k_bscreen_list<RMAX>, 256,
+                                                     0) != hipSuccess || nb < 1) {
+      (void)hipGetLastError();
+      nb = 1;
+    }
+    resident = nb;
+  }
+  hipLaunchKernelGGL((k_bscreen_list<RMAX>), dim3(resident * cu), dim3(256), 0, s, xy, xy32, meta,
+                     cands, cand_cap, entries, cap, state, c);
+}
+
+void launch_bscreen_list(hipStream_t s, int c, int cu, const double* xy, const float2* xy32,
+                         PMeta* meta, const uint2* cands, int cand_cap, uint2* entries, int cap,
+                         BState* state) {
+  switch (c) {
+    case 0: launch_bscreen_list_r<8>(s, c, cu, xy, xy32, meta, cands, cand_cap, entries, cap, state); break;
+    case 1: launch_bscreen_list_r<16>(s, c, cu, xy, xy32, meta, cands, cand_cap, entries, cap, state); break;
+    case 2: launch_bscreen_list_r<32>(s, c, cu, xy, xy32, meta, cands, cand_cap, entries, cap, state); break;
+    default: launch_bscreen_list_r<64>(s, c, cu, xy, xy32, meta, cands, cand_cap, entries, cap, state); break;
+  }
+}
+
 // Enqueues the whole batched pipeline on s (capturable: kernels only).
 lms_status enqueue_batch(const BPlan& P, char* base, const double* d_xy, const int64_t* d_off,
                          const int32_t* d_h, lms_result* d_out, hipStream_t s,
-                         lms_host::StageEvents* prof) {
+                         lms_host::StageEvents* prof, bool bins) {
   PMeta* meta = (PMeta*)(base + P.o_meta);
   BState* state = (BState*)(base + P.o_state);
   const int* pad = (const int*)(base + P.o_pad);
@@ -692,28 +1070,26 @@ lms_status enqueue_batch(const BPlan& P, char* base, const double* d_xy, const i
   if (prof) prof->mark();
   hipLaunchKernelGGL(k_bmerge_clear, dim3(std::min<unsigned>(P.tab_size / 256, 8u * cu)), dim3(256), 0,
                      s, tab, P.tab_size);
+  uint2* cands = (uint2*)(base + P.o_cands);
+  if (bins) {
+    for (int c = 0; c < kClasses; ++c)
+      if (P.n_items[c])
+        launch_bbins(s, c, cu, d_xy, meta, items + P.items_off[c], P.n_items[c],
+                     cands + P.cand_off[c], (int)P.cand_cap[c], entries, cap, state);
+  }
+  if (prof) prof->mark();
   for (int c = 0; c < kClasses; ++c) {
     if (P.n_items[c] == 0) continue;
     const uint2* it = items + P.items_off[c];
-    // persistent blocks: as many as fit on the chip at once
-    const int grid = std::max(1, std::min((P.n_items[c] + 3) / 4, bscreen_blocks_per_cu(c) * cu));
-    switch (c) {
-      case 0:
-        hipLaunchKernelGGL((k_bscreen<8>), dim3(grid), dim3(256), 0, s, d_xy, xy32, meta, it,
-                           P.n_items[c], entries, cap, state, c);
-        break;
-      case 1:
-        hipLaunchKernelGGL((k_bscreen<16>), dim3(grid), dim3(256), 0, s, d_xy, xy32, meta, it,
-                           P.n_items[c], entries, cap, state, c);
-        break;
-      case 2:
-        hipLaunchKernelGGL((k_bscreen<32>), dim3(grid), dim3(256), 0, s, d_xy, xy32, meta, it,
-                           P.n_items[c], entries, cap, state, c);
-        break;
-      default:
-        hipLaunchKernelGGL((k_bscreen<64>), dim3(grid), dim3(256), 0, s, d_xy, xy32, meta, it,
-                           P.n_items[c], entries, cap, state, c);
-        break;
+    if (bins) {
+      launch_bscreen_list(s, c, cu, d_xy, xy32, meta, cands + P.cand_off[c], (int)P.cand_cap[c],
+                          entries, cap, state);
+      // The exhaustive screen, in case the class's list overflowed (blocks
+      // reserve slots ahead, so even a list sized for every pair can); it
+      // returns at once otherwise.
+      launch_bscreen(s, c, cu, d_xy, xy32, meta, it, P.n_items[c], entries, cap, state, 1);
+    } else {
+      launch_bscreen(s, c, cu, d_xy, xy32, meta, it, P.n_items[c], entries, cap, state, 0);
     }
   }
   if (prof) prof->mark();
@@ -769,7 +1145,9 @@ lms_status lms_solve_batched(const double* d_xy, const int64_t* d_offsets,
       seed_pairs = t.seed_pairs;
   }
   const int S = 1 + seed_pairs;
-  const BatchKey key{d_xy, d_offsets, d_h, d_out, stream, (int)B, S};
+  // slope-bin first screen unless bins_log2 = -1 (bins per class are fixed)
+  const bool bins = !(opt && opt->bins_log2 == -1);
+  const BatchKey key{d_xy, d_offsets, d_h, d_out, stream, (int)B, S, bins};
   std::lock_guard<std::mutex> lk(g_bmu);
   BatchCache& bc = g_batches[key];
   const bool same = bc.plan.B == (int)B && bc.offsets == off;
@@ -810,7 +1188,8 @@ lms_status lms_solve_batched(const double* d_xy, const int64_t* d_offsets,
         (void)hipStreamDestroy(cs);
         return fail(LMS_ERR_DEVICE, "hipStreamBeginCapture failed");
       }
-      const lms_status st = enqueue_batch(bc.plan, bc.base, d_xy, d_offsets, d_h, d_out, cs, nullptr);
+      const lms_status st =
+          enqueue_batch(bc.plan, bc.base, d_xy, d_offsets, d_h, d_out, cs, nullptr, bins);
       hipGraph_t g = nullptr;
       const hipError_t e = hipStreamEndCapture(cs, &g);
       (void)hipStreamDestroy(cs);
@@ -831,7 +1210,7 @@ lms_status lms_solve_batched(const double* d_xy, const int64_t* d_offsets,
   }
   lms_host::StageEvents prof;
   prof.start(s);
-  const lms_status st = enqueue_batch(bc.plan, bc.base, d_xy, d_offsets, d_h, d_out, s, &prof);
+  const lms_status st = enqueue_batch(bc.plan, bc.base, d_xy, d_offsets, d_h, d_out, s, &prof, bins);
   prof.finish();
   return st;
 }

@@ -108,6 +108,122 @@ __device__ __forceinline__ void window_f64(const double* __restrict__ xy, int n,
   window_f64_rt<N2, NT>(xy, n, h, N2, theta, z, s_w, s_s, width, z_lo, z_hi);
 }
 
+// ---------------------------------------------------------------- slope bins
+//
+// Anchor i, point k, Dx = x_k - x_i, Dy = y_k - y_i (exact reals). The anchored
+// residual d_k(theta) = Dy - theta Dx lies in the upper window [0, W] for theta
+// in one closed interval and in the lower window [-W, 0] for theta in the
+// adjacent one; both end at the slope of (i, k). Counted over k at a partner's
+// slope, they give the pair's window counts U and D. Bins are uniform in
+// u = theta / (1 + |theta|); a bin holds U in its low and D in its high 16
+// bits, so one u32 difference array and one prefix sum serve both.
+
+// Bin of slope t: bins are uniform in u = t' / (1 + |t'|), t' = t * sc, with sc
+// the data's x/y aspect ratio so that typical slopes land near |t'| ~ 1. The
+// map is evaluated in FP32 with the hardware reciprocal: its error, below
+// 4e-7 in u, is far below one bin (2 / NB >= 6e-5), so the computed bin is
+// within one of the exact map's bin. t is finite or +-inf here.
+template <int NB>
+__device__ __forceinline__ int ubin(double t, float sc) {
+  float f = (float)t * sc;
+  f = fminf(fmaxf(f, -1e30f), 1e30f);
+  const float u = f * __builtin_amdgcn_rcpf(1.0f + fabsf(f));
+  const int b = (int)floorf((u + 1.0f) * (0.5f * NB));
+  return b < 0 ? 0 : (b > NB - 1 ? NB - 1 : b);
+}
+
+// Bins covering [a, b] widened by two on each side (one for the bin map's
+// rounding at the ends, one for that of the partner's slope and its bin); a
+// NaN end (an interval whose rounding bound overflowed) opens that side fully.
+template <int NB>
+__device__ __forceinline__ int2 bin_range(double a, double b, float sc) {
+  const int lo = (a == a) ? ubin<NB>(a, sc) - 2 : 0;
+  const int hi = (b == b) ? ubin<NB>(b, sc) + 2 : NB - 1;
+  return make_int2(lo < 0 ? 0 : lo, hi > NB - 1 ? NB - 1 : hi);
+}
+
+// Prefix sums use one padding word per S = NB / NT bins so that each thread's
+// S consecutive bins sit in distinct banks across a wavefront.
+template <int NB, int NT>
+__device__ __forceinline__ int bin_addr(int b) {
+  return b + b / (NB / NT);
+}
+
+// Adds point (dx, dy)'s two window intervals to the difference array. Ends
+// e = (Dy + c) / Dx, c in {-W, 0, W}, are formed as (Dy + c) * (1 / Dx): one
+// rounding each of Dx, Dy, the sum, the reciprocal and the product give
+// |e - e_exact| <= 2^-50 (|Dy| + |Dy + c|) / |Dx| (about twice the first-order
+// bound), by which each end is widened before its bin is taken. Returns the
+// packed counts of a point with Dx = 0, which is in a window at every slope
+// or at none (lim: W raised past its rounding).
+template <int NB, int NT>
+__device__ __forceinline__ unsigned add_point_bins(unsigned* bins, double dx, double dy, double W,
+                                                   double lim, float sc) {
+  if (dx == 0.0)
+    return (dy >= 0.0 && dy <= lim ? 1u : 0u) + (dy <= 0.0 && dy >= -lim ? 65536u : 0u);
+  const double inv = 1.0 / dx;
+  const double ainv = fabs(inv), ady = fabs(dy);
+  const double nm = dy - W, np = dy + W;
+  const double e0 = nm * inv, e1 = dy * inv, e2 = np * inv;
+  const double r0 = 0x1p-50 * ((ady + fabs(nm)) * ainv);
+  const double r1 = 0x1p-50 * ((ady + ady) * ainv);
+  const double r2 = 0x1p-50 * ((ady + fabs(np)) * ainv);
+  int2 bu, bd;
+  if (dx > 0.0) {
+    bu = bin_range<NB>(e0 - r0, e1 + r1, sc);
+    bd = bin_range<NB>(e1 - r1, e2 + r2, sc);
+  } else {
+    bu = bin_range<NB>(e1 - r1, e0 + r0, sc);
+    bd = bin_range<NB>(e2 - r2, e1 + r1, sc);
+  }
+  atomicAdd(&bins[bin_addr<NB, NT>(bu.x)], 1u);
+  if (bu.y + 1 < NB) atomicAdd(&bins[bin_addr<NB, NT>(bu.y + 1)], 0xFFFFFFFFu);
+  atomicAdd(&bins[bin_addr<NB, NT>(bd.x)], 65536u);
+  if (bd.y + 1 < NB) atomicAdd(&bins[bin_addr<NB, NT>(bd.y + 1)], 0xFFFF0000u);
+  return 0u;
+}
+
+// Aspect scale of the bin map: xh / yh in FP32, kept finite and positive.
+__device__ __forceinline__ float bin_scale(double xh, double yh) {
+  const double r = yh > 0.0 ? xh / yh : 1.0;
+  return (float)fmin(fmax(r, 1e-30), 1e30);
+}
+
+// In-place prefix sum of the NB-bin difference array by the NT threads of the
+// block (all must call; ends with the sums in LDS, before a barrier). Modular
+// u32 arithmetic is exact: every true sum U + 65536 D is below 2^31.
+template <int NB, int NT>
+__device__ __forceinline__ void scan_bins(unsigned* bins, unsigned* part) {
+  constexpr int S = NB / NT;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  unsigned v[S];
+  unsigned run = 0;
+#pragma unroll
+  for (int r = 0; r < S; ++r) {
+    run += bins[t * (S + 1) + r];
+    v[r] = run;
+  }
+  unsigned x = run;  // inclusive scan of the thread totals within the wavefront
+#pragma unroll
+  for (int m = 1; m < 64; m <<= 1) {
+    const unsigned y = __shfl_up(x, m);
+    if (lane >= m) x += y;
+  }
+  if (NT > 64) {
+    if (lane == 63) part[wave] = x;
+    __syncthreads();
+  }
+  unsigned off = x - run;
+  for (int w = 0; w < wave; ++w) off += part[w];
+#pragma unroll
+  for (int r = 0; r < S; ++r) bins[t * (S + 1) + r] = v[r] + off;
+}
+
+// A pair passes when its bin bounds U or D (plus the every-slope points) at h.
+__device__ __forceinline__ bool bins_pass(unsigned pb, unsigned pall, int h) {
+  return (int)((pb & 0xFFFFu) + (pall & 0xFFFFu)) >= h || (int)((pb >> 16) + (pall >> 16)) >= h;
+}
+
 // ---------------------------------------------------------------- FP32 screen
 
 // Error bound tau. With u = 2^-24, centred coordinates a_k = x_k - cx (exact),

@@ -20,6 +20,7 @@ from . import _check, _stream, load
 
 N_PARAMS = 8642
 HIDDEN = 64
+MAX_POINTS = 2048  # points the network sees per set (larger sets are subsampled)
 # packed parameter layout (row-major W[out][in])
 LAYOUT = (("W1", (HIDDEN, 2)), ("b1", (HIDDEN,)), ("W2", (HIDDEN, HIDDEN)), ("b2", (HIDDEN,)),
           ("W3", (HIDDEN, HIDDEN)), ("b3", (HIDDEN,)), ("W4", (2, HIDDEN)), ("b4", (2,)))
@@ -135,9 +136,28 @@ class SeedNet:
         return loss
 
     # -- inference ------------------------------------------------------------
-    def predict_slopes(self, xy: torch.Tensor, offsets, stream=None) -> torch.Tensor:
-        """Seed slope per set, FP64 on the device (no host synchronisation)."""
-        pts, scale, off = self.prepare(xy, offsets, stream)
+    def plan(self, offsets, max_points: int = MAX_POINTS):
+        """Gather plan for inference: a set of n > max_points points is read at
+        max_points evenly strided indices (the network was trained on sets of
+        up to MAX_POINTS). Returns (device index or None, device offsets); it
+        can be reused for every call with the same offsets."""
+        off = np.asarray(offsets.cpu() if isinstance(offsets, torch.Tensor) else offsets,
+                         dtype=np.int64)
+        n = np.diff(off)
+        if np.all(n <= max_points):
+            return None, _offsets_dev(off, self.device)
+        m = np.minimum(n, max_points)
+        idx = np.concatenate([off[b] + (np.arange(m[b]) * n[b]) // m[b] for b in range(len(n))])
+        new_off = np.concatenate([[0], np.cumsum(m)]).astype(np.int64)
+        return (torch.as_tensor(idx, device=self.device), _offsets_dev(new_off, self.device))
+
+    def predict_slopes(self, xy: torch.Tensor, offsets=None, plan=None,
+                       stream=None) -> torch.Tensor:
+        """Seed slope per set, FP64 on the device. With a plan from plan() there
+        is no host synchronisation or host-to-device copy."""
+        idx, off = plan if plan is not None else self.plan(offsets)
+        src = xy if idx is None else xy.index_select(0, idx)
+        pts, scale, off = self.prepare(src, off, stream)
         out, _ = self.forward(pts, off, False, stream)
         B = off.numel() - 1
         theta = torch.empty(B, dtype=torch.float64, device=self.device)

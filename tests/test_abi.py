@@ -111,3 +111,18 @@ def test_tile_and_tuning_argument_errors():
     t = lms._Tuning()
     assert L.lms_autotune(None, 100, 0, 3, None, ctypes.byref(t)) == lms.LMS_ERR_ARG
     assert L.lms_autotune(fake, 100, 0, 0, None, ctypes.byref(t)) == lms.LMS_ERR_ARG
+
+
+def test_result_decoding_on_host_buffers():
+    """parse/parse_batch decode every lms_result field (host tensors suffice)."""
+    import numpy as np
+    import torch
+    r = lms._Result()
+    r.width, r.status, r.bin_pass, r.band_pass = 2.5, 1, 7, 9
+    raw = torch.from_numpy(np.frombuffer(bytes(r), dtype=np.uint8).copy())
+    assert raw.numel() == lms.RESULT_BYTES
+    p = lms.parse(raw)
+    assert (p.width, p.status, p.bin_pass, p.band_pass) == (2.5, 1, 7, 9)
+    rb = lms.parse_batch(torch.stack([raw, raw]))
+    assert rb.shape == (2,) and list(rb.bin_pass) == [7, 7]
+    assert list(lms.STAGES) == ["prep", "seed", "bins", "screen", "recheck", "finalize"]

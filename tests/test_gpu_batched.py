@@ -58,6 +58,43 @@ def test_batched_equals_single_solves(gpu):
         check_pair(xy[off[b]:off[b + 1]], res[b])
 
 
+def test_bin_screen_equals_exhaustive(gpu):
+    """The batched slope-bin screen gives the same lines as the exhaustive
+    FP32 screen (bins_log2=-1), on tied pixel data and on every class."""
+    xy, off = gen.hough_patches(300, 16)
+    sizes = [2, 3, 33, 513, 1500, 3000]
+    parts = [planted(n, 0.4, 600 + n) for n in sizes]
+    xy2 = np.concatenate([xy] + parts)
+    off2 = np.concatenate([off, off[-1] + np.cumsum([len(p) for p in parts])]).astype(np.int64)
+    d = dev(xy2)
+    a = gpu.solve_batched(d, off2)
+    b = gpu.solve_batched(d, off2, bins_log2=-1)
+    for k in range(len(off2) - 1):
+        assert key(a[k]) == key(b[k]), k
+        assert a[k].vertical == b[k].vertical and a[k].survivors <= b[k].survivors
+        assert a[k].bin_pass <= a[k].candidates
+    assert int(a.bin_pass.sum()) < 0.1 * int(a.candidates.sum())
+
+
+def test_many_tiny_problems(gpu, orc):
+    """Thousands of 5..40-point problems: the slope-bin list reserves slots
+    ahead per block, so it can overflow even when few pairs pass; the
+    exhaustive fallback must then still give every exact line."""
+    st = Stream(17, 170)
+    sizes = st.integers(3000, 5, 40)
+    parts = [planted(int(n), 0.35, 7000 + k) for k, n in enumerate(sizes)]
+    off = np.concatenate([[0], np.cumsum([len(p) for p in parts])]).astype(np.int64)
+    d = dev(np.concatenate(parts))
+    a = gpu.solve_batched(d, off)
+    b = gpu.solve_batched(d, off, bins_log2=-1)
+    assert np.all(a.status == 0)
+    for k in range(len(parts)):
+        assert key(a[k]) == key(b[k]), k
+    for k in st.integers(40, 0, len(parts) - 1):
+        o = orc.solve(parts[k])
+        assert key(a[k]) == (o.width, o.theta1, o.z_lo, o.z_hi, o.theta2), k
+
+
 def test_mixed_sizes_all_classes(gpu, orc):
     """Problems in every register class (<= 512, 1024, 2048, 4096 points)."""
     sizes = [2, 3, 33, 64, 65, 511, 512, 513, 1024, 1025, 2000, 2048, 2049, 3000]

@@ -99,3 +99,22 @@ def test_seed_slope_keeps_result_exact(gpu):
         a = gpu.solve(d)
         b = gpu.solve(d, seed_pairs=0, seed_theta=th)
         assert (a.width, a.theta1, a.z_lo) == (b.width, b.theta1, b.z_lo)
+
+
+def test_inference_subsamples_large_sets(gpu):
+    """Sets above MAX_POINTS points are read at evenly strided indices, the
+    same as solving the strided subset directly; smaller sets are untouched."""
+    from paper_1510_01041_amd import seednet
+    from workloads.gen import planted
+    net = seednet.SeedNet(seed=5)
+    xy = np.concatenate([planted(5000, 0.4, 77), planted(300, 0.4, 78)])
+    off = np.array([0, 5000, 5300])
+    idx, doff = net.plan(off)
+    assert idx.numel() == seednet.MAX_POINTS + 300
+    assert doff.cpu().tolist() == [0, seednet.MAX_POINTS, seednet.MAX_POINTS + 300]
+    th = net.predict_slopes(torch.from_numpy(xy).cuda(), plan=(idx, doff)).cpu().numpy()
+    keep = (np.arange(seednet.MAX_POINTS) * 5000) // seednet.MAX_POINTS
+    sub = np.concatenate([xy[keep], xy[5000:]])
+    th2 = net.predict_slopes(torch.from_numpy(sub).cuda(),
+                             np.array([0, seednet.MAX_POINTS, seednet.MAX_POINTS + 300]))
+    assert np.array_equal(th, th2.cpu().numpy())
