@@ -26,11 +26,36 @@ sys.path.insert(0, ROOT)
 METRIC = "candidate slopes/sec and LMS solves/sec at n=4096; learned vs plain speedup"
 
 # VALU issue peak of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one 32-bit
-# lane-op per lane per clock (packed FP32 is not used).
+# (or FP64) lane-op per lane per clock (packed FP32 is not used).
 VALU_PEAK_LANE_OPS = 256 * 64 * 2.4e9
-# Algorithmic lane-ops per FP32 residual: band test = FMA + |d| <= t compare;
-# one-sided tests = FMA + four compares.
+# Algorithmic lane-ops of the FP32 test per residual: band test = FMA + |d| <= t
+# compare; one-sided tests = FMA + four compares.
 OPS_BAND, OPS_DIR = 2, 5
+# Algorithmic lane-ops of the slope-bin screen: per (anchor, point) insertion,
+# the reciprocal of dx, two sums and three products for the interval ends,
+# three bin maps and four histogram increments (13); per (anchor, bin), one
+# prefix-sum add; per (anchor, partner) query, the slope, its bin map, the
+# lookup and two compares (5).
+OPS_INSERT, OPS_BIN, OPS_QUERY = 13, 1, 5
+
+
+def roofline(stage_ms, n, pairs, r):
+    """Roofline of the dominant screen kernel (slope bins or the FP32 test),
+    timed by the library's HIP events on the solve's stream."""
+    kernels = {}
+    if r.bins:
+        ops = OPS_INSERT * n * (n - 1) + OPS_BIN * n * r.bins + OPS_QUERY * pairs
+        kernels["k_bins"] = (ops, stage_ms["bins"])
+    ops = OPS_BAND * r.point_evals + OPS_DIR * r.dir_evals
+    kernels["k_screen_list" if r.bins else "k_screen"] = (ops, stage_ms["screen"])
+    name = max(kernels, key=lambda k: kernels[k][1])
+    ops, ms = kernels[name]
+    achieved = ops / (ms * 1e-3)
+    return {"bound": "alu", "kernel": name, "achieved": achieved / 1e12,
+            "peak": VALU_PEAK_LANE_OPS / 1e12, "unit": "T lane-op/s",
+            "frac": achieved / VALU_PEAK_LANE_OPS, "traffic": None, "ops_per_launch": ops,
+            "kernels": {k: {"ms": v[1], "ops": v[0], "frac": v[0] / (v[1] * 1e-3) /
+                            VALU_PEAK_LANE_OPS} for k, v in kernels.items()}}
 
 
 def parse_args():
@@ -42,6 +67,8 @@ def parse_args():
     ap.add_argument("--seed", type=int, default=None)
     ap.add_argument("--tile-regs", type=int, default=0,
                     help="64-point chunks of the screen kept in registers (0 = automatic)")
+    ap.add_argument("--bins-log2", type=int, default=0,
+                    help="slope bins per anchor, 2^k (0 = automatic, -1 = no slope-bin screen)")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the seeding comparison")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
@@ -118,27 +145,40 @@ def main():
     d = torch.from_numpy(xy).to(dev)
     out = torch.empty(lms.RESULT_BYTES, dtype=torch.uint8, device=dev)
 
+    kw = dict(tile_regs=args.tile_regs, bins_log2=args.bins_log2)
     for _ in range(args.warmup):
-        lms.solve_async(d, 0, out, tile_regs=args.tile_regs)
+        lms.solve_async(d, 0, out, graph=True, **kw)
     torch.cuda.synchronize()
     first = lms.parse(out)
     if first.status < 0:
         raise SystemExit(f"solve failed: {lms.status_str(first.status)}")
 
-    lms.profile_begin()
+    # timed: the whole solve replayed from a captured hipGraph
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        lms.solve_async(d, 0, out, tile_regs=args.tile_regs)
+        lms.solve_async(d, 0, out, graph=True, **kw)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    n_prof, stage_ms = lms.profile_end()
     r = lms.parse(out)
-
     ms_step = (t1 - t0) * 1e3 / args.steps
-    screen_ms = stage_ms["screen"] / max(n_prof, 1)
-    ops = OPS_BAND * r.point_evals + OPS_DIR * r.dir_evals
-    achieved = ops / (screen_ms * 1e-3)
+
+    # stage split: eager launches with HIP events on the solve's stream
+    eager_steps = max(3, min(args.steps, 20))
+    lms.solve_async(d, 0, out, **kw)
+    lms.profile_begin()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for _ in range(eager_steps):
+        lms.solve_async(d, 0, out, **kw)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    n_prof, stage_ms = lms.profile_end()
+    stages = {k: v / max(n_prof, 1) for k, v in stage_ms.items()}
+    ms_eager = (t3 - t2) * 1e3 / eager_steps
+    re = lms.parse(out)
+    if (re.width, re.theta1, re.z_lo) != (r.width, r.theta1, r.z_lo):
+        raise SystemExit("graph replay and eager solve differ")
 
     parity = "not checked"
     gold_path = os.path.join(ROOT, "tests", "golden", "oracle_results.json")
@@ -161,14 +201,14 @@ def main():
             f"planted line y=0.7x+2+N(0,0.05^2), n={n}, {cfg.get('f_out', 0):.0%} uniform "
             f"outliers" if cfg["kind"] == "planted" else
             f"integer points in [0,1023]^2, n={n}, 30% duplicated x"),
-            "n": n, "h": h, "pairs": pairs, "seed": seed, "tile_regs": args.tile_regs},
+            "n": n, "h": h, "pairs": pairs, "seed": seed, "tile_regs": args.tile_regs,
+            "bins_log2": args.bins_log2},
         "solves_per_sec": 1e3 / ms_step,
-        "stages_ms_per_solve": {k: v / max(n_prof, 1) for k, v in stage_ms.items()},
-        "roofline": {"bound": "alu", "kernel": "k_screen", "achieved": achieved / 1e12,
-                     "peak": VALU_PEAK_LANE_OPS / 1e12, "unit": "T lane-op/s",
-                     "frac": achieved / VALU_PEAK_LANE_OPS, "traffic": None,
-                     "ops_per_launch": ops},
-        "search": {"survivors": r.survivors, "band_pass": r.band_pass,
+        "mode": "hipGraph replay of the whole solve",
+        "eager_ms_per_step": ms_eager,
+        "stages_ms_per_solve": stages,
+        "roofline": roofline(stages, n, pairs, r),
+        "search": {"survivors": r.survivors, "band_pass": r.band_pass, "bin_pass": r.bin_pass,
                    "vertical": r.vertical, "band_evals": r.point_evals,
                    "dir_evals": r.dir_evals,
                    "evals_per_pair": r.point_evals / max(r.candidates, 1)},
@@ -297,8 +337,14 @@ def bench_batched(args):
     single = lms.parse_batch(outs)
     same = bool(np.all(single.width == res.width) and np.all(single.theta1 == res.theta1))
 
-    ops = 2 * int(res.point_evals.sum()) + 5 * int(res.dir_evals.sum())
-    screen_ms = stage_ms["screen"]
+    nb = np.diff(off).astype(np.int64)
+    kernels = {"k_bscreen_list": (OPS_BAND * int(res.point_evals.sum()) +
+                                  OPS_DIR * int(res.dir_evals.sum()), stage_ms["screen"])}
+    if int(res.bins.max()) > 0:
+        kernels["k_bbins"] = (int((OPS_INSERT * nb * (nb - 1) + OPS_BIN * nb * res.bins.astype(np.int64)
+                                   + OPS_QUERY * (nb * (nb - 1) // 2)).sum()), stage_ms["bins"])
+    name = max(kernels, key=lambda k: kernels[k][1])
+    ops, kms = kernels[name]
     line = {
         "metric": "LMS solves/sec, batched Hough patches",
         "value": B / (ms_batched * 1e-3), "unit": "solves/s",
@@ -312,10 +358,15 @@ def bench_batched(args):
                                    "bitwise_equal": same},
         "speedup_vs_per_problem": ms_loop / ms_batched,
         "stages_ms_eager": stage_ms,
-        "roofline": {"bound": "alu", "kernel": "k_bscreen", "achieved": ops / (screen_ms * 1e-3) / 1e12,
+        "roofline": {"bound": "alu", "kernel": name, "achieved": ops / (kms * 1e-3) / 1e12,
                      "peak": VALU_PEAK_LANE_OPS / 1e12, "unit": "T lane-op/s",
-                     "frac": ops / (screen_ms * 1e-3) / VALU_PEAK_LANE_OPS, "traffic": None},
+                     "frac": ops / (kms * 1e-3) / VALU_PEAK_LANE_OPS, "traffic": None,
+                     "ops_per_launch": ops,
+                     "kernels": {k: {"ms": v[1], "ops": v[0],
+                                     "frac": v[0] / (v[1] * 1e-3) / VALU_PEAK_LANE_OPS}
+                                 for k, v in kernels.items()}},
         "search": {"survivors": int(res.survivors.sum()), "band_pass": int(res.band_pass.sum()),
+                   "bin_pass": int(res.bin_pass.sum()),
                    "vertical": int(res.vertical.sum())},
     }
     print(json.dumps(line), flush=True)

@@ -69,13 +69,15 @@ typedef struct lms_result {
   uint64_t band_pass;     /* pairs that passed the band test */
   uint64_t bin_pass;      /* pairs the slope-bin screen passed to the FP32 test
                              (lms_solve; 0 where that screen did not run) */
-  uint64_t reserved;
+  uint64_t bins;          /* slope bins per anchor of that screen (0: not run) */
 } lms_result;
 
 /* Flags for lms_options.flags */
-#define LMS_F_GRAPH 2u    /* lms_solve_batched: capture the pipeline in a hipGraph on the
-                             first call and replay it on later calls with the same
-                             pointers, batch shape and stream */
+#define LMS_F_GRAPH 2u    /* lms_solve and lms_solve_batched: capture the pipeline in a
+                             hipGraph on the first call and replay it on later calls
+                             with the same pointers, problem shape, options and
+                             stream (the input values may change). The graph owns a
+                             workspace until lms_shutdown. */
 #define LMS_F_NO_PRUNE 1u /* no width bound: the screen keeps every pair whose anchored
                              window can hold h points at all (slow; for tests) */
 

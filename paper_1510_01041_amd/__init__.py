@@ -40,7 +40,7 @@ class _Result(ctypes.Structure):
                 ("candidates", ctypes.c_uint64), ("vertical", ctypes.c_uint64),
                 ("survivors", ctypes.c_uint64), ("point_evals", ctypes.c_uint64),
                 ("dir_evals", ctypes.c_uint64), ("band_pass", ctypes.c_uint64),
-                ("bin_pass", ctypes.c_uint64), ("reserved", ctypes.c_uint64)]
+                ("bin_pass", ctypes.c_uint64), ("bins", ctypes.c_uint64)]
 
 
 assert ctypes.sizeof(_Result) == RESULT_BYTES
@@ -79,7 +79,7 @@ class LmsResult:
     dir_evals: int
     band_pass: int
     bin_pass: int
-    reserved: int
+    bins: int
 
 
 class LmsError(RuntimeError):
@@ -182,18 +182,21 @@ def solve_async(xy: torch.Tensor, h: int = 0, out: torch.Tensor | None = None, *
                 no_prune: bool = False, seed_pairs: int | None = None,
                 seed_theta: torch.Tensor | None = None, tile_regs: int = 0,
                 tile_batches: int = 0, window_pairs: int = 0, bins_log2: int = 0,
-                stream=None) -> torch.Tensor:
+                graph: bool = False, stream=None) -> torch.Tensor:
     """Enqueue one exact LMS solve; returns the device uint8[128] result buffer.
 
     seed_theta: optional CUDA float64 slopes whose exact widths seed the bound;
     window_pairs: with seed_theta, pairs drawn from the best seed line's window
     (two rounds) as further seeds. bins_log2: slope bins per anchor of the
-    first screen (0 automatic, -1 off)."""
+    first screen (0 automatic, -1 off). graph=True captures the solve in a
+    hipGraph on the first call and replays it on later calls with the same
+    buffers and options."""
     xy = _points(xy)
     if out is None:
         out = torch.empty(RESULT_BYTES, dtype=torch.uint8, device=xy.device)
-    opt = _options(LMS_F_NO_PRUNE if no_prune else 0, seed_pairs, seed_theta, tile_regs,
-                   tile_batches, window_pairs, bins_log2)
+    flags = (LMS_F_NO_PRUNE if no_prune else 0) | (LMS_F_GRAPH if graph else 0)
+    opt = _options(flags, seed_pairs, seed_theta, tile_regs, tile_batches, window_pairs,
+                   bins_log2)
     st = load().lms_solve(xy.data_ptr(), xy.shape[0], h, out.data_ptr(), ctypes.byref(opt),
                           _stream(stream))
     _check(st)

@@ -39,6 +39,7 @@
 #include <array>
 #include <vector>
 #include <map>
+#include <tuple>
 #include <mutex>
 #include <string>
 #include <utility>
@@ -69,6 +70,8 @@ struct __align__(16) Ctx {
   unsigned int next_item;     // work counter of the exhaustive screen
   unsigned int n_cands;       // pairs passed by the slope-bin screen
   unsigned int cand_overflow;
+  unsigned int bins;          // slope bins per anchor (0: no slope-bin screen)
+  unsigned int pad;
 };
 
 // Search counters, each spread over kSlots addresses (slot = block index mod
@@ -93,7 +96,8 @@ __device__ __forceinline__ void stat_add(Ctx* ctx, int k, unsigned long long v) 
 __global__ __launch_bounds__(1024) void k_prep(const double* __restrict__ xy, int n, int h,
                                                int n_pad, Ctx* ctx, float2* __restrict__ xy32,
                                                uint2* __restrict__ entries, int n_seeds,
-                                               int n_random, unsigned long long seed_key) {
+                                               int n_random, unsigned long long seed_key,
+                                               unsigned bins) {
   __shared__ double s_mn[1024], s_mx[1024], s_my[1024], s_My[1024];
   __shared__ int s_amn[1024], s_amx[1024], s_fin[1024];
   const int t = threadIdx.x;
@@ -132,6 +136,7 @@ __global__ __launch_bounds__(1024) void k_prep(const double* __restrict__ xy, in
     Ctx c;
     memset(&c, 0, sizeof(c));
     c.n = n; c.h = h; c.n_pad = n_pad; c.n_seeds = n_seeds;
+    c.bins = bins;
     c.status = finite ? LMS_OK : LMS_ERR_NONFINITE;
     c.all_x_equal = finite && (minx == maxx);
     c.argminx = s_amn[0]; c.argmaxx = s_amx[0];
@@ -438,7 +443,9 @@ __global__ __launch_bounds__(NT, 3) void k_screen(
 template <int NB, int NT>
 __global__ __launch_bounds__(NT) void k_bins(const double* __restrict__ xy, Ctx* ctx,
                                              uint2* __restrict__ cands, int cand_cap,
-                                             uint2* __restrict__ entries, int cap) {
+                                             uint2* __restrict__ entries, int cap,
+                                             const double4* __restrict__ seed_res,
+                                             const double4* __restrict__ seed_rec, int n_rec) {
   constexpr int S = NB / NT;  // bins per thread in the prefix sum
   static_assert(S >= 1 && (NB % NT) == 0, "bins must be a multiple of the block");
   __shared__ unsigned bins[NB + NB / S];
@@ -450,12 +457,16 @@ __global__ __launch_bounds__(NT) void k_bins(const double* __restrict__ xy, Ctx*
   __shared__ uint2 pbuf[PB];
   __shared__ unsigned s_part[NT / 64];
   __shared__ unsigned s_all, s_cnt, s_base, s_fill;
+  __shared__ unsigned long long s_key;
+  __shared__ double s_th;
   const Ctx c = *ctx;
   if (c.status != LMS_OK || c.all_x_equal) return;
   const int n = c.n, h = c.h, t = threadIdx.x, lane = t & 63;
   const double W = __longlong_as_double((long long)c.wbound);
   const double lim = W * (1.0 + 0x1p-50);
   const float sc = bin_scale(c.xh, c.yh);
+  const double tc = best_slope<NT>(seed_res, c.n_seeds, seed_rec, n_rec, &s_key, &s_th);
+  const double nbsc = 0x1p-46 * NB * (double)sc;
   const int half = n >> 1;
   unsigned long long n_vert = 0, n_scr = 0, n_forced = 0, n_pass = 0;
   // reserves cnt list slots (thread 0; the base goes to s_base)
@@ -492,7 +503,8 @@ __global__ __launch_bounds__(NT) void k_bins(const double* __restrict__ xy, Ctx*
     // 1. intervals of every point (packed counts: U in the low, D in the high half)
     unsigned all = 0;
     for (int k = t; k < n; k += NT)
-      all += add_point_bins<NB, NT>(bins, xy[2 * k] - xi, xy[2 * k + 1] - yi, W, lim, sc);
+      all += add_point_bins<NB, NT>(bins, xy[2 * k] - xi, xy[2 * k + 1] - yi, W, lim, tc, sc,
+                                    nbsc);
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1) all += __shfl_xor(all, m);
     if (lane == 0) atomicAdd(&s_all, all);
@@ -518,7 +530,7 @@ __global__ __launch_bounds__(NT) void k_bins(const double* __restrict__ xy, Ctx*
       const bool test = valid && !vert && !force;
       bool pass = false;
       if (test) {
-        pass = bins_pass(bins[bin_addr<NB, NT>(ubin<NB>(th, sc))], pall, h);
+        pass = bins_pass(bins[bin_addr<NB, NT>(ubin<NB>(th, tc, sc))], pall, h);
       }
       const unsigned long long mv = __ballot(vert), mf = __ballot(force),
                                mt = __ballot(test), mp = __ballot(pass);
@@ -572,12 +584,12 @@ __global__ __launch_bounds__(NT) void k_bins(const double* __restrict__ xy, Ctx*
   }
 }
 
-// FP32 test of the listed pairs: a wavefront takes kListBlock consecutive
-// list entries (mostly of one anchor, as the list is written per anchor),
-// loads the points shifted by each distinct anchor among them, and runs the
-// band and split tests of the exhaustive screen on every pair. Each pair
-// costs up to two passes over the points, so blocks are small to spread the
-// pairs over many wavefronts.
+// FP32 test of the listed pairs: a wavefront takes a task of up to
+// kListBlock consecutive list entries (mostly of one anchor, as the list is
+// written per anchor), loads the points shifted by each distinct anchor among
+// them, and runs the band and split tests of the exhaustive screen on every
+// pair. A pair costs up to two serial passes over the points, so tasks shrink
+// to one pair when the list is short and the wavefronts would otherwise idle.
 constexpr int kListBlock = 16;
 template <int R, bool LDS_PART, int NT>
 __global__ __launch_bounds__(NT, 3) void k_screen_list(
@@ -592,7 +604,9 @@ __global__ __launch_bounds__(NT, 3) void k_screen_list(
     __syncthreads();
   }
   const unsigned total = min(c.n_cands, (unsigned)cand_cap);
-  const unsigned n_blocks = (total + kListBlock - 1u) / kListBlock;
+  const unsigned n_waves = gridDim.x * (blockDim.x / 64u);
+  const unsigned task = max(1u, min((unsigned)kListBlock, (total + n_waves - 1u) / n_waves));
+  const unsigned n_blocks = (total + task - 1u) / task;
   const double W = __longlong_as_double((long long)c.wbound);
   unsigned long long n_evals = 0, n_devals = 0;
   unsigned n_band = 0;
@@ -601,14 +615,13 @@ __global__ __launch_bounds__(NT, 3) void k_screen_list(
   float2 pi = make_float2(0.0f, 0.0f);
 #pragma unroll
   for (int r = 0; r < R; ++r) X[r] = Y[r] = 0.0f;
-  // Static round-robin over the blocks: no shared counter, so the waves that
+  // Static round-robin over the tasks: no shared counter, so the waves that
   // find no work leave at once (a contended counter costs tens of us).
-  const unsigned n_waves = gridDim.x * (blockDim.x / 64u);
   const unsigned w0 = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x / 64u) +
                                                      threadIdx.x / 64u);
   for (unsigned blk = w0; blk < n_blocks; blk += n_waves) {
-    const unsigned e = blk * kListBlock + (unsigned)lane;
-    const bool valid = lane < kListBlock && e < total;
+    const unsigned e = blk * task + (unsigned)lane;
+    const bool valid = (unsigned)lane < task && e < total;
     const uint2 cd = valid ? cands[e] : make_uint2(0u, 0u);
     const int ai = (int)cd.x, aj = (int)cd.y;
     unsigned long long todo = __ballot(valid);
@@ -777,6 +790,7 @@ __global__ __launch_bounds__(1024) void k_finalize(Ctx* ctx, const uint2* __rest
   o.dir_evals = s_stat[ST_DEVALS];
   o.band_pass = s_stat[ST_BAND];
   o.bin_pass = s_stat[ST_BIN];
+  o.bins = c.bins;
   *out = o;
 }
 
@@ -980,7 +994,8 @@ constexpr int bins_threads() {
 
 template <int NB>
 hipError_t launch_bins_nb(hipStream_t s, int cu, int n, const double* xy, Ctx* ctx, uint2* cands,
-                          int cand_cap, uint2* e, int cap) {
+                          int cand_cap, uint2* e, int cap, const double4* res,
+                          const double4* rec, int n_rec) {
   constexpr int nt = bins_threads<NB>();
   static int resident = 0;
   if (resident == 0) {
@@ -994,18 +1009,19 @@ hipError_t launch_bins_nb(hipStream_t s, int cu, int n, const double* xy, Ctx* c
   }
   const int grid = std::max(1, std::min(n, cu * resident));
   hipLaunchKernelGGL((k_bins<NB, nt>), dim3(grid), dim3(nt), 0, s, xy, ctx, cands, cand_cap, e,
-                     cap);
+                     cap, res, rec, rec ? n_rec : 0);
   return hipGetLastError();
 }
 
 hipError_t launch_bins(hipStream_t s, int nb_log2, int cu, int n, const double* xy, Ctx* ctx,
-                       uint2* cands, int cand_cap, uint2* e, int cap) {
+                       uint2* cands, int cand_cap, uint2* e, int cap, const double4* res,
+                       const double4* rec, int n_rec) {
   switch (nb_log2) {
-    case 11: return launch_bins_nb<2048>(s, cu, n, xy, ctx, cands, cand_cap, e, cap);
-    case 12: return launch_bins_nb<4096>(s, cu, n, xy, ctx, cands, cand_cap, e, cap);
-    case 13: return launch_bins_nb<8192>(s, cu, n, xy, ctx, cands, cand_cap, e, cap);
-    case 14: return launch_bins_nb<16384>(s, cu, n, xy, ctx, cands, cand_cap, e, cap);
-    default: return launch_bins_nb<32768>(s, cu, n, xy, ctx, cands, cand_cap, e, cap);
+    case 11: return launch_bins_nb<2048>(s, cu, n, xy, ctx, cands, cand_cap, e, cap, res, rec, n_rec);
+    case 12: return launch_bins_nb<4096>(s, cu, n, xy, ctx, cands, cand_cap, e, cap, res, rec, n_rec);
+    case 13: return launch_bins_nb<8192>(s, cu, n, xy, ctx, cands, cand_cap, e, cap, res, rec, n_rec);
+    case 14: return launch_bins_nb<16384>(s, cu, n, xy, ctx, cands, cand_cap, e, cap, res, rec, n_rec);
+    default: return launch_bins_nb<32768>(s, cu, n, xy, ctx, cands, cand_cap, e, cap, res, rec, n_rec);
   }
 }
 
@@ -1025,9 +1041,8 @@ hipError_t launch_list_rl(hipStream_t s, int cu, const double* xy, const float2*
     (void)hipGetLastError();
     nb = 1;
   }
-  // persistent blocks, but no more than the list could ever fill
-  const long long most = ((long long)cand_cap + kListBlock - 1) / kListBlock;
-  const long long need = (most + nt / 64 - 1) / (nt / 64);
+  // persistent blocks, but no more than the list could ever occupy one pair each
+  const long long need = ((long long)cand_cap + nt / 64 - 1) / (nt / 64);
   const int grid = (int)std::max<long long>(1, std::min<long long>((long long)cu * nb, need));
   hipLaunchKernelGGL((k_screen_list<R, L, nt>), dim3(grid), dim3(nt), shm, s, xy, xy32, ctx,
                      cands, cand_cap, e, cap, nq);
@@ -1096,30 +1111,22 @@ lms_status make_plan(const void* d_xy, int64_t n, int64_t h, Plan* p, int tile_r
   return LMS_OK;
 }
 
-}  // namespace
+// Everything one solve needs, from its arguments and options.
+struct Setup {
+  Plan p;
+  const double* xy = nullptr;
+  lms_result* out = nullptr;
+  unsigned flags = 0;
+  int seeds = 0, window_pairs = 0, bins_log2 = 0, G = 1, ipa = 1;
+  bool no_prune = false, use_bins = false;
+  const double* seed_theta = nullptr;
+  int64_t n_seed_theta = 0;
+  long long pairs = 0, cand_cap = 0, n_items = 0;
+  Layout L;
+};
 
-// ---------------------------------------------------------------- C ABI
-
-extern "C" {
-
-const char* lms_status_str(int s) {
-  switch (s) {
-    case LMS_OK: return "ok";
-    case LMS_OK_DEGENERATE: return "ok (all x equal: slope set to 0)";
-    case LMS_ERR_ARG: return "invalid argument";
-    case LMS_ERR_NONFINITE: return "non-finite coordinate";
-    case LMS_ERR_DEVICE: return "HIP device error";
-    case LMS_ERR_NOMEM: return "out of device memory";
-    case LMS_ERR_CAPACITY: return "survivor list overflow";
-    default: return "unknown status";
-  }
-}
-
-const char* lms_last_error(void) { return lms_host::last_error(); }
-
-lms_status lms_solve(const double* d_xy, int64_t n, int64_t h, lms_result* d_out,
-                     const lms_options* opt, void* stream) {
-  lms_host::clear_error();
+lms_status make_setup(const double* d_xy, int64_t n, int64_t h, lms_result* d_out,
+                      const lms_options* opt, Setup* S) {
   if (opt && opt->struct_size < sizeof(lms_options)) return fail(LMS_ERR_ARG, "bad options size");
   // automatic tiles and seeds: the autotuned choice for this size class, if any
   lms_tuning tuned{0, 0, -1, 0, 0.0};
@@ -1134,7 +1141,7 @@ lms_status lms_solve(const double* d_xy, int64_t n, int64_t h, lms_result* d_out
   if (tile_batches < 0 || tile_batches > 64) return fail(LMS_ERR_ARG, "tile_batches must be in [0, 64]");
   if (bins_log2 != 0 && bins_log2 != -1 && (bins_log2 < 11 || bins_log2 > 15))
     return fail(LMS_ERR_ARG, "bins_log2 must be 0, -1 or in [11, 15]");
-  Plan p;
+  Plan& p = S->p;
   lms_status st = make_plan(d_xy, n, h, &p, tile_regs);
   if (st != LMS_OK) return st;
   if (!d_out) return fail(LMS_ERR_ARG, "null result pointer");
@@ -1171,39 +1178,59 @@ lms_status lms_solve(const double* d_xy, int64_t n, int64_t h, lms_result* d_out
     if (bins_log2 == 0) bins_log2 = default_bins_log2(p.n);
     while (bins_log2 < 15 && (1 << bins_log2) < p.n) ++bins_log2;
   }
-  const long long cand_cap = use_bins ? screen_cap : 0;
-  const Layout L = layout(p.n_pad, p.cap, window_pairs ? n_seed_theta : 0, cand_cap);
-  char* base = nullptr;
-  st = lms_host::get_workspace(0, stream, L.total, &base);
-  if (st != LMS_OK) return st;
-  hipStream_t s = (hipStream_t)stream;
+  const int Pmax = p.n / 2;
+  const int batches = (Pmax + 63) / 64;
+  S->G = std::min(tile_batches > 0 ? tile_batches : 4, std::max(1, batches));
+  S->ipa = (batches + S->G - 1) / S->G;
+  S->n_items = (long long)p.n * S->ipa;
+  S->xy = d_xy;
+  S->out = d_out;
+  S->flags = flags;
+  S->seeds = seeds;
+  S->window_pairs = window_pairs;
+  S->bins_log2 = bins_log2;
+  S->no_prune = no_prune;
+  S->use_bins = use_bins;
+  S->seed_theta = d_seed_theta;
+  S->n_seed_theta = n_seed_theta;
+  S->pairs = pairs;
+  S->cand_cap = use_bins ? screen_cap : 0;
+  S->L = layout(p.n_pad, p.cap, n_seed_theta, S->cand_cap);
+  return LMS_OK;
+}
+
+// Enqueues one solve on s (kernels only, so it can be captured in a graph).
+lms_status enqueue_solve(const Setup& S, char* base, hipStream_t s, lms_host::StageEvents* prof) {
+  const Plan& p = S.p;
+  const Layout& L = S.L;
+  const double* d_xy = S.xy;
   Ctx* ctx = (Ctx*)(base + L.ctx);
   float2* xy32 = (float2*)(base + L.xy32);
   uint2* entries = (uint2*)(base + L.entries);
   double4* res = (double4*)(base + L.res);
+  double4* rec = (double4*)(base + L.rec);
   const int cu = lms_host::num_cu();
-
-  lms_host::StageEvents prof;
-  prof.start(s);
+  const int seeds = S.seeds, window_pairs = S.window_pairs;
+  const int64_t n_seed_theta = S.n_seed_theta;
+  auto mark = [&]() { if (prof) prof->mark(); };
   const unsigned long long key = 0x5EEDull + (unsigned long long)p.n * 0x100000001ull;
   hipLaunchKernelGGL(k_prep, dim3(1), dim3(1024), 0, s, d_xy, p.n, p.h, p.n_pad, ctx, xy32,
-                     entries, p.n_seeds, seeds, key);
-  prof.mark();
+                     entries, p.n_seeds, seeds, key, S.use_bins ? 1u << S.bins_log2 : 0u);
+  mark();
   // Seeds: exact FP64 widths of a few slopes set the screen's bound: the
   // device seed slopes, the extreme-x and random pairs, and with window pairs
   // two rounds of pairs drawn from the narrowest window found so far. Without
   // pruning the bound stays +inf and the screen keeps every pair whose
   // anchored window can hold h points at all.
-  double4* rec = (double4*)(base + L.rec);
-  if (n_seed_theta > 0 && !no_prune)
-    launch_eval(s, (int)std::min<int64_t>(n_seed_theta, 4 * cu), d_xy, p.n, p.h, d_seed_theta,
-                (int)n_seed_theta, nullptr, ctx, window_pairs ? rec : nullptr);
+  if (n_seed_theta > 0 && !S.no_prune)
+    launch_eval(s, (int)std::min<int64_t>(n_seed_theta, 4 * cu), d_xy, p.n, p.h, S.seed_theta,
+                (int)n_seed_theta, nullptr, ctx, rec);
   const int first_w = 1 + seeds;
   if (window_pairs)
     hipLaunchKernelGGL(k_window_pairs, dim3(1), dim3(kWinNT), 0, s, d_xy, ctx, rec,
                        (int)n_seed_theta, entries, first_w, window_pairs, key ^ 0xA1ull);
   launch_recheck(s, p.n, std::min(first_w + window_pairs, 4 * cu), d_xy, ctx, entries, res, 0,
-                 first_w + window_pairs, no_prune ? 0 : 1);
+                 first_w + window_pairs, S.no_prune ? 0 : 1);
   if (window_pairs) {
     // second round: from the narrowest window of the first round's pairs
     hipLaunchKernelGGL(k_window_pairs, dim3(1), dim3(kWinNT), 0, s, d_xy, ctx, res + first_w,
@@ -1211,47 +1238,155 @@ lms_status lms_solve(const double* d_xy, int64_t n, int64_t h, lms_result* d_out
     launch_recheck(s, p.n, std::min(window_pairs, 4 * cu), d_xy, ctx, entries, res,
                    first_w + window_pairs, p.n_seeds, 1);
   }
-  prof.mark();
-  {
-    // Screen. With slope bins: per-anchor bin counts, then the FP32 test of
-    // the pairs they pass, and the exhaustive FP32 screen only if their list
-    // could overflow and did. Without: the exhaustive FP32 screen.
-    const int Pmax = p.n / 2;
-    const int batches = (Pmax + 63) / 64;
-    const int G = std::min(tile_batches > 0 ? tile_batches : 4, std::max(1, batches));
-    const int ipa = (batches + G - 1) / G;
-    const long long n_items = (long long)p.n * ipa;
-    hipError_t err = hipSuccess;
-    if (use_bins) {
-      uint2* cands = (uint2*)(base + L.cands);
-      err = launch_bins(s, bins_log2, cu, p.n, d_xy, ctx, cands, (int)cand_cap, entries,
-                        (int)p.cap);
-      prof.mark();
-      if (err == hipSuccess)
-        err = launch_list(s, p.R, p.lds, cu, d_xy, xy32, ctx, cands, (int)cand_cap, entries,
-                          (int)p.cap, p.nq);
-      if (err == hipSuccess && pairs > cand_cap)
-        err = launch_screen(s, p.R, p.lds, cu, d_xy, xy32, ctx, entries, (int)p.cap, G, ipa,
-                            (int)n_items, p.nq, 1);
-    } else {
-      prof.mark();  // no slope-bin stage
-      err = launch_screen(s, p.R, p.lds, cu, d_xy, xy32, ctx, entries, (int)p.cap, G, ipa,
-                          (int)n_items, p.nq);
-    }
-    if (err != hipSuccess) {
-      prof.finish();
-      return fail(LMS_ERR_DEVICE, std::string("screen launch: ") + hipGetErrorString(err));
-    }
+  mark();
+  // Screen. With slope bins: per-anchor bin counts, then the FP32 test of the
+  // pairs they pass, and the exhaustive FP32 screen only if their list could
+  // overflow and did. Without: the exhaustive FP32 screen.
+  hipError_t err = hipSuccess;
+  if (S.use_bins) {
+    uint2* cands = (uint2*)(base + L.cands);
+    err = launch_bins(s, S.bins_log2, cu, p.n, d_xy, ctx, cands, (int)S.cand_cap, entries,
+                      (int)p.cap, res, n_seed_theta > 0 && !S.no_prune ? rec : nullptr,
+                      (int)n_seed_theta);
+    mark();
+    if (err == hipSuccess)
+      err = launch_list(s, p.R, p.lds, cu, d_xy, xy32, ctx, cands, (int)S.cand_cap, entries,
+                        (int)p.cap, p.nq);
+    if (err == hipSuccess && S.pairs > S.cand_cap)
+      err = launch_screen(s, p.R, p.lds, cu, d_xy, xy32, ctx, entries, (int)p.cap, S.G, S.ipa,
+                          (int)S.n_items, p.nq, 1);
+  } else {
+    mark();  // no slope-bin stage
+    err = launch_screen(s, p.R, p.lds, cu, d_xy, xy32, ctx, entries, (int)p.cap, S.G, S.ipa,
+                        (int)S.n_items, p.nq);
   }
-  prof.mark();
+  if (err != hipSuccess)
+    return fail(LMS_ERR_DEVICE, std::string("screen launch: ") + hipGetErrorString(err));
+  mark();
   launch_recheck(s, p.n, 4 * cu, d_xy, ctx, entries, res, p.n_seeds, (int)p.cap, 0);
-  prof.mark();
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, s, ctx, entries, res, (int)p.cap, d_out);
-  prof.mark();
-  prof.finish();
-  hipError_t err = hipGetLastError();
+  mark();
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, s, ctx, entries, res, (int)p.cap, S.out);
+  mark();
+  err = hipGetLastError();
   if (err != hipSuccess) return fail(LMS_ERR_DEVICE, std::string("launch: ") + hipGetErrorString(err));
   return LMS_OK;
+}
+
+// Graph replay of single solves (LMS_F_GRAPH): one captured graph, with its
+// own workspace, per (input, output, stream, problem and option values).
+struct SolveKey {
+  const void* xy;
+  const void* out;
+  const void* seed_theta;
+  void* stream;
+  int64_t n_seed_theta;
+  int n, h, seeds, window_pairs, bins_log2, R, G;
+  unsigned flags;
+  bool operator<(const SolveKey& o) const {
+    return std::tie(xy, out, seed_theta, stream, n_seed_theta, n, h, seeds, window_pairs,
+                    bins_log2, R, G, flags) <
+           std::tie(o.xy, o.out, o.seed_theta, o.stream, o.n_seed_theta, o.n, o.h, o.seeds,
+                    o.window_pairs, o.bins_log2, o.R, o.G, o.flags);
+  }
+};
+struct SolveGraph {
+  char* base = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+std::mutex g_smu;
+std::map<SolveKey, SolveGraph> g_solves;
+
+lms_status solve_graph(const Setup& S, hipStream_t s) {
+  const SolveKey key{S.xy, S.out, S.seed_theta, (void*)s, S.n_seed_theta, S.p.n, S.p.h, S.seeds,
+                     S.window_pairs, S.bins_log2, S.p.R, S.G, S.flags};
+  std::lock_guard<std::mutex> lk(g_smu);
+  auto it = g_solves.find(key);
+  if (it == g_solves.end()) {
+    SolveGraph sg;
+    if (hipMalloc(&sg.base, S.L.total) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(LMS_ERR_NOMEM, "hipMalloc of the graph workspace failed");
+    }
+    // capture on a private stream (the legacy null stream cannot be captured)
+    hipStream_t cs = nullptr;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {
+      (void)hipFree(sg.base);
+      return fail(LMS_ERR_DEVICE, "hipStreamCreate failed");
+    }
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      (void)hipStreamDestroy(cs);
+      (void)hipFree(sg.base);
+      return fail(LMS_ERR_DEVICE, "hipStreamBeginCapture failed");
+    }
+    const lms_status st = enqueue_solve(S, sg.base, cs, nullptr);
+    const hipError_t e = hipStreamEndCapture(cs, &sg.graph);
+    (void)hipStreamDestroy(cs);
+    if (st != LMS_OK || e != hipSuccess || !sg.graph ||
+        hipGraphInstantiate(&sg.exec, sg.graph, nullptr, nullptr, 0) != hipSuccess) {
+      if (sg.graph) (void)hipGraphDestroy(sg.graph);
+      (void)hipFree(sg.base);
+      (void)hipGetLastError();
+      return st != LMS_OK ? st : fail(LMS_ERR_DEVICE, "capturing the solve graph failed");
+    }
+    it = g_solves.emplace(key, sg).first;
+  }
+  lms_host::StageEvents prof;
+  prof.start(s);
+  if (hipGraphLaunch(it->second.exec, s) != hipSuccess)
+    return fail(LMS_ERR_DEVICE, "hipGraphLaunch failed");
+  for (int k = 0; k < LMS_NSTAGES; ++k) prof.mark();  // the whole graph is stage 0
+  prof.finish();
+  return LMS_OK;
+}
+
+void release_solves() {
+  std::lock_guard<std::mutex> lk(g_smu);
+  for (auto& kv : g_solves) {
+    if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+    if (kv.second.graph) (void)hipGraphDestroy(kv.second.graph);
+    if (kv.second.base) (void)hipFree(kv.second.base);
+  }
+  g_solves.clear();
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- C ABI
+
+extern "C" {
+
+const char* lms_status_str(int s) {
+  switch (s) {
+    case LMS_OK: return "ok";
+    case LMS_OK_DEGENERATE: return "ok (all x equal: slope set to 0)";
+    case LMS_ERR_ARG: return "invalid argument";
+    case LMS_ERR_NONFINITE: return "non-finite coordinate";
+    case LMS_ERR_DEVICE: return "HIP device error";
+    case LMS_ERR_NOMEM: return "out of device memory";
+    case LMS_ERR_CAPACITY: return "survivor list overflow";
+    default: return "unknown status";
+  }
+}
+
+const char* lms_last_error(void) { return lms_host::last_error(); }
+
+lms_status lms_solve(const double* d_xy, int64_t n, int64_t h, lms_result* d_out,
+                     const lms_options* opt, void* stream) {
+  lms_host::clear_error();
+  Setup S;
+  lms_status st = make_setup(d_xy, n, h, d_out, opt, &S);
+  if (st != LMS_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  if (S.flags & LMS_F_GRAPH) return solve_graph(S, s);
+  char* base = nullptr;
+  st = lms_host::get_workspace(0, stream, S.L.total, &base);
+  if (st != LMS_OK) return st;
+  lms_host::StageEvents prof;
+  prof.start(s);
+  st = enqueue_solve(S, base, s, &prof);
+  prof.finish();
+  return st;
 }
 
 lms_status lms_autotune(const double* d_xy, int64_t n, int64_t h, int32_t reps, void* stream,
@@ -1378,7 +1513,7 @@ lms_status lms_screen_pairs(const double* d_xy, int64_t n, int64_t h, double W,
   float2* xy32 = (float2*)(base + L.xy32);
   uint2* entries = (uint2*)(base + L.entries);
   hipLaunchKernelGGL(k_prep, dim3(1), dim3(1024), 0, s, d_xy, p.n, p.h, p.n_pad, ctx, xy32,
-                     entries, 1, 0, 0ull);
+                     entries, 1, 0, 0ull, 0u);
   hipError_t err = launch_pairs(s, p.R, p.lds, d_xy, xy32, ctx, W, d_pairs, (int)m, d_verdict, p.nq);
   if (err != hipSuccess) return fail(LMS_ERR_DEVICE, hipGetErrorString(err));
   return LMS_OK;
@@ -1389,6 +1524,7 @@ void lms_profile_begin(void) { lms_host::profile_begin(); }
 int64_t lms_profile_end(double* ms) { return lms_host::profile_end(ms); }
 
 void lms_shutdown(void) {
+  release_solves();
   lms_host::release_batches();
   lms_host::free_workspaces();
 }

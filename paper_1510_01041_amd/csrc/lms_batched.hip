@@ -64,6 +64,8 @@ struct __align__(16) PMeta {
   unsigned long long best_w, best_th, best_lo, best_pair;
   double best_hi;
   unsigned long long vertical, survivors, evals, dir_evals, band_pass, bin_pass;
+  double center;  // slope of the narrowest seed window (centre of the bin map)
+  double pad2;
 };
 
 struct __align__(16) BState {
@@ -355,6 +357,22 @@ __global__ __launch_bounds__(256, 3) void k_bscreen(
 
 // ---------------------------------------------------------------- slope-bin screen
 
+// Centre of each problem's bin map: the slope of its narrowest seed window.
+__global__ __launch_bounds__(256) void k_bcenter(const double4* __restrict__ res, PMeta* meta,
+                                                 int B, int S) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  double bw = INFINITY, th = 0.0;
+  for (int e = 0; e < S; ++e) {
+    const double4 r = res[(size_t)b * S + e];
+    if (r.x < bw) {
+      bw = r.x;
+      th = r.y;
+    }
+  }
+  meta[b].center = th;
+}
+
 // One work item (problem b, anchor i) at a time per block, items taken
 // round-robin (no shared counter): the two window intervals of every point of
 // b in NB slope bins (see add_point_bins), their prefix sum, and each
@@ -398,10 +416,13 @@ __global__ __launch_bounds__(NT) void k_bbins(const double* __restrict__ xy, PMe
     const double W = __longlong_as_double((long long)m.wbound);
     const double lim = W * (1.0 + 0x1p-50);
     const float sc = bin_scale(m.xh, m.yh);
+    const double tc = m.center;
+    const double nbsc = 0x1p-46 * NB * (double)sc;
     const double xi = gxy[2 * i], yi = gxy[2 * i + 1];
     unsigned all = 0;
     for (int k = t; k < n; k += NT)
-      all += add_point_bins<NB, NT>(bins, gxy[2 * k] - xi, gxy[2 * k + 1] - yi, W, lim, sc);
+      all += add_point_bins<NB, NT>(bins, gxy[2 * k] - xi, gxy[2 * k + 1] - yi, W, lim, tc, sc,
+                                    nbsc);
 #pragma unroll
     for (int q = 32; q >= 1; q >>= 1) all += __shfl_xor(all, q);
     if (lane == 0) atomicAdd(&s_all, all);
@@ -425,7 +446,7 @@ __global__ __launch_bounds__(NT) void k_bbins(const double* __restrict__ xy, PMe
       const double tau = tau_bound(th, m.xh, m.yh);
       const bool force = valid && !vert && !(fabs(th) < 1e30 && tau < 1e30);
       const bool test = valid && !vert && !force;
-      const bool pass = test && bins_pass(bins[bin_addr<NB, NT>(ubin<NB>(th, sc))], pall, h);
+      const bool pass = test && bins_pass(bins[bin_addr<NB, NT>(ubin<NB>(th, tc, sc))], pall, h);
       const unsigned long long mv = __ballot(vert), mf = __ballot(force), mp = __ballot(pass);
       n_vert += __popcll(mv);
       n_forced += __popcll(mf);
@@ -741,7 +762,7 @@ __global__ __launch_bounds__(256) void k_bselect(const uint2* __restrict__ entri
 }
 
 __global__ __launch_bounds__(256) void k_bfinal(const PMeta* __restrict__ meta, int B,
-                                                const BState* state, lms_result* out) {
+                                                const BState* state, lms_result* out, int bins) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= B) return;
   const PMeta m = meta[b];
@@ -779,6 +800,7 @@ __global__ __launch_bounds__(256) void k_bfinal(const PMeta* __restrict__ meta, 
   o.dir_evals = m.dir_evals;
   o.band_pass = m.band_pass;
   o.bin_pass = m.bin_pass;
+  o.bins = bins ? (m.R <= kClassChunks[1] ? 4096u : 8192u) : 0u;  // the class's bins
   out[b] = o;
 }
 
@@ -1070,6 +1092,7 @@ lms_status enqueue_batch(const BPlan& P, char* base, const double* d_xy, const i
   if (prof) prof->mark();
   hipLaunchKernelGGL(k_bmerge_clear, dim3(std::min<unsigned>(P.tab_size / 256, 8u * cu)), dim3(256), 0,
                      s, tab, P.tab_size);
+  hipLaunchKernelGGL(k_bcenter, dim3((P.B + 255) / 256), dim3(256), 0, s, res, meta, P.B, P.S);
   uint2* cands = (uint2*)(base + P.o_cands);
   if (bins) {
     for (int c = 0; c < kClasses; ++c)
@@ -1102,7 +1125,8 @@ lms_status enqueue_batch(const BPlan& P, char* base, const double* d_xy, const i
   for (int pass = 1; pass <= 3; ++pass)
     hipLaunchKernelGGL(k_bselect, dim3(4 * cu), dim3(256), 0, s, entries, res, meta, state, cap,
                        pass);
-  hipLaunchKernelGGL(k_bfinal, dim3((P.B + 255) / 256), dim3(256), 0, s, meta, P.B, state, d_out);
+  hipLaunchKernelGGL(k_bfinal, dim3((P.B + 255) / 256), dim3(256), 0, s, meta, P.B, state, d_out,
+                     bins ? 1 : 0);
   if (prof) prof->mark();
   const hipError_t err = hipGetLastError();
   if (err != hipSuccess) return fail(LMS_ERR_DEVICE, std::string("launch: ") + hipGetErrorString(err));

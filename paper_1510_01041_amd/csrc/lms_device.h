@@ -97,15 +97,108 @@ __device__ void window_f64_rt(const double* __restrict__ xy, int n, int h, int n
   __syncthreads();
 }
 
+// Narrowest window and its ends from z[0..N2), sorted, by the whole block
+// (the scan of window_f64_rt).
+template <int NT>
+__device__ __forceinline__ void window_scan(const double* z, int n, int h, unsigned long long* s_w,
+                                            int* s_s, double* width, double* z_lo,
+                                            double* z_hi) {
+  const int t = threadIdx.x;
+  double bw = INFINITY;
+  int bs = INT_MAX;
+  for (int s = t; s + h <= n; s += NT) {
+    const double w = z[s + h - 1] - z[s];
+    if (w < bw) { bw = w; bs = s; }
+  }
+  const unsigned long long bwb = (unsigned long long)__double_as_longlong(bw);
+  atomicMin(s_w, bwb);
+  __syncthreads();
+  if (bs != INT_MAX && bwb == *s_w) atomicMin(s_s, bs);
+  __syncthreads();
+  const int s = (*s_s == INT_MAX) ? 0 : *s_s;
+  *width = (*s_s == INT_MAX) ? NAN : __longlong_as_double((long long)*s_w);
+  *z_lo = z[s];
+  *z_hi = z[s + h - 1];
+  __syncthreads();
+}
+
 // Narrowest window of h consecutive values of z_k = fma(-theta, x_k, y_k),
 // k < n, computed by the whole block; z is an LDS array of N2 >= n doubles.
 // Same operation sequence as the reference: fma, full sort, subtraction, and
 // the lowest window among equally narrow ones.
+//
+// With N2 >= NT the sort runs in registers: value g = (wave * E + r) * 64 +
+// lane (E = N2 / NT) sits in register r of that lane. A bitonic stage with
+// partner distance j < 64 exchanges across lanes (wavefront shuffles), one
+// with 64 <= j < 64 E within a thread, and one with j >= 64 E through LDS
+// (two barriers). It is the same network with the same compare-and-swap rule
+// as window_f64_rt's LDS sort, so the sorted sequence is identical (also for
+// NaN and signed zeros).
 template <int N2, int NT>
 __device__ __forceinline__ void window_f64(const double* __restrict__ xy, int n, int h,
                                            double theta, double* z, unsigned long long* s_w,
                                            int* s_s, double* width, double* z_lo, double* z_hi) {
-  window_f64_rt<N2, NT>(xy, n, h, N2, theta, z, s_w, s_s, width, z_lo, z_hi);
+  if constexpr (N2 < NT) {
+    window_f64_rt<N2, NT>(xy, n, h, N2, theta, z, s_w, s_s, width, z_lo, z_hi);
+  } else {
+    constexpr int E = N2 / NT;
+    static_assert(N2 % NT == 0 && NT % 64 == 0, "block must tile the sort");
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    double v[E];
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+      const int g = (wave * E + r) * 64 + lane;
+      v[r] = g < n ? fma(-theta, xy[2 * g], xy[2 * g + 1]) : INFINITY;
+    }
+    if (t == 0) { *s_w = ~0ull; *s_s = INT_MAX; }
+#pragma unroll
+    for (int k = 2; k <= N2; k <<= 1) {
+#pragma unroll
+      for (int j = k >> 1; j > 0; j >>= 1) {
+        if (j < 64) {
+#pragma unroll
+          for (int r = 0; r < E; ++r) {
+            const int g = (wave * E + r) * 64 + lane;
+            const double p = __shfl_xor(v[r], j);
+            const bool up = (g & k) == 0;
+            // pair (a, b) = (lower, upper) index; swap iff (a > b) == up
+            const bool sw = (g & j) == 0 ? ((v[r] > p) == up) : ((p > v[r]) == up);
+            v[r] = sw ? p : v[r];
+          }
+        } else if (j < 64 * E) {
+          const int d = j / 64;
+#pragma unroll
+          for (int r = 0; r < E; ++r) {
+            if ((r & d) == 0) {
+              const int g = (wave * E + r) * 64 + lane;
+              const bool up = (g & k) == 0;
+              const double a = v[r], b = v[r | d];
+              const bool sw = (a > b) == up;
+              v[r] = sw ? b : a;
+              v[r | d] = sw ? a : b;
+            }
+          }
+        } else {
+#pragma unroll
+          for (int r = 0; r < E; ++r) z[(wave * E + r) * 64 + lane] = v[r];
+          __syncthreads();
+#pragma unroll
+          for (int r = 0; r < E; ++r) {
+            const int g = (wave * E + r) * 64 + lane;
+            const double p = z[g ^ j];
+            const bool up = (g & k) == 0;
+            const bool sw = (g & j) == 0 ? ((v[r] > p) == up) : ((p > v[r]) == up);
+            v[r] = sw ? p : v[r];
+          }
+          __syncthreads();
+        }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < E; ++r) z[(wave * E + r) * 64 + lane] = v[r];
+    __syncthreads();
+    window_scan<NT>(z, n, h, s_w, s_s, width, z_lo, z_hi);
+  }
 }
 
 // ---------------------------------------------------------------- slope bins
@@ -118,28 +211,20 @@ __device__ __forceinline__ void window_f64(const double* __restrict__ xy, int n,
 // u = theta / (1 + |theta|); a bin holds U in its low and D in its high 16
 // bits, so one u32 difference array and one prefix sum serve both.
 
-// Bin of slope t: bins are uniform in u = t' / (1 + |t'|), t' = t * sc, with sc
-// the data's x/y aspect ratio so that typical slopes land near |t'| ~ 1. The
-// map is evaluated in FP32 with the hardware reciprocal: its error, below
-// 4e-7 in u, is far below one bin (2 / NB >= 6e-5), so the computed bin is
-// within one of the exact map's bin. t is finite or +-inf here.
+// Bin of slope t: bins are uniform in u = t' / (1 + |t'|), t' = (t - tc) * sc.
+// The centre tc is the slope of the narrowest seed window and sc a magnified
+// x/y aspect ratio: every pair that can pass has a slope near the optimum, so
+// the map spends its resolution there (any monotone map is sound). The map is
+// evaluated in FP32 with the hardware reciprocal: its error, below 4e-7 in u,
+// is far below one bin (2 / NB >= 6e-5), so the computed bin is within one of
+// the exact map's bin. t is finite or +-inf here.
 template <int NB>
-__device__ __forceinline__ int ubin(double t, float sc) {
-  float f = (float)t * sc;
+__device__ __forceinline__ int ubin(double t, double tc, float sc) {
+  float f = (float)(t - tc) * sc;
   f = fminf(fmaxf(f, -1e30f), 1e30f);
   const float u = f * __builtin_amdgcn_rcpf(1.0f + fabsf(f));
-  const int b = (int)floorf((u + 1.0f) * (0.5f * NB));
+  const int b = (int)floorf(fmaf(u, 0.5f * NB, 0.5f * NB));
   return b < 0 ? 0 : (b > NB - 1 ? NB - 1 : b);
-}
-
-// Bins covering [a, b] widened by two on each side (one for the bin map's
-// rounding at the ends, one for that of the partner's slope and its bin); a
-// NaN end (an interval whose rounding bound overflowed) opens that side fully.
-template <int NB>
-__device__ __forceinline__ int2 bin_range(double a, double b, float sc) {
-  const int lo = (a == a) ? ubin<NB>(a, sc) - 2 : 0;
-  const int hi = (b == b) ? ubin<NB>(b, sc) + 2 : NB - 1;
-  return make_int2(lo < 0 ? 0 : lo, hi > NB - 1 ? NB - 1 : hi);
 }
 
 // Prefix sums use one padding word per S = NB / NT bins so that each thread's
@@ -152,41 +237,75 @@ __device__ __forceinline__ int bin_addr(int b) {
 // Adds point (dx, dy)'s two window intervals to the difference array. Ends
 // e = (Dy + c) / Dx, c in {-W, 0, W}, are formed as (Dy + c) * (1 / Dx): one
 // rounding each of Dx, Dy, the sum, the reciprocal and the product give
-// |e - e_exact| <= 2^-50 (|Dy| + |Dy + c|) / |Dx| (about twice the first-order
-// bound), by which each end is widened before its bin is taken. Returns the
-// packed counts of a point with Dx = 0, which is in a window at every slope
-// or at none (lim: W raised past its rounding).
+// |e - e_exact| <= d = 2^-50 (2 |Dy| + W) / |Dx|. The bin coordinate moves by
+// at most (NB / 2) sc per unit of slope, so d shifts it by at most a quarter
+// bin whenever |Dx| >= 2^-47 (2 |Dy| + W) NB sc; the check uses 2^-46. Then
+// the end's rounding, the FP32 bin map (at the ends and at the partner's
+// slope) and the partner slope's rounding together move bin coordinates by
+// less than one bin, so the two-bin margin keeps every exact slope of the
+// interval inside the bins it adds to. A point failing the check, or with
+// Dx = 0 and in a window, is counted in that window at every slope
+// (returned packed: 1 = upper window, 65536 = lower window), which can only
+// raise the bounds. nbsc = 2^-46 NB sc.
 template <int NB, int NT>
 __device__ __forceinline__ unsigned add_point_bins(unsigned* bins, double dx, double dy, double W,
-                                                   double lim, float sc) {
+                                                   double lim, double tc, float sc, double nbsc) {
+  const double adx = fabs(dx), ady = fabs(dy);
   if (dx == 0.0)
     return (dy >= 0.0 && dy <= lim ? 1u : 0u) + (dy <= 0.0 && dy >= -lim ? 65536u : 0u);
+  if (!(adx >= (2.0 * ady + W) * nbsc)) return 1u + 65536u;  // also W = inf
   const double inv = 1.0 / dx;
-  const double ainv = fabs(inv), ady = fabs(dy);
-  const double nm = dy - W, np = dy + W;
-  const double e0 = nm * inv, e1 = dy * inv, e2 = np * inv;
-  const double r0 = 0x1p-50 * ((ady + fabs(nm)) * ainv);
-  const double r1 = 0x1p-50 * ((ady + ady) * ainv);
-  const double r2 = 0x1p-50 * ((ady + fabs(np)) * ainv);
-  int2 bu, bd;
-  if (dx > 0.0) {
-    bu = bin_range<NB>(e0 - r0, e1 + r1, sc);
-    bd = bin_range<NB>(e1 - r1, e2 + r2, sc);
-  } else {
-    bu = bin_range<NB>(e1 - r1, e0 + r0, sc);
-    bd = bin_range<NB>(e2 - r2, e1 + r1, sc);
-  }
-  atomicAdd(&bins[bin_addr<NB, NT>(bu.x)], 1u);
-  if (bu.y + 1 < NB) atomicAdd(&bins[bin_addr<NB, NT>(bu.y + 1)], 0xFFFFFFFFu);
-  atomicAdd(&bins[bin_addr<NB, NT>(bd.x)], 65536u);
-  if (bd.y + 1 < NB) atomicAdd(&bins[bin_addr<NB, NT>(bd.y + 1)], 0xFFFF0000u);
+  const int b0 = ubin<NB>((dy - W) * inv, tc, sc);
+  const int b1 = ubin<NB>(dy * inv, tc, sc);
+  const int b2 = ubin<NB>((dy + W) * inv, tc, sc);
+  // dx > 0: upper window on [e0, e1], lower on [e1, e2]; dx < 0: reversed
+  const int ul = (dx > 0.0 ? b0 : b1) - 2, uh = (dx > 0.0 ? b1 : b0) + 2;
+  const int dl = (dx > 0.0 ? b1 : b2) - 2, dh = (dx > 0.0 ? b2 : b1) + 2;
+  atomicAdd(&bins[bin_addr<NB, NT>(ul < 0 ? 0 : ul)], 1u);
+  if (uh + 1 < NB) atomicAdd(&bins[bin_addr<NB, NT>(uh + 1)], 0xFFFFFFFFu);
+  atomicAdd(&bins[bin_addr<NB, NT>(dl < 0 ? 0 : dl)], 65536u);
+  if (dh + 1 < NB) atomicAdd(&bins[bin_addr<NB, NT>(dh + 1)], 0xFFFF0000u);
   return 0u;
 }
 
-// Aspect scale of the bin map: xh / yh in FP32, kept finite and positive.
+// Scale of the bin map: the x/y aspect ratio times kBinMag, in FP32, kept
+// finite and positive. With the map centred on a slope within a few degrees
+// of the optimum, a magnification of 16 leaves of the order of 1e-5 of the
+// pairs of a 4096-point set above the bound, against 5e-3 unmagnified.
+constexpr double kBinMag = 16.0;
 __device__ __forceinline__ float bin_scale(double xh, double yh) {
-  const double r = yh > 0.0 ? xh / yh : 1.0;
+  const double r = yh > 0.0 ? kBinMag * xh / yh : 1.0;
   return (float)fmin(fmax(r, 1e-30), 1e30);
+}
+
+// Slope of the narrowest of the candidate windows (width, theta, z_lo, z_hi)
+// in a[0..ma) and b[0..mb), by the NT threads of the block (ties by the low
+// bits of the width, then the index); 0 if none is finite. Ends with a
+// barrier.
+template <int NT>
+__device__ __forceinline__ double best_slope(const double4* __restrict__ a, int ma,
+                                             const double4* __restrict__ b, int mb,
+                                             unsigned long long* s_key, double* s_th) {
+  const int t = threadIdx.x;
+  if (t == 0) *s_key = ~0ull;
+  __syncthreads();
+  unsigned long long key = ~0ull;
+  for (int e = t; e < ma + mb; e += NT) {
+    const double w = e < ma ? a[e].x : b[e - ma].x;
+    if (w < INFINITY) {  // finite (NaN compares false)
+      const unsigned long long k = ((unsigned long long)__double_as_longlong(w) & ~0xFFFFFull) |
+                                   (unsigned long long)(e & 0xFFFFF);
+      key = k < key ? k : key;
+    }
+  }
+  atomicMin(s_key, key);
+  __syncthreads();
+  if (t == 0) {
+    const int e = (int)(*s_key & 0xFFFFF);
+    *s_th = *s_key == ~0ull ? 0.0 : (e < ma ? a[e].y : b[e - ma].y);
+  }
+  __syncthreads();
+  return *s_th;
 }
 
 // In-place prefix sum of the NB-bin difference array by the NT threads of the

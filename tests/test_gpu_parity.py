@@ -237,6 +237,31 @@ def test_determinism_and_permutation(gpu):
     assert (p.width, p.theta1, p.z_lo) == (rs[0].width, rs[0].theta1, rs[0].z_lo)
 
 
+def test_graph_replays_match_eager(gpu):
+    """Single solves replayed from a captured hipGraph: several replays with
+    eager work in between, then new values in the same buffer, each equal to
+    an eager solve (bit for bit)."""
+    xy = gen.make("c2", 203)
+    d = dev(xy)
+    out = torch.empty(gpu.RESULT_BYTES, dtype=torch.uint8, device="cuda:0")
+    eager = gpu.solve(d)
+    for k in range(3):
+        gpu.solve_async(d, 0, out, graph=True)
+        torch.cuda.synchronize()
+        g = gpu.parse(out)
+        assert (g.width, g.theta1, g.z_lo, g.z_hi, g.survivors) == \
+               (eager.width, eager.theta1, eager.z_lo, eager.z_hi, eager.survivors), k
+        _ = (d * 2).sum().item()  # unrelated eager work between replays
+    xy2 = xy.copy()
+    xy2[:, 1] = -xy2[:, 1] + 3.0
+    d.copy_(dev(xy2))
+    gpu.solve_async(d, 0, out, graph=True)
+    torch.cuda.synchronize()
+    g = gpu.parse(out)
+    e2 = gpu.solve(dev(xy2))
+    assert (g.width, g.theta1, g.z_lo, g.z_hi) == (e2.width, e2.theta1, e2.z_lo, e2.z_hi)
+
+
 def test_solve_host_matches_device(gpu):
     xy = planted(333, 0.4, 12)
     a = gpu.solve(dev(xy))
