@@ -69,6 +69,8 @@ def parse_args():
                     help="64-point chunks of the screen kept in registers (0 = automatic)")
     ap.add_argument("--bins-log2", type=int, default=0,
                     help="slope bins per anchor, 2^k (0 = automatic, -1 = no slope-bin screen)")
+    ap.add_argument("--seed-pairs", type=int, default=None,
+                    help="random seed pairs of a single solve (default: the library's)")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the seeding comparison")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
@@ -145,7 +147,7 @@ def main():
     d = torch.from_numpy(xy).to(dev)
     out = torch.empty(lms.RESULT_BYTES, dtype=torch.uint8, device=dev)
 
-    kw = dict(tile_regs=args.tile_regs, bins_log2=args.bins_log2)
+    kw = dict(tile_regs=args.tile_regs, bins_log2=args.bins_log2, seed_pairs=args.seed_pairs)
     for _ in range(args.warmup):
         lms.solve_async(d, 0, out, graph=True, **kw)
     torch.cuda.synchronize()
@@ -202,7 +204,7 @@ def main():
             f"outliers" if cfg["kind"] == "planted" else
             f"integer points in [0,1023]^2, n={n}, 30% duplicated x"),
             "n": n, "h": h, "pairs": pairs, "seed": seed, "tile_regs": args.tile_regs,
-            "bins_log2": args.bins_log2},
+            "bins_log2": args.bins_log2, "seed_pairs": args.seed_pairs},
         "solves_per_sec": 1e3 / ms_step,
         "mode": "hipGraph replay of the whole solve",
         "eager_ms_per_step": ms_eager,

@@ -105,7 +105,8 @@ typedef struct lms_options {
                            line puts mostly inliers in its window, so these pairs
                            give a tight bound. Ignored by lms_solve_batched. */
   int32_t bins_log2;    /* lms_solve: slope bins per anchor of the first screen,
-                           2^bins_log2 (11..15; raised to at least n); 0 = automatic
+                           2^bins_log2 plus one per thread of its workgroup
+                           (11..15; raised to at least 2n); 0 = automatic
                            (tuned, else about 2n); -1 = no slope-bin screen (every
                            pair goes through the FP32 test) */
   int32_t reserved;

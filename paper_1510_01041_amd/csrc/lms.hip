@@ -191,8 +191,6 @@ __global__ __launch_bounds__(NT) void k_recheck(const double* __restrict__ xy, C
                                                 double4* __restrict__ res, int begin, int cap,
                                                 int update_bound) {
   __shared__ double z[N2];
-  __shared__ unsigned long long s_w;
-  __shared__ int s_s;
   const Ctx c = *ctx;
   if (c.status < 0) return;
   const unsigned end = min(c.n_entries, (unsigned)cap);
@@ -208,13 +206,107 @@ __global__ __launch_bounds__(NT) void k_recheck(const double* __restrict__ xy, C
       theta = (xy[2 * p.y + 1] - xy[2 * p.x + 1]) / (xr - xl);
     }
     double w, lo, hi;
-    window_f64<N2, NT>(xy, c.n, c.h, theta, z, &s_w, &s_s, &w, &lo, &hi);
+    window_f64<N2, NT>(xy, c.n, c.h, theta, z, &w, &lo, &hi);
     if (threadIdx.x == 0) {
       res[e] = make_double4(w, theta, lo, hi);
       if (update_bound)
         atomicMin(&ctx->wbound,
                   (unsigned long long)__double_as_longlong(width_bound(w, theta, c.xabs, c.yabs)));
     }
+  }
+}
+
+// The same re-evaluation split over several workgroups per entry, for
+// n > kSplitChunk, to cut the latency of a few large sorts: workgroup
+// (p, y) of k_sort_chunks sorts intercepts p C .. p C + C - 1 (+inf past n) of
+// entry begin + y into tmp[y NP + p C ..]; workgroup y of k_merge_window then
+// merges the NP / C sorted runs of entry begin + y and takes its narrowest
+// window. Entries past the slots [begin, begin + slots) are re-evaluated whole
+// by k_merge_window's workgroups in turn. Results equal k_recheck's: the
+// sorted values are the same.
+constexpr int kSplitChunk = 512;
+constexpr int kSplitNT = 256;
+constexpr int kSplitSlots = 512;  // entries per launch pair (tmp: slots x NP doubles)
+constexpr int kFinalSlots = 128;  // split slots of the survivors' re-evaluation
+
+__device__ __forceinline__ bool entry_slope(const double* __restrict__ xy, uint2 p, double* theta) {
+  *theta = 0.0;
+  if (p.x == kDegenerate) return true;
+  const double xl = xy[2 * p.x], xr = xy[2 * p.y];
+  if (xl == xr) return false;
+  *theta = (xy[2 * p.y + 1] - xy[2 * p.x + 1]) / (xr - xl);
+  return true;
+}
+
+template <int C, int NT>
+__global__ __launch_bounds__(NT) void k_sort_chunks(const double* __restrict__ xy,
+                                                    const Ctx* ctx,
+                                                    const uint2* __restrict__ entries, int begin,
+                                                    int cap, double* __restrict__ tmp, int np) {
+  constexpr int E = C / NT;
+  __shared__ double z[C];
+  if (ctx->status < 0) return;
+  const unsigned end = min(ctx->n_entries, (unsigned)cap);
+  const unsigned e = begin + blockIdx.y;
+  if (e >= end) return;
+  double theta;
+  if (!entry_slope(xy, entries[e], &theta)) return;
+  const int n = ctx->n, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int k0 = blockIdx.x * C;
+  double v[E];
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    const int k = k0 + (wave * E + r) * 64 + lane;
+    v[r] = k < n ? fma(-theta, xy[2 * k], xy[2 * k + 1]) : INFINITY;
+  }
+  sort_regs<C, NT>(v, z);
+  double* out = tmp + (size_t)blockIdx.y * np + k0;
+#pragma unroll
+  for (int r = 0; r < E; ++r) out[(wave * E + r) * 64 + lane] = v[r];
+}
+
+template <int NP, int NT>
+__global__ __launch_bounds__(NT) void k_merge_window(const double* __restrict__ xy, Ctx* ctx,
+                                                     const uint2* __restrict__ entries,
+                                                     double4* __restrict__ res, int begin,
+                                                     int cap, int update_bound,
+                                                     const double* __restrict__ tmp, int slots) {
+  __shared__ double z[NP + NP / 16];  // merge_slot layout (NP for whole sorts)
+  const Ctx c = *ctx;
+  if (c.status < 0) return;
+  const unsigned end = min(c.n_entries, (unsigned)cap);
+  const unsigned split_end = min(end, (unsigned)begin + (unsigned)slots);
+  auto finish = [&](unsigned e, double w, double theta, double lo, double hi) {
+    if (threadIdx.x == 0) {
+      res[e] = make_double4(w, theta, lo, hi);
+      if (update_bound)
+        atomicMin(&ctx->wbound,
+                  (unsigned long long)__double_as_longlong(width_bound(w, theta, c.xabs, c.yabs)));
+    }
+  };
+  for (unsigned e = begin + blockIdx.x; e < split_end; e += gridDim.x) {
+    double theta;
+    if (!entry_slope(xy, entries[e], &theta)) {
+      if (threadIdx.x == 0) res[e] = make_double4(INFINITY, NAN, NAN, NAN);
+      continue;
+    }
+    const double* src = tmp + (size_t)(e - begin) * NP;
+    for (int k = threadIdx.x; k < NP; k += NT) z[merge_slot(k)] = src[k];
+    __syncthreads();
+    merge_runs<NP, NT>(z, kSplitChunk);
+    double w, lo, hi;
+    window_scan_at<NT>(z, merge_slot, c.n, c.h, &w, &lo, &hi);
+    finish(e, w, theta, lo, hi);
+  }
+  for (unsigned e = split_end + blockIdx.x; e < end; e += gridDim.x) {
+    double theta;
+    if (!entry_slope(xy, entries[e], &theta)) {
+      if (threadIdx.x == 0) res[e] = make_double4(INFINITY, NAN, NAN, NAN);
+      continue;
+    }
+    double w, lo, hi;
+    window_f64<NP, NT>(xy, c.n, c.h, theta, z, &w, &lo, &hi);
+    finish(e, w, theta, lo, hi);
   }
 }
 
@@ -225,15 +317,13 @@ __global__ __launch_bounds__(NT) void k_eval_slopes(const double* __restrict__ x
                                                     double* __restrict__ out, Ctx* ctx,
                                                     double4* __restrict__ rec) {
   __shared__ double z[N2];
-  __shared__ unsigned long long s_w;
-  __shared__ int s_s;
   if (ctx) {
     if (ctx->status < 0) return;
   }
   for (int e = blockIdx.x; e < m; e += gridDim.x) {
     const double th = theta[e];
     double w, lo, hi;
-    window_f64<N2, NT>(xy, n, h, th, z, &s_w, &s_s, &w, &lo, &hi);
+    window_f64<N2, NT>(xy, n, h, th, z, &w, &lo, &hi);
     if (threadIdx.x == 0) {
       if (out) { out[3 * e] = w; out[3 * e + 1] = lo; out[3 * e + 2] = hi; }
       if (rec) rec[e] = make_double4(w, th, lo, hi);
@@ -433,11 +523,11 @@ __global__ __launch_bounds__(NT, 3) void k_screen(
 // and the optimal pair, with the optimal slab's boundary through both its
 // points (Section 3.3), has U >= h or D >= h for every W >= the optimal width.
 // Per anchor the kernel adds every point's two intervals to a difference
-// array of NB slope bins in LDS (bins uniform in u = theta / (1 + |theta|)),
-// takes its prefix sum, and reads the bounds on U and D of each partner from
+// array of slope bins in LDS (a compact monotone map of the slope, centred
+// on the best seed slope), takes its prefix sum, and reads the bounds on U and D of each partner from
 // the bin of its slope. Each interval is widened by a rigorous bound on its
-// FP64 rounding and by two bins (rounding of the bin map and of the partner's
-// slope), so a bin's count is never below the exact count of any slope in
+// FP64 rounding's effect on the bins and by two bins (rounding of the bin map
+// and of the partner's slope), so a bin's count is never below the exact count of any slope in
 // it. Pairs whose bound reaches h are listed for the FP32 test.
 
 template <int NB, int NT>
@@ -446,28 +536,40 @@ __global__ __launch_bounds__(NT) void k_bins(const double* __restrict__ xy, Ctx*
                                              uint2* __restrict__ entries, int cap,
                                              const double4* __restrict__ seed_res,
                                              const double4* __restrict__ seed_rec, int n_rec) {
-  constexpr int S = NB / NT;  // bins per thread in the prefix sum
-  static_assert(S >= 1 && (NB % NT) == 0, "bins must be a multiple of the block");
-  __shared__ unsigned bins[NB + NB / S];
-  // partner offsets o - 1 that pass; P(i) <= n / 2 <= NB / 2 as NB >= n
+  // NB + NT bins, an odd number per thread in the prefix sum, and one word
+  // for the decrements past the last bin
+  constexpr int NBINS = NB + NT;
+  constexpr int kRLog = __builtin_ctz(NB) - 1;  // the map spans bins [3, NB + 3]
+  static_assert((NB % NT) == 0 && ((NB / NT) & 1) == 0, "bins must be 2^k per thread");
+  // Up to 2^14 bins the insertion also stores each point's query code
+  // (add_point_bins_coded) and the queries only read it; passes are marked
+  // in place and gathered afterwards. Larger bin arrays leave no LDS for the
+  // codes: the queries compute the pair's bin themselves and list the passes.
+  constexpr bool CODED = NB <= 16384;
+  __shared__ unsigned bins[NBINS + 1];
+  // codes of the n <= NB / 2 points, or partner offsets o - 1 that pass
+  // (P(i) <= n / 2 <= LMS_MAX_N / 2)
   __shared__ unsigned short list[NB / 2 < LMS_MAX_N / 2 ? NB / 2 : LMS_MAX_N / 2];
   // passes of the block's anchors so far, written out together (one
   // reservation per flush instead of one per anchor)
   constexpr int PB = 512;
   __shared__ uint2 pbuf[PB];
   __shared__ unsigned s_part[NT / 64];
-  __shared__ unsigned s_all, s_cnt, s_base, s_fill;
-  __shared__ unsigned long long s_key;
-  __shared__ double s_th;
+  __shared__ unsigned s_all, s_cnt, s_base, s_fill, s_pos;
   const Ctx c = *ctx;
   if (c.status != LMS_OK || c.all_x_equal) return;
   const int n = c.n, h = c.h, t = threadIdx.x, lane = t & 63;
   const double W = __longlong_as_double((long long)c.wbound);
   const double lim = W * (1.0 + 0x1p-50);
-  const float sc = bin_scale(c.xh, c.yh);
-  const double tc = best_slope<NT>(seed_res, c.n_seeds, seed_rec, n_rec, &s_key, &s_th);
-  const double nbsc = 0x1p-46 * NB * (double)sc;
+  const BinFrame F = bin_frame(best_slope<NT>(seed_res, c.n_seeds, seed_rec, n_rec),
+                               c.xh, c.yh, W, NBINS);
   const int half = n >> 1;
+  // slopes whose FP32 test bound (affine in |theta|) would pass 1e29 go to the
+  // FP64 entries; half the solved limit covers the roundings
+  const double tau0 = tau_bound(0.0, c.xh, c.yh), tau1 = tau_bound(1.0, c.xh, c.yh) - tau0;
+  const double th_lim = tau0 < 1e29 ? fmin(1e29, 0.5 * (1e29 - tau0) / tau1) : 0.0;
+  const double2* pts = reinterpret_cast<const double2*>(xy);
+  // per-wavefront counts (uniform)
   unsigned long long n_vert = 0, n_scr = 0, n_forced = 0, n_pass = 0;
   // reserves cnt list slots (thread 0; the base goes to s_base)
   auto reserve = [&](unsigned cnt) {
@@ -496,56 +598,89 @@ __global__ __launch_bounds__(NT) void k_bins(const double* __restrict__ xy, Ctx*
     if (t == 0) {
       s_all = 0;
       s_cnt = 0;
+      s_pos = 0;
     }
-    for (int b = t; b < NB + NB / S; b += NT) bins[b] = 0u;
+    for (int b = t; b <= NBINS; b += NT) bins[b] = 0u;
     __syncthreads();
     const double xi = xy[2 * i], yi = xy[2 * i + 1];
     // 1. intervals of every point (packed counts: U in the low, D in the high half)
     unsigned all = 0;
-    for (int k = t; k < n; k += NT)
-      all += add_point_bins<NB, NT>(bins, xy[2 * k] - xi, xy[2 * k + 1] - yi, W, lim, tc, sc,
-                                    nbsc);
+    // the next point's load is issued before this point's work
+    double2 nxt = t < n ? pts[t] : make_double2(0.0, 0.0);
+    for (int k = t; k < n; k += NT) {
+      const double2 cur = nxt;
+      if (k + NT < n) nxt = pts[k + NT];
+      if (CODED)
+        all += add_point_bins_coded<kRLog>(bins, cur.x - xi, cur.y - yi, W, lim, F, th_lim,
+                                           &list[k]);
+      else
+        all += add_point_bins<kRLog>(bins, cur.x - xi, cur.y - yi, W, lim, F);
+    }
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1) all += __shfl_xor(all, m);
     if (lane == 0) atomicAdd(&s_all, all);
     __syncthreads();
     // 2. prefix sum of the difference array
-    scan_bins<NB, NT>(bins, s_part);
+    scan_bins<NBINS, NT>(bins, s_part);
     __syncthreads();
-    // 3. partners: j = (i + o) mod n, o = 1..P(i)
+    // 3. partners: j = (i + o) mod n, o = 1..P(i). A pair's bin comes from
+    //    its offset to the anchor as in add_point_bins; without the far-point
+    //    check its error is still relative (below 2^-44), so it is within one
+    //    of the exact bin. Pairs whose |Dx| is outside the reciprocal's range,
+    //    or whose slope is beyond the FP32 test's, go to the FP64 entries.
     const unsigned pall = s_all;
     const int P = (n & 1) ? half : (i < half ? half : half - 1);
-    for (int o0 = 1; o0 <= P; o0 += NT) {
-      const int o = o0 + t;
-      const bool valid = o <= P;
-      int j = i + (valid ? o : 1);
-      if (j >= n) j -= n;
-      const int lo = min(i, j), hi = max(i, j);
-      const double xl = xy[2 * lo], yl = xy[2 * lo + 1];
-      const double xr = xy[2 * hi], yr = xy[2 * hi + 1];
-      const bool vert = valid && (xl == xr);
-      const double th = (yr - yl) / (xr - xl);
-      const double tau = tau_bound(th, c.xh, c.yh);
-      const bool force = valid && !vert && !(fabs(th) < 1e30 && tau < 1e30);
-      const bool test = valid && !vert && !force;
-      bool pass = false;
-      if (test) {
-        pass = bins_pass(bins[bin_addr<NB, NT>(ubin<NB>(th, tc, sc))], pall, h);
-      }
-      const unsigned long long mv = __ballot(vert), mf = __ballot(force),
-                               mt = __ballot(test), mp = __ballot(pass);
-      if (lane == 0) {
-        n_vert += __popcll(mv);
-        n_forced += __popcll(mf);
-        n_scr += __popcll(mt);
+    auto partner = [&](int o) { return i + o >= n ? i + o - n : i + o; };
+    if (CODED) {
+      for (int o0 = 1; o0 <= P; o0 += NT) {
+        const int o = o0 + t;
+        const bool valid = o <= P;
+        const int j = partner(valid ? o : 1);
+        const unsigned cj = list[j];
+        const bool vert = valid && cj == kCodeVertical;
+        const bool force = valid && cj == kCodeFP64;
+        const bool test = valid && cj > kCodePass;
+        const bool pass = test && bins_pass(bins[cj], pall, h);
+        const unsigned long long mp = lane_mask(pass);
+        n_vert += __popcll(lane_mask(vert));
+        n_forced += __popcll(lane_mask(force));
+        n_scr += __popcll(lane_mask(test));
         n_pass += __popcll(mp);
+        if (force) append_entry(ctx, entries, cap, (unsigned)min(i, j), (unsigned)max(i, j));
+        if (pass) list[j] = kCodePass;
+        if (mp && lane == 0) atomicAdd(&s_cnt, (unsigned)__popcll(mp));
       }
-      if (force) append_entry(ctx, entries, cap, (unsigned)lo, (unsigned)hi);
-      if (mp) {
-        unsigned base = 0;
-        if (lane == 0) base = atomicAdd(&s_cnt, (unsigned)__popcll(mp));
-        base = __shfl(base, 0);
-        if (pass) list[base + __popcll(mp & ((1ull << lane) - 1ull))] = (unsigned short)(o - 1);
+    } else {
+      double2 pn = 1 + t <= P ? pts[partner(1 + t)] : make_double2(0.0, 0.0);
+      for (int o0 = 1; o0 <= P; o0 += NT) {
+        const int o = o0 + t;
+        const bool valid = o <= P;
+        const double2 pj = pn;  // the next partner's load goes out first
+        if (o + NT <= P) pn = pts[partner(o + NT)];
+        const double dx = pj.x - xi, dy = pj.y - yi, adx = fabs(dx);
+        const bool vert = valid && dx == 0.0;
+        const double r = recip(dx);
+        const double th = dy * r;  // within a relative 2^-40 of the pair's slope
+        const bool ok = adx >= 0x1p-900 && adx <= 0x1p900 && fabs(th) < th_lim;
+        const bool force = valid && !vert && !ok;
+        const bool test = valid && !vert && ok;
+        bool pass = false;
+        if (test) pass = bins_pass(bins[slope_bin<kRLog>(dx, dy, r, F)], pall, h);
+        const unsigned long long mp = lane_mask(pass);
+        n_vert += __popcll(lane_mask(vert));
+        n_forced += __popcll(lane_mask(force));
+        n_scr += __popcll(lane_mask(test));
+        n_pass += __popcll(mp);
+        if (force) {
+          const int j = partner(o);
+          append_entry(ctx, entries, cap, (unsigned)min(i, j), (unsigned)max(i, j));
+        }
+        if (mp) {
+          unsigned base = 0;
+          if (lane == 0) base = atomicAdd(&s_cnt, (unsigned)__popcll(mp));
+          base = __shfl(base, 0);
+          if (pass) list[base + __popcll(mp & ((1ull << lane) - 1ull))] = (unsigned short)(o - 1);
+        }
       }
     }
     __syncthreads();
@@ -554,24 +689,40 @@ __global__ __launch_bounds__(NT) void k_bins(const double* __restrict__ xy, Ctx*
     const unsigned cnt = s_cnt;
     if (cnt) {
       if (s_fill + cnt > (unsigned)PB) flush();
-      if (cnt > (unsigned)PB) {
+      const bool direct = cnt > (unsigned)PB;
+      if (direct) {
         if (t == 0) reserve(cnt);
         __syncthreads();
-        const unsigned base = s_base;
-        for (unsigned q = t; q < cnt; q += NT) {
-          int j = i + 1 + (int)list[q];
-          if (j >= n) j -= n;
-          if (base + q < (unsigned)cand_cap) cands[base + q] = make_uint2((unsigned)i, (unsigned)j);
+      }
+      const unsigned base = direct ? s_base : s_fill;
+      auto put = [&](unsigned q, int j) {
+        const uint2 pr = make_uint2((unsigned)i, (unsigned)j);
+        if (!direct) pbuf[base + q] = pr;
+        else if (base + q < (unsigned)cand_cap) cands[base + q] = pr;
+      };
+      if (CODED) {  // gather the marked partners
+        for (int o0 = 1; o0 <= P; o0 += NT) {
+          const int o = o0 + t;
+          const int j = partner(o <= P ? o : 1);
+          const bool m = o <= P && list[j] == kCodePass;
+          const unsigned long long mm = lane_mask(m);
+          if (mm) {
+            unsigned p0 = 0;
+            if (lane == 0) p0 = atomicAdd(&s_pos, (unsigned)__popcll(mm));
+            p0 = __shfl(p0, 0);
+            if (m) put(p0 + (unsigned)__popcll(mm & ((1ull << lane) - 1ull)), j);
+          }
         }
       } else {
-        const unsigned fill = s_fill;
         for (unsigned q = t; q < cnt; q += NT) {
           int j = i + 1 + (int)list[q];
           if (j >= n) j -= n;
-          pbuf[fill + q] = make_uint2((unsigned)i, (unsigned)j);
+          put(q, j);
         }
+      }
+      if (!direct) {
         __syncthreads();
-        if (t == 0) s_fill = fill + cnt;
+        if (t == 0) s_fill = base + cnt;
       }
     }
   }
@@ -797,12 +948,14 @@ __global__ __launch_bounds__(1024) void k_finalize(Ctx* ctx, const uint2* __rest
 // ---------------------------------------------------------------- host side
 
 struct Layout {
-  size_t ctx, xy32, entries, res, rec, cands, total;
+  size_t ctx, xy32, entries, res, rec, cands, sort_tmp, total;
 };
 
 // n_rec: windows of the device seed slopes (kept only for window pairs);
-// cand_cap: list of the slope-bin screen's passes
-Layout layout(int n_pad, long long cap, long long n_rec = 0, long long cand_cap = 0) {
+// cand_cap: list of the slope-bin screen's passes; sort_tmp: doubles of the
+// split FP64 re-evaluation
+Layout layout(int n_pad, long long cap, long long n_rec = 0, long long cand_cap = 0,
+              long long sort_tmp = 0) {
   auto up = [](size_t v) { return (v + 255) & ~size_t(255); };
   Layout L;
   L.ctx = 0;
@@ -811,7 +964,8 @@ Layout layout(int n_pad, long long cap, long long n_rec = 0, long long cand_cap 
   L.res = L.entries + up((size_t)cap * sizeof(uint2));
   L.rec = L.res + up((size_t)cap * sizeof(double4));
   L.cands = L.rec + up((size_t)n_rec * sizeof(double4));
-  L.total = L.cands + up((size_t)cand_cap * sizeof(uint2));
+  L.sort_tmp = L.cands + up((size_t)cand_cap * sizeof(uint2));
+  L.total = L.sort_tmp + up((size_t)sort_tmp * sizeof(double));
   return L;
 }
 
@@ -838,8 +992,38 @@ void launch_recheck_n2(hipStream_t s, int grid, const double* xy, Ctx* ctx, cons
                      upd);
 }
 
+template <int NP>
+void launch_split_np(hipStream_t s, int grid, int slots, const double* xy, Ctx* ctx,
+                     const uint2* e, double4* res, int begin, int cap, int upd, double* tmp) {
+  constexpr int NT = NP >= 2048 ? 1024 : 256;
+  hipLaunchKernelGGL((k_sort_chunks<kSplitChunk, kSplitNT>), dim3(NP / kSplitChunk, slots),
+                     dim3(kSplitNT), 0, s, xy, ctx, e, begin, cap, tmp, NP);
+  hipLaunchKernelGGL((k_merge_window<NP, NT>), dim3(grid), dim3(NT), 0, s, xy, ctx, e, res, begin,
+                     cap, upd, tmp, slots);
+}
+
+// Number of entries that one split launch pair sorts in pieces (0: whole-sort
+// path, for n <= kSplitChunk).
+int split_slots(int n, int expected) {
+  if (next_pow2(n) <= kSplitChunk) return 0;
+  return std::max(1, std::min(expected, kSplitSlots));
+}
+
+// Re-evaluation of entries [begin, min(n_entries, cap)) in FP64; `expected`
+// is how many there usually are (the split path's slots), tmp holds
+// split_slots(n, expected) x next_pow2(n) doubles.
 void launch_recheck(hipStream_t s, int n, int grid, const double* xy, Ctx* ctx, const uint2* e,
-                    double4* res, int begin, int cap, int upd) {
+                    double4* res, int begin, int cap, int upd, double* tmp, int expected) {
+  const int slots = tmp ? split_slots(n, expected) : 0;
+  if (slots > 0) {
+    switch (next_pow2(n)) {
+      case 1024: launch_split_np<1024>(s, grid, slots, xy, ctx, e, res, begin, cap, upd, tmp); return;
+      case 2048: launch_split_np<2048>(s, grid, slots, xy, ctx, e, res, begin, cap, upd, tmp); return;
+      case 4096: launch_split_np<4096>(s, grid, slots, xy, ctx, e, res, begin, cap, upd, tmp); return;
+      case 8192: launch_split_np<8192>(s, grid, slots, xy, ctx, e, res, begin, cap, upd, tmp); return;
+      default: launch_split_np<16384>(s, grid, slots, xy, ctx, e, res, begin, cap, upd, tmp); return;
+    }
+  }
   switch (next_pow2(n)) {
     case 64: launch_recheck_n2<64>(s, grid, xy, ctx, e, res, begin, cap, upd); break;
     case 128: launch_recheck_n2<128>(s, grid, xy, ctx, e, res, begin, cap, upd); break;
@@ -1076,6 +1260,12 @@ hipError_t launch_list(hipStream_t s, int R, bool L, int cu, const double* xy, c
 }
 
 // Default slope bins per anchor: about 2n, at least 2^11, at most 2^15.
+// Bins per anchor for 2^nb_log2 nominal ones: one more per thread of k_bins.
+unsigned bins_count(int nb_log2) {
+  const int nb = 1 << nb_log2;
+  return (unsigned)(nb + (nb >= 32768 ? 1024 : (nb >= 16384 ? 512 : 256)));
+}
+
 int default_bins_log2(int n) {
   int b = 11;
   while (b < 15 && (1 << b) < 2 * n) ++b;
@@ -1118,6 +1308,7 @@ struct Setup {
   lms_result* out = nullptr;
   unsigned flags = 0;
   int seeds = 0, window_pairs = 0, bins_log2 = 0, G = 1, ipa = 1;
+  int seed_slots = 0, final_slots = 0;
   bool no_prune = false, use_bins = false;
   const double* seed_theta = nullptr;
   int64_t n_seed_theta = 0;
@@ -1176,7 +1367,7 @@ lms_status make_setup(const double* d_xy, int64_t n, int64_t h, lms_result* d_ou
   const bool use_bins = bins_log2 != -1;
   if (use_bins) {
     if (bins_log2 == 0) bins_log2 = default_bins_log2(p.n);
-    while (bins_log2 < 15 && (1 << bins_log2) < p.n) ++bins_log2;
+    while (bins_log2 < 15 && (1 << bins_log2) < 2 * p.n) ++bins_log2;
   }
   const int Pmax = p.n / 2;
   const int batches = (Pmax + 63) / 64;
@@ -1195,7 +1386,12 @@ lms_status make_setup(const double* d_xy, int64_t n, int64_t h, lms_result* d_ou
   S->n_seed_theta = n_seed_theta;
   S->pairs = pairs;
   S->cand_cap = use_bins ? screen_cap : 0;
-  S->L = layout(p.n_pad, p.cap, n_seed_theta, S->cand_cap);
+  // split re-evaluation slots: the seed entries of the first round, and the
+  // usual number of survivors
+  S->seed_slots = split_slots(p.n, 1 + seeds + window_pairs);
+  S->final_slots = split_slots(p.n, kFinalSlots);
+  const long long tmp = (long long)std::max(S->seed_slots, S->final_slots) * next_pow2(p.n);
+  S->L = layout(p.n_pad, p.cap, n_seed_theta, S->cand_cap, tmp);
   return LMS_OK;
 }
 
@@ -1215,7 +1411,7 @@ lms_status enqueue_solve(const Setup& S, char* base, hipStream_t s, lms_host::St
   auto mark = [&]() { if (prof) prof->mark(); };
   const unsigned long long key = 0x5EEDull + (unsigned long long)p.n * 0x100000001ull;
   hipLaunchKernelGGL(k_prep, dim3(1), dim3(1024), 0, s, d_xy, p.n, p.h, p.n_pad, ctx, xy32,
-                     entries, p.n_seeds, seeds, key, S.use_bins ? 1u << S.bins_log2 : 0u);
+                     entries, p.n_seeds, seeds, key, S.use_bins ? bins_count(S.bins_log2) : 0u);
   mark();
   // Seeds: exact FP64 widths of a few slopes set the screen's bound: the
   // device seed slopes, the extreme-x and random pairs, and with window pairs
@@ -1229,14 +1425,15 @@ lms_status enqueue_solve(const Setup& S, char* base, hipStream_t s, lms_host::St
   if (window_pairs)
     hipLaunchKernelGGL(k_window_pairs, dim3(1), dim3(kWinNT), 0, s, d_xy, ctx, rec,
                        (int)n_seed_theta, entries, first_w, window_pairs, key ^ 0xA1ull);
+  double* tmp = (double*)(base + L.sort_tmp);
   launch_recheck(s, p.n, std::min(first_w + window_pairs, 4 * cu), d_xy, ctx, entries, res, 0,
-                 first_w + window_pairs, S.no_prune ? 0 : 1);
+                 first_w + window_pairs, S.no_prune ? 0 : 1, tmp, S.seed_slots);
   if (window_pairs) {
     // second round: from the narrowest window of the first round's pairs
     hipLaunchKernelGGL(k_window_pairs, dim3(1), dim3(kWinNT), 0, s, d_xy, ctx, res + first_w,
                        window_pairs, entries, first_w + window_pairs, window_pairs, key ^ 0xA2ull);
     launch_recheck(s, p.n, std::min(window_pairs, 4 * cu), d_xy, ctx, entries, res,
-                   first_w + window_pairs, p.n_seeds, 1);
+                   first_w + window_pairs, p.n_seeds, 1, tmp, S.seed_slots);
   }
   mark();
   // Screen. With slope bins: per-anchor bin counts, then the FP32 test of the
@@ -1263,7 +1460,8 @@ lms_status enqueue_solve(const Setup& S, char* base, hipStream_t s, lms_host::St
   if (err != hipSuccess)
     return fail(LMS_ERR_DEVICE, std::string("screen launch: ") + hipGetErrorString(err));
   mark();
-  launch_recheck(s, p.n, 4 * cu, d_xy, ctx, entries, res, p.n_seeds, (int)p.cap, 0);
+  launch_recheck(s, p.n, 4 * cu, d_xy, ctx, entries, res, p.n_seeds, (int)p.cap, 0, tmp,
+                 S.final_slots);
   mark();
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, s, ctx, entries, res, (int)p.cap, S.out);
   mark();

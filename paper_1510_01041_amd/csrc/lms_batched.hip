@@ -205,8 +205,6 @@ __global__ __launch_bounds__(NT) void k_bwindow(const double* __restrict__ xy, P
                                                 int update_bound,
                                                 const unsigned* __restrict__ reps) {
   __shared__ double z[NMAX];
-  __shared__ unsigned long long s_w;
-  __shared__ int s_s;
   // entries [begin, fixed_end), or the listed representatives
   const unsigned end = reps ? min(state->n_reps, (unsigned)cap)
                             : fixed_end >= 0 ? (unsigned)fixed_end
@@ -232,7 +230,7 @@ __global__ __launch_bounds__(NT) void k_bwindow(const double* __restrict__ xy, P
     int n2 = 64;
     while (n2 < m.n) n2 <<= 1;
     double w, lo, hi;
-    window_f64_rt<NMAX, NT>(xy + 2 * m.off, m.n, m.h, n2, theta, z, &s_w, &s_s, &w, &lo, &hi);
+    window_f64_rt<NMAX, NT>(xy + 2 * m.off, m.n, m.h, n2, theta, z, &w, &lo, &hi);
     if (threadIdx.x == 0) {
       res[e] = make_double4(w, theta, lo, hi);
       if (w == w) atomicMin(&meta[en.x].best_w, (unsigned long long)__double_as_longlong(w));
@@ -389,9 +387,12 @@ __global__ __launch_bounds__(NT) void k_bbins(const double* __restrict__ xy, PMe
                                               uint2* __restrict__ cands, int cand_cap,
                                               uint2* __restrict__ entries, int cap, BState* state,
                                               int cls) {
-  constexpr int S = NB / NT;
-  static_assert(S >= 1 && (NB % NT) == 0, "bins must be a multiple of the block");
-  __shared__ unsigned bins[NB + NT];
+  // NB + NT bins, an odd number per thread in the prefix sum, and one word
+  // for the decrements past the last bin
+  constexpr int NBINS = NB + NT;
+  constexpr int kRLog = __builtin_ctz(NB) - 1;  // the map spans bins [3, NB + 3]
+  static_assert((NB % NT) == 0 && ((NB / NT) & 1) == 0, "bins must be 2^k per thread");
+  __shared__ unsigned bins[NBINS + 1];
   __shared__ unsigned short list[NB / 2];  // partner offsets o - 1 (P <= n / 2 <= NB / 2)
   __shared__ unsigned s_part[NT / 64 > 0 ? NT / 64 : 1];
   __shared__ unsigned s_all, s_cnt, s_next, s_end;
@@ -403,7 +404,7 @@ __global__ __launch_bounds__(NT) void k_bbins(const double* __restrict__ xy, PMe
       s_all = 0;
       s_cnt = 0;
     }
-    for (int b = t; b < NB + NT; b += NT) bins[b] = 0u;
+    for (int b = t; b <= NBINS; b += NT) bins[b] = 0u;
     __syncthreads();
     const uint2 it = items[item];
     const int b = __builtin_amdgcn_readfirstlane((int)it.x);
@@ -415,40 +416,49 @@ __global__ __launch_bounds__(NT) void k_bbins(const double* __restrict__ xy, PMe
     const double* gxy = xy + 2 * m.off;
     const double W = __longlong_as_double((long long)m.wbound);
     const double lim = W * (1.0 + 0x1p-50);
-    const float sc = bin_scale(m.xh, m.yh);
-    const double tc = m.center;
-    const double nbsc = 0x1p-46 * NB * (double)sc;
+    const BinFrame F = bin_frame(m.center, m.xh, m.yh, W, NBINS);
     const double xi = gxy[2 * i], yi = gxy[2 * i + 1];
+    const double2* pts = reinterpret_cast<const double2*>(gxy);
     unsigned all = 0;
-    for (int k = t; k < n; k += NT)
-      all += add_point_bins<NB, NT>(bins, gxy[2 * k] - xi, gxy[2 * k + 1] - yi, W, lim, tc, sc,
-                                    nbsc);
+    // the next point's load is issued before this point's work
+    double2 nxt = t < n ? pts[t] : make_double2(0.0, 0.0);
+    for (int k = t; k < n; k += NT) {
+      const double2 cur = nxt;
+      if (k + NT < n) nxt = pts[k + NT];
+      all += add_point_bins<kRLog>(bins, cur.x - xi, cur.y - yi, W, lim, F);
+    }
 #pragma unroll
     for (int q = 32; q >= 1; q >>= 1) all += __shfl_xor(all, q);
     if (lane == 0) atomicAdd(&s_all, all);
     __syncthreads();
-    scan_bins<NB, NT>(bins, s_part);
+    scan_bins<NBINS, NT>(bins, s_part);
     __syncthreads();
     const unsigned pall = s_all;
     const int half = n >> 1;
     const int P = (n & 1) ? half : (i < half ? half : half - 1);
-    unsigned long long n_vert = 0, n_forced = 0, n_pass = 0;
+    unsigned long long n_vert = 0, n_forced = 0, n_pass = 0;  // per wavefront (uniform)
+    const double tau0 = tau_bound(0.0, m.xh, m.yh), tau1 = tau_bound(1.0, m.xh, m.yh) - tau0;
+    const double th_lim = tau0 < 1e29 ? fmin(1e29, 0.5 * (1e29 - tau0) / tau1) : 0.0;
+    auto partner = [&](int o) { return i + o >= n ? i + o - n : i + o; };
+    double2 pn = 1 + t <= P ? pts[partner(1 + t)] : make_double2(0.0, 0.0);
     for (int o0 = 1; o0 <= P; o0 += NT) {
       const int o = o0 + t;
       const bool valid = o <= P;
-      int j = i + (valid ? o : 1);
-      if (j >= n) j -= n;
+      const int j = partner(valid ? o : 1);
       const int lo = min(i, j), hi = max(i, j);
-      const double xl = gxy[2 * lo], yl = gxy[2 * lo + 1];
-      const double xr = gxy[2 * hi], yr = gxy[2 * hi + 1];
-      const bool vert = valid && (xl == xr);
-      const double th = (yr - yl) / (xr - xl);
-      const double tau = tau_bound(th, m.xh, m.yh);
-      const bool force = valid && !vert && !(fabs(th) < 1e30 && tau < 1e30);
-      const bool test = valid && !vert && !force;
-      const bool pass = test && bins_pass(bins[bin_addr<NB, NT>(ubin<NB>(th, tc, sc))], pall, h);
-      const unsigned long long mv = __ballot(vert), mf = __ballot(force), mp = __ballot(pass);
-      n_vert += __popcll(mv);
+      // the pair's bin and FP64 hand-off as in k_bins
+      const double2 pj = pn;  // the next partner's load goes out first
+      if (o + NT <= P) pn = pts[partner(o + NT)];
+      const double dx = pj.x - xi, dy = pj.y - yi, adx = fabs(dx);
+      const bool vert = valid && dx == 0.0;
+      const double r = recip(dx);
+      const double th = dy * r;
+      const bool ok = adx >= 0x1p-900 && adx <= 0x1p900 && fabs(th) < th_lim;
+      const bool force = valid && !vert && !ok;
+      const bool test = valid && !vert && ok;
+      const bool pass = test && bins_pass(bins[slope_bin<kRLog>(dx, dy, r, F)], pall, h);
+      const unsigned long long mf = __ballot(force), mp = __ballot(pass);
+      n_vert += __popcll(__ballot(vert));
       n_forced += __popcll(mf);
       n_pass += __popcll(mp);
       if (mf) {
@@ -800,7 +810,7 @@ __global__ __launch_bounds__(256) void k_bfinal(const PMeta* __restrict__ meta, 
   o.dir_evals = m.dir_evals;
   o.band_pass = m.band_pass;
   o.bin_pass = m.bin_pass;
-  o.bins = bins ? (m.R <= kClassChunks[1] ? 4096u : 8192u) : 0u;  // the class's bins
+  o.bins = bins ? (m.R <= kClassChunks[1] ? 4096u : 8192u) + 256u : 0u;  // the class's bins
   out[b] = o;
 }
 

@@ -44,6 +44,12 @@ __device__ __forceinline__ double tau_bound(double theta, double xh, double yh) 
   return 0x1p-24 * (6.25 * yh + 8.25 * fabs(theta) * xh);
 }
 
+// Lanes of the wavefront (among the active ones) whose predicate holds: the
+// compare mask itself, without materialising the predicate as an integer.
+__device__ __forceinline__ unsigned long long lane_mask(bool p) {
+  return __builtin_amdgcn_ballot_w64(p);
+}
+
 // Order-preserving map of a non-NaN double to u64 (for atomicMin keys).
 __device__ __forceinline__ unsigned long long order_key(double v) {
   const unsigned long long b = (unsigned long long)__double_as_longlong(v);
@@ -52,18 +58,72 @@ __device__ __forceinline__ unsigned long long order_key(double v) {
 
 // ---------------------------------------------------------------- FP64 window
 
+// Lexicographic minimum of the (w, s) pairs of the NT threads of the block,
+// w compared as doubles (equal widths, signed zeros included, go to the lower
+// s); every thread gets it. A thread without a candidate holds (+inf,
+// INT_MAX), and NaN never wins. Wavefront shuffles, then one LDS slot per
+// wavefront: no contended atomics. Ends with a barrier.
+template <int NT>
+__device__ __forceinline__ void block_argmin(double& w, int& s) {
+  __shared__ double red_w[NT / 64];
+  __shared__ int red_s[NT / 64];
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    const double ow = __shfl_xor(w, m);
+    const int os = __shfl_xor(s, m);
+    if (ow < w || (ow == w && os < s)) { w = ow; s = os; }
+  }
+  if (NT > 64) {
+    if ((threadIdx.x & 63) == 0) { red_w[threadIdx.x >> 6] = w; red_s[threadIdx.x >> 6] = s; }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NT / 64; ++k) {
+      const double ow = red_w[k];
+      const int os = red_s[k];
+      if (ow < w || (ow == w && os < s)) { w = ow; s = os; }
+    }
+  }
+  __syncthreads();
+}
+
+// Narrowest window and its ends from the sorted values z[at(0..n)], by the
+// whole block (`at` maps a rank to its LDS slot): the smallest z_{s+h-1} - z_s,
+// the lowest s among equally narrow windows. No window compares below +inf
+// only if the slope or the data overflow to NaN; then the width is NaN and
+// window 0, which always exists, is read. Ends with a barrier.
+template <int NT, class At>
+__device__ __forceinline__ void window_scan_at(const double* z, At at, int n, int h,
+                                               double* width, double* z_lo, double* z_hi) {
+  double bw = INFINITY;
+  int bs = INT_MAX;
+  for (int s = threadIdx.x; s + h <= n; s += NT) {
+    const double w = z[at(s + h - 1)] - z[at(s)];
+    if (w < bw) { bw = w; bs = s; }
+  }
+  block_argmin<NT>(bw, bs);
+  const int s = bs == INT_MAX ? 0 : bs;
+  *width = bs == INT_MAX ? NAN : bw;
+  *z_lo = z[at(s)];
+  *z_hi = z[at(s + h - 1)];
+  __syncthreads();
+}
+
+template <int NT>
+__device__ __forceinline__ void window_scan(const double* z, int n, int h, double* width,
+                                            double* z_lo, double* z_hi) {
+  window_scan_at<NT>(z, [](int k) { return k; }, n, h, width, z_lo, z_hi);
+}
+
 // Narrowest window of h consecutive values of z_k = fma(-theta, x_k, y_k),
 // k < n, computed by the whole block; z is an LDS array of N2 >= n doubles.
 // Same operation sequence as the reference: fma, full sort, subtraction, and
 // the lowest window among equally narrow ones.
 template <int NMAX, int NT>
 __device__ void window_f64_rt(const double* __restrict__ xy, int n, int h, int n2, double theta,
-                              double* z, unsigned long long* s_w, int* s_s, double* width,
-                              double* z_lo, double* z_hi) {
+                              double* z, double* width, double* z_lo, double* z_hi) {
   const int t = threadIdx.x;
   for (int k = t; k < n2; k += NT)
     z[k] = (k < n) ? fma(-theta, xy[2 * k], xy[2 * k + 1]) : INFINITY;
-  if (t == 0) { *s_w = ~0ull; *s_s = INT_MAX; }
   __syncthreads();
   for (int k = 2; k <= n2; k <<= 1) {
     for (int j = k >> 1; j > 0; j >>= 1) {
@@ -77,127 +137,136 @@ __device__ void window_f64_rt(const double* __restrict__ xy, int n, int h, int n
       __syncthreads();
     }
   }
-  double bw = INFINITY;
-  int bs = INT_MAX;
-  for (int s = t; s + h <= n; s += NT) {
-    const double w = z[s + h - 1] - z[s];
-    if (w < bw) { bw = w; bs = s; }
-  }
-  const unsigned long long bwb = (unsigned long long)__double_as_longlong(bw);
-  atomicMin(s_w, bwb);
-  __syncthreads();
-  if (bs != INT_MAX && bwb == *s_w) atomicMin(s_s, bs);
-  __syncthreads();
-  // No window compares below +inf only if the slope or the data overflow to
-  // NaN; report NaN and read window 0, which always exists.
-  const int s = (*s_s == INT_MAX) ? 0 : *s_s;
-  *width = (*s_s == INT_MAX) ? NAN : __longlong_as_double((long long)*s_w);
-  *z_lo = z[s];
-  *z_hi = z[s + h - 1];
-  __syncthreads();
+  window_scan<NT>(z, n, h, width, z_lo, z_hi);
 }
 
-// Narrowest window and its ends from z[0..N2), sorted, by the whole block
-// (the scan of window_f64_rt).
-template <int NT>
-__device__ __forceinline__ void window_scan(const double* z, int n, int h, unsigned long long* s_w,
-                                            int* s_s, double* width, double* z_lo,
-                                            double* z_hi) {
-  const int t = threadIdx.x;
-  double bw = INFINITY;
-  int bs = INT_MAX;
-  for (int s = t; s + h <= n; s += NT) {
-    const double w = z[s + h - 1] - z[s];
-    if (w < bw) { bw = w; bs = s; }
+// Bitonic sort of N2 values held by the NT threads of the block: value
+// g = (wave * E + r) * 64 + lane (E = N2 / NT) sits in v[r] of that lane. A
+// stage with partner distance j < 64 exchanges across lanes (wavefront
+// shuffles), one with 64 <= j < 64 E within a thread, and one with j >= 64 E
+// through z (N2 doubles of LDS, two barriers). It is the same network with the
+// same compare-and-swap rule as window_f64_rt's LDS sort, so the sorted
+// sequence is identical (also for NaN and signed zeros).
+template <int N2, int NT>
+__device__ __forceinline__ void sort_regs(double (&v)[N2 / NT], double* z) {
+  constexpr int E = N2 / NT;
+  static_assert(N2 % NT == 0 && NT % 64 == 0, "block must tile the sort");
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+#pragma unroll
+  for (int k = 2; k <= N2; k <<= 1) {
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      if (j < 64) {
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+          const int g = (wave * E + r) * 64 + lane;
+          const double p = __shfl_xor(v[r], j);
+          const bool up = (g & k) == 0;
+          // pair (a, b) = (lower, upper) index; swap iff (a > b) == up
+          const bool sw = (g & j) == 0 ? ((v[r] > p) == up) : ((p > v[r]) == up);
+          v[r] = sw ? p : v[r];
+        }
+      } else if (j < 64 * E) {
+        const int d = j / 64;
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+          if ((r & d) == 0) {
+            const int g = (wave * E + r) * 64 + lane;
+            const bool up = (g & k) == 0;
+            const double a = v[r], b = v[r | d];
+            const bool sw = (a > b) == up;
+            v[r] = sw ? b : a;
+            v[r | d] = sw ? a : b;
+          }
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < E; ++r) z[(wave * E + r) * 64 + lane] = v[r];
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+          const int g = (wave * E + r) * 64 + lane;
+          const double p = z[g ^ j];
+          const bool up = (g & k) == 0;
+          const bool sw = (g & j) == 0 ? ((v[r] > p) == up) : ((p > v[r]) == up);
+          v[r] = sw ? p : v[r];
+        }
+        __syncthreads();
+      }
+    }
   }
-  const unsigned long long bwb = (unsigned long long)__double_as_longlong(bw);
-  atomicMin(s_w, bwb);
-  __syncthreads();
-  if (bs != INT_MAX && bwb == *s_w) atomicMin(s_s, bs);
-  __syncthreads();
-  const int s = (*s_s == INT_MAX) ? 0 : *s_s;
-  *width = (*s_s == INT_MAX) ? NAN : __longlong_as_double((long long)*s_w);
-  *z_lo = z[s];
-  *z_hi = z[s + h - 1];
-  __syncthreads();
 }
 
 // Narrowest window of h consecutive values of z_k = fma(-theta, x_k, y_k),
 // k < n, computed by the whole block; z is an LDS array of N2 >= n doubles.
 // Same operation sequence as the reference: fma, full sort, subtraction, and
-// the lowest window among equally narrow ones.
-//
-// With N2 >= NT the sort runs in registers: value g = (wave * E + r) * 64 +
-// lane (E = N2 / NT) sits in register r of that lane. A bitonic stage with
-// partner distance j < 64 exchanges across lanes (wavefront shuffles), one
-// with 64 <= j < 64 E within a thread, and one with j >= 64 E through LDS
-// (two barriers). It is the same network with the same compare-and-swap rule
-// as window_f64_rt's LDS sort, so the sorted sequence is identical (also for
-// NaN and signed zeros).
+// the lowest window among equally narrow ones. With N2 >= NT the values are
+// sorted in registers (sort_regs).
 template <int N2, int NT>
 __device__ __forceinline__ void window_f64(const double* __restrict__ xy, int n, int h,
-                                           double theta, double* z, unsigned long long* s_w,
-                                           int* s_s, double* width, double* z_lo, double* z_hi) {
+                                           double theta, double* z, double* width, double* z_lo,
+                                           double* z_hi) {
   if constexpr (N2 < NT) {
-    window_f64_rt<N2, NT>(xy, n, h, N2, theta, z, s_w, s_s, width, z_lo, z_hi);
+    window_f64_rt<N2, NT>(xy, n, h, N2, theta, z, width, z_lo, z_hi);
   } else {
     constexpr int E = N2 / NT;
-    static_assert(N2 % NT == 0 && NT % 64 == 0, "block must tile the sort");
-    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     double v[E];
 #pragma unroll
     for (int r = 0; r < E; ++r) {
       const int g = (wave * E + r) * 64 + lane;
       v[r] = g < n ? fma(-theta, xy[2 * g], xy[2 * g + 1]) : INFINITY;
     }
-    if (t == 0) { *s_w = ~0ull; *s_s = INT_MAX; }
-#pragma unroll
-    for (int k = 2; k <= N2; k <<= 1) {
-#pragma unroll
-      for (int j = k >> 1; j > 0; j >>= 1) {
-        if (j < 64) {
-#pragma unroll
-          for (int r = 0; r < E; ++r) {
-            const int g = (wave * E + r) * 64 + lane;
-            const double p = __shfl_xor(v[r], j);
-            const bool up = (g & k) == 0;
-            // pair (a, b) = (lower, upper) index; swap iff (a > b) == up
-            const bool sw = (g & j) == 0 ? ((v[r] > p) == up) : ((p > v[r]) == up);
-            v[r] = sw ? p : v[r];
-          }
-        } else if (j < 64 * E) {
-          const int d = j / 64;
-#pragma unroll
-          for (int r = 0; r < E; ++r) {
-            if ((r & d) == 0) {
-              const int g = (wave * E + r) * 64 + lane;
-              const bool up = (g & k) == 0;
-              const double a = v[r], b = v[r | d];
-              const bool sw = (a > b) == up;
-              v[r] = sw ? b : a;
-              v[r | d] = sw ? a : b;
-            }
-          }
-        } else {
-#pragma unroll
-          for (int r = 0; r < E; ++r) z[(wave * E + r) * 64 + lane] = v[r];
-          __syncthreads();
-#pragma unroll
-          for (int r = 0; r < E; ++r) {
-            const int g = (wave * E + r) * 64 + lane;
-            const double p = z[g ^ j];
-            const bool up = (g & k) == 0;
-            const bool sw = (g & j) == 0 ? ((v[r] > p) == up) : ((p > v[r]) == up);
-            v[r] = sw ? p : v[r];
-          }
-          __syncthreads();
-        }
-      }
-    }
+    sort_regs<N2, NT>(v, z);
 #pragma unroll
     for (int r = 0; r < E; ++r) z[(wave * E + r) * 64 + lane] = v[r];
     __syncthreads();
-    window_scan<NT>(z, n, h, s_w, s_s, width, z_lo, z_hi);
+    window_scan<NT>(z, n, h, width, z_lo, z_hi);
+  }
+}
+
+// LDS slot of rank k in merge_runs' layout: one pad word every 16 values, so
+// that the lanes of a wavefront, whose merge positions lie about E / 2 apart,
+// fall in different banks.
+__device__ __forceinline__ int merge_slot(int k) { return k + (k >> 4); }
+
+// z holds NP values in merge_slot layout (NP + NP / 16 doubles), as sorted runs
+// of length L (a power of two dividing NP); merges them pairwise, stably (on
+// ties the lower run first), until they are sorted. In each round thread t
+// writes the E = NP / NT outputs from rank t E on: a binary search on the
+// merge path finds how many of the outputs before it come from the lower run,
+// then E merge steps follow. The sorted values equal those of any other sort
+// of the same data, up to the order of values that compare equal (signed
+// zeros) or unordered (NaN). Each round ends with a barrier.
+template <int NP, int NT>
+__device__ __forceinline__ void merge_runs(double* z, int L) {
+  constexpr int E = NP / NT;
+  static_assert(NP % NT == 0, "block must tile the merge");
+  const int o = threadIdx.x * E;
+  for (; L < NP; L <<= 1) {
+    const int a0 = o & ~(2 * L - 1), b0 = a0 + L;  // ranks of the two runs
+    const int d = o - a0;  // outputs of this pair of runs before o
+    // smallest i whose A[i] comes after B[d - 1 - i]: all reads in [0, L)
+    int lo = d > L ? d - L : 0, hi = d < L ? d : L;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (z[merge_slot(a0 + mid)] <= z[merge_slot(b0 + d - 1 - mid)]) lo = mid + 1; else hi = mid;
+    }
+    int ia = lo, ib = d - lo;
+    double out[E];
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+      const double a = z[merge_slot(a0 + (ia < L ? ia : L - 1))];
+      const double b = z[merge_slot(b0 + (ib < L ? ib : L - 1))];
+      const bool ta = ib >= L || (ia < L && a <= b);
+      out[r] = ta ? a : b;
+      ia += ta ? 1 : 0;
+      ib += ta ? 0 : 1;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < E; ++r) z[merge_slot(o + r)] = out[r];
+    __syncthreads();
   }
 }
 
@@ -207,119 +276,167 @@ __device__ __forceinline__ void window_f64(const double* __restrict__ xy, int n,
 // residual d_k(theta) = Dy - theta Dx lies in the upper window [0, W] for theta
 // in one closed interval and in the lower window [-W, 0] for theta in the
 // adjacent one; both end at the slope of (i, k). Counted over k at a partner's
-// slope, they give the pair's window counts U and D. Bins are uniform in
-// u = theta / (1 + |theta|); a bin holds U in its low and D in its high 16
-// bits, so one u32 difference array and one prefix sum serve both.
+// slope, they give the pair's window counts U and D. Bins cover the slopes
+// through a compact monotone map (fbin); a bin holds U in its low and D in its
+// high 16 bits, so one u32 difference array and one prefix sum serve both.
 
-// Bin of slope t: bins are uniform in u = t' / (1 + |t'|), t' = (t - tc) * sc.
-// The centre tc is the slope of the narrowest seed window and sc a magnified
-// x/y aspect ratio: every pair that can pass has a slope near the optimum, so
-// the map spends its resolution there (any monotone map is sound). The map is
-// evaluated in FP32 with the hardware reciprocal: its error, below 4e-7 in u,
-// is far below one bin (2 / NB >= 6e-5), so the computed bin is within one of
-// the exact map's bin. t is finite or +-inf here.
-template <int NB>
-__device__ __forceinline__ int ubin(double t, double tc, float sc) {
-  float f = (float)(t - tc) * sc;
-  f = fminf(fmaxf(f, -1e30f), 1e30f);
-  const float u = f * __builtin_amdgcn_rcpf(1.0f + fabsf(f));
-  const int b = (int)floorf(fmaf(u, 0.5f * NB, 0.5f * NB));
-  return b < 0 ? 0 : (b > NB - 1 ? NB - 1 : b);
+// Bin of f, a slope's offset from the map's centre in units of 1 / sc. The
+// bins are uniform in u(f) = sign(f) (1 - r(|f| + 1)) over [-1, 1], where
+// r(g) is the reciprocal of g read off its bit pattern (the high word of the
+// FP64 g subtracted, as one saturating integer, from that of 2^1023; adding
+// RLOG to the exponent gives R r(g), R = 2^RLOG, in the same step): exact at
+// powers of two, within 12.5 % of 1 / g between them, piecewise linear,
+// decreasing, and 0 from g = 2^1023 on (also for +inf and NaN). So u is
+// monotone with |du/df| <= 1/2 and |f du/df| <= 1 and, like f / (1 + |f|),
+// spends half of the bins on |f| < 1, where the optimum's neighbours are. The
+// bin coordinate R + 3 + R u spans [3, 2R + 3], so the two-bin margins stay
+// inside [0, 2R + 6] with no clamp. Each step is monotone; dropping the low
+// word of g (relative 2^-20) and the roundings move the coordinate by less
+// than 2^-4 for R <= 2^15.
+template <int RLOG>
+__device__ __forceinline__ int fbin(double f) {
+  constexpr double R = (double)(1 << RLOG), C = R + 3.0;
+  const double g = fabs(f) + 1.0;
+  const unsigned hi = __builtin_elementwise_sub_sat(
+      0x7FE00000u + ((unsigned)RLOG << 20),
+      (unsigned)((unsigned long long)__double_as_longlong(g) >> 32));
+  const double v = __longlong_as_double((long long)((unsigned long long)hi << 32));  // R r(g)
+  return (int)(C + copysign(R - v, f));
 }
 
-// Prefix sums use one padding word per S = NB / NT bins so that each thread's
-// S consecutive bins sit in distinct banks across a wavefront.
-template <int NB, int NT>
-__device__ __forceinline__ int bin_addr(int b) {
-  return b + b / (NB / NT);
+// Reciprocal of d for 2^-900 <= |d| <= 2^900: the hardware estimate and one
+// Newton step, relative error below 2^-40.
+__device__ __forceinline__ double recip(double d) {
+  const double r = __builtin_amdgcn_rcp(d);
+  return fma(r, fma(-d, r, 1.0), r);
 }
 
-// Adds point (dx, dy)'s two window intervals to the difference array. Ends
-// e = (Dy + c) / Dx, c in {-W, 0, W}, are formed as (Dy + c) * (1 / Dx): one
-// rounding each of Dx, Dy, the sum, the reciprocal and the product give
-// |e - e_exact| <= d = 2^-50 (2 |Dy| + W) / |Dx|. The bin coordinate moves by
-// at most (NB / 2) sc per unit of slope, so d shifts it by at most a quarter
-// bin whenever |Dx| >= 2^-47 (2 |Dy| + W) NB sc; the check uses 2^-46. Then
-// the end's rounding, the FP32 bin map (at the ends and at the partner's
-// slope) and the partner slope's rounding together move bin coordinates by
-// less than one bin, so the two-bin margin keeps every exact slope of the
-// interval inside the bins it adds to. A point failing the check, or with
-// Dx = 0 and in a window, is counted in that window at every slope
-// (returned packed: 1 = upper window, 65536 = lower window), which can only
-// raise the bounds. nbsc = 2^-46 NB sc.
-template <int NB, int NT>
+// The map's frame, uniform over a block: a slope theta has offset
+// f = (theta - tc) sc. The centre tc is the slope of the narrowest seed
+// window (0 if |tc| sc > 2^20) and sc = kBinMag x-range / y-range, in
+// [2^-100, 2^100]: every pair that can pass has a slope near the optimum, so
+// the map spends its resolution there (any monotone map is sound). A point
+// with |Dx| < q |Dy| + 2^-900, or |Dx| > 2^900, counts in both windows at
+// every slope; q is infinite when W is (then every point does).
+constexpr double kBinMag = 32.0;
+struct BinFrame {
+  double tc, sc, q;
+};
+__device__ __forceinline__ BinFrame bin_frame(double tc, double xh, double yh, double W, int nb) {
+  BinFrame F;
+  const double r = yh > 0.0 ? kBinMag * xh / yh : 1.0;
+  F.sc = fmin(fmax(r, 0x1p-100), 0x1p100);
+  F.tc = fabs(tc) * F.sc <= 0x1p20 ? tc : 0.0;
+  F.q = W < INFINITY ? 0x1p-46 * nb * F.sc : INFINITY;
+  return F;
+}
+
+// Bin of the slope of the pair (anchor, partner) at offset (dx, dy), with
+// r = recip(dx): f = fma(-tc, dx, dy) (sc r). Identical to the middle bin
+// add_point_bins computes for that partner.
+template <int RLOG>
+__device__ __forceinline__ int slope_bin(double dx, double dy, double r, const BinFrame& F) {
+  return fbin<RLOG>(fma(-F.tc, dx, dy) * (F.sc * r));
+}
+
+// Adds point (dx, dy)'s two window intervals to the difference array of the
+// bins of fbin<RLOG> (2^(RLOG+1) + 7 words at least). In
+// offset units the ends are f_c = (a + c) s, c in {-W, 0, W}, with
+// a = fma(-tc, Dx, Dy) and s = sc recip(Dx). Against the exact
+// (Dy + c - tc Dx) sc / Dx, the roundings of Dx, Dy, a, the sum, s and the
+// product leave a relative error below 2^-44 and an absolute one below
+// 2^-52 (|Dy / Dx| + |tc|) sc. As |f du/df| <= 1 and |du/df| <= 1/2, they move
+// the bin coordinate by less than R 2^-44 + (R / 2) 2^-52 (2^46 / NB + 2^20)
+// < 2^-7 when |Dx| >= q |Dy| (NB >= 2R the bins of the frame's q). With the map's own error (below 2^-4), every
+// computed bin (ends here, a pair's slope_bin) is within one of the exact
+// map's bin, so the two-bin margins keep every exact slope of an interval
+// inside the bins it adds to. A point outside the check's range, or with
+// Dx = 0 and in a window, is counted in that window at every slope (returned
+// packed: 1 = upper window, 65536 = lower window), which can only raise the
+// bounds.
+template <int RLOG>
 __device__ __forceinline__ unsigned add_point_bins(unsigned* bins, double dx, double dy, double W,
-                                                   double lim, double tc, float sc, double nbsc) {
+                                                   double lim, const BinFrame& F) {
   const double adx = fabs(dx), ady = fabs(dy);
   if (dx == 0.0)
     return (dy >= 0.0 && dy <= lim ? 1u : 0u) + (dy <= 0.0 && dy >= -lim ? 65536u : 0u);
-  if (!(adx >= (2.0 * ady + W) * nbsc)) return 1u + 65536u;  // also W = inf
-  const double inv = 1.0 / dx;
-  const int b0 = ubin<NB>((dy - W) * inv, tc, sc);
-  const int b1 = ubin<NB>(dy * inv, tc, sc);
-  const int b2 = ubin<NB>((dy + W) * inv, tc, sc);
-  // dx > 0: upper window on [e0, e1], lower on [e1, e2]; dx < 0: reversed
-  const int ul = (dx > 0.0 ? b0 : b1) - 2, uh = (dx > 0.0 ? b1 : b0) + 2;
-  const int dl = (dx > 0.0 ? b1 : b2) - 2, dh = (dx > 0.0 ? b2 : b1) + 2;
-  atomicAdd(&bins[bin_addr<NB, NT>(ul < 0 ? 0 : ul)], 1u);
-  if (uh + 1 < NB) atomicAdd(&bins[bin_addr<NB, NT>(uh + 1)], 0xFFFFFFFFu);
-  atomicAdd(&bins[bin_addr<NB, NT>(dl < 0 ? 0 : dl)], 65536u);
-  if (dh + 1 < NB) atomicAdd(&bins[bin_addr<NB, NT>(dh + 1)], 0xFFFF0000u);
+  if (!(adx >= fma(ady, F.q, 0x1p-900)) || adx > 0x1p900) return 1u + 65536u;
+  const double s = F.sc * recip(dx);
+  const double a = fma(-F.tc, dx, dy);
+  const int b0 = fbin<RLOG>((a - W) * s), b1 = fbin<RLOG>(a * s), b2 = fbin<RLOG>((a + W) * s);
+  // dx > 0: upper window on [f_-W, f_0], lower on [f_0, f_W]; dx < 0: reversed
+  atomicAdd(&bins[min(b0, b1) - 2], 1u);
+  atomicAdd(&bins[max(b0, b1) + 3], 0xFFFFFFFFu);
+  atomicAdd(&bins[min(b1, b2) - 2], 65536u);
+  atomicAdd(&bins[max(b1, b2) + 3], 0xFFFF0000u);
   return 0u;
 }
 
-// Scale of the bin map: the x/y aspect ratio times kBinMag, in FP32, kept
-// finite and positive. With the map centred on a slope within a few degrees
-// of the optimum, a magnification of 16 leaves of the order of 1e-5 of the
-// pairs of a 4096-point set above the bound, against 5e-3 unmagnified.
-constexpr double kBinMag = 16.0;
-__device__ __forceinline__ float bin_scale(double xh, double yh) {
-  const double r = yh > 0.0 ? kBinMag * xh / yh : 1.0;
-  return (float)fmin(fmax(r, 1e-30), 1e30);
+// add_point_bins, and the point's code for the queries of this anchor's
+// pairs: kCodeVertical (Dx = 0), kCodeFP64 (|Dx| outside [2^-900, 2^900], or
+// a slope of magnitude th_lim or more: the pair goes to the FP64 entries),
+// else the bin of the pair's slope (slope_bin, >= 3). The bin is taken for
+// far points too: its error is relative (below 2^-44), so it is within one
+// of the exact bin whatever the far-point check says.
+constexpr unsigned short kCodeVertical = 0, kCodeFP64 = 1, kCodePass = 2;
+template <int RLOG>
+__device__ __forceinline__ unsigned add_point_bins_coded(unsigned* bins, double dx, double dy,
+                                                         double W, double lim, const BinFrame& F,
+                                                         double th_lim, unsigned short* code) {
+  const double adx = fabs(dx), ady = fabs(dy);
+  if (dx == 0.0) {
+    *code = kCodeVertical;
+    return (dy >= 0.0 && dy <= lim ? 1u : 0u) + (dy <= 0.0 && dy >= -lim ? 65536u : 0u);
+  }
+  if (!(adx >= 0x1p-900) || adx > 0x1p900) {
+    *code = kCodeFP64;
+    return 1u + 65536u;
+  }
+  const double r = recip(dx);
+  const double s = F.sc * r;
+  const double a = fma(-F.tc, dx, dy);
+  const int b1 = fbin<RLOG>(a * s);
+  *code = fabs(dy * r) < th_lim ? (unsigned short)b1 : kCodeFP64;
+  if (!(adx >= fma(ady, F.q, 0x1p-900))) return 1u + 65536u;
+  const int b0 = fbin<RLOG>((a - W) * s), b2 = fbin<RLOG>((a + W) * s);
+  atomicAdd(&bins[min(b0, b1) - 2], 1u);
+  atomicAdd(&bins[max(b0, b1) + 3], 0xFFFFFFFFu);
+  atomicAdd(&bins[min(b1, b2) - 2], 65536u);
+  atomicAdd(&bins[max(b1, b2) + 3], 0xFFFF0000u);
+  return 0u;
 }
 
 // Slope of the narrowest of the candidate windows (width, theta, z_lo, z_hi)
-// in a[0..ma) and b[0..mb), by the NT threads of the block (ties by the low
-// bits of the width, then the index); 0 if none is finite. Ends with a
-// barrier.
+// in a[0..ma) and b[0..mb), by the NT threads of the block (ties to the lower
+// index); 0 if none is finite. Ends with a barrier.
 template <int NT>
 __device__ __forceinline__ double best_slope(const double4* __restrict__ a, int ma,
-                                             const double4* __restrict__ b, int mb,
-                                             unsigned long long* s_key, double* s_th) {
-  const int t = threadIdx.x;
-  if (t == 0) *s_key = ~0ull;
-  __syncthreads();
-  unsigned long long key = ~0ull;
-  for (int e = t; e < ma + mb; e += NT) {
+                                             const double4* __restrict__ b, int mb) {
+  double bw = INFINITY;
+  int be = INT_MAX;
+  for (int e = threadIdx.x; e < ma + mb; e += NT) {
     const double w = e < ma ? a[e].x : b[e - ma].x;
-    if (w < INFINITY) {  // finite (NaN compares false)
-      const unsigned long long k = ((unsigned long long)__double_as_longlong(w) & ~0xFFFFFull) |
-                                   (unsigned long long)(e & 0xFFFFF);
-      key = k < key ? k : key;
-    }
+    if (w < bw) { bw = w; be = e; }  // finite only (NaN compares false)
   }
-  atomicMin(s_key, key);
-  __syncthreads();
-  if (t == 0) {
-    const int e = (int)(*s_key & 0xFFFFF);
-    *s_th = *s_key == ~0ull ? 0.0 : (e < ma ? a[e].y : b[e - ma].y);
-  }
-  __syncthreads();
-  return *s_th;
+  block_argmin<NT>(bw, be);
+  return be == INT_MAX ? 0.0 : (be < ma ? a[be].y : b[be - ma].y);
 }
 
 // In-place prefix sum of the NB-bin difference array by the NT threads of the
-// block (all must call; ends with the sums in LDS, before a barrier). Modular
-// u32 arithmetic is exact: every true sum U + 65536 D is below 2^31.
+// block (all must call; ends with the sums in LDS, before a barrier). Thread t
+// takes bins t S .. t S + S - 1, S = NB / NT odd, so that the lanes of a
+// wavefront read distinct banks. Modular u32 arithmetic is exact: every true
+// sum U + 65536 D is below 2^31.
 template <int NB, int NT>
 __device__ __forceinline__ void scan_bins(unsigned* bins, unsigned* part) {
   constexpr int S = NB / NT;
+  static_assert(S * NT == NB && (S & 1), "bins per thread must be odd");
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   unsigned v[S];
   unsigned run = 0;
 #pragma unroll
   for (int r = 0; r < S; ++r) {
-    run += bins[t * (S + 1) + r];
+    run += bins[t * S + r];
     v[r] = run;
   }
   unsigned x = run;  // inclusive scan of the thread totals within the wavefront
@@ -335,7 +452,7 @@ __device__ __forceinline__ void scan_bins(unsigned* bins, unsigned* part) {
   unsigned off = x - run;
   for (int w = 0; w < wave; ++w) off += part[w];
 #pragma unroll
-  for (int r = 0; r < S; ++r) bins[t * (S + 1) + r] = v[r] + off;
+  for (int r = 0; r < S; ++r) bins[t * S + r] = v[r] + off;
 }
 
 // A pair passes when its bin bounds U or D (plus the every-slope points) at h.
