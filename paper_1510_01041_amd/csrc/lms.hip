@@ -97,7 +97,7 @@ __global__ __launch_bounds__(1024) void k_prep(const double* __restrict__ xy, in
                                                int n_pad, Ctx* ctx, float2* __restrict__ xy32,
                                                uint2* __restrict__ entries, int n_seeds,
                                                int n_random, unsigned long long seed_key,
-                                               unsigned bins) {
+                                               unsigned bins, int cap) {
   __shared__ double s_mn[1024], s_mx[1024], s_my[1024], s_My[1024];
   __shared__ int s_amn[1024], s_amx[1024], s_fin[1024];
   const int t = threadIdx.x;
@@ -147,6 +147,12 @@ __global__ __launch_bounds__(1024) void k_prep(const double* __restrict__ xy, in
     c.yabs = fmax(fabs(miny), fabs(maxy));
     c.wbound = 0x7FF0000000000000ull;  // +inf
     c.n_entries = (unsigned)n_seeds;
+    // all x equal: slope 0 is the answer; it is re-evaluated exactly as the
+    // one survivor (the seeds give bounds only)
+    if (c.all_x_equal && n_seeds < cap) {
+      entries[n_seeds] = make_uint2(kDegenerate, kDegenerate);
+      c.n_entries = (unsigned)n_seeds + 1u;
+    }
     *ctx = c;
   }
   {
@@ -227,7 +233,8 @@ __global__ __launch_bounds__(NT) void k_recheck(const double* __restrict__ xy, C
 constexpr int kSplitChunk = 512;
 constexpr int kSplitNT = 256;
 constexpr int kSplitSlots = 512;  // entries per launch pair (tmp: slots x NP doubles)
-constexpr int kFinalSlots = 128;  // split slots of the survivors' re-evaluation
+constexpr int kFinalSlots = 128;       // split slots of the survivors' re-evaluation,
+constexpr int kFinalSlotsLarge = 512;  // n > 4096 (a whole sort is slower there)
 
 __device__ __forceinline__ bool entry_slope(const double* __restrict__ xy, uint2 p, double* theta) {
   *theta = 0.0;
@@ -242,27 +249,29 @@ template <int C, int NT>
 __global__ __launch_bounds__(NT) void k_sort_chunks(const double* __restrict__ xy,
                                                     const Ctx* ctx,
                                                     const uint2* __restrict__ entries, int begin,
-                                                    int cap, double* __restrict__ tmp, int np) {
+                                                    int cap, int slots, double* __restrict__ tmp,
+                                                    int np) {
   constexpr int E = C / NT;
   __shared__ double z[C];
   if (ctx->status < 0) return;
-  const unsigned end = min(ctx->n_entries, (unsigned)cap);
-  const unsigned e = begin + blockIdx.y;
-  if (e >= end) return;
-  double theta;
-  if (!entry_slope(xy, entries[e], &theta)) return;
+  const unsigned end = min(min(ctx->n_entries, (unsigned)cap), (unsigned)begin + (unsigned)slots);
   const int n = ctx->n, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int k0 = blockIdx.x * C;
-  double v[E];
+  for (unsigned y = blockIdx.y; begin + y < end; y += gridDim.y) {
+    double theta;
+    if (!entry_slope(xy, entries[begin + y], &theta)) continue;
+    double v[E];
 #pragma unroll
-  for (int r = 0; r < E; ++r) {
-    const int k = k0 + (wave * E + r) * 64 + lane;
-    v[r] = k < n ? fma(-theta, xy[2 * k], xy[2 * k + 1]) : INFINITY;
+    for (int r = 0; r < E; ++r) {
+      const int k = k0 + (wave * E + r) * 64 + lane;
+      v[r] = k < n ? fma(-theta, xy[2 * k], xy[2 * k + 1]) : INFINITY;
+    }
+    sort_regs<C, NT>(v, z);
+    double* out = tmp + (size_t)y * np + k0;
+#pragma unroll
+    for (int r = 0; r < E; ++r) out[(wave * E + r) * 64 + lane] = v[r];
+    __syncthreads();  // z is reused by the next entry's sort
   }
-  sort_regs<C, NT>(v, z);
-  double* out = tmp + (size_t)blockIdx.y * np + k0;
-#pragma unroll
-  for (int r = 0; r < E; ++r) out[(wave * E + r) * 64 + lane] = v[r];
 }
 
 template <int NP, int NT>
@@ -310,6 +319,187 @@ __global__ __launch_bounds__(NT) void k_merge_window(const double* __restrict__ 
   }
 }
 
+// Seed bounds. The screen needs only an upper bound W on the optimal width,
+// and any window of h points at any slope gives one: so for each seed entry
+// a window of at least h intercepts z_k = fma(-theta, x_k, y_k) is found
+// without sorting. Level 1 counts the z in kSeedBins equal buckets over
+// [min z, max z] and takes the shortest run of buckets holding h; each
+// further level re-buckets the points of the previous run, widened by its
+// length on either side, over their span and does the same.
+// The window's ends are the smallest and largest z of the points in the
+// final run (at least h of them), so its FP64 width z_hi - z_lo is at least
+// F(theta) and, with the last level's buckets at about 1 / kSeedBins^3 of the
+// z range, within a few of them of the narrowest h-window near the runs. The record
+// (+inf, theta, z_lo, z_hi) keeps the entry out of the exact minimum (the
+// optimal pair survives the screen at any W >= the optimal width); its
+// window still serves the bin map's centre and window pairs. One workgroup
+// per entry.
+constexpr int kSeedBins = 4096;
+constexpr int kSeedLevels = 3;
+
+// Shortest run of buckets [b, b + len) with P[b + len] - P[b] >= h in the
+// exclusive prefix sums P[0..NB] (lowest b on ties), by the NT threads;
+// len = INT_MAX if there is none. Each thread takes NB / NT consecutive
+// starts; once it has a run of length L, a start needs a binary search only
+// if one read shows a shorter run from it.
+template <int NB, int NT>
+__device__ __forceinline__ void shortest_run(const unsigned* P, unsigned h, int* b_out,
+                                             int* len_out) {
+  constexpr int S = NB / NT;
+  const int b0 = threadIdx.x * S;
+  const unsigned top = P[NB];
+  double best = INFINITY;  // run length, as a double for block_argmin
+  int bb = INT_MAX;
+  for (int b = b0; b < b0 + S; ++b) {
+    const unsigned pb = P[b];
+    if (top - pb < h) break;  // no run from here on
+    int hi = NB;
+    if (bb != INT_MAX) {
+      hi = min(b + (int)best - 1, NB);
+      if (P[hi] - pb < h) continue;  // nothing shorter from b
+    }
+    int lo = b + 1;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (P[mid] - pb >= h) hi = mid; else lo = mid + 1;
+    }
+    best = lo - b;
+    bb = b;
+  }
+  block_argmin<NT>(best, bb);
+  *b_out = bb;
+  *len_out = bb == INT_MAX ? INT_MAX : (int)best;
+}
+
+// Exclusive prefix sums of hist[0..NB) into hist[0..NB] (hist[NB] = total)
+// by the NT threads. Ends with a barrier.
+template <int NB, int NT>
+__device__ __forceinline__ void prefix_counts(unsigned* hist, unsigned* part) {
+  constexpr int S = NB / NT;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  unsigned v[S];
+  unsigned run = 0;
+#pragma unroll
+  for (int r = 0; r < S; ++r) { v[r] = run; run += hist[t * S + r]; }
+  unsigned x = run;
+#pragma unroll
+  for (int m = 1; m < 64; m <<= 1) {
+    const unsigned y = __shfl_up(x, m);
+    if (lane >= m) x += y;
+  }
+  if (lane == 63) part[wave] = x;
+  __syncthreads();
+  unsigned off = x - run;
+  for (int w = 0; w < wave; ++w) off += part[w];
+#pragma unroll
+  for (int r = 0; r < S; ++r) hist[t * S + r] = v[r] + off;
+  if (t == NT - 1) hist[NB] = off + run;
+  __syncthreads();
+}
+
+template <int NT, int E>
+__global__ __launch_bounds__(NT) void k_seed_bounds(const double* __restrict__ xy, Ctx* ctx,
+                                                    const uint2* __restrict__ entries,
+                                                    double4* __restrict__ res, int begin,
+                                                    int cap, int update_bound) {
+  constexpr int NB = kSeedBins;
+  static_assert(E <= 32, "point mask is 32 bits");
+  __shared__ unsigned hist[NB + 1];
+  __shared__ unsigned s_part[NT / 64];
+  const Ctx c = *ctx;
+  if (c.status < 0) return;
+  const unsigned end = min(c.n_entries, (unsigned)cap);
+  const int n = c.n, t = threadIdx.x;
+  for (unsigned e = begin + blockIdx.x; e < end; e += gridDim.x) {
+    double theta;
+    if (!entry_slope(xy, entries[e], &theta)) {
+      if (t == 0) res[e] = make_double4(INFINITY, NAN, NAN, NAN);
+      continue;
+    }
+    // the thread's intercepts z_k, k = t + r NT, stay in registers
+    double z[E];
+    unsigned alive = 0u;  // bit r: z[r] is in the current level's domain
+    double zmn = INFINITY, zmx = -INFINITY;
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+      const int k = t + r * NT;
+      z[r] = k < n ? fma(-theta, xy[2 * k], xy[2 * k + 1]) : 0.0;
+      if (k < n) {
+        alive |= 1u << r;
+        zmn = fmin(zmn, z[r]);
+        zmx = fmax(zmx, z[r]);
+      }
+    }
+    block_min_max<NT>(zmn, zmx);
+    double lo = zmn, hi = zmx;  // the whole set: n >= h points
+    const double span = zmx - zmn;
+    if (span > 0.0 && span < INFINITY) {
+      // Level l buckets its domain over [za, za + NB / sc). The next domain
+      // is the run widened by its length on either side, so that a narrowest
+      // window which the run's bucket edges cut stays whole; it holds the
+      // run's h points, so every level finds a run (else the whole range
+      // stands).
+      double za = zmn, sc = NB / span;
+      int r0 = 0, len = NB;
+      auto bucket = [&](double v) { return (int)fmin(fmax((v - za) * sc, 0.0), (double)(NB - 1)); };
+      for (int l = 0; l < kSeedLevels; ++l) {
+        for (int b = t; b <= NB; b += NT) hist[b] = 0u;
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < E; ++r)
+          if ((alive >> r) & 1u) atomicAdd(&hist[bucket(z[r])], 1u);
+        __syncthreads();
+        prefix_counts<NB, NT>(hist, s_part);
+        shortest_run<NB, NT>(hist, (unsigned)c.h, &r0, &len);
+        if (len == INT_MAX) break;
+        const bool last = l + 1 == kSeedLevels;
+        const int q0 = last ? r0 : max(r0 - len, 0), q1 = last ? r0 + len : min(r0 + 2 * len, NB);
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+          const int b = bucket(z[r]);
+          if (b < q0 || b >= q1) alive &= ~(1u << r);
+        }
+        if (!last) {
+          const double w = (q1 - q0) / sc;
+          za += q0 / sc;
+          sc = w > 0.0 ? NB / w : 0.0;
+        }
+      }
+      // the last run's own points: their smallest and largest z
+      double mn = INFINITY, mx = -INFINITY;
+#pragma unroll
+      for (int r = 0; r < E; ++r)
+        if ((alive >> r) & 1u) { mn = fmin(mn, z[r]); mx = fmax(mx, z[r]); }
+      block_min_max<NT>(mn, mx);
+      if (len != INT_MAX) {
+        lo = mn;
+        hi = mx;
+      }
+    }
+    if (t == 0) {
+      res[e] = make_double4(INFINITY, theta, lo, hi);
+      const double w = hi - lo;
+      if (update_bound && w >= 0.0 && w < INFINITY)
+        atomicMin(&ctx->wbound,
+                  (unsigned long long)__double_as_longlong(width_bound(w, theta, c.xabs, c.yabs)));
+    }
+    __syncthreads();  // hist is reused by the next entry
+  }
+}
+
+// Seed bounds of entries [begin, min(n_entries, cap)), `grid` workgroups of
+// 1024 threads, each holding E intercepts (the levels are latency-bound:
+// more threads shorten each one's share of the counts, sums and searches).
+void launch_seed_bounds(hipStream_t s, int n, int grid, const double* xy, Ctx* ctx,
+                        const uint2* e, double4* res, int begin, int cap, int upd) {
+  if (n <= 1024)
+    hipLaunchKernelGGL((k_seed_bounds<1024, 1>), dim3(grid), dim3(1024), 0, s, xy, ctx, e, res, begin, cap, upd);
+  else if (n <= 4096)
+    hipLaunchKernelGGL((k_seed_bounds<1024, 4>), dim3(grid), dim3(1024), 0, s, xy, ctx, e, res, begin, cap, upd);
+  else
+    hipLaunchKernelGGL((k_seed_bounds<1024, 16>), dim3(grid), dim3(1024), 0, s, xy, ctx, e, res, begin, cap, upd);
+}
+
 // F(theta) at arbitrary slopes (seed slopes and lms_eval_slopes).
 template <int N2, int NT>
 __global__ __launch_bounds__(NT) void k_eval_slopes(const double* __restrict__ xy, int n, int h,
@@ -354,10 +544,12 @@ __global__ __launch_bounds__(kWinNT) void k_window_pairs(const double* __restric
   const Ctx c = *ctx;
   if (c.status != LMS_OK || c.all_x_equal) return;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  if (t == 0) {
+  if (t == 0) {  // narrowest window (z_hi - z_lo: exact or a seed bound's)
     int b = -1;
-    for (int k = 0; k < m; ++k)
-      if (cand[k].x < INFINITY && (b < 0 || cand[k].x < cand[b].x)) b = k;
+    for (int k = 0; k < m; ++k) {
+      const double wk = cand[k].w - cand[k].z;
+      if (wk < INFINITY && (b < 0 || wk < cand[b].w - cand[b].z)) b = k;
+    }
     s_best = b;
   }
   __syncthreads();
@@ -992,12 +1184,14 @@ void launch_recheck_n2(hipStream_t s, int grid, const double* xy, Ctx* ctx, cons
                      upd);
 }
 
+// gy: workgroups per chunk (each sorts that chunk of entries y, y + gy, ...);
+// grid: k_merge_window's workgroups.
 template <int NP>
-void launch_split_np(hipStream_t s, int grid, int slots, const double* xy, Ctx* ctx,
+void launch_split_np(hipStream_t s, int grid, int gy, int slots, const double* xy, Ctx* ctx,
                      const uint2* e, double4* res, int begin, int cap, int upd, double* tmp) {
   constexpr int NT = NP >= 2048 ? 1024 : 256;
-  hipLaunchKernelGGL((k_sort_chunks<kSplitChunk, kSplitNT>), dim3(NP / kSplitChunk, slots),
-                     dim3(kSplitNT), 0, s, xy, ctx, e, begin, cap, tmp, NP);
+  hipLaunchKernelGGL((k_sort_chunks<kSplitChunk, kSplitNT>), dim3(NP / kSplitChunk, gy),
+                     dim3(kSplitNT), 0, s, xy, ctx, e, begin, cap, slots, tmp, NP);
   hipLaunchKernelGGL((k_merge_window<NP, NT>), dim3(grid), dim3(NT), 0, s, xy, ctx, e, res, begin,
                      cap, upd, tmp, slots);
 }
@@ -1009,19 +1203,20 @@ int split_slots(int n, int expected) {
   return std::max(1, std::min(expected, kSplitSlots));
 }
 
-// Re-evaluation of entries [begin, min(n_entries, cap)) in FP64; `expected`
-// is how many there usually are (the split path's slots), tmp holds
-// split_slots(n, expected) x next_pow2(n) doubles.
+// Re-evaluation of entries [begin, min(n_entries, cap)) in FP64. The split
+// path takes the first `slots` of them (tmp holds slots x next_pow2(n)
+// doubles), gy at a time per chunk; `grid` workgroups merge them and sort any
+// further ones whole.
 void launch_recheck(hipStream_t s, int n, int grid, const double* xy, Ctx* ctx, const uint2* e,
-                    double4* res, int begin, int cap, int upd, double* tmp, int expected) {
-  const int slots = tmp ? split_slots(n, expected) : 0;
-  if (slots > 0) {
+                    double4* res, int begin, int cap, int upd, double* tmp, int slots, int gy) {
+  if (tmp && slots > 0) {
+    gy = std::max(1, std::min(gy, slots));
     switch (next_pow2(n)) {
-      case 1024: launch_split_np<1024>(s, grid, slots, xy, ctx, e, res, begin, cap, upd, tmp); return;
-      case 2048: launch_split_np<2048>(s, grid, slots, xy, ctx, e, res, begin, cap, upd, tmp); return;
-      case 4096: launch_split_np<4096>(s, grid, slots, xy, ctx, e, res, begin, cap, upd, tmp); return;
-      case 8192: launch_split_np<8192>(s, grid, slots, xy, ctx, e, res, begin, cap, upd, tmp); return;
-      default: launch_split_np<16384>(s, grid, slots, xy, ctx, e, res, begin, cap, upd, tmp); return;
+      case 1024: launch_split_np<1024>(s, grid, gy, slots, xy, ctx, e, res, begin, cap, upd, tmp); return;
+      case 2048: launch_split_np<2048>(s, grid, gy, slots, xy, ctx, e, res, begin, cap, upd, tmp); return;
+      case 4096: launch_split_np<4096>(s, grid, gy, slots, xy, ctx, e, res, begin, cap, upd, tmp); return;
+      case 8192: launch_split_np<8192>(s, grid, gy, slots, xy, ctx, e, res, begin, cap, upd, tmp); return;
+      default: launch_split_np<16384>(s, grid, gy, slots, xy, ctx, e, res, begin, cap, upd, tmp); return;
     }
   }
   switch (next_pow2(n)) {
@@ -1173,7 +1368,7 @@ hipError_t launch_pairs(hipStream_t s, int R, bool L, const double* xy, const fl
 // NB / NT bins per thread in registers).
 template <int NB>
 constexpr int bins_threads() {
-  return NB >= 32768 ? 1024 : (NB >= 16384 ? 512 : 256);
+  return NB >= 32768 ? 1024 : (NB >= 8192 ? 512 : 256);
 }
 
 template <int NB>
@@ -1263,7 +1458,7 @@ hipError_t launch_list(hipStream_t s, int R, bool L, int cu, const double* xy, c
 // Bins per anchor for 2^nb_log2 nominal ones: one more per thread of k_bins.
 unsigned bins_count(int nb_log2) {
   const int nb = 1 << nb_log2;
-  return (unsigned)(nb + (nb >= 32768 ? 1024 : (nb >= 16384 ? 512 : 256)));
+  return (unsigned)(nb + (nb >= 32768 ? 1024 : (nb >= 8192 ? 512 : 256)));
 }
 
 int default_bins_log2(int n) {
@@ -1308,7 +1503,7 @@ struct Setup {
   lms_result* out = nullptr;
   unsigned flags = 0;
   int seeds = 0, window_pairs = 0, bins_log2 = 0, G = 1, ipa = 1;
-  int seed_slots = 0, final_slots = 0;
+  int final_slots = 0;
   bool no_prune = false, use_bins = false;
   const double* seed_theta = nullptr;
   int64_t n_seed_theta = 0;
@@ -1386,11 +1581,9 @@ lms_status make_setup(const double* d_xy, int64_t n, int64_t h, lms_result* d_ou
   S->n_seed_theta = n_seed_theta;
   S->pairs = pairs;
   S->cand_cap = use_bins ? screen_cap : 0;
-  // split re-evaluation slots: the seed entries of the first round, and the
-  // usual number of survivors
-  S->seed_slots = split_slots(p.n, 1 + seeds + window_pairs);
-  S->final_slots = split_slots(p.n, kFinalSlots);
-  const long long tmp = (long long)std::max(S->seed_slots, S->final_slots) * next_pow2(p.n);
+  // split re-evaluation slots: the usual number of survivors
+  S->final_slots = split_slots(p.n, p.n > 4096 ? kFinalSlotsLarge : kFinalSlots);
+  const long long tmp = (long long)S->final_slots * next_pow2(p.n);
   S->L = layout(p.n_pad, p.cap, n_seed_theta, S->cand_cap, tmp);
   return LMS_OK;
 }
@@ -1411,7 +1604,8 @@ lms_status enqueue_solve(const Setup& S, char* base, hipStream_t s, lms_host::St
   auto mark = [&]() { if (prof) prof->mark(); };
   const unsigned long long key = 0x5EEDull + (unsigned long long)p.n * 0x100000001ull;
   hipLaunchKernelGGL(k_prep, dim3(1), dim3(1024), 0, s, d_xy, p.n, p.h, p.n_pad, ctx, xy32,
-                     entries, p.n_seeds, seeds, key, S.use_bins ? bins_count(S.bins_log2) : 0u);
+                     entries, p.n_seeds, seeds, key, S.use_bins ? bins_count(S.bins_log2) : 0u,
+                     (int)p.cap);
   mark();
   // Seeds: exact FP64 widths of a few slopes set the screen's bound: the
   // device seed slopes, the extreme-x and random pairs, and with window pairs
@@ -1426,14 +1620,14 @@ lms_status enqueue_solve(const Setup& S, char* base, hipStream_t s, lms_host::St
     hipLaunchKernelGGL(k_window_pairs, dim3(1), dim3(kWinNT), 0, s, d_xy, ctx, rec,
                        (int)n_seed_theta, entries, first_w, window_pairs, key ^ 0xA1ull);
   double* tmp = (double*)(base + L.sort_tmp);
-  launch_recheck(s, p.n, std::min(first_w + window_pairs, 4 * cu), d_xy, ctx, entries, res, 0,
-                 first_w + window_pairs, S.no_prune ? 0 : 1, tmp, S.seed_slots);
+  launch_seed_bounds(s, p.n, std::min(first_w + window_pairs, 4 * cu), d_xy, ctx, entries, res, 0,
+                     first_w + window_pairs, S.no_prune ? 0 : 1);
   if (window_pairs) {
     // second round: from the narrowest window of the first round's pairs
     hipLaunchKernelGGL(k_window_pairs, dim3(1), dim3(kWinNT), 0, s, d_xy, ctx, res + first_w,
                        window_pairs, entries, first_w + window_pairs, window_pairs, key ^ 0xA2ull);
-    launch_recheck(s, p.n, std::min(window_pairs, 4 * cu), d_xy, ctx, entries, res,
-                   first_w + window_pairs, p.n_seeds, 1, tmp, S.seed_slots);
+    launch_seed_bounds(s, p.n, std::min(window_pairs, 4 * cu), d_xy, ctx, entries, res,
+                       first_w + window_pairs, p.n_seeds, 1);
   }
   mark();
   // Screen. With slope bins: per-anchor bin counts, then the FP32 test of the
@@ -1460,8 +1654,10 @@ lms_status enqueue_solve(const Setup& S, char* base, hipStream_t s, lms_host::St
   if (err != hipSuccess)
     return fail(LMS_ERR_DEVICE, std::string("screen launch: ") + hipGetErrorString(err));
   mark();
-  launch_recheck(s, p.n, 4 * cu, d_xy, ctx, entries, res, p.n_seeds, (int)p.cap, 0, tmp,
-                 S.final_slots);
+  // survivors: usually few; their number is known only on the device
+  launch_recheck(s, p.n, std::min(S.final_slots > 0 ? S.final_slots : 4 * cu, 4 * cu), d_xy, ctx,
+                 entries, res, p.n_seeds, (int)p.cap, 0, tmp, S.final_slots,
+                 p.n > 4096 ? 64 : 32);
   mark();
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, s, ctx, entries, res, (int)p.cap, S.out);
   mark();
@@ -1711,7 +1907,7 @@ lms_status lms_screen_pairs(const double* d_xy, int64_t n, int64_t h, double W,
   float2* xy32 = (float2*)(base + L.xy32);
   uint2* entries = (uint2*)(base + L.entries);
   hipLaunchKernelGGL(k_prep, dim3(1), dim3(1024), 0, s, d_xy, p.n, p.h, p.n_pad, ctx, xy32,
-                     entries, 1, 0, 0ull, 0u);
+                     entries, 1, 0, 0ull, 0u, 0);
   hipError_t err = launch_pairs(s, p.R, p.lds, d_xy, xy32, ctx, W, d_pairs, (int)m, d_verdict, p.nq);
   if (err != hipSuccess) return fail(LMS_ERR_DEVICE, hipGetErrorString(err));
   return LMS_OK;

@@ -86,6 +86,25 @@ __device__ __forceinline__ void block_argmin(double& w, int& s) {
   __syncthreads();
 }
 
+// Block-wide minimum and maximum of the NT threads' values (every thread gets
+// both). Ends with a barrier.
+template <int NT>
+__device__ __forceinline__ void block_min_max(double& mn, double& mx) {
+  __shared__ double red_mn[NT / 64], red_mx[NT / 64];
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    mn = fmin(mn, __shfl_xor(mn, m));
+    mx = fmax(mx, __shfl_xor(mx, m));
+  }
+  if (NT > 64) {
+    if ((threadIdx.x & 63) == 0) { red_mn[threadIdx.x >> 6] = mn; red_mx[threadIdx.x >> 6] = mx; }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NT / 64; ++k) { mn = fmin(mn, red_mn[k]); mx = fmax(mx, red_mx[k]); }
+  }
+  __syncthreads();
+}
+
 // Narrowest window and its ends from the sorted values z[at(0..n)], by the
 // whole block (`at` maps a rank to its LDS slot): the smallest z_{s+h-1} - z_s,
 // the lowest s among equally narrow windows. No window compares below +inf
@@ -407,7 +426,8 @@ __device__ __forceinline__ unsigned add_point_bins_coded(unsigned* bins, double 
 }
 
 // Slope of the narrowest of the candidate windows (width, theta, z_lo, z_hi)
-// in a[0..ma) and b[0..mb), by the NT threads of the block (ties to the lower
+// in a[0..ma) and b[0..mb), by z_hi - z_lo (the width of an exact window, the
+// bound of a seed's), by the NT threads of the block (ties to the lower
 // index); 0 if none is finite. Ends with a barrier.
 template <int NT>
 __device__ __forceinline__ double best_slope(const double4* __restrict__ a, int ma,
@@ -415,7 +435,8 @@ __device__ __forceinline__ double best_slope(const double4* __restrict__ a, int 
   double bw = INFINITY;
   int be = INT_MAX;
   for (int e = threadIdx.x; e < ma + mb; e += NT) {
-    const double w = e < ma ? a[e].x : b[e - ma].x;
+    const double4 r = e < ma ? a[e] : b[e - ma];
+    const double w = r.w - r.z;
     if (w < bw) { bw = w; be = e; }  // finite only (NaN compares false)
   }
   block_argmin<NT>(bw, be);
