@@ -335,6 +335,7 @@ __global__ __launch_bounds__(NT) void k_merge_window(const double* __restrict__ 
 // window still serves the bin map's centre and window pairs. One workgroup
 // per entry.
 constexpr int kSeedBins = 4096;
+constexpr int kSeedExactMax = 2048;  // smaller sets: exact seed windows (k_recheck)
 constexpr int kSeedLevels = 3;
 
 // Shortest run of buckets [b, b + len) with P[b + len] - P[b] >= h in the
@@ -1620,14 +1621,21 @@ lms_status enqueue_solve(const Setup& S, char* base, hipStream_t s, lms_host::St
     hipLaunchKernelGGL(k_window_pairs, dim3(1), dim3(kWinNT), 0, s, d_xy, ctx, rec,
                        (int)n_seed_theta, entries, first_w, window_pairs, key ^ 0xA1ull);
   double* tmp = (double*)(base + L.sort_tmp);
-  launch_seed_bounds(s, p.n, std::min(first_w + window_pairs, 4 * cu), d_xy, ctx, entries, res, 0,
-                     first_w + window_pairs, S.no_prune ? 0 : 1);
+  // up to kSeedExactMax points one workgroup sorts a seed's intercepts
+  // faster than the histogram levels take, and the window is exact
+  auto seed_windows = [&](int grid, int begin, int end, int upd) {
+    if (p.n <= kSeedExactMax)
+      launch_recheck(s, p.n, grid, d_xy, ctx, entries, res, begin, end, upd, nullptr, 0, 0);
+    else
+      launch_seed_bounds(s, p.n, grid, d_xy, ctx, entries, res, begin, end, upd);
+  };
+  seed_windows(std::min(first_w + window_pairs, 4 * cu), 0, first_w + window_pairs,
+               S.no_prune ? 0 : 1);
   if (window_pairs) {
     // second round: from the narrowest window of the first round's pairs
     hipLaunchKernelGGL(k_window_pairs, dim3(1), dim3(kWinNT), 0, s, d_xy, ctx, res + first_w,
                        window_pairs, entries, first_w + window_pairs, window_pairs, key ^ 0xA2ull);
-    launch_seed_bounds(s, p.n, std::min(window_pairs, 4 * cu), d_xy, ctx, entries, res,
-                       first_w + window_pairs, p.n_seeds, 1);
+    seed_windows(std::min(window_pairs, 4 * cu), first_w + window_pairs, p.n_seeds, 1);
   }
   mark();
   // Screen. With slope bins: per-anchor bin counts, then the FP32 test of the
