@@ -324,19 +324,18 @@ __global__ __launch_bounds__(NT) void k_merge_window(const double* __restrict__ 
 // a window of at least h intercepts z_k = fma(-theta, x_k, y_k) is found
 // without sorting. Level 1 counts the z in kSeedBins equal buckets over
 // [min z, max z] and takes the shortest run of buckets holding h; each
-// further level re-buckets the points of the previous run, widened by its
-// length on either side, over their span and does the same.
+// further level (LV in all) re-buckets the points of the previous run,
+// widened by its length on either side, over their span and does the same.
 // The window's ends are the smallest and largest z of the points in the
 // final run (at least h of them), so its FP64 width z_hi - z_lo is at least
-// F(theta) and, with the last level's buckets at about 1 / kSeedBins^3 of the
-// z range, within a few of them of the narrowest h-window near the runs. The record
+// F(theta) and, with the last level's buckets at about 1 / kSeedBins^LV of
+// the z range, within a few of them of the narrowest h-window near the runs. The record
 // (+inf, theta, z_lo, z_hi) keeps the entry out of the exact minimum (the
 // optimal pair survives the screen at any W >= the optimal width); its
 // window still serves the bin map's centre and window pairs. One workgroup
 // per entry.
 constexpr int kSeedBins = 4096;
 constexpr int kSeedExactMax = 2048;  // smaller sets: exact seed windows (k_recheck)
-constexpr int kSeedLevels = 3;
 
 // Shortest run of buckets [b, b + len) with P[b + len] - P[b] >= h in the
 // exclusive prefix sums P[0..NB] (lowest b on ties), by the NT threads;
@@ -398,7 +397,7 @@ __device__ __forceinline__ void prefix_counts(unsigned* hist, unsigned* part) {
   __syncthreads();
 }
 
-template <int NT, int E>
+template <int NT, int E, int LV>
 __global__ __launch_bounds__(NT) void k_seed_bounds(const double* __restrict__ xy, Ctx* ctx,
                                                     const uint2* __restrict__ entries,
                                                     double4* __restrict__ res, int begin,
@@ -435,7 +434,7 @@ __global__ __launch_bounds__(NT) void k_seed_bounds(const double* __restrict__ x
     double lo = zmn, hi = zmx;  // the whole set: n >= h points
     const double span = zmx - zmn;
     if (span > 0.0 && span < INFINITY) {
-      // Level l buckets its domain over [za, za + NB / sc). The next domain
+      // Level l < LV buckets its domain over [za, za + NB / sc). The next domain
       // is the run widened by its length on either side, so that a narrowest
       // window which the run's bucket edges cut stays whole; it holds the
       // run's h points, so every level finds a run (else the whole range
@@ -443,7 +442,7 @@ __global__ __launch_bounds__(NT) void k_seed_bounds(const double* __restrict__ x
       double za = zmn, sc = NB / span;
       int r0 = 0, len = NB;
       auto bucket = [&](double v) { return (int)fmin(fmax((v - za) * sc, 0.0), (double)(NB - 1)); };
-      for (int l = 0; l < kSeedLevels; ++l) {
+      for (int l = 0; l < LV; ++l) {
         for (int b = t; b <= NB; b += NT) hist[b] = 0u;
         __syncthreads();
 #pragma unroll
@@ -453,7 +452,7 @@ __global__ __launch_bounds__(NT) void k_seed_bounds(const double* __restrict__ x
         prefix_counts<NB, NT>(hist, s_part);
         shortest_run<NB, NT>(hist, (unsigned)c.h, &r0, &len);
         if (len == INT_MAX) break;
-        const bool last = l + 1 == kSeedLevels;
+        const bool last = l + 1 == LV;
         const int q0 = last ? r0 : max(r0 - len, 0), q1 = last ? r0 + len : min(r0 + 2 * len, NB);
 #pragma unroll
         for (int r = 0; r < E; ++r) {
@@ -491,14 +490,16 @@ __global__ __launch_bounds__(NT) void k_seed_bounds(const double* __restrict__ x
 // Seed bounds of entries [begin, min(n_entries, cap)), `grid` workgroups of
 // 1024 threads, each holding E intercepts (the levels are latency-bound:
 // more threads shorten each one's share of the counts, sums and searches).
+// Two levels up to 4096 points, three above: the larger sets' screen is more
+// sensitive to a bound a few 1e-4 loose, and a level costs about 8 us.
 void launch_seed_bounds(hipStream_t s, int n, int grid, const double* xy, Ctx* ctx,
                         const uint2* e, double4* res, int begin, int cap, int upd) {
   if (n <= 1024)
-    hipLaunchKernelGGL((k_seed_bounds<1024, 1>), dim3(grid), dim3(1024), 0, s, xy, ctx, e, res, begin, cap, upd);
+    hipLaunchKernelGGL((k_seed_bounds<1024, 1, 2>), dim3(grid), dim3(1024), 0, s, xy, ctx, e, res, begin, cap, upd);
   else if (n <= 4096)
-    hipLaunchKernelGGL((k_seed_bounds<1024, 4>), dim3(grid), dim3(1024), 0, s, xy, ctx, e, res, begin, cap, upd);
+    hipLaunchKernelGGL((k_seed_bounds<1024, 4, 2>), dim3(grid), dim3(1024), 0, s, xy, ctx, e, res, begin, cap, upd);
   else
-    hipLaunchKernelGGL((k_seed_bounds<1024, 16>), dim3(grid), dim3(1024), 0, s, xy, ctx, e, res, begin, cap, upd);
+    hipLaunchKernelGGL((k_seed_bounds<1024, 16, 3>), dim3(grid), dim3(1024), 0, s, xy, ctx, e, res, begin, cap, upd);
 }
 
 // F(theta) at arbitrary slopes (seed slopes and lms_eval_slopes).
