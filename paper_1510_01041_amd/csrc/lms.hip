@@ -64,6 +64,8 @@ struct __align__(16) Ctx {
   double cx, cy;      // centre (midrange) used for the FP32 copy
   double xh, yh;      // bounds on |x - cx| and |y - cy|
   double xabs, yabs;  // max |x|, max |y| of the raw input
+  double xr, yr;      // bounds on max x - min x and max y - min y
+  double th_lo, th_hi;  // every pair that can be optimal has its slope in here
   unsigned long long wbound;  // FP64 width bound, as bits (monotone atomicMin)
   unsigned int n_entries;     // seeds + survivors appended so far
   unsigned int overflow;
@@ -71,7 +73,7 @@ struct __align__(16) Ctx {
   unsigned int n_cands;       // pairs passed by the slope-bin screen
   unsigned int cand_overflow;
   unsigned int bins;          // slope bins per anchor (0: no slope-bin screen)
-  unsigned int pad;
+  int n_live;                 // anchors left by the slope range (-1: no range)
 };
 
 // Search counters, each spread over kSlots addresses (slot = block index mod
@@ -145,6 +147,11 @@ __global__ __launch_bounds__(1024) void k_prep(const double* __restrict__ xy, in
     c.yh = fmax(fabs(miny - cy), fabs(maxy - cy)) * (1.0 + 0x1p-40);
     c.xabs = fmax(fabs(minx), fabs(maxx));
     c.yabs = fmax(fabs(miny), fabs(maxy));
+    c.xr = (maxx - minx) * (1.0 + 0x1p-50);
+    c.yr = (maxy - miny) * (1.0 + 0x1p-50);
+    c.th_lo = -INFINITY;
+    c.th_hi = INFINITY;
+    c.n_live = -1;
     c.wbound = 0x7FF0000000000000ull;  // +inf
     c.n_entries = (unsigned)n_seeds;
     // all x equal: slope 0 is the answer; it is re-evaluated exactly as the
@@ -250,16 +257,17 @@ __global__ __launch_bounds__(NT) void k_sort_chunks(const double* __restrict__ x
                                                     const Ctx* ctx,
                                                     const uint2* __restrict__ entries, int begin,
                                                     int cap, int slots, double* __restrict__ tmp,
-                                                    int np) {
+                                                    int np, const double* __restrict__ thetas) {
   constexpr int E = C / NT;
   __shared__ double z[C];
   if (ctx->status < 0) return;
-  const unsigned end = min(min(ctx->n_entries, (unsigned)cap), (unsigned)begin + (unsigned)slots);
+  const unsigned end = min(thetas ? (unsigned)cap : min(ctx->n_entries, (unsigned)cap),
+                           (unsigned)begin + (unsigned)slots);
   const int n = ctx->n, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int k0 = blockIdx.x * C;
   for (unsigned y = blockIdx.y; begin + y < end; y += gridDim.y) {
-    double theta;
-    if (!entry_slope(xy, entries[begin + y], &theta)) continue;
+    double theta = thetas ? thetas[begin + y] : 0.0;
+    if (!thetas && !entry_slope(xy, entries[begin + y], &theta)) continue;
     double v[E];
 #pragma unroll
     for (int r = 0; r < E; ++r) {
@@ -279,11 +287,12 @@ __global__ __launch_bounds__(NT) void k_merge_window(const double* __restrict__ 
                                                      const uint2* __restrict__ entries,
                                                      double4* __restrict__ res, int begin,
                                                      int cap, int update_bound,
-                                                     const double* __restrict__ tmp, int slots) {
+                                                     const double* __restrict__ tmp, int slots,
+                                                     const double* __restrict__ thetas) {
   __shared__ double z[NP + NP / 16];  // merge_slot layout (NP for whole sorts)
   const Ctx c = *ctx;
   if (c.status < 0) return;
-  const unsigned end = min(c.n_entries, (unsigned)cap);
+  const unsigned end = thetas ? (unsigned)cap : min(c.n_entries, (unsigned)cap);
   const unsigned split_end = min(end, (unsigned)begin + (unsigned)slots);
   auto finish = [&](unsigned e, double w, double theta, double lo, double hi) {
     if (threadIdx.x == 0) {
@@ -294,8 +303,8 @@ __global__ __launch_bounds__(NT) void k_merge_window(const double* __restrict__ 
     }
   };
   for (unsigned e = begin + blockIdx.x; e < split_end; e += gridDim.x) {
-    double theta;
-    if (!entry_slope(xy, entries[e], &theta)) {
+    double theta = thetas ? thetas[e] : 0.0;
+    if (!thetas && !entry_slope(xy, entries[e], &theta)) {
       if (threadIdx.x == 0) res[e] = make_double4(INFINITY, NAN, NAN, NAN);
       continue;
     }
@@ -308,8 +317,8 @@ __global__ __launch_bounds__(NT) void k_merge_window(const double* __restrict__ 
     finish(e, w, theta, lo, hi);
   }
   for (unsigned e = split_end + blockIdx.x; e < end; e += gridDim.x) {
-    double theta;
-    if (!entry_slope(xy, entries[e], &theta)) {
+    double theta = thetas ? thetas[e] : 0.0;
+    if (!thetas && !entry_slope(xy, entries[e], &theta)) {
       if (threadIdx.x == 0) res[e] = make_double4(INFINITY, NAN, NAN, NAN);
       continue;
     }
@@ -500,6 +509,300 @@ void launch_seed_bounds(hipStream_t s, int n, int grid, const double* xy, Ctx* c
     hipLaunchKernelGGL((k_seed_bounds<1024, 4, 2>), dim3(grid), dim3(1024), 0, s, xy, ctx, e, res, begin, cap, upd);
   else
     hipLaunchKernelGGL((k_seed_bounds<1024, 16, 3>), dim3(grid), dim3(1024), 0, s, xy, ctx, e, res, begin, cap, upd);
+}
+
+// ---------------------------------------------------------------- slope range
+//
+// A pair can be optimal only if its slope theta has F(theta) <= W: its
+// anchored window of width W holds h points. F is Lipschitz in theta with
+// constant xr (each intercept moves by (theta - theta') x_k), so an exact
+// F(theta_g) > W excludes the slopes within (F(theta_g) - W) / xr of
+// theta_g. And for |theta| >= |theta_g| of the same sign,
+// F(theta) >= F(theta_g) - yr (F(theta) / |theta| is the narrowest window of
+// y / theta - x, Lipschitz in 1 / theta with constant yr). kGridSide slopes
+// on either side of the best seed slope tc, at offsets d0 2^k, are evaluated
+// exactly; where their exclusions join up from the far end inwards, the
+// slopes beyond are ruled out, which leaves [th_lo, th_hi] around tc.
+constexpr int kGridSide = 16;
+constexpr int kGrid = 2 * kGridSide;
+
+// Grid slopes: entry 2k at tc + d0 2^k, entry 2k + 1 at tc - d0 2^k, with d0
+// 2^-13 of the y / x aspect ratio. One block.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_grid_slopes(const Ctx* ctx, const double4* seed_res,
+                                                    int n_res, const double4* seed_rec,
+                                                    int n_rec, double* grid_theta) {
+  const double tc = best_slope<NT>(seed_res, n_res, seed_rec, n_rec);
+  const Ctx& c = *ctx;
+  const double d0 = c.xh > 0.0 && c.yh > 0.0 ? 0x1p-13 * (c.yh / c.xh) : 0x1p-13;
+  if (threadIdx.x < kGridSide) {
+    const double d = ldexp(d0, threadIdx.x);
+    grid_theta[2 * threadIdx.x] = tc + d;
+    grid_theta[2 * threadIdx.x + 1] = tc - d;
+  }
+}
+
+// [lo, hi] from the grid's exact windows (width in .x, as in k_recheck; NaN
+// or +inf widths exclude nothing) against the bound W, by the whole block
+// (all threads call; the result goes to every thread); (-inf, +inf) when the
+// far grid slopes are not ruled out.
+template <int NT>
+__device__ void slope_range(const Ctx& c, double W, const double* __restrict__ grid_theta,
+                            const double4* __restrict__ grid_res, double* lo_out,
+                            double* hi_out) {
+  static_assert(NT >= kGrid, "one thread per grid slope");
+  __shared__ double s_t[kGrid], s_m[kGrid], s_r[kGrid], s_lohi[2];
+  const int t = threadIdx.x;
+  const bool usable = W < INFINITY && c.xr > 0.0 && c.xr < INFINITY && c.yr < INFINITY;
+  if (usable && t < kGrid) {
+    // lower bound of the exact width at grid slope t, minus W, and the
+    // radius it excludes
+    const double th = grid_theta[t], w = grid_res[t].x;
+    const double err = 4.0 * 0x1p-53 * (c.yabs + fabs(th) * c.xabs);
+    const double m = w < INFINITY ? (w - err) * (1.0 - 0x1p-50) - W : -1.0;
+    s_t[t] = th;
+    s_m[t] = m;
+    s_r[t] = m > 0.0 ? m / c.xr * (1.0 - 0x1p-40) : 0.0;
+  }
+  __syncthreads();
+  if (t == 0) {
+    double lo = -INFINITY, hi = INFINITY;
+    if (usable) {
+      {  // upper side: entries 2k
+        const int far = 2 * (kGridSide - 1);
+        if (s_t[far] > 0.0 && s_m[far] > c.yr * (1.0 + 0x1p-40)) {
+          double from = s_t[far] - s_r[far];
+          for (int k = kGridSide - 2; k >= 0; --k) {
+            const double r = s_r[2 * k], th = s_t[2 * k];
+            if (!(r > 0.0) || th + r < from) break;
+            from = fmin(from, th - r);
+          }
+          hi = from;
+        }
+      }
+      {  // lower side: entries 2k + 1
+        const int far = 2 * (kGridSide - 1) + 1;
+        if (s_t[far] < 0.0 && s_m[far] > c.yr * (1.0 + 0x1p-40)) {
+          double to = s_t[far] + s_r[far];
+          for (int k = kGridSide - 2; k >= 0; --k) {
+            const double r = s_r[2 * k + 1], th = s_t[2 * k + 1];
+            if (!(r > 0.0) || th - r > to) break;
+            to = fmax(to, th + r);
+          }
+          lo = to;
+        }
+      }
+    }
+    if (!(lo < hi)) {  // (never, as the best seed slope is not excluded)
+      lo = -INFINITY;
+      hi = INFINITY;
+    }
+    s_lohi[0] = lo;
+    s_lohi[1] = hi;
+  }
+  __syncthreads();
+  *lo_out = s_lohi[0];
+  *hi_out = s_lohi[1];
+}
+
+// Anchors the slope range leaves. With th in [lo, hi] = [tm - dl, tm + dl], a
+// point's residual from anchor i, Dy - th Dx, is within dl xr of its value
+// at tm, which is the difference of the keys z = y - tm x. So the points
+// that can be in the anchor's upper window [0, W] at a slope of the range
+// have keys in [z_i - s, z_i + W + s], s = dl xr (plus the keys' roundings),
+// and those of the lower window [-W, 0] in [z_i - W - s, z_i + s]. An anchor
+// whose key intervals hold fewer than h points each is in no pair that can
+// be optimal; a pair's partner has its key in the anchor's intervals too.
+//
+// Block 0 sorts the points into kRangeBuckets buckets of equal key width
+// (counting sort: perm lists the points bucket by bucket, sxy holds them in
+// that order) and lists the
+// anchors that are left, with the range [r0, r1) of perm that covers the
+// intervals that can reach h (whole buckets: a superset). The other blocks
+// count the vertical pairs (equal x), which the slope-bin kernel no longer
+// meets when it skips anchors. Without a finite range nothing changes.
+constexpr int kRangeBuckets = 4096;
+constexpr int kPrunedBins = 2048;
+constexpr int kVertSlice = 256;
+template <int NT, int E>
+__global__ __launch_bounds__(NT) void k_range(const double* __restrict__ xy, Ctx* ctx,
+                                              const double* __restrict__ grid_theta,
+                                              const double4* __restrict__ grid_res,
+                                              unsigned* __restrict__ perm,
+                                              double2* __restrict__ sxy,
+                                              uint2* __restrict__ live) {
+  __shared__ unsigned s_start[kRangeBuckets + 1], s_cur[kRangeBuckets];
+  __shared__ unsigned s_part[NT / 64];
+  __shared__ unsigned s_live;
+  __shared__ double xs[kVertSlice];
+  const Ctx c = *ctx;
+  if (c.status != LMS_OK || c.all_x_equal) return;
+  const int n = c.n, h = c.h, t = threadIdx.x, lane = t & 63;
+  const double W = __longlong_as_double((long long)c.wbound);
+  // the bins count the windows of width W (1 + 2^-50)
+  const double Wl = W * (1.0 + 0x1p-50) * (1.0 + 0x1p-40);
+  double lo, hi;
+  slope_range<NT>(c, Wl, grid_theta, grid_res, &lo, &hi);
+  if (!(lo > -INFINITY && hi < INFINITY)) return;  // n_live stays -1
+  {  // the pairs' computed slopes carry a relative error below 2^-39
+    const double m = 0x1p-30 * fmax(fabs(lo), fabs(hi)) + 0x1p-1000;
+    lo -= m;
+    hi += m;
+  }
+  // The pruned screen spreads the range over kPrunedBins bins; a range so wide
+  // that their centre would be over 4 times coarser than the full screen's
+  // (NB bins, scale kBinMag x-range / y-range) stays with the full screen.
+  {
+    const unsigned nb = 1u << (31 - __builtin_clz(c.bins));
+    const double sc_full = fmin(fmax(c.yh > 0.0 ? kBinMag * c.xh / c.yh : 1.0, 0x1p-100), 0x1p100);
+    const double dl = 0.5 * (hi - lo);
+    if (!(c.bins > 0u) || !(3.0 / dl * 4.0 >= sc_full * (double)(nb / kPrunedBins))) return;
+  }
+  if (blockIdx.x > 0) {
+    // vertical pairs (i < j, x_i == x_j): items of NT anchors by kVertSlice partners
+    const int tiles = (n + NT - 1) / NT, slices = (n + kVertSlice - 1) / kVertSlice;
+    unsigned long long cnt = 0;
+    for (int it = blockIdx.x - 1; it < tiles * slices; it += gridDim.x - 1) {
+      const int a0 = (it / slices) * NT, j0 = (it % slices) * kVertSlice;
+      if (j0 + kVertSlice <= a0 + 1) continue;  // no partner above the tile's anchors
+      __syncthreads();
+      for (int q = t; q < kVertSlice; q += NT)
+        xs[q] = j0 + q < n ? xy[2 * (j0 + q)] : __longlong_as_double(0x7FF8000000000000ll);
+      __syncthreads();
+      const int i = a0 + t;
+      if (i < n) {
+        const double xi = xy[2 * i];
+        const int after = i - j0;  // partners j = j0 + q > i
+        unsigned c32 = 0;
+#pragma unroll 16
+        for (int q = 0; q < kVertSlice; ++q) c32 += (xs[q] == xi && q > after) ? 1u : 0u;
+        cnt += c32;
+      }
+    }
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) cnt += __shfl_xor(cnt, m);
+    if (lane == 0) stat_add(ctx, ST_VERT, cnt);
+    return;
+  }
+  const double tm = lo + 0.5 * (hi - lo);
+  const double dl = fmax(hi - tm, tm - lo) * (1.0 + 0x1p-40);
+  // two key roundings, each below 2^-53 (|y| + |tm| |x|)
+  const double s = dl * c.xr * (1.0 + 0x1p-40) + 8.0 * 0x1p-53 * (c.yabs + fabs(tm) * c.xabs);
+  double z[E];
+  double2 pt[E];
+  double mn = INFINITY, mx = -INFINITY;
+  const double2* pts = reinterpret_cast<const double2*>(xy);
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int k = t + e * NT;
+    pt[e] = k < n ? pts[k] : make_double2(0.0, 0.0);
+    z[e] = fma(-tm, pt[e].x, pt[e].y);
+    if (k < n) {
+      mn = fmin(mn, z[e]);
+      mx = fmax(mx, z[e]);
+    }
+  }
+  block_min_max<NT>(mn, mx);
+  // bucket of a key: monotone in the key (a rounded difference, a rounded
+  // product by sc >= 0, truncation, clamps), so a key interval maps into the
+  // buckets between those of its ends
+  const double span = mx - mn;
+  const double sc = span > 0.0 && span < INFINITY ? kRangeBuckets / span : 0.0;
+  auto bucket = [&](double v) {
+    const double f = (v - mn) * sc;
+    return f >= (double)(kRangeBuckets - 1) ? kRangeBuckets - 1 : (f > 0.0 ? (int)f : 0);
+  };
+  for (int b = t; b < kRangeBuckets; b += NT) s_cur[b] = 0u;
+  if (t == 0) s_live = 0u;
+  __syncthreads();
+  int bk[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    bk[e] = bucket(z[e]);
+    if (t + e * NT < n) atomicAdd(&s_cur[bk[e]], 1u);
+  }
+  __syncthreads();
+  {  // exclusive prefix sum of the counts into s_start, thread t: buckets t S ..
+    constexpr int S = kRangeBuckets / NT;
+    static_assert(S * NT == kRangeBuckets, "buckets per thread");
+    unsigned v[S], run = 0;
+#pragma unroll
+    for (int r = 0; r < S; ++r) {
+      v[r] = run;
+      run += s_cur[t * S + r];
+    }
+    unsigned x = run;
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) {
+      const unsigned y = __shfl_up(x, m);
+      if (lane >= m) x += y;
+    }
+    if (lane == 63) s_part[t >> 6] = x;
+    __syncthreads();
+    unsigned off = x - run;
+    for (int w = 0; w < (t >> 6); ++w) off += s_part[w];
+#pragma unroll
+    for (int r = 0; r < S; ++r) {
+      s_start[t * S + r] = v[r] + off;
+      s_cur[t * S + r] = v[r] + off;
+    }
+    if (t == NT - 1) s_start[kRangeBuckets] = off + run;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int k = t + e * NT;
+    if (k < n) {
+      const unsigned pos = atomicAdd(&s_cur[bk[e]], 1u);
+      perm[pos] = (unsigned)k;
+      sxy[pos] = pt[e];
+    }
+  }
+  // anchors left, with the perm range of the intervals that can reach h
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int i = t + e * NT;
+    bool keep = false;
+    unsigned r0 = 0, r1 = 0;
+    if (i < n) {
+      const double zi = z[e];
+      // interval ends, rounded outwards past the subtraction's rounding
+      const double g = 0x1p-50 * (fabs(zi) + Wl + s);
+      const int bA = bucket(zi - Wl - s - g), bB = bucket(zi - s - g);
+      const int bC = bucket(zi + s + g), bD = bucket(zi + Wl + s + g);
+      const unsigned cD = s_start[bC + 1] - s_start[bA], cU = s_start[bD + 1] - s_start[bB];
+      const bool okU = cU >= (unsigned)h, okD = cD >= (unsigned)h;
+      keep = okU || okD;
+      r0 = okD ? s_start[bA] : s_start[bB];
+      r1 = okU ? s_start[bD + 1] : s_start[bC + 1];
+    }
+    const unsigned long long mk = lane_mask(keep);
+    if (mk) {
+      unsigned base = 0;
+      if (lane == 0) base = atomicAdd(&s_live, (unsigned)__popcll(mk));
+      base = __shfl(base, 0);
+      if (keep) live[base + __popcll(mk & ((1ull << lane) - 1ull))] = make_uint2((unsigned)i, r0 | (r1 << 16));
+    }
+  }
+  __syncthreads();
+  if (t == 0) {
+    ctx->th_lo = lo;
+    ctx->th_hi = hi;
+    ctx->n_live = (int)s_live;
+  }
+}
+
+void launch_range(hipStream_t s, int n, int cu, const double* xy, Ctx* ctx,
+                  const double* grid_theta, const double4* grid_res, unsigned* perm,
+                  double2* sxy, uint2* live) {
+  const int tiles = (n + 1023) / 1024, slices = (n + kVertSlice - 1) / kVertSlice;
+  const int grid = 1 + std::min(tiles * slices, 2 * cu);
+  if (n <= 1024)
+    hipLaunchKernelGGL((k_range<1024, 1>), dim3(grid), dim3(1024), 0, s, xy, ctx, grid_theta, grid_res, perm, sxy, live);
+  else if (n <= 4096)
+    hipLaunchKernelGGL((k_range<1024, 4>), dim3(grid), dim3(1024), 0, s, xy, ctx, grid_theta, grid_res, perm, sxy, live);
+  else
+    hipLaunchKernelGGL((k_range<1024, 16>), dim3(grid), dim3(1024), 0, s, xy, ctx, grid_theta, grid_res, perm, sxy, live);
 }
 
 // F(theta) at arbitrary slopes (seed slopes and lms_eval_slopes).
@@ -729,7 +1032,10 @@ __global__ __launch_bounds__(NT) void k_bins(const double* __restrict__ xy, Ctx*
                                              uint2* __restrict__ cands, int cand_cap,
                                              uint2* __restrict__ entries, int cap,
                                              const double4* __restrict__ seed_res,
-                                             const double4* __restrict__ seed_rec, int n_rec) {
+                                             const double4* __restrict__ seed_rec, int n_rec,
+                                             const unsigned* __restrict__ perm,
+                                             const double2* __restrict__ sxy,
+                                             const uint2* __restrict__ live) {
   // NB + NT bins, an odd number per thread in the prefix sum, and one word
   // for the decrements past the last bin
   constexpr int NBINS = NB + NT;
@@ -786,8 +1092,123 @@ __global__ __launch_bounds__(NT) void k_bins(const double* __restrict__ xy, Ctx*
     }
   };
   if (t == 0) s_fill = 0;
+  // With a slope range (k_range), only the anchors it leaves, only the
+  // points of their key intervals (the others are in no window of theirs at
+  // a slope of the range), and only the partners among those points whose
+  // slope bin can hold a slope of the range. The frame is centred on the
+  // best seed slope, as the full one, and scaled to spread the range over
+  // most of NBP bins (offsets up to 3 in map units), but no coarser near its
+  // centre than the full frame. Vertical pairs are counted by k_range then.
+  constexpr int NBP = kPrunedBins, NBINSP = NBP + NT, kRLogP = __builtin_ctz(NBP) - 1;
+  static_assert((NBP % NT) == 0 && ((NBP / NT) & 1) == 0 && NBINSP <= NBINS, "pruned bins");
+  const int n_live = c.n_live;
+  BinFrame FP = F;
+  int blo = 0, bhi = 0;
+  if (n_live >= 0) {
+    const double tm = c.th_lo + 0.5 * (c.th_hi - c.th_lo);
+    const double dl = fmax(c.th_hi - tm, tm - c.th_lo);
+    double sc = fmax(3.0 / dl, F.sc * (double)(NB / NBP));
+    if (fabs(F.tc) * sc > 0x1p20) sc = 0x1p20 / fabs(F.tc);
+    FP.sc = fmin(fmax(sc, 0x1p-100), 0x1p100);
+    FP.tc = fabs(F.tc) * FP.sc <= 0x1p20 ? F.tc : 0.0;
+    FP.q = W < INFINITY ? 0x1p-46 * NBINSP * FP.sc : INFINITY;
+    blo = fbin<kRLogP>((c.th_lo - FP.tc) * FP.sc) - 2;
+    bhi = fbin<kRLogP>((c.th_hi - FP.tc) * FP.sc) + 2;
+  }
+  // Pruned anchors always store their points' codes, and their indices,
+  // past the NBINSP pruned bins when the bin array has room for both (NB >=
+  // 2 NBP; runs hold at most NB / 2 points), else codes in list and indices
+  // read from perm.
+  constexpr bool PIDX = NB >= 2 * NBP;
+  unsigned short* pcode = PIDX ? reinterpret_cast<unsigned short*>(bins + NBINSP + 1) : list;
+  unsigned short* pidx = pcode + NB / 2;
+  for (int q = blockIdx.x; q < n_live; q += gridDim.x) {
+    __syncthreads();  // the previous anchor's queries are done with the bins
+    if (t == 0) {
+      s_all = 0;
+      s_cnt = 0;
+      s_pos = 0;
+    }
+    for (int b = t; b <= NBINSP; b += NT) bins[b] = 0u;
+    __syncthreads();
+    const uint2 lv = live[q];
+    const int i = (int)lv.x, r0 = (int)(lv.y & 0xFFFFu), len = (int)(lv.y >> 16) - r0;
+    const unsigned* run = perm + r0;
+    const double2* rxy = sxy + r0;
+    const double xi = xy[2 * i], yi = xy[2 * i + 1];
+    unsigned all = 0;
+    double2 nxt = t < len ? rxy[t] : make_double2(0.0, 0.0);
+    for (int p = t; p < len; p += NT) {
+      const double2 cur = nxt;
+      if (p + NT < len) nxt = rxy[p + NT];
+      if (PIDX) pidx[p] = (unsigned short)run[p];
+      all += add_point_bins_coded<kRLogP>(bins, cur.x - xi, cur.y - yi, W, lim, FP, th_lim,
+                                          &pcode[p]);
+    }
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) all += __shfl_xor(all, m);
+    if (lane == 0) atomicAdd(&s_all, all);
+    __syncthreads();
+    scan_bins<NBINSP, NT>(bins, s_part);
+    __syncthreads();
+    const unsigned pall = s_all;
+    const int P = (n & 1) ? half : (i < half ? half : half - 1);
+    // the anchor's partners are j = (i + o) mod n, o = 1..P
+    auto owned = [&](int j) {
+      const int o = j >= i ? j - i : j - i + n;
+      return o >= 1 && o <= P;
+    };
+    auto index = [&](int p) { return PIDX ? (int)pidx[p] : (int)run[p]; };
+    for (int p0 = 0; p0 < len; p0 += NT) {
+      const int p = p0 + t;
+      const int j = p < len ? index(p) : i;
+      const bool valid = p < len && owned(j);
+      const unsigned cj = valid ? pcode[p] : 0u;
+      const bool force = valid && cj == kCodeFP64;
+      const bool test = valid && cj > kCodePass && (int)cj >= blo && (int)cj <= bhi;
+      const bool pass = test && bins_pass(bins[cj], pall, h);
+      const unsigned long long mp = lane_mask(pass);
+      n_forced += __popcll(lane_mask(force));
+      n_scr += __popcll(lane_mask(test));
+      n_pass += __popcll(mp);
+      if (force) append_entry(ctx, entries, cap, (unsigned)min(i, j), (unsigned)max(i, j));
+      if (pass) pcode[p] = kCodePass;
+      if (mp && lane == 0) atomicAdd(&s_cnt, (unsigned)__popcll(mp));
+    }
+    __syncthreads();
+    const unsigned cnt = s_cnt;
+    if (cnt) {
+      if (s_fill + cnt > (unsigned)PB) flush();
+      const bool direct = cnt > (unsigned)PB;
+      if (direct) {
+        if (t == 0) reserve(cnt);
+        __syncthreads();
+      }
+      const unsigned base = direct ? s_base : s_fill;
+      for (int p0 = 0; p0 < len; p0 += NT) {
+        const int p = p0 + t;
+        const bool m = p < len && pcode[p] == kCodePass;
+        const unsigned long long mm = lane_mask(m);
+        if (mm) {
+          unsigned q0 = 0;
+          if (lane == 0) q0 = atomicAdd(&s_pos, (unsigned)__popcll(mm));
+          q0 = __shfl(q0, 0);
+          if (m) {
+            const unsigned q2 = base + q0 + (unsigned)__popcll(mm & ((1ull << lane) - 1ull));
+            const uint2 pr = make_uint2((unsigned)i, (unsigned)index(p));
+            if (!direct) pbuf[q2] = pr;
+            else if (q2 < (unsigned)cand_cap) cands[q2] = pr;
+          }
+        }
+      }
+      if (!direct) {
+        __syncthreads();
+        if (t == 0) s_fill = base + cnt;
+      }
+    }
+  }
   // anchors round-robin over the blocks (no shared counter)
-  for (int i = blockIdx.x; i < n; i += gridDim.x) {
+  for (int i = n_live >= 0 ? n : blockIdx.x; i < n; i += gridDim.x) {
     __syncthreads();  // the previous anchor's queries are done with the bins
     if (t == 0) {
       s_all = 0;
@@ -1142,7 +1563,7 @@ __global__ __launch_bounds__(1024) void k_finalize(Ctx* ctx, const uint2* __rest
 // ---------------------------------------------------------------- host side
 
 struct Layout {
-  size_t ctx, xy32, entries, res, rec, cands, sort_tmp, total;
+  size_t ctx, xy32, entries, res, rec, cands, sort_tmp, grid, range, total;
 };
 
 // n_rec: windows of the device seed slopes (kept only for window pairs);
@@ -1159,7 +1580,9 @@ Layout layout(int n_pad, long long cap, long long n_rec = 0, long long cand_cap 
   L.rec = L.res + up((size_t)cap * sizeof(double4));
   L.cands = L.rec + up((size_t)n_rec * sizeof(double4));
   L.sort_tmp = L.cands + up((size_t)cand_cap * sizeof(uint2));
-  L.total = L.sort_tmp + up((size_t)sort_tmp * sizeof(double));
+  L.grid = L.sort_tmp + up((size_t)sort_tmp * sizeof(double));
+  L.range = L.grid + up(kGrid * (sizeof(double) + sizeof(double4)));
+  L.total = L.range + up((size_t)n_pad * (sizeof(unsigned) + sizeof(uint2) + sizeof(double2)));
   return L;
 }
 
@@ -1190,12 +1613,13 @@ void launch_recheck_n2(hipStream_t s, int grid, const double* xy, Ctx* ctx, cons
 // grid: k_merge_window's workgroups.
 template <int NP>
 void launch_split_np(hipStream_t s, int grid, int gy, int slots, const double* xy, Ctx* ctx,
-                     const uint2* e, double4* res, int begin, int cap, int upd, double* tmp) {
+                     const uint2* e, double4* res, int begin, int cap, int upd, double* tmp,
+                     const double* thetas) {
   constexpr int NT = NP >= 2048 ? 1024 : 256;
   hipLaunchKernelGGL((k_sort_chunks<kSplitChunk, kSplitNT>), dim3(NP / kSplitChunk, gy),
-                     dim3(kSplitNT), 0, s, xy, ctx, e, begin, cap, slots, tmp, NP);
+                     dim3(kSplitNT), 0, s, xy, ctx, e, begin, cap, slots, tmp, NP, thetas);
   hipLaunchKernelGGL((k_merge_window<NP, NT>), dim3(grid), dim3(NT), 0, s, xy, ctx, e, res, begin,
-                     cap, upd, tmp, slots);
+                     cap, upd, tmp, slots, thetas);
 }
 
 // Number of entries that one split launch pair sorts in pieces (0: whole-sort
@@ -1210,15 +1634,16 @@ int split_slots(int n, int expected) {
 // doubles), gy at a time per chunk; `grid` workgroups merge them and sort any
 // further ones whole.
 void launch_recheck(hipStream_t s, int n, int grid, const double* xy, Ctx* ctx, const uint2* e,
-                    double4* res, int begin, int cap, int upd, double* tmp, int slots, int gy) {
+                    double4* res, int begin, int cap, int upd, double* tmp, int slots, int gy,
+                    const double* thetas = nullptr) {
   if (tmp && slots > 0) {
     gy = std::max(1, std::min(gy, slots));
     switch (next_pow2(n)) {
-      case 1024: launch_split_np<1024>(s, grid, gy, slots, xy, ctx, e, res, begin, cap, upd, tmp); return;
-      case 2048: launch_split_np<2048>(s, grid, gy, slots, xy, ctx, e, res, begin, cap, upd, tmp); return;
-      case 4096: launch_split_np<4096>(s, grid, gy, slots, xy, ctx, e, res, begin, cap, upd, tmp); return;
-      case 8192: launch_split_np<8192>(s, grid, gy, slots, xy, ctx, e, res, begin, cap, upd, tmp); return;
-      default: launch_split_np<16384>(s, grid, gy, slots, xy, ctx, e, res, begin, cap, upd, tmp); return;
+      case 1024: launch_split_np<1024>(s, grid, gy, slots, xy, ctx, e, res, begin, cap, upd, tmp, thetas); return;
+      case 2048: launch_split_np<2048>(s, grid, gy, slots, xy, ctx, e, res, begin, cap, upd, tmp, thetas); return;
+      case 4096: launch_split_np<4096>(s, grid, gy, slots, xy, ctx, e, res, begin, cap, upd, tmp, thetas); return;
+      case 8192: launch_split_np<8192>(s, grid, gy, slots, xy, ctx, e, res, begin, cap, upd, tmp, thetas); return;
+      default: launch_split_np<16384>(s, grid, gy, slots, xy, ctx, e, res, begin, cap, upd, tmp, thetas); return;
     }
   }
   switch (next_pow2(n)) {
@@ -1376,7 +1801,8 @@ constexpr int bins_threads() {
 template <int NB>
 hipError_t launch_bins_nb(hipStream_t s, int cu, int n, const double* xy, Ctx* ctx, uint2* cands,
                           int cand_cap, uint2* e, int cap, const double4* res,
-                          const double4* rec, int n_rec) {
+                          const double4* rec, int n_rec, const unsigned* perm,
+                          const double2* sxy, const uint2* live) {
   constexpr int nt = bins_threads<NB>();
   static int resident = 0;
   if (resident == 0) {
@@ -1390,19 +1816,20 @@ hipError_t launch_bins_nb(hipStream_t s, int cu, int n, const double* xy, Ctx* c
   }
   const int grid = std::max(1, std::min(n, cu * resident));
   hipLaunchKernelGGL((k_bins<NB, nt>), dim3(grid), dim3(nt), 0, s, xy, ctx, cands, cand_cap, e,
-                     cap, res, rec, rec ? n_rec : 0);
+                     cap, res, rec, rec ? n_rec : 0, perm, sxy, live);
   return hipGetLastError();
 }
 
 hipError_t launch_bins(hipStream_t s, int nb_log2, int cu, int n, const double* xy, Ctx* ctx,
                        uint2* cands, int cand_cap, uint2* e, int cap, const double4* res,
-                       const double4* rec, int n_rec) {
+                       const double4* rec, int n_rec, const unsigned* perm,
+                       const double2* sxy, const uint2* live) {
   switch (nb_log2) {
-    case 11: return launch_bins_nb<2048>(s, cu, n, xy, ctx, cands, cand_cap, e, cap, res, rec, n_rec);
-    case 12: return launch_bins_nb<4096>(s, cu, n, xy, ctx, cands, cand_cap, e, cap, res, rec, n_rec);
-    case 13: return launch_bins_nb<8192>(s, cu, n, xy, ctx, cands, cand_cap, e, cap, res, rec, n_rec);
-    case 14: return launch_bins_nb<16384>(s, cu, n, xy, ctx, cands, cand_cap, e, cap, res, rec, n_rec);
-    default: return launch_bins_nb<32768>(s, cu, n, xy, ctx, cands, cand_cap, e, cap, res, rec, n_rec);
+    case 11: return launch_bins_nb<2048>(s, cu, n, xy, ctx, cands, cand_cap, e, cap, res, rec, n_rec, perm, sxy, live);
+    case 12: return launch_bins_nb<4096>(s, cu, n, xy, ctx, cands, cand_cap, e, cap, res, rec, n_rec, perm, sxy, live);
+    case 13: return launch_bins_nb<8192>(s, cu, n, xy, ctx, cands, cand_cap, e, cap, res, rec, n_rec, perm, sxy, live);
+    case 14: return launch_bins_nb<16384>(s, cu, n, xy, ctx, cands, cand_cap, e, cap, res, rec, n_rec, perm, sxy, live);
+    default: return launch_bins_nb<32768>(s, cu, n, xy, ctx, cands, cand_cap, e, cap, res, rec, n_rec, perm, sxy, live);
   }
 }
 
@@ -1638,6 +2065,24 @@ lms_status enqueue_solve(const Setup& S, char* base, hipStream_t s, lms_host::St
                        window_pairs, entries, first_w + window_pairs, window_pairs, key ^ 0xA2ull);
     seed_windows(std::min(window_pairs, 4 * cu), first_w + window_pairs, p.n_seeds, 1);
   }
+  // Slope range of the slope-bin screen: exact windows at kGrid slopes around
+  // the best seed slope (they may lower W too), then the range, the key
+  // buckets and the anchors it leaves.
+  unsigned* perm = (unsigned*)(base + L.range);
+  uint2* live = (uint2*)(perm + p.n_pad);
+  double2* sxy = (double2*)(live + p.n_pad);
+  if (S.use_bins && !S.no_prune) {
+    double* grid_theta = (double*)(base + L.grid);
+    double4* grid_res = (double4*)(grid_theta + kGrid);
+    hipLaunchKernelGGL(k_grid_slopes<256>, dim3(1), dim3(256), 0, s, ctx, res, p.n_seeds,
+                       n_seed_theta > 0 ? rec : nullptr, (int)n_seed_theta, grid_theta);
+    if (p.n <= kSeedExactMax)
+      launch_eval(s, kGrid, d_xy, p.n, p.h, grid_theta, kGrid, nullptr, ctx, grid_res);
+    else
+      launch_recheck(s, p.n, kGrid, d_xy, ctx, entries, grid_res, 0, kGrid, 1, tmp, kGrid, kGrid,
+                     grid_theta);
+    launch_range(s, p.n, cu, d_xy, ctx, grid_theta, grid_res, perm, sxy, live);
+  }
   mark();
   // Screen. With slope bins: per-anchor bin counts, then the FP32 test of the
   // pairs they pass, and the exhaustive FP32 screen only if their list could
@@ -1647,7 +2092,7 @@ lms_status enqueue_solve(const Setup& S, char* base, hipStream_t s, lms_host::St
     uint2* cands = (uint2*)(base + L.cands);
     err = launch_bins(s, S.bins_log2, cu, p.n, d_xy, ctx, cands, (int)S.cand_cap, entries,
                       (int)p.cap, res, n_seed_theta > 0 && !S.no_prune ? rec : nullptr,
-                      (int)n_seed_theta);
+                      (int)n_seed_theta, perm, sxy, live);
     mark();
     if (err == hipSuccess)
       err = launch_list(s, p.R, p.lds, cu, d_xy, xy32, ctx, cands, (int)S.cand_cap, entries,

@@ -176,13 +176,15 @@ def test_seed_slopes_do_not_change_result(gpu):
 def test_window_pairs_do_not_change_result(gpu, orc, n):
     """Window-pair seeds (drawn from the best seed line's window) only tighten
     the bound: every seed line, good, poor, absurd or NaN, gives the same
-    exact line, and a good one prunes at least as well as no seed."""
+    exact line, and a good one prunes at least as well as no seed. (The
+    reference run has neither seeds nor the slope-bin screen, whose slope grid
+    would act as seeds of its own.)"""
     xy = planted(n, 0.45, 7000 + n)
     base = gpu.solve(dev(xy))
     if n <= 2000:
         o = orc.solve(xy)
         assert (base.width, base.theta1, base.z_lo) == (o.width, o.theta1, o.z_lo)
-    none = gpu.solve(dev(xy), seed_pairs=0)
+    none = gpu.solve(dev(xy), seed_pairs=0, bins_log2=-1)
     for th in ([base.theta1], [base.theta1 + 0.05], [0.7, -2.0], [1e6], [float("nan")]):
         t = torch.tensor(th, dtype=torch.float64, device="cuda:0")
         for wp in (1, 63, 1000):
