@@ -80,6 +80,12 @@ typedef struct lms_result {
                              workspace until lms_shutdown. */
 #define LMS_F_NO_PRUNE 1u /* no width bound: the screen keeps every pair whose anchored
                              window can hold h points at all (slow; for tests) */
+#define LMS_F_RANGE 4u    /* lms_solve: bound the optimal slope by exact windows at a
+                             grid of slopes (two grids) and run the slope-bin screen
+                             on the anchors and points that range leaves, at any n
+                             (by default above 4096 points; the second grid above
+                             8192) */
+#define LMS_F_NO_RANGE 8u /* lms_solve: never (LMS_F_RANGE wins over it) */
 
 typedef struct lms_options {
   uint32_t struct_size; /* sizeof(lms_options) */

@@ -26,6 +26,8 @@ LMS_OK, LMS_OK_DEGENERATE = 0, 1
 LMS_ERR_ARG, LMS_ERR_NONFINITE, LMS_ERR_DEVICE, LMS_ERR_NOMEM, LMS_ERR_CAPACITY = -1, -2, -3, -4, -5
 LMS_F_NO_PRUNE = 1
 LMS_F_GRAPH = 2
+LMS_F_RANGE = 4
+LMS_F_NO_RANGE = 8
 BATCH_MAX_N = 4096
 MAX_N = 16384
 RESULT_BYTES = 128
@@ -182,7 +184,8 @@ def solve_async(xy: torch.Tensor, h: int = 0, out: torch.Tensor | None = None, *
                 no_prune: bool = False, seed_pairs: int | None = None,
                 seed_theta: torch.Tensor | None = None, tile_regs: int = 0,
                 tile_batches: int = 0, window_pairs: int = 0, bins_log2: int = 0,
-                graph: bool = False, stream=None) -> torch.Tensor:
+                graph: bool = False, slope_range: bool | None = None,
+                stream=None) -> torch.Tensor:
     """Enqueue one exact LMS solve; returns the device uint8[128] result buffer.
 
     seed_theta: optional CUDA float64 slopes whose exact widths seed the bound;
@@ -190,11 +193,14 @@ def solve_async(xy: torch.Tensor, h: int = 0, out: torch.Tensor | None = None, *
     (two rounds) as further seeds. bins_log2: slope bins per anchor of the
     first screen (0 automatic, -1 off). graph=True captures the solve in a
     hipGraph on the first call and replays it on later calls with the same
-    buffers and options."""
+    buffers and options. slope_range: None automatic (above 4096 points),
+    True at any n, False never."""
     xy = _points(xy)
     if out is None:
         out = torch.empty(RESULT_BYTES, dtype=torch.uint8, device=xy.device)
     flags = (LMS_F_NO_PRUNE if no_prune else 0) | (LMS_F_GRAPH if graph else 0)
+    if slope_range is not None:
+        flags |= LMS_F_RANGE if slope_range else LMS_F_NO_RANGE
     opt = _options(flags, seed_pairs, seed_theta, tile_regs, tile_batches, window_pairs,
                    bins_log2)
     st = load().lms_solve(xy.data_ptr(), xy.shape[0], h, out.data_ptr(), ctypes.byref(opt),

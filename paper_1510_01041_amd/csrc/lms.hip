@@ -267,7 +267,7 @@ __global__ __launch_bounds__(NT) void k_sort_chunks(const double* __restrict__ x
   const int k0 = blockIdx.x * C;
   for (unsigned y = blockIdx.y; begin + y < end; y += gridDim.y) {
     double theta = thetas ? thetas[begin + y] : 0.0;
-    if (!thetas && !entry_slope(xy, entries[begin + y], &theta)) continue;
+    if (thetas ? !(theta == theta) : !entry_slope(xy, entries[begin + y], &theta)) continue;
     double v[E];
 #pragma unroll
     for (int r = 0; r < E; ++r) {
@@ -304,7 +304,7 @@ __global__ __launch_bounds__(NT) void k_merge_window(const double* __restrict__ 
   };
   for (unsigned e = begin + blockIdx.x; e < split_end; e += gridDim.x) {
     double theta = thetas ? thetas[e] : 0.0;
-    if (!thetas && !entry_slope(xy, entries[e], &theta)) {
+    if (thetas ? !(theta == theta) : !entry_slope(xy, entries[e], &theta)) {
       if (threadIdx.x == 0) res[e] = make_double4(INFINITY, NAN, NAN, NAN);
       continue;
     }
@@ -318,7 +318,7 @@ __global__ __launch_bounds__(NT) void k_merge_window(const double* __restrict__ 
   }
   for (unsigned e = split_end + blockIdx.x; e < end; e += gridDim.x) {
     double theta = thetas ? thetas[e] : 0.0;
-    if (!thetas && !entry_slope(xy, entries[e], &theta)) {
+    if (thetas ? !(theta == theta) : !entry_slope(xy, entries[e], &theta)) {
       if (threadIdx.x == 0) res[e] = make_double4(INFINITY, NAN, NAN, NAN);
       continue;
     }
@@ -545,16 +545,18 @@ __global__ __launch_bounds__(NT) void k_grid_slopes(const Ctx* ctx, const double
 // [lo, hi] from the grid's exact windows (width in .x, as in k_recheck; NaN
 // or +inf widths exclude nothing) against the bound W, by the whole block
 // (all threads call; the result goes to every thread); (-inf, +inf) when the
-// far grid slopes are not ruled out.
+// far grid slopes are not ruled out. With `refine`, entries kGrid..2 kGrid-1
+// are a second grid, of ascending slopes inside the range, whose exclusions
+// then move the range's ends inwards.
 template <int NT>
 __device__ void slope_range(const Ctx& c, double W, const double* __restrict__ grid_theta,
-                            const double4* __restrict__ grid_res, double* lo_out,
+                            const double4* __restrict__ grid_res, bool refine, double* lo_out,
                             double* hi_out) {
-  static_assert(NT >= kGrid, "one thread per grid slope");
-  __shared__ double s_t[kGrid], s_m[kGrid], s_r[kGrid], s_lohi[2];
+  static_assert(NT >= 2 * kGrid, "one thread per grid slope");
+  __shared__ double s_t[2 * kGrid], s_m[2 * kGrid], s_r[2 * kGrid], s_lohi[2];
   const int t = threadIdx.x;
   const bool usable = W < INFINITY && c.xr > 0.0 && c.xr < INFINITY && c.yr < INFINITY;
-  if (usable && t < kGrid) {
+  if (usable && t < (refine ? 2 * kGrid : kGrid)) {
     // lower bound of the exact width at grid slope t, minus W, and the
     // radius it excludes
     const double th = grid_theta[t], w = grid_res[t].x;
@@ -597,12 +599,60 @@ __device__ void slope_range(const Ctx& c, double W, const double* __restrict__ g
       lo = -INFINITY;
       hi = INFINITY;
     }
+    if (refine && lo > -INFINITY && hi < INFINITY) {
+      // from each end inwards, while the second grid's exclusions join up
+      double a = lo, b = hi;
+      for (int k = kGrid; k < 2 * kGrid; ++k) {
+        const double r = s_r[k], th = s_t[k];
+        if (r > 0.0 && th - r <= a) a = fmax(a, th + r);
+        else if (!(th + r < a)) break;
+      }
+      for (int k = 2 * kGrid - 1; k >= kGrid; --k) {
+        const double r = s_r[k], th = s_t[k];
+        if (r > 0.0 && th + r >= b) b = fmin(b, th - r);
+        else if (!(th - r > b)) break;
+      }
+      if (a < b) {  // (always, as above)
+        lo = a;
+        hi = b;
+      }
+    }
     s_lohi[0] = lo;
     s_lohi[1] = hi;
   }
   __syncthreads();
   *lo_out = s_lohi[0];
   *hi_out = s_lohi[1];
+}
+
+// The pruned screen spreads a slope range over kPrunedBins bins; a range so
+// wide that their centre would be over 4 times coarser than the full
+// screen's (NB bins, scale kBinMag x-range / y-range) stays with the full
+// screen.
+constexpr int kPrunedBins = 2048;
+__device__ bool narrow_range(const Ctx& c, double lo, double hi) {
+  if (!(lo > -INFINITY && hi < INFINITY) || c.bins == 0u) return false;
+  const unsigned nb = 1u << (31 - __builtin_clz(c.bins));
+  const double sc_full = fmin(fmax(c.yh > 0.0 ? kBinMag * c.xh / c.yh : 1.0, 0x1p-100), 0x1p100);
+  const double dl = 0.5 * (hi - lo);
+  return 3.0 / dl * 4.0 >= sc_full * (double)(nb / kPrunedBins);
+}
+
+// Second grid: kGrid ascending slopes spread over the range of the first
+// grid's windows against the bound they left; NaN (the windows of the grid
+// kernels skip them) when that range is not narrow enough to prune with.
+// One block.
+__global__ __launch_bounds__(64) void k_grid_refine(const Ctx* ctx, double* grid_theta,
+                                                    const double4* grid_res) {
+  const Ctx c = *ctx;
+  const double W = __longlong_as_double((long long)c.wbound);
+  const double Wl = W * (1.0 + 0x1p-50) * (1.0 + 0x1p-40);
+  double lo = -INFINITY, hi = INFINITY;
+  if (c.status == LMS_OK && !c.all_x_equal)
+    slope_range<64>(c, Wl, grid_theta, grid_res, false, &lo, &hi);
+  const int t = threadIdx.x;
+  if (t < kGrid)
+    grid_theta[kGrid + t] = narrow_range(c, lo, hi) ? lo + (t + 0.5) * ((hi - lo) / kGrid) : NAN;
 }
 
 // Anchors the slope range leaves. With th in [lo, hi] = [tm - dl, tm + dl], a
@@ -622,13 +672,13 @@ __device__ void slope_range(const Ctx& c, double W, const double* __restrict__ g
 // count the vertical pairs (equal x), which the slope-bin kernel no longer
 // meets when it skips anchors. Without a finite range nothing changes.
 constexpr int kRangeBuckets = 4096;
-constexpr int kPrunedBins = 2048;
+constexpr int kRangeMinN = 4096, kRefineMinN = 8192;
 constexpr int kVertSlice = 256;
 template <int NT, int E>
 __global__ __launch_bounds__(NT) void k_range(const double* __restrict__ xy, Ctx* ctx,
                                               const double* __restrict__ grid_theta,
                                               const double4* __restrict__ grid_res,
-                                              unsigned* __restrict__ perm,
+                                              bool refine, unsigned* __restrict__ perm,
                                               double2* __restrict__ sxy,
                                               uint2* __restrict__ live) {
   __shared__ unsigned s_start[kRangeBuckets + 1], s_cur[kRangeBuckets];
@@ -642,22 +692,14 @@ __global__ __launch_bounds__(NT) void k_range(const double* __restrict__ xy, Ctx
   // the bins count the windows of width W (1 + 2^-50)
   const double Wl = W * (1.0 + 0x1p-50) * (1.0 + 0x1p-40);
   double lo, hi;
-  slope_range<NT>(c, Wl, grid_theta, grid_res, &lo, &hi);
+  slope_range<NT>(c, Wl, grid_theta, grid_res, refine, &lo, &hi);
   if (!(lo > -INFINITY && hi < INFINITY)) return;  // n_live stays -1
   {  // the pairs' computed slopes carry a relative error below 2^-39
     const double m = 0x1p-30 * fmax(fabs(lo), fabs(hi)) + 0x1p-1000;
     lo -= m;
     hi += m;
   }
-  // The pruned screen spreads the range over kPrunedBins bins; a range so wide
-  // that their centre would be over 4 times coarser than the full screen's
-  // (NB bins, scale kBinMag x-range / y-range) stays with the full screen.
-  {
-    const unsigned nb = 1u << (31 - __builtin_clz(c.bins));
-    const double sc_full = fmin(fmax(c.yh > 0.0 ? kBinMag * c.xh / c.yh : 1.0, 0x1p-100), 0x1p100);
-    const double dl = 0.5 * (hi - lo);
-    if (!(c.bins > 0u) || !(3.0 / dl * 4.0 >= sc_full * (double)(nb / kPrunedBins))) return;
-  }
+  if (!narrow_range(c, lo, hi)) return;
   if (blockIdx.x > 0) {
     // vertical pairs (i < j, x_i == x_j): items of NT anchors by kVertSlice partners
     const int tiles = (n + NT - 1) / NT, slices = (n + kVertSlice - 1) / kVertSlice;
@@ -793,16 +835,16 @@ __global__ __launch_bounds__(NT) void k_range(const double* __restrict__ xy, Ctx
 }
 
 void launch_range(hipStream_t s, int n, int cu, const double* xy, Ctx* ctx,
-                  const double* grid_theta, const double4* grid_res, unsigned* perm,
-                  double2* sxy, uint2* live) {
+                  const double* grid_theta, const double4* grid_res, bool refine,
+                  unsigned* perm, double2* sxy, uint2* live) {
   const int tiles = (n + 1023) / 1024, slices = (n + kVertSlice - 1) / kVertSlice;
   const int grid = 1 + std::min(tiles * slices, 2 * cu);
   if (n <= 1024)
-    hipLaunchKernelGGL((k_range<1024, 1>), dim3(grid), dim3(1024), 0, s, xy, ctx, grid_theta, grid_res, perm, sxy, live);
+    hipLaunchKernelGGL((k_range<1024, 1>), dim3(grid), dim3(1024), 0, s, xy, ctx, grid_theta, grid_res, refine, perm, sxy, live);
   else if (n <= 4096)
-    hipLaunchKernelGGL((k_range<1024, 4>), dim3(grid), dim3(1024), 0, s, xy, ctx, grid_theta, grid_res, perm, sxy, live);
+    hipLaunchKernelGGL((k_range<1024, 4>), dim3(grid), dim3(1024), 0, s, xy, ctx, grid_theta, grid_res, refine, perm, sxy, live);
   else
-    hipLaunchKernelGGL((k_range<1024, 16>), dim3(grid), dim3(1024), 0, s, xy, ctx, grid_theta, grid_res, perm, sxy, live);
+    hipLaunchKernelGGL((k_range<1024, 16>), dim3(grid), dim3(1024), 0, s, xy, ctx, grid_theta, grid_res, refine, perm, sxy, live);
 }
 
 // F(theta) at arbitrary slopes (seed slopes and lms_eval_slopes).
@@ -1032,10 +1074,7 @@ __global__ __launch_bounds__(NT) void k_bins(const double* __restrict__ xy, Ctx*
                                              uint2* __restrict__ cands, int cand_cap,
                                              uint2* __restrict__ entries, int cap,
                                              const double4* __restrict__ seed_res,
-                                             const double4* __restrict__ seed_rec, int n_rec,
-                                             const unsigned* __restrict__ perm,
-                                             const double2* __restrict__ sxy,
-                                             const uint2* __restrict__ live) {
+                                             const double4* __restrict__ seed_rec, int n_rec) {
   // NB + NT bins, an odd number per thread in the prefix sum, and one word
   // for the decrements past the last bin
   constexpr int NBINS = NB + NT;
@@ -1057,7 +1096,7 @@ __global__ __launch_bounds__(NT) void k_bins(const double* __restrict__ xy, Ctx*
   __shared__ unsigned s_part[NT / 64];
   __shared__ unsigned s_all, s_cnt, s_base, s_fill, s_pos;
   const Ctx c = *ctx;
-  if (c.status != LMS_OK || c.all_x_equal) return;
+  if (c.status != LMS_OK || c.all_x_equal || c.n_live >= 0) return;  // (k_bins_pruned)
   const int n = c.n, h = c.h, t = threadIdx.x, lane = t & 63;
   const double W = __longlong_as_double((long long)c.wbound);
   const double lim = W * (1.0 + 0x1p-50);
@@ -1092,123 +1131,8 @@ __global__ __launch_bounds__(NT) void k_bins(const double* __restrict__ xy, Ctx*
     }
   };
   if (t == 0) s_fill = 0;
-  // With a slope range (k_range), only the anchors it leaves, only the
-  // points of their key intervals (the others are in no window of theirs at
-  // a slope of the range), and only the partners among those points whose
-  // slope bin can hold a slope of the range. The frame is centred on the
-  // best seed slope, as the full one, and scaled to spread the range over
-  // most of NBP bins (offsets up to 3 in map units), but no coarser near its
-  // centre than the full frame. Vertical pairs are counted by k_range then.
-  constexpr int NBP = kPrunedBins, NBINSP = NBP + NT, kRLogP = __builtin_ctz(NBP) - 1;
-  static_assert((NBP % NT) == 0 && ((NBP / NT) & 1) == 0 && NBINSP <= NBINS, "pruned bins");
-  const int n_live = c.n_live;
-  BinFrame FP = F;
-  int blo = 0, bhi = 0;
-  if (n_live >= 0) {
-    const double tm = c.th_lo + 0.5 * (c.th_hi - c.th_lo);
-    const double dl = fmax(c.th_hi - tm, tm - c.th_lo);
-    double sc = fmax(3.0 / dl, F.sc * (double)(NB / NBP));
-    if (fabs(F.tc) * sc > 0x1p20) sc = 0x1p20 / fabs(F.tc);
-    FP.sc = fmin(fmax(sc, 0x1p-100), 0x1p100);
-    FP.tc = fabs(F.tc) * FP.sc <= 0x1p20 ? F.tc : 0.0;
-    FP.q = W < INFINITY ? 0x1p-46 * NBINSP * FP.sc : INFINITY;
-    blo = fbin<kRLogP>((c.th_lo - FP.tc) * FP.sc) - 2;
-    bhi = fbin<kRLogP>((c.th_hi - FP.tc) * FP.sc) + 2;
-  }
-  // Pruned anchors always store their points' codes, and their indices,
-  // past the NBINSP pruned bins when the bin array has room for both (NB >=
-  // 2 NBP; runs hold at most NB / 2 points), else codes in list and indices
-  // read from perm.
-  constexpr bool PIDX = NB >= 2 * NBP;
-  unsigned short* pcode = PIDX ? reinterpret_cast<unsigned short*>(bins + NBINSP + 1) : list;
-  unsigned short* pidx = pcode + NB / 2;
-  for (int q = blockIdx.x; q < n_live; q += gridDim.x) {
-    __syncthreads();  // the previous anchor's queries are done with the bins
-    if (t == 0) {
-      s_all = 0;
-      s_cnt = 0;
-      s_pos = 0;
-    }
-    for (int b = t; b <= NBINSP; b += NT) bins[b] = 0u;
-    __syncthreads();
-    const uint2 lv = live[q];
-    const int i = (int)lv.x, r0 = (int)(lv.y & 0xFFFFu), len = (int)(lv.y >> 16) - r0;
-    const unsigned* run = perm + r0;
-    const double2* rxy = sxy + r0;
-    const double xi = xy[2 * i], yi = xy[2 * i + 1];
-    unsigned all = 0;
-    double2 nxt = t < len ? rxy[t] : make_double2(0.0, 0.0);
-    for (int p = t; p < len; p += NT) {
-      const double2 cur = nxt;
-      if (p + NT < len) nxt = rxy[p + NT];
-      if (PIDX) pidx[p] = (unsigned short)run[p];
-      all += add_point_bins_coded<kRLogP>(bins, cur.x - xi, cur.y - yi, W, lim, FP, th_lim,
-                                          &pcode[p]);
-    }
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) all += __shfl_xor(all, m);
-    if (lane == 0) atomicAdd(&s_all, all);
-    __syncthreads();
-    scan_bins<NBINSP, NT>(bins, s_part);
-    __syncthreads();
-    const unsigned pall = s_all;
-    const int P = (n & 1) ? half : (i < half ? half : half - 1);
-    // the anchor's partners are j = (i + o) mod n, o = 1..P
-    auto owned = [&](int j) {
-      const int o = j >= i ? j - i : j - i + n;
-      return o >= 1 && o <= P;
-    };
-    auto index = [&](int p) { return PIDX ? (int)pidx[p] : (int)run[p]; };
-    for (int p0 = 0; p0 < len; p0 += NT) {
-      const int p = p0 + t;
-      const int j = p < len ? index(p) : i;
-      const bool valid = p < len && owned(j);
-      const unsigned cj = valid ? pcode[p] : 0u;
-      const bool force = valid && cj == kCodeFP64;
-      const bool test = valid && cj > kCodePass && (int)cj >= blo && (int)cj <= bhi;
-      const bool pass = test && bins_pass(bins[cj], pall, h);
-      const unsigned long long mp = lane_mask(pass);
-      n_forced += __popcll(lane_mask(force));
-      n_scr += __popcll(lane_mask(test));
-      n_pass += __popcll(mp);
-      if (force) append_entry(ctx, entries, cap, (unsigned)min(i, j), (unsigned)max(i, j));
-      if (pass) pcode[p] = kCodePass;
-      if (mp && lane == 0) atomicAdd(&s_cnt, (unsigned)__popcll(mp));
-    }
-    __syncthreads();
-    const unsigned cnt = s_cnt;
-    if (cnt) {
-      if (s_fill + cnt > (unsigned)PB) flush();
-      const bool direct = cnt > (unsigned)PB;
-      if (direct) {
-        if (t == 0) reserve(cnt);
-        __syncthreads();
-      }
-      const unsigned base = direct ? s_base : s_fill;
-      for (int p0 = 0; p0 < len; p0 += NT) {
-        const int p = p0 + t;
-        const bool m = p < len && pcode[p] == kCodePass;
-        const unsigned long long mm = lane_mask(m);
-        if (mm) {
-          unsigned q0 = 0;
-          if (lane == 0) q0 = atomicAdd(&s_pos, (unsigned)__popcll(mm));
-          q0 = __shfl(q0, 0);
-          if (m) {
-            const unsigned q2 = base + q0 + (unsigned)__popcll(mm & ((1ull << lane) - 1ull));
-            const uint2 pr = make_uint2((unsigned)i, (unsigned)index(p));
-            if (!direct) pbuf[q2] = pr;
-            else if (q2 < (unsigned)cand_cap) cands[q2] = pr;
-          }
-        }
-      }
-      if (!direct) {
-        __syncthreads();
-        if (t == 0) s_fill = base + cnt;
-      }
-    }
-  }
   // anchors round-robin over the blocks (no shared counter)
-  for (int i = n_live >= 0 ? n : blockIdx.x; i < n; i += gridDim.x) {
+  for (int i = blockIdx.x; i < n; i += gridDim.x) {
     __syncthreads();  // the previous anchor's queries are done with the bins
     if (t == 0) {
       s_all = 0;
@@ -1344,6 +1268,170 @@ __global__ __launch_bounds__(NT) void k_bins(const double* __restrict__ xy, Ctx*
   flush();
   if (lane == 0) {
     stat_add(ctx, ST_VERT, n_vert);
+    stat_add(ctx, ST_SCREENED, n_scr);
+    stat_add(ctx, ST_FORCED, n_forced);
+    stat_add(ctx, ST_BIN, n_pass);
+  }
+}
+
+// The slope-bin screen over the anchors the slope range leaves (k_range):
+// only the points of their key intervals (the others are in no window of
+// theirs at a slope of the range), and only the partners among those points
+// whose slope bin can hold a slope of the range. The frame is centred on the
+// best seed slope, as the full one, and scaled to spread the range over most
+// of NBP bins (offsets up to 3 in map units), but no coarser near its centre
+// than the full frame of nb_full bins. The points' codes and indices stay in
+// LDS (runs hold at most NMAX points). Vertical pairs are counted by k_range.
+// Does nothing without a range (then k_bins runs).
+template <int NT, int NMAX>
+__global__ __launch_bounds__(NT) void k_bins_pruned(const double* __restrict__ xy, Ctx* ctx,
+                                                    uint2* __restrict__ cands, int cand_cap,
+                                                    uint2* __restrict__ entries, int cap,
+                                                    const double4* __restrict__ seed_res,
+                                                    const double4* __restrict__ seed_rec,
+                                                    int n_rec, const unsigned* __restrict__ perm,
+                                                    const double2* __restrict__ sxy,
+                                                    const uint2* __restrict__ live, int nb_full) {
+  constexpr int NBP = kPrunedBins, NBINSP = NBP + NT, kRLogP = __builtin_ctz(NBP) - 1;
+  static_assert((NBP % NT) == 0 && ((NBP / NT) & 1) == 0, "bins must be 2^k per thread");
+  __shared__ unsigned bins[NBINSP + 1];
+  __shared__ unsigned short pcode[NMAX], pidx[NMAX];
+  constexpr int PB = 512;
+  __shared__ uint2 pbuf[PB];
+  __shared__ unsigned s_part[NT / 64];
+  __shared__ unsigned s_all, s_cnt, s_base, s_fill, s_pos;
+  const Ctx c = *ctx;
+  if (c.status != LMS_OK || c.all_x_equal || c.n_live < 0) return;
+  const int n = c.n, h = c.h, t = threadIdx.x, lane = t & 63;
+  const double W = __longlong_as_double((long long)c.wbound);
+  const double lim = W * (1.0 + 0x1p-50);
+  const BinFrame F = bin_frame(best_slope<NT>(seed_res, c.n_seeds, seed_rec, n_rec),
+                               c.xh, c.yh, W, NBINSP);
+  const int half = n >> 1;
+  const double tau0 = tau_bound(0.0, c.xh, c.yh), tau1 = tau_bound(1.0, c.xh, c.yh) - tau0;
+  const double th_lim = tau0 < 1e29 ? fmin(1e29, 0.5 * (1e29 - tau0) / tau1) : 0.0;
+  unsigned long long n_scr = 0, n_forced = 0, n_pass = 0;
+  auto reserve = [&](unsigned cnt) {
+    const unsigned base = atomicAdd(&ctx->n_cands, cnt);
+    if (base + cnt > (unsigned)cand_cap || base + cnt < base) atomicOr(&ctx->cand_overflow, 1u);
+    s_base = base;
+  };
+  auto flush = [&]() {  // all threads; leaves s_fill = 0
+    __syncthreads();
+    const unsigned fill = s_fill;
+    if (fill) {
+      if (t == 0) reserve(fill);
+      __syncthreads();
+      const unsigned base = s_base;
+      for (unsigned q = t; q < fill; q += NT)
+        if (base + q < (unsigned)cand_cap) cands[base + q] = pbuf[q];
+      __syncthreads();
+      if (t == 0) s_fill = 0;
+      __syncthreads();
+    }
+  };
+  if (t == 0) s_fill = 0;
+  const int n_live = c.n_live;
+  BinFrame FP = F;
+  int blo = 0, bhi = 0;
+  if (n_live >= 0) {
+    const double tm = c.th_lo + 0.5 * (c.th_hi - c.th_lo);
+    const double dl = fmax(c.th_hi - tm, tm - c.th_lo);
+    double sc = fmax(3.0 / dl, F.sc * (double)(nb_full / NBP));
+    if (fabs(F.tc) * sc > 0x1p20) sc = 0x1p20 / fabs(F.tc);
+    FP.sc = fmin(fmax(sc, 0x1p-100), 0x1p100);
+    FP.tc = fabs(F.tc) * FP.sc <= 0x1p20 ? F.tc : 0.0;
+    FP.q = W < INFINITY ? 0x1p-46 * NBINSP * FP.sc : INFINITY;
+    blo = fbin<kRLogP>((c.th_lo - FP.tc) * FP.sc) - 2;
+    bhi = fbin<kRLogP>((c.th_hi - FP.tc) * FP.sc) + 2;
+  }
+  for (int q = blockIdx.x; q < n_live; q += gridDim.x) {
+    __syncthreads();  // the previous anchor's queries are done with the bins
+    if (t == 0) {
+      s_all = 0;
+      s_cnt = 0;
+      s_pos = 0;
+    }
+    for (int b = t; b <= NBINSP; b += NT) bins[b] = 0u;
+    __syncthreads();
+    const uint2 lv = live[q];
+    const int i = (int)lv.x, r0 = (int)(lv.y & 0xFFFFu), len = (int)(lv.y >> 16) - r0;
+    const unsigned* run = perm + r0;
+    const double2* rxy = sxy + r0;
+    const double xi = xy[2 * i], yi = xy[2 * i + 1];
+    unsigned all = 0;
+    double2 nxt = t < len ? rxy[t] : make_double2(0.0, 0.0);
+    for (int p = t; p < len; p += NT) {
+      const double2 cur = nxt;
+      if (p + NT < len) nxt = rxy[p + NT];
+      pidx[p] = (unsigned short)run[p];
+      all += add_point_bins_coded<kRLogP>(bins, cur.x - xi, cur.y - yi, W, lim, FP, th_lim,
+                                          &pcode[p]);
+    }
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) all += __shfl_xor(all, m);
+    if (lane == 0) atomicAdd(&s_all, all);
+    __syncthreads();
+    scan_bins<NBINSP, NT>(bins, s_part);
+    __syncthreads();
+    const unsigned pall = s_all;
+    const int P = (n & 1) ? half : (i < half ? half : half - 1);
+    // the anchor's partners are j = (i + o) mod n, o = 1..P
+    auto owned = [&](int j) {
+      const int o = j >= i ? j - i : j - i + n;
+      return o >= 1 && o <= P;
+    };
+    auto index = [&](int p) { return (int)pidx[p]; };
+    for (int p0 = 0; p0 < len; p0 += NT) {
+      const int p = p0 + t;
+      const int j = p < len ? index(p) : i;
+      const bool valid = p < len && owned(j);
+      const unsigned cj = valid ? pcode[p] : 0u;
+      const bool force = valid && cj == kCodeFP64;
+      const bool test = valid && cj > kCodePass && (int)cj >= blo && (int)cj <= bhi;
+      const bool pass = test && bins_pass(bins[cj], pall, h);
+      const unsigned long long mp = lane_mask(pass);
+      n_forced += __popcll(lane_mask(force));
+      n_scr += __popcll(lane_mask(test));
+      n_pass += __popcll(mp);
+      if (force) append_entry(ctx, entries, cap, (unsigned)min(i, j), (unsigned)max(i, j));
+      if (pass) pcode[p] = kCodePass;
+      if (mp && lane == 0) atomicAdd(&s_cnt, (unsigned)__popcll(mp));
+    }
+    __syncthreads();
+    const unsigned cnt = s_cnt;
+    if (cnt) {
+      if (s_fill + cnt > (unsigned)PB) flush();
+      const bool direct = cnt > (unsigned)PB;
+      if (direct) {
+        if (t == 0) reserve(cnt);
+        __syncthreads();
+      }
+      const unsigned base = direct ? s_base : s_fill;
+      for (int p0 = 0; p0 < len; p0 += NT) {
+        const int p = p0 + t;
+        const bool m = p < len && pcode[p] == kCodePass;
+        const unsigned long long mm = lane_mask(m);
+        if (mm) {
+          unsigned q0 = 0;
+          if (lane == 0) q0 = atomicAdd(&s_pos, (unsigned)__popcll(mm));
+          q0 = __shfl(q0, 0);
+          if (m) {
+            const unsigned q2 = base + q0 + (unsigned)__popcll(mm & ((1ull << lane) - 1ull));
+            const uint2 pr = make_uint2((unsigned)i, (unsigned)index(p));
+            if (!direct) pbuf[q2] = pr;
+            else if (q2 < (unsigned)cand_cap) cands[q2] = pr;
+          }
+        }
+      }
+      if (!direct) {
+        __syncthreads();
+        if (t == 0) s_fill = base + cnt;
+      }
+    }
+  }
+  flush();
+  if (lane == 0) {
     stat_add(ctx, ST_SCREENED, n_scr);
     stat_add(ctx, ST_FORCED, n_forced);
     stat_add(ctx, ST_BIN, n_pass);
@@ -1581,7 +1669,7 @@ Layout layout(int n_pad, long long cap, long long n_rec = 0, long long cand_cap 
   L.cands = L.rec + up((size_t)n_rec * sizeof(double4));
   L.sort_tmp = L.cands + up((size_t)cand_cap * sizeof(uint2));
   L.grid = L.sort_tmp + up((size_t)sort_tmp * sizeof(double));
-  L.range = L.grid + up(kGrid * (sizeof(double) + sizeof(double4)));
+  L.range = L.grid + up(2 * kGrid * (sizeof(double) + sizeof(double4)));
   L.total = L.range + up((size_t)n_pad * (sizeof(unsigned) + sizeof(uint2) + sizeof(double2)));
   return L;
 }
@@ -1801,8 +1889,7 @@ constexpr int bins_threads() {
 template <int NB>
 hipError_t launch_bins_nb(hipStream_t s, int cu, int n, const double* xy, Ctx* ctx, uint2* cands,
                           int cand_cap, uint2* e, int cap, const double4* res,
-                          const double4* rec, int n_rec, const unsigned* perm,
-                          const double2* sxy, const uint2* live) {
+                          const double4* rec, int n_rec) {
   constexpr int nt = bins_threads<NB>();
   static int resident = 0;
   if (resident == 0) {
@@ -1816,7 +1903,28 @@ hipError_t launch_bins_nb(hipStream_t s, int cu, int n, const double* xy, Ctx* c
   }
   const int grid = std::max(1, std::min(n, cu * resident));
   hipLaunchKernelGGL((k_bins<NB, nt>), dim3(grid), dim3(nt), 0, s, xy, ctx, cands, cand_cap, e,
-                     cap, res, rec, rec ? n_rec : 0, perm, sxy, live);
+                     cap, res, rec, rec ? n_rec : 0);
+  return hipGetLastError();
+}
+
+template <int NT, int NMAX>
+hipError_t launch_pruned_nt(hipStream_t s, int cu, int n, const double* xy, Ctx* ctx,
+                            uint2* cands, int cand_cap, uint2* e, int cap, const double4* res,
+                            const double4* rec, int n_rec, const unsigned* perm,
+                            const double2* sxy, const uint2* live, int nb_full) {
+  static int resident = 0;
+  if (resident == 0) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)k_bins_pruned<NT, NMAX>,
+                                                     NT, 0) != hipSuccess || nb < 1) {
+      (void)hipGetLastError();
+      nb = 1;
+    }
+    resident = nb;
+  }
+  const int grid = std::max(1, std::min(n, cu * resident));
+  hipLaunchKernelGGL((k_bins_pruned<NT, NMAX>), dim3(grid), dim3(NT), 0, s, xy, ctx, cands,
+                     cand_cap, e, cap, res, rec, rec ? n_rec : 0, perm, sxy, live, nb_full);
   return hipGetLastError();
 }
 
@@ -1824,13 +1932,26 @@ hipError_t launch_bins(hipStream_t s, int nb_log2, int cu, int n, const double* 
                        uint2* cands, int cand_cap, uint2* e, int cap, const double4* res,
                        const double4* rec, int n_rec, const unsigned* perm,
                        const double2* sxy, const uint2* live) {
+  // the full screen, then (with a slope range; each kernel returns at once
+  // when the other one's case holds) the pruned one
+  hipError_t err;
   switch (nb_log2) {
-    case 11: return launch_bins_nb<2048>(s, cu, n, xy, ctx, cands, cand_cap, e, cap, res, rec, n_rec, perm, sxy, live);
-    case 12: return launch_bins_nb<4096>(s, cu, n, xy, ctx, cands, cand_cap, e, cap, res, rec, n_rec, perm, sxy, live);
-    case 13: return launch_bins_nb<8192>(s, cu, n, xy, ctx, cands, cand_cap, e, cap, res, rec, n_rec, perm, sxy, live);
-    case 14: return launch_bins_nb<16384>(s, cu, n, xy, ctx, cands, cand_cap, e, cap, res, rec, n_rec, perm, sxy, live);
-    default: return launch_bins_nb<32768>(s, cu, n, xy, ctx, cands, cand_cap, e, cap, res, rec, n_rec, perm, sxy, live);
+    case 11: err = launch_bins_nb<2048>(s, cu, n, xy, ctx, cands, cand_cap, e, cap, res, rec, n_rec); break;
+    case 12: err = launch_bins_nb<4096>(s, cu, n, xy, ctx, cands, cand_cap, e, cap, res, rec, n_rec); break;
+    case 13: err = launch_bins_nb<8192>(s, cu, n, xy, ctx, cands, cand_cap, e, cap, res, rec, n_rec); break;
+    case 14: err = launch_bins_nb<16384>(s, cu, n, xy, ctx, cands, cand_cap, e, cap, res, rec, n_rec); break;
+    default: err = launch_bins_nb<32768>(s, cu, n, xy, ctx, cands, cand_cap, e, cap, res, rec, n_rec); break;
   }
+  if (err != hipSuccess || !live) return err;
+  const int nb_full = 1 << nb_log2;
+  if (n <= 4096)
+    return launch_pruned_nt<256, 4096>(s, cu, n, xy, ctx, cands, cand_cap, e, cap, res, rec, n_rec,
+                                       perm, sxy, live, nb_full);
+  if (n <= 8192)
+    return launch_pruned_nt<512, 8192>(s, cu, n, xy, ctx, cands, cand_cap, e, cap, res, rec, n_rec,
+                                       perm, sxy, live, nb_full);
+  return launch_pruned_nt<1024, 16384>(s, cu, n, xy, ctx, cands, cand_cap, e, cap, res, rec, n_rec,
+                                       perm, sxy, live, nb_full);
 }
 
 template <int R, bool L>
@@ -1934,6 +2055,7 @@ struct Setup {
   int seeds = 0, window_pairs = 0, bins_log2 = 0, G = 1, ipa = 1;
   int final_slots = 0;
   bool no_prune = false, use_bins = false;
+  bool range = false, refine = false;  // slope range: first grid; second grid
   const double* seed_theta = nullptr;
   int64_t n_seed_theta = 0;
   long long pairs = 0, cand_cap = 0, n_items = 0;
@@ -2006,6 +2128,12 @@ lms_status make_setup(const double* d_xy, int64_t n, int64_t h, lms_result* d_ou
   S->bins_log2 = bins_log2;
   S->no_prune = no_prune;
   S->use_bins = use_bins;
+  // The slope range costs two or three short launches and kGrid (2 kGrid)
+  // exact windows; the anchors and points it drops pay for that above
+  // kRangeMinN (kRefineMinN) points.
+  const bool force_range = (flags & LMS_F_RANGE) != 0, no_range = (flags & LMS_F_NO_RANGE) != 0;
+  S->range = use_bins && !no_prune && !no_range && (force_range || p.n > kRangeMinN);
+  S->refine = S->range && (force_range || p.n > kRefineMinN);
   S->seed_theta = d_seed_theta;
   S->n_seed_theta = n_seed_theta;
   S->pairs = pairs;
@@ -2071,17 +2199,23 @@ lms_status enqueue_solve(const Setup& S, char* base, hipStream_t s, lms_host::St
   unsigned* perm = (unsigned*)(base + L.range);
   uint2* live = (uint2*)(perm + p.n_pad);
   double2* sxy = (double2*)(live + p.n_pad);
-  if (S.use_bins && !S.no_prune) {
+  if (S.range) {
     double* grid_theta = (double*)(base + L.grid);
-    double4* grid_res = (double4*)(grid_theta + kGrid);
+    double4* grid_res = (double4*)(grid_theta + 2 * kGrid);
     hipLaunchKernelGGL(k_grid_slopes<256>, dim3(1), dim3(256), 0, s, ctx, res, p.n_seeds,
                        n_seed_theta > 0 ? rec : nullptr, (int)n_seed_theta, grid_theta);
-    if (p.n <= kSeedExactMax)
-      launch_eval(s, kGrid, d_xy, p.n, p.h, grid_theta, kGrid, nullptr, ctx, grid_res);
-    else
-      launch_recheck(s, p.n, kGrid, d_xy, ctx, entries, grid_res, 0, kGrid, 1, tmp, kGrid, kGrid,
-                     grid_theta);
-    launch_range(s, p.n, cu, d_xy, ctx, grid_theta, grid_res, perm, sxy, live);
+    auto eval_grid = [&](double* th, double4* out) {
+      if (p.n <= kSeedExactMax)
+        launch_eval(s, kGrid, d_xy, p.n, p.h, th, kGrid, nullptr, ctx, out);
+      else
+        launch_recheck(s, p.n, kGrid, d_xy, ctx, entries, out, 0, kGrid, 1, tmp, kGrid, kGrid, th);
+    };
+    eval_grid(grid_theta, grid_res);
+    if (S.refine) {
+      hipLaunchKernelGGL(k_grid_refine, dim3(1), dim3(64), 0, s, ctx, grid_theta, grid_res);
+      eval_grid(grid_theta + kGrid, grid_res + kGrid);
+    }
+    launch_range(s, p.n, cu, d_xy, ctx, grid_theta, grid_res, S.refine, perm, sxy, live);
   }
   mark();
   // Screen. With slope bins: per-anchor bin counts, then the FP32 test of the
@@ -2092,7 +2226,7 @@ lms_status enqueue_solve(const Setup& S, char* base, hipStream_t s, lms_host::St
     uint2* cands = (uint2*)(base + L.cands);
     err = launch_bins(s, S.bins_log2, cu, p.n, d_xy, ctx, cands, (int)S.cand_cap, entries,
                       (int)p.cap, res, n_seed_theta > 0 && !S.no_prune ? rec : nullptr,
-                      (int)n_seed_theta, perm, sxy, live);
+                      (int)n_seed_theta, perm, sxy, S.range ? live : nullptr);
     mark();
     if (err == hipSuccess)
       err = launch_list(s, p.R, p.lds, cu, d_xy, xy32, ctx, cands, (int)S.cand_cap, entries,

@@ -205,16 +205,32 @@ def test_bin_screen_equals_exhaustive(gpu, orc, n):
         if n <= 1000:
             o = orc.solve(xy)
             assert close(ref.width, o.width)
-        for b in (0, 11, 13, 15):
-            r = gpu.solve(dev(xy), bins_log2=b)
+        for b, rng in ((0, None), (11, None), (13, None), (15, None), (0, True), (13, True)):
+            r = gpu.solve(dev(xy), bins_log2=b, slope_range=rng)
             assert (r.width, r.theta1, r.z_lo, r.z_hi) == \
-                   (ref.width, ref.theta1, ref.z_lo, ref.z_hi), (n, b)
+                   (ref.width, ref.theta1, ref.z_lo, ref.z_hi), (n, b, rng)
             assert r.vertical == ref.vertical and r.candidates == ref.candidates
             assert r.survivors <= ref.survivors
             assert r.bin_pass <= r.candidates
     if n == 4096:
         r = gpu.solve(dev(planted(n, 0.45, 5000 + n)))
         assert 0 < r.bin_pass < 0.02 * r.candidates, r.bin_pass
+
+
+@pytest.mark.parametrize("n", [4097, 6000, 9000])
+def test_slope_range_equals_full(gpu, n):
+    """The slope range (exact windows at one or two grids of slopes around
+    the best seed slope, then only the anchors and points of key intervals
+    that can reach h) drops only pairs that cannot be optimal: off, on with
+    one grid or two, the line and the vertical count are the same."""
+    for xy in (planted(n, 0.45, 8000 + n), degenerate_int(n, 8100 + n)):
+        ref = gpu.solve(dev(xy), slope_range=False)
+        for rng in (None, True):
+            r = gpu.solve(dev(xy), slope_range=rng)
+            assert (r.width, r.theta1, r.z_lo, r.z_hi) == \
+                   (ref.width, ref.theta1, ref.z_lo, ref.z_hi), (n, rng)
+            assert r.vertical == ref.vertical and r.candidates == ref.candidates
+            assert r.survivors <= ref.survivors
 
 
 def test_bin_screen_no_prune_and_seedless(gpu):
