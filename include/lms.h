@@ -69,7 +69,8 @@ typedef struct lms_result {
   uint64_t band_pass;     /* pairs that passed the band test */
   uint64_t bin_pass;      /* pairs the slope-bin screen passed to the FP32 test
                              (lms_solve; 0 where that screen did not run) */
-  uint64_t bins;          /* slope bins per anchor of that screen (0: not run) */
+  uint64_t bins;          /* slope bins per anchor of that screen (0: not run;
+                             2048: the pruned screen of the slope range ran) */
 } lms_result;
 
 /* Flags for lms_options.flags */

@@ -1644,7 +1644,7 @@ __global__ __launch_bounds__(1024) void k_finalize(Ctx* ctx, const uint2* __rest
   o.dir_evals = s_stat[ST_DEVALS];
   o.band_pass = s_stat[ST_BAND];
   o.bin_pass = s_stat[ST_BIN];
-  o.bins = c.bins;
+  o.bins = c.n_live >= 0 ? (unsigned long long)kPrunedBins : c.bins;
   *out = o;
 }
 
