@@ -668,12 +668,47 @@ __global__ __launch_bounds__(64) void k_grid_refine(const Ctx* ctx, double* grid
 // (counting sort: perm lists the points bucket by bucket, sxy holds them in
 // that order) and lists the
 // anchors that are left, with the range [r0, r1) of perm that covers the
-// intervals that can reach h (whole buckets: a superset). The other blocks
-// count the vertical pairs (equal x), which the slope-bin kernel no longer
-// meets when it skips anchors. Without a finite range nothing changes.
+// intervals that can reach h (whole buckets: a superset). Block 1 counts the
+// vertical pairs (equal x), which the pruned screen no longer meets: equal x
+// share a bucket of a hash of their bits (-0 taken as +0), so a counting sort
+// by that hash and compares within each bucket find them all. Without a
+// finite range nothing changes.
 constexpr int kRangeBuckets = 4096;
 constexpr int kRangeMinN = 4096, kRefineMinN = 8192;
-constexpr int kVertSlice = 256;
+
+// Exclusive prefix sum of the kRangeBuckets counts in cur into start and cur
+// (insertion cursors); start[kRangeBuckets] = the total. All NT threads call;
+// ends with a barrier.
+template <int NT>
+__device__ void bucket_starts(unsigned* start, unsigned* cur, unsigned* part) {
+  constexpr int S = kRangeBuckets / NT;
+  static_assert(S * NT == kRangeBuckets, "buckets per thread");
+  const int t = threadIdx.x, lane = t & 63;
+  unsigned v[S], run = 0;
+#pragma unroll
+  for (int r = 0; r < S; ++r) {
+    v[r] = run;
+    run += cur[t * S + r];
+  }
+  unsigned x = run;
+#pragma unroll
+  for (int m = 1; m < 64; m <<= 1) {
+    const unsigned y = __shfl_up(x, m);
+    if (lane >= m) x += y;
+  }
+  if (lane == 63) part[t >> 6] = x;
+  __syncthreads();
+  unsigned off = x - run;
+  for (int w = 0; w < (t >> 6); ++w) off += part[w];
+#pragma unroll
+  for (int r = 0; r < S; ++r) {
+    start[t * S + r] = v[r] + off;
+    cur[t * S + r] = v[r] + off;
+  }
+  if (t == NT - 1) start[kRangeBuckets] = off + run;
+  __syncthreads();
+}
+
 template <int NT, int E>
 __global__ __launch_bounds__(NT) void k_range(const double* __restrict__ xy, Ctx* ctx,
                                               const double* __restrict__ grid_theta,
@@ -684,7 +719,7 @@ __global__ __launch_bounds__(NT) void k_range(const double* __restrict__ xy, Ctx
   __shared__ unsigned s_start[kRangeBuckets + 1], s_cur[kRangeBuckets];
   __shared__ unsigned s_part[NT / 64];
   __shared__ unsigned s_live;
-  __shared__ double xs[kVertSlice];
+  __shared__ unsigned short s_xperm[LMS_MAX_N];
   const Ctx c = *ctx;
   if (c.status != LMS_OK || c.all_x_equal) return;
   const int n = c.n, h = c.h, t = threadIdx.x, lane = t & 63;
@@ -701,25 +736,24 @@ __global__ __launch_bounds__(NT) void k_range(const double* __restrict__ xy, Ctx
   }
   if (!narrow_range(c, lo, hi)) return;
   if (blockIdx.x > 0) {
-    // vertical pairs (i < j, x_i == x_j): items of NT anchors by kVertSlice partners
-    const int tiles = (n + NT - 1) / NT, slices = (n + kVertSlice - 1) / kVertSlice;
+    // vertical pairs (i < j, x_i == x_j)
+    auto hb = [](double x) {
+      const unsigned long long u = (unsigned long long)__double_as_longlong(x + 0.0);
+      return (int)((u * 0x9E3779B97F4A7C15ull) >> (64 - 12));
+    };
+    static_assert(kRangeBuckets == 1 << 12, "hash buckets");
+    for (int b = t; b < kRangeBuckets; b += NT) s_cur[b] = 0u;
+    __syncthreads();
+    for (int k = t; k < n; k += NT) atomicAdd(&s_cur[hb(xy[2 * k])], 1u);
+    __syncthreads();
+    bucket_starts<NT>(s_start, s_cur, s_part);
+    for (int k = t; k < n; k += NT) s_xperm[atomicAdd(&s_cur[hb(xy[2 * k])], 1u)] = (unsigned short)k;
+    __syncthreads();
     unsigned long long cnt = 0;
-    for (int it = blockIdx.x - 1; it < tiles * slices; it += gridDim.x - 1) {
-      const int a0 = (it / slices) * NT, j0 = (it % slices) * kVertSlice;
-      if (j0 + kVertSlice <= a0 + 1) continue;  // no partner above the tile's anchors
-      __syncthreads();
-      for (int q = t; q < kVertSlice; q += NT)
-        xs[q] = j0 + q < n ? xy[2 * (j0 + q)] : __longlong_as_double(0x7FF8000000000000ll);
-      __syncthreads();
-      const int i = a0 + t;
-      if (i < n) {
-        const double xi = xy[2 * i];
-        const int after = i - j0;  // partners j = j0 + q > i
-        unsigned c32 = 0;
-#pragma unroll 16
-        for (int q = 0; q < kVertSlice; ++q) c32 += (xs[q] == xi && q > after) ? 1u : 0u;
-        cnt += c32;
-      }
+    for (int p = t; p < n; p += NT) {
+      const double xk = xy[2 * s_xperm[p]];
+      const int end = (int)s_start[hb(xk) + 1];
+      for (int q = p + 1; q < end; ++q) cnt += xy[2 * s_xperm[q]] == xk ? 1u : 0u;
     }
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1) cnt += __shfl_xor(cnt, m);
@@ -730,15 +764,15 @@ __global__ __launch_bounds__(NT) void k_range(const double* __restrict__ xy, Ctx
   const double dl = fmax(hi - tm, tm - lo) * (1.0 + 0x1p-40);
   // two key roundings, each below 2^-53 (|y| + |tm| |x|)
   const double s = dl * c.xr * (1.0 + 0x1p-40) + 8.0 * 0x1p-53 * (c.yabs + fabs(tm) * c.xabs);
+  // only the keys stay in registers (points are read again for the copy)
   double z[E];
-  double2 pt[E];
   double mn = INFINITY, mx = -INFINITY;
   const double2* pts = reinterpret_cast<const double2*>(xy);
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int k = t + e * NT;
-    pt[e] = k < n ? pts[k] : make_double2(0.0, 0.0);
-    z[e] = fma(-tm, pt[e].x, pt[e].y);
+    const double2 pt = k < n ? pts[k] : make_double2(0.0, 0.0);
+    z[e] = fma(-tm, pt.x, pt.y);
     if (k < n) {
       mn = fmin(mn, z[e]);
       mx = fmax(mx, z[e]);
@@ -757,50 +791,14 @@ __global__ __launch_bounds__(NT) void k_range(const double* __restrict__ xy, Ctx
   for (int b = t; b < kRangeBuckets; b += NT) s_cur[b] = 0u;
   if (t == 0) s_live = 0u;
   __syncthreads();
-  int bk[E];
 #pragma unroll
-  for (int e = 0; e < E; ++e) {
-    bk[e] = bucket(z[e]);
-    if (t + e * NT < n) atomicAdd(&s_cur[bk[e]], 1u);
-  }
+  for (int e = 0; e < E; ++e)
+    if (t + e * NT < n) atomicAdd(&s_cur[bucket(z[e])], 1u);
   __syncthreads();
-  {  // exclusive prefix sum of the counts into s_start, thread t: buckets t S ..
-    constexpr int S = kRangeBuckets / NT;
-    static_assert(S * NT == kRangeBuckets, "buckets per thread");
-    unsigned v[S], run = 0;
-#pragma unroll
-    for (int r = 0; r < S; ++r) {
-      v[r] = run;
-      run += s_cur[t * S + r];
-    }
-    unsigned x = run;
-#pragma unroll
-    for (int m = 1; m < 64; m <<= 1) {
-      const unsigned y = __shfl_up(x, m);
-      if (lane >= m) x += y;
-    }
-    if (lane == 63) s_part[t >> 6] = x;
-    __syncthreads();
-    unsigned off = x - run;
-    for (int w = 0; w < (t >> 6); ++w) off += s_part[w];
-#pragma unroll
-    for (int r = 0; r < S; ++r) {
-      s_start[t * S + r] = v[r] + off;
-      s_cur[t * S + r] = v[r] + off;
-    }
-    if (t == NT - 1) s_start[kRangeBuckets] = off + run;
-  }
+  bucket_starts<NT>(s_start, s_cur, s_part);
   __syncthreads();
-#pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const int k = t + e * NT;
-    if (k < n) {
-      const unsigned pos = atomicAdd(&s_cur[bk[e]], 1u);
-      perm[pos] = (unsigned)k;
-      sxy[pos] = pt[e];
-    }
-  }
   // anchors left, with the perm range of the intervals that can reach h
+  // (before the copy, so that the keys are dead by then)
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int i = t + e * NT;
@@ -826,6 +824,19 @@ __global__ __launch_bounds__(NT) void k_range(const double* __restrict__ xy, Ctx
       if (keep) live[base + __popcll(mk & ((1ull << lane) - 1ull))] = make_uint2((unsigned)i, r0 | (r1 << 16));
     }
   }
+  // the sorted copy: positions first, then every point load at once
+  unsigned pos[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e)
+    pos[e] = t + e * NT < n ? atomicAdd(&s_cur[bucket(z[e])], 1u) : 0u;
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int k = t + e * NT;
+    if (k < n) {
+      perm[pos[e]] = (unsigned)k;
+      sxy[pos[e]] = pts[k];
+    }
+  }
   __syncthreads();
   if (t == 0) {
     ctx->th_lo = lo;
@@ -837,8 +848,8 @@ __global__ __launch_bounds__(NT) void k_range(const double* __restrict__ xy, Ctx
 void launch_range(hipStream_t s, int n, int cu, const double* xy, Ctx* ctx,
                   const double* grid_theta, const double4* grid_res, bool refine,
                   unsigned* perm, double2* sxy, uint2* live) {
-  const int tiles = (n + 1023) / 1024, slices = (n + kVertSlice - 1) / kVertSlice;
-  const int grid = 1 + std::min(tiles * slices, 2 * cu);
+  const int grid = 2;  // block 0: buckets and anchors; block 1: vertical pairs
+  (void)cu;
   if (n <= 1024)
     hipLaunchKernelGGL((k_range<1024, 1>), dim3(grid), dim3(1024), 0, s, xy, ctx, grid_theta, grid_res, refine, perm, sxy, live);
   else if (n <= 4096)
