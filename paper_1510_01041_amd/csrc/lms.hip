@@ -1961,8 +1961,9 @@ hipError_t launch_bins(hipStream_t s, int nb_log2, int cu, int n, const double* 
   if (n <= 8192)
     return launch_pruned_nt<512, 8192>(s, cu, n, xy, ctx, cands, cand_cap, e, cap, res, rec, n_rec,
                                        perm, sxy, live, nb_full);
-  return launch_pruned_nt<1024, 16384>(s, cu, n, xy, ctx, cands, cand_cap, e, cap, res, rec, n_rec,
-                                       perm, sxy, live, nb_full);
+  // (512 threads: two workgroups per CU; 1024 fit only one, at 5 % more time)
+  return launch_pruned_nt<512, 16384>(s, cu, n, xy, ctx, cands, cand_cap, e, cap, res, rec, n_rec,
+                                      perm, sxy, live, nb_full);
 }
 
 template <int R, bool L>
