@@ -21,15 +21,15 @@ _LIB = os.path.join(_HERE, "liblms_oracle.so")
 OK, OK_DEGENERATE, ERR_ARG, ERR_NONFINITE = 0, 1, -1, -2
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, src: str = _SRC, out: str = _LIB) -> str:
     """Compile liblms_oracle.so with gcc (FP64, no contraction, OpenMP)."""
     cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
-           "-fPIC", "-shared", "-Wall", "-Wextra", "-o", _LIB + ".tmp", _SRC, "-lm"]
+           "-fPIC", "-shared", "-Wall", "-Wextra", "-I", _HERE, "-o", out + ".tmp", src, "-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)
-    os.replace(_LIB + ".tmp", _LIB)
-    return _LIB
+    os.replace(out + ".tmp", out)
+    return out
 
 
 class _Result(ctypes.Structure):
@@ -60,30 +60,39 @@ class OracleResult:
 _lib = None
 
 
+def bind(path: str):
+    """Load an oracle library from path and declare its entry points."""
+    L = ctypes.CDLL(path)
+    dp = ctypes.POINTER(ctypes.c_double)
+    L.lms_oracle_solve.argtypes = [dp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int,
+                                   ctypes.POINTER(_Result)]
+    L.lms_oracle_solve.restype = ctypes.c_int
+    L.lms_oracle_solve_bounded.argtypes = [dp, ctypes.c_int64, ctypes.c_int64,
+                                           ctypes.c_int, ctypes.POINTER(_Result),
+                                           ctypes.POINTER(ctypes.c_int64)]
+    L.lms_oracle_solve_bounded.restype = ctypes.c_int
+    L.lms_oracle_window.argtypes = [dp, ctypes.c_int64, ctypes.c_int64, ctypes.c_double,
+                                    dp, dp, dp]
+    L.lms_oracle_window.restype = ctypes.c_int
+    L.lms_oracle_eval_pairs.argtypes = [dp, ctypes.c_int64, ctypes.c_int64,
+                                        ctypes.POINTER(ctypes.c_int64), ctypes.c_int64,
+                                        ctypes.c_int, dp, dp, dp, dp]
+    L.lms_oracle_eval_pairs.restype = ctypes.c_int
+    L.lms_oracle_anchored.argtypes = [dp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
+                                      ctypes.c_int64, dp, dp]
+    L.lms_oracle_anchored.restype = ctypes.c_int
+    L.lms_oracle_hth_abs_residual.argtypes = [dp, ctypes.c_int64, ctypes.c_int64,
+                                              ctypes.c_double, ctypes.c_double]
+    L.lms_oracle_hth_abs_residual.restype = ctypes.c_double
+    return L
+
+
 def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(_LIB):
             build()
-        L = ctypes.CDLL(_LIB)
-        dp = ctypes.POINTER(ctypes.c_double)
-        L.lms_oracle_solve.argtypes = [dp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int,
-                                       ctypes.POINTER(_Result)]
-        L.lms_oracle_solve.restype = ctypes.c_int
-        L.lms_oracle_window.argtypes = [dp, ctypes.c_int64, ctypes.c_int64, ctypes.c_double,
-                                        dp, dp, dp]
-        L.lms_oracle_window.restype = ctypes.c_int
-        L.lms_oracle_eval_pairs.argtypes = [dp, ctypes.c_int64, ctypes.c_int64,
-                                            ctypes.POINTER(ctypes.c_int64), ctypes.c_int64,
-                                            ctypes.c_int, dp, dp, dp, dp]
-        L.lms_oracle_eval_pairs.restype = ctypes.c_int
-        L.lms_oracle_anchored.argtypes = [dp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
-                                          ctypes.c_int64, dp, dp]
-        L.lms_oracle_anchored.restype = ctypes.c_int
-        L.lms_oracle_hth_abs_residual.argtypes = [dp, ctypes.c_int64, ctypes.c_int64,
-                                                  ctypes.c_double, ctypes.c_double]
-        L.lms_oracle_hth_abs_residual.restype = ctypes.c_double
-        _lib = L
+        _lib = bind(_LIB)
     return _lib
 
 
@@ -104,6 +113,18 @@ def solve(xy, h: int = 0, nthreads: int = 0) -> OracleResult:
     r = _Result()
     lib().lms_oracle_solve(_dp(a), a.shape[0], h, nthreads, ctypes.byref(r))
     return OracleResult(**{f: getattr(r, f) for f, _ in _Result._fields_})
+
+
+def solve_bounded(xy, h: int = 0, nthreads: int = 0):
+    """Same result as solve(), skipping slopes the Lipschitz bound rules out.
+
+    Returns (OracleResult, number of distinct slopes evaluated)."""
+    a = _xy(xy)
+    r = _Result()
+    ev = ctypes.c_int64()
+    lib().lms_oracle_solve_bounded(_dp(a), a.shape[0], h, nthreads, ctypes.byref(r),
+                                   ctypes.byref(ev))
+    return OracleResult(**{f: getattr(r, f) for f, _ in _Result._fields_}), ev.value
 
 
 def window(xy, theta: float, h: int = 0) -> tuple[float, float, float]:

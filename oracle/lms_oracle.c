@@ -261,3 +261,216 @@ double lms_oracle_hth_abs_residual(const double* xy, int64_t n, int64_t h,
   free(r);
   return v;
 }
+
+/* ------------------------------------------------------------------------
+ * The same exact search, skipping slopes that provably cannot win.
+ *
+ * The exhaustive search above costs about 100 core-hours at 16384 points.
+ * This variant returns the same result (every field bitwise) with far fewer
+ * evaluations of F. It uses one fact beyond the definition:
+ *
+ *   Lipschitz bound. For slopes a and b, |F(a) - F(b)| <= L |a - b| with
+ *   L = max x - min x. For a fixed set H of h points the slab height
+ *   max_H z - min_H z, z = y - theta x, changes with theta at the rate
+ *   x_q - x_p of its current top and bottom points, at most L in size; F is
+ *   the minimum over all H of such functions, so it inherits the bound.
+ *
+ * Every F here is computed exactly as in lms_oracle_solve (same intercepts,
+ * same sort, same window scan), so the two agree bitwise on every slope that
+ * is evaluated. A slope is skipped only when an evaluated slope a gives
+ *   F(theta) >= F(a) - L |theta - a| - (rounding allowances) > best so far,
+ * so it can neither beat nor tie the final minimum. Slopes equal in binary64
+ * have the same intercepts, hence the same window: one evaluation serves all
+ * pairs with that slope, and the smallest (i, j) among them is kept, as the
+ * exhaustive search's tie rule would.
+ *
+ * Rounding allowance at slope t: the computed intercepts and differences
+ * each carry an error below 2^-53 M(t), M(t) = max|y| + |t| max|x|, so the
+ * computed F is within 4 * 2^-53 M(t) of the exact one; 2^-46 M(t) is used.
+ * ---------------------------------------------------------------------- */
+
+typedef struct {
+  double theta;
+  int32_t i, j;
+} pair_slope_t;
+
+static int cmp_pair_slope(const void* a, const void* b) {
+  const pair_slope_t* p = (const pair_slope_t*)a;
+  const pair_slope_t* q = (const pair_slope_t*)b;
+  if (p->theta != q->theta) return (p->theta > q->theta) - (p->theta < q->theta);
+  if (p->i != q->i) return (p->i > q->i) - (p->i < q->i);
+  return (p->j > q->j) - (p->j < q->j);
+}
+
+typedef struct {
+  const double* xy;
+  int64_t n, h;
+  const pair_slope_t* s; /* sorted pair slopes */
+  const int64_t* g;      /* start of each group of equal slopes; g[ng] = #pairs */
+  int64_t ng;
+  double* F;             /* computed width per group (NaN = not evaluated) */
+  double L, xmax, ymax;
+  double best;           /* smallest width found so far */
+  int64_t evaluated;
+} bound_ctx;
+
+static double allowance(const bound_ctx* c, double t) {
+  return ldexp(c->ymax + fabs(t) * c->xmax, -46);
+}
+
+/* Evaluate group k (its slope's narrowest window); keeps the best width. */
+static double eval_group(bound_ctx* c, int64_t k, double* z) {
+  const double t = c->s[c->g[k]].theta;
+  double w, lo, hi;
+  sorted_intercepts(c->xy, c->n, t, z);
+  narrowest_window(z, c->n, c->h, &w, &lo, &hi);
+  c->F[k] = w;
+#pragma omp critical(lms_oracle_bound)
+  {
+    if (w < c->best) c->best = w;
+    c->evaluated++;
+  }
+  return w;
+}
+
+/* Groups strictly between evaluated groups a < b: skip them all if the bound
+ * from a and b exceeds the best width, else evaluate the middle one and split. */
+static void search_between(bound_ctx* c, int64_t a, int64_t b, double* z) {
+  if (b - a < 2) return;
+  const double ta = c->s[c->g[a]].theta, tb = c->s[c->g[b]].theta;
+  const double p = c->s[c->g[a + 1]].theta, q = c->s[c->g[b - 1]].theta;
+  const double Fa = c->F[a] - allowance(c, ta), Fb = c->F[b] - allowance(c, tb);
+  const double L = c->L * (1.0 + 0x1p-40);
+  /* On [p, q], F >= max(Fa - L (t - ta), Fb - L (tb - t)); each term below is a
+   * lower bound of that maximum over the whole interval. */
+  double lb = Fa - L * (q - ta);
+  const double from_b = Fb - L * (tb - p);
+  const double meet = 0.5 * (Fa + Fb - L * (tb - ta));
+  if (from_b > lb) lb = from_b;
+  if (meet > lb) lb = meet;
+  lb -= fmax(allowance(c, p), allowance(c, q)) + ldexp(fabs(c->F[a]) + fabs(c->F[b]), -46);
+  double best;
+#pragma omp atomic read
+  best = c->best;
+  if (lb > best) return;
+  const int64_t m = a + (b - a) / 2;
+  eval_group(c, m, z);
+  search_between(c, a, m, z);
+  search_between(c, m, b, z);
+}
+
+int lms_oracle_solve_bounded(const double* xy, int64_t n, int64_t h, int nthreads,
+                             lms_oracle_result* out, int64_t* evaluated) {
+  if (!out) return LMS_ORACLE_ERR_ARG;
+  if (evaluated) *evaluated = -1;
+  int64_t hh = h;
+  int st = check_args(xy, n, &hh);
+  if (st != LMS_ORACLE_OK || n > INT32_MAX) return lms_oracle_solve(xy, n, h, nthreads, out);
+
+  /* all pair slopes with x_i != x_j, as the exhaustive search computes them */
+  int64_t m = 0, vertical = 0;
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t j = i + 1; j < n; ++j) m += xy[2 * j] != xy[2 * i];
+  pair_slope_t* s = (pair_slope_t*)malloc((size_t)(m > 0 ? m : 1) * sizeof(*s));
+  if (!s) return lms_oracle_solve(xy, n, h, nthreads, out);
+  int finite = 1;
+  int64_t t = 0;
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t j = i + 1; j < n; ++j) {
+      if (xy[2 * j] == xy[2 * i]) {
+        ++vertical;
+        continue;
+      }
+      s[t].theta = (xy[2 * j + 1] - xy[2 * i + 1]) / (xy[2 * j] - xy[2 * i]);
+      s[t].i = (int32_t)i;
+      s[t].j = (int32_t)j;
+      finite &= isfinite(s[t].theta) != 0;
+      ++t;
+    }
+  if (m == 0 || !finite) { /* all x equal, or overflowing slopes: no bound to use */
+    free(s);
+    return lms_oracle_solve(xy, n, h, nthreads, out);
+  }
+  qsort(s, (size_t)m, sizeof(*s), cmp_pair_slope);
+
+  int64_t ng = 0;
+  int64_t* g = (int64_t*)malloc((size_t)(m + 1) * sizeof(int64_t));
+  for (int64_t k = 0; k < m; ++k)
+    if (k == 0 || s[k].theta != s[k - 1].theta) g[ng++] = k;
+  g[ng] = m;
+
+  bound_ctx c;
+  c.xy = xy;
+  c.n = n;
+  c.h = hh;
+  c.s = s;
+  c.g = g;
+  c.ng = ng;
+  c.F = (double*)malloc((size_t)ng * sizeof(double));
+  for (int64_t k = 0; k < ng; ++k) c.F[k] = NAN;
+  double xlo = xy[0], xhi = xy[0];
+  c.xmax = c.ymax = 0.0;
+  for (int64_t k = 0; k < n; ++k) {
+    xlo = fmin(xlo, xy[2 * k]);
+    xhi = fmax(xhi, xy[2 * k]);
+    c.xmax = fmax(c.xmax, fabs(xy[2 * k]));
+    c.ymax = fmax(c.ymax, fabs(xy[2 * k + 1]));
+  }
+  c.L = xhi - xlo;
+  c.best = INFINITY;
+  c.evaluated = 0;
+
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+  /* a coarse pass of evenly spaced groups (both ends included), then the
+   * intervals between them, each searched independently */
+  const int64_t K = ng < 4096 ? ng : 4096;
+  int64_t* anchor = (int64_t*)malloc((size_t)K * sizeof(int64_t));
+  for (int64_t k = 0; k < K; ++k) anchor[k] = K == 1 ? 0 : (ng - 1) * k / (K - 1);
+#pragma omp parallel
+  {
+    double* z = (double*)malloc((size_t)n * sizeof(double));
+#pragma omp for schedule(dynamic, 1)
+    for (int64_t k = 0; k < K; ++k) eval_group(&c, anchor[k], z);
+#pragma omp for schedule(dynamic, 1)
+    for (int64_t k = 1; k < K; ++k) search_between(&c, anchor[k - 1], anchor[k], z);
+    free(z);
+  }
+
+  /* the canonical minimum over the evaluated groups; a group's first pair
+   * is its smallest (i, j) */
+  best_t best = {INFINITY, 0.0, 0.0, 0.0, -1, -1};
+  double* z = (double*)malloc((size_t)n * sizeof(double));
+  for (int64_t k = 0; k < ng; ++k) {
+    if (!(c.F[k] <= c.best)) continue; /* skipped (NaN) or wider than the best */
+    best_t cand;
+    cand.theta = s[g[k]].theta;
+    cand.i = s[g[k]].i;
+    cand.j = s[g[k]].j;
+    sorted_intercepts(xy, n, cand.theta, z);
+    narrowest_window(z, n, hh, &cand.width, &cand.z_lo, &cand.z_hi);
+    if (better(&cand, &best)) best = cand;
+  }
+  free(z);
+
+  memset(out, 0, sizeof(*out));
+  out->status = LMS_ORACLE_OK;
+  out->h = (int32_t)hh;
+  out->theta1 = best.theta;
+  out->theta2 = 0.5 * (best.z_lo + best.z_hi);
+  out->width = best.width;
+  out->half_width = 0.5 * best.width;
+  out->z_lo = best.z_lo;
+  out->z_hi = best.z_hi;
+  out->pair_i = best.i;
+  out->pair_j = best.j;
+  out->candidates = m;
+  out->vertical = vertical;
+  if (evaluated) *evaluated = c.evaluated;
+  free(anchor);
+  free(c.F);
+  free(g);
+  free(s);
+  return LMS_ORACLE_OK;
+}

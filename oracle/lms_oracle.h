@@ -57,6 +57,16 @@ typedef struct {
 int lms_oracle_solve(const double* xy, int64_t n, int64_t h, int nthreads,
                      lms_oracle_result* out);
 
+/* The same result as lms_oracle_solve (every field), from fewer evaluations
+ * of F: a slope is skipped only when the Lipschitz bound of F in theta
+ * (constant max x - min x), measured from evaluated slopes and less rounding
+ * allowances, proves it wider than the best width found. Slopes equal in
+ * binary64 share one evaluation. Needs about 16 bytes per pair of host
+ * memory. evaluated (may be NULL) receives the number of distinct slopes
+ * whose window was computed. */
+int lms_oracle_solve_bounded(const double* xy, int64_t n, int64_t h, int nthreads,
+                             lms_oracle_result* out, int64_t* evaluated);
+
 /* F(theta) at one slope: the narrowest h-window of z = fma(-theta, x, y);
  * among equally narrow windows the lowest one. Writes width, z_lo, z_hi. */
 int lms_oracle_window(const double* xy, int64_t n, int64_t h, double theta,
