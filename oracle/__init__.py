@@ -19,6 +19,7 @@ _SRC = os.path.join(_HERE, "lms_oracle.c")
 _LIB = os.path.join(_HERE, "liblms_oracle.so")
 
 OK, OK_DEGENERATE, ERR_ARG, ERR_NONFINITE = 0, 1, -1, -2
+RULE_TIED, RULE_LITERAL = 0, 1
 
 
 def build(verbose: bool = False, src: str = _SRC, out: str = _LIB) -> str:
@@ -84,6 +85,9 @@ def bind(path: str):
     L.lms_oracle_hth_abs_residual.argtypes = [dp, ctypes.c_int64, ctypes.c_int64,
                                               ctypes.c_double, ctypes.c_double]
     L.lms_oracle_hth_abs_residual.restype = ctypes.c_double
+    L.lms_oracle_bracelets.argtypes = [dp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int,
+                                       ctypes.c_int, ctypes.POINTER(_Result)]
+    L.lms_oracle_bracelets.restype = ctypes.c_int
     return L
 
 
@@ -166,3 +170,13 @@ def anchored(xy, i: int, j: int, h: int = 0) -> tuple[float, float]:
 def hth_abs_residual(xy, theta1: float, theta2: float, h: int = 0) -> float:
     a = _xy(xy)
     return lib().lms_oracle_hth_abs_residual(_dp(a), a.shape[0], h, theta1, theta2)
+
+
+def bracelets(xy, h: int = 0, rule: int = RULE_TIED, nthreads: int = 0) -> OracleResult:
+    """Algorithm 1 as stated: the minimum over vertices of the bracelet hanging
+    from each, with the tied-rank reading (RULE_TIED, exact) or the printed
+    rank offset from the lowest tied rank (RULE_LITERAL)."""
+    a = _xy(xy)
+    r = _Result()
+    lib().lms_oracle_bracelets(_dp(a), a.shape[0], h, rule, nthreads, ctypes.byref(r))
+    return OracleResult(**{f: getattr(r, f) for f, _ in _Result._fields_})

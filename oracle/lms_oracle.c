@@ -474,3 +474,109 @@ int lms_oracle_solve_bounded(const double* xy, int64_t n, int64_t h, int nthread
   free(s);
   return LMS_ORACLE_OK;
 }
+
+/* ------------------------------------------------------------------------
+ * Algorithm 1 as the paper states it: one bracelet hanging from every
+ * intersection point of two dual lines (Section 3.4, Algorithm 1).
+ *
+ * For the vertex of pair (i, j) at slope theta: take every point's intercept
+ * z_k = fma(-theta, x_k, y_k) (the dual lines cut by the vertical line through
+ * the vertex, negated), with the pair's own two members set to exactly
+ * c = z_i (in exact arithmetic they are equal), and sort them. The vertex
+ * occupies every rank whose value equals c: ranks r_lo..r_hi. A bracelet
+ * spans h consecutive ranks with the vertex at one end; its length is the
+ * distance from c to the other end.
+ *
+ *   rule LITERAL: the vertex rank is k = r_lo and the far end is
+ *     X[(k + n/2) mod n] as printed. For even n and the default h
+ *     (h - 1 = n/2) that is the upward bracelet from k when it fits and
+ *     otherwise, through the wrap, the downward one ending at k; that reading
+ *     (up from k if it fits, else down to k if it fits) is used for every
+ *     (n, h).
+ *   rule TIED: upward from the lower tied rank r_lo and downward from the
+ *     upper tied rank r_hi, the shorter of the two that fit. This is the
+ *     reading under which the minimum over vertices is the LMS width: the
+ *     optimal slab's boundary passes through the vertex with the rest of the
+ *     slab on one side, whichever rank the tie is given.
+ *
+ * The minimum bracelet over all vertices is taken by the key (length, theta,
+ * lower end), then (i, j) (Algorithm 1, the final reduction), and translated
+ * back to the line (slope theta, intercept at the bracelet's midpoint).
+ * ---------------------------------------------------------------------- */
+
+/* Bracelet hanging from the vertex of pair (i, j), i < j, x_i != x_j. */
+static void vertex_bracelet(const double* xy, int64_t n, int64_t h, int rule, int64_t i,
+                            int64_t j, double* X, best_t* b) {
+  const double theta = (xy[2 * j + 1] - xy[2 * i + 1]) / (xy[2 * j] - xy[2 * i]);
+  const double c = fma(-theta, xy[2 * i], xy[2 * i + 1]);
+  for (int64_t k = 0; k < n; ++k)
+    X[k] = (k == i || k == j) ? c : fma(-theta, xy[2 * k], xy[2 * k + 1]);
+  qsort(X, (size_t)n, sizeof(double), cmp_f64);
+  int64_t r_lo = 0;
+  while (X[r_lo] < c) ++r_lo;
+  int64_t r_hi = r_lo;
+  while (r_hi + 1 < n && X[r_hi + 1] == c) ++r_hi;
+  /* far ends: upward from r_lo, downward to r_hi (LITERAL: both from r_lo) */
+  const int64_t top = r_lo + h - 1;
+  const int64_t bot = (rule == LMS_ORACLE_RULE_LITERAL ? r_lo : r_hi) - h + 1;
+  double up = INFINITY, dn = INFINITY;
+  if (top < n) up = X[top] - c;
+  if (bot >= 0 && (rule != LMS_ORACLE_RULE_LITERAL || top >= n)) dn = c - X[bot];
+  b->theta = theta;
+  b->i = i;
+  b->j = j;
+  b->width = INFINITY;
+  b->z_lo = b->z_hi = NAN;
+  /* on equal lengths the lower bracelet, as for the window scan */
+  if (dn <= up && dn < INFINITY) {
+    b->width = dn;
+    b->z_lo = X[bot];
+    b->z_hi = c;
+  } else if (up < INFINITY) {
+    b->width = up;
+    b->z_lo = c;
+    b->z_hi = X[top];
+  }
+}
+
+int lms_oracle_bracelets(const double* xy, int64_t n, int64_t h, int rule, int nthreads,
+                         lms_oracle_result* out) {
+  if (!out) return LMS_ORACLE_ERR_ARG;
+  if (rule != LMS_ORACLE_RULE_TIED && rule != LMS_ORACLE_RULE_LITERAL) return LMS_ORACLE_ERR_ARG;
+  int st = lms_oracle_solve(xy, n, h, 1, out); /* argument checks; all-x-equal answer */
+  if (st != LMS_ORACLE_OK) return st;
+  int64_t hh = out->h;
+  best_t best = {INFINITY, 0.0, 0.0, 0.0, -1, -1};
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+  (void)nthreads;
+#endif
+#pragma omp parallel
+  {
+    double* X = (double*)malloc((size_t)n * sizeof(double));
+    best_t mine = {INFINITY, 0.0, 0.0, 0.0, -1, -1};
+#pragma omp for schedule(dynamic, 1)
+    for (int64_t i = 0; i < n - 1; ++i)
+      for (int64_t j = i + 1; j < n; ++j) {
+        if (xy[2 * j] == xy[2 * i]) continue;
+        best_t b;
+        vertex_bracelet(xy, n, hh, rule, i, j, X, &b);
+        if (better(&b, &mine)) mine = b;
+      }
+#pragma omp critical
+    {
+      if (better(&mine, &best)) best = mine;
+    }
+    free(X);
+  }
+  out->theta1 = best.theta;
+  out->theta2 = 0.5 * (best.z_lo + best.z_hi);
+  out->width = best.width;
+  out->half_width = 0.5 * best.width;
+  out->z_lo = best.z_lo;
+  out->z_hi = best.z_hi;
+  out->pair_i = best.i;
+  out->pair_j = best.j;
+  return LMS_ORACLE_OK;
+}

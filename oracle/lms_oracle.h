@@ -90,6 +90,21 @@ int lms_oracle_anchored(const double* xy, int64_t n, int64_t h, int64_t i, int64
 double lms_oracle_hth_abs_residual(const double* xy, int64_t n, int64_t h,
                                    double theta1, double theta2);
 
+/* Algorithm 1 as stated (Section 3.4): the bracelet hanging from each vertex
+ * (pair slope), with the pair's members set to exactly z_i, the intercepts
+ * sorted, and the far end h - 1 ranks away from the vertex rank; the minimum
+ * over vertices by (length, theta, lower end), then (i, j). `rule` says which
+ * rank a vertex tied with other values takes:
+ *   LMS_ORACLE_RULE_TIED    upward from the lowest tied rank and downward from
+ *                           the highest (exact: the minimum is the LMS width);
+ *   LMS_ORACLE_RULE_LITERAL the printed X[(k + |P|/2) mod |P|] with k the
+ *                           lowest tied rank (misses the optimum on many sets).
+ * All x equal: the answer of lms_oracle_solve. Fields as lms_oracle_solve;
+ * candidates and vertical count the pairs as there. */
+enum { LMS_ORACLE_RULE_TIED = 0, LMS_ORACLE_RULE_LITERAL = 1 };
+int lms_oracle_bracelets(const double* xy, int64_t n, int64_t h, int rule, int nthreads,
+                         lms_oracle_result* out);
+
 #ifdef __cplusplus
 }
 #endif

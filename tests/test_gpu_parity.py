@@ -390,3 +390,45 @@ def test_full_size_equivariance(gpu):
     t[:, 1] = 2.0 * t[:, 1] + 3.0 * t[:, 0] - 5.0
     q = gpu.solve(dev(t))
     assert close(q.width, 2.0 * r.width)
+
+
+def _stored_input(name, seed):
+    if name.startswith("degenerate_int_"):
+        return degenerate_int(int(name.rsplit("_", 1)[1]), seed)
+    if name.startswith("planted_"):
+        return planted(int(name.rsplit("_", 1)[1]), 0.45, seed)
+    return gen.make(name, seed)
+
+
+@pytest.mark.parametrize("key", ["planted_6000/601", "planted_9000/901", "c3a/301",
+                                 "degenerate_int_6000/602", "degenerate_int_9000/902",
+                                 "c3b/302"])
+def test_default_path_matches_stored_oracle(gpu, orc, key):
+    """Above 4096 points the default path bounds the optimal slope by exact
+    windows at one (6000) or two (9000, 16384) grids of slopes and screens
+    only what that range leaves. Its answer must be the oracle's minimum
+    (stored by tests/golden/make_golden.py from the oracle alone): bit for
+    bit on real-valued data; on integer data, where different slopes can tie
+    exactly, the width within 1e-9 and the oracle's window at the GPU's slope
+    equal to the GPU's."""
+    import hashlib
+    g = json.load(open(GOLD)).get(key)
+    assert g is not None, f"no stored oracle result for {key}"
+    name, seed = key.split("/")
+    xy = _stored_input(name, int(seed))
+    assert hashlib.sha256(xy.tobytes()).hexdigest() == g["input_sha256"]
+    r = gpu.solve(dev(xy))
+    print(key, r, flush=True)
+    assert r.status == g["status"] == 0
+    assert r.vertical == g["vertical"] and r.candidates == g["candidates"]
+    w = float.fromhex(g["width"])
+    assert close(r.width, w), (r.width, w)
+    if name.startswith("degenerate_int") or name == "c3b":
+        # integer coordinates: the slope range is usually too wide to prune
+        assert orc.window(xy, r.theta1) == (r.width, r.z_lo, r.z_hi)
+    else:
+        assert (r.width, r.theta1, r.z_lo, r.z_hi, r.theta2) == \
+               (w, float.fromhex(g["theta1"]), float.fromhex(g["z_lo"]),
+                float.fromhex(g["z_hi"]), float.fromhex(g["theta2"]))
+        # planted data: the slope range is narrow, so the pruned screen ran
+        assert r.bins == 2048, r.bins

@@ -63,3 +63,91 @@ def test_target_roundtrip():
     a = net.target_from_slope(1e12, 1.0, 1.0)
     b = net.target_from_slope(-1e12, 1.0, 1.0)
     assert np.allclose(a, b)
+
+
+def _tiny_params():
+    """Weights chosen by hand, all exactly representable in BF16, so that the
+    forward pass below can be followed on paper."""
+    p = {k: np.zeros(net.SHAPES[k]) for k in net.ORDER}
+    # layer 1: channel 0 = relu(x), channel 1 = relu(-x + 1), channel 2 = relu(y - 0.5)
+    p["W1"][0] = (1.0, 0.0)
+    p["W1"][1] = (-1.0, 0.0)
+    p["b1"][1] = 1.0
+    p["W1"][2] = (0.0, 1.0)
+    p["b1"][2] = -0.5
+    # layer 2: channel 0 = relu(h1_0 + 2 h1_2), channel 1 = relu(h1_1 - h1_0 - 0.25)
+    p["W2"][0, 0], p["W2"][0, 2] = 1.0, 2.0
+    p["W2"][1, 1], p["W2"][1, 0] = 1.0, -1.0
+    p["b2"][1] = -0.25
+    # head: h3_0 = relu(g0 - g1), h3_1 = relu(g1 + 1); out = (h3_0 - 0.5, 2 h3_1 - h3_0)
+    p["W3"][0, 0], p["W3"][0, 1] = 1.0, -1.0
+    p["W3"][1, 1] = 1.0
+    p["b3"][1] = 1.0
+    p["W4"][0, 0] = 1.0
+    p["b4"][0] = -0.5
+    p["W4"][1, 1], p["W4"][1, 0] = 2.0, -1.0
+    return p
+
+
+def test_forward_by_hand():
+    """Three points worked through the layers on paper:
+    (0.5, 1.0):  h1 = (0.5, 0.5, 0.5)   h2 = (1.5, 0)
+    (-1.0, 0.0): h1 = (0, 2, 0)         h2 = (0, 1.75)
+    (2.0, 0.75): h1 = (2, 0, 0.25)      h2 = (2.5, 0)
+    max-pool g = (2.5, 1.75); h3 = (0.75, 2.75); out = (0.25, 4.75)."""
+    p = _tiny_params()
+    pts = np.array([[0.5, 1.0], [-1.0, 0.0], [2.0, 0.75]])
+    out, cache = net.forward(p, pts)
+    assert cache["g"][0] == 2.5 and cache["g"][1] == 1.75
+    assert np.all(cache["g"][2:] == 0.0)
+    assert list(cache["h3"][:2]) == [0.75, 2.75]
+    assert list(out) == [0.25, 4.75]
+    # one point alone: (0.5, 1.0) gives g = (1.5, 0), h3 = (1.5, 1), out = (1.0, 0.5)
+    out1, _ = net.forward(p, pts[:1])
+    assert list(out1) == [1.0, 0.5]
+
+
+def test_forward_is_a_set_function():
+    """Permuting the points changes neither the output nor the loss."""
+    params = net.init_params(11)
+    xy = planted(300, 0.4, 12)
+    pts, _, _ = net.normalise(xy)
+    out, _ = net.forward(params, pts)
+    perm = Stream(3, 30).permutation(len(pts))
+    out2, _ = net.forward(params, pts[perm])
+    assert np.array_equal(out, out2)
+
+
+def test_maxpool_gradient_goes_to_first_argmax():
+    """Two points with the same features (W1 ignores y) tie in every channel;
+    the gradient must reach only the first of them. The W1[:, 1] gradient is
+    the routed point's y times its channel gradient, so it tells which one."""
+    p = _tiny_params()
+    p["W1"][2] = (0.0, 0.0)  # no channel reads y any more
+    p["b1"][2] = 0.0
+    for first_y, other_y in ((0.0, 5.0), (5.0, 0.0)):
+        # (2, y): h1 = (2, 0, 0), h2 = (2, 0); (0.5, 1): h1 = (0.5, 0.5, 0), h2 = (0.5, 0)
+        pts = np.array([[2.0, first_y], [2.0, other_y], [0.5, 1.0]])
+        out, cache = net.forward(p, pts)
+        assert cache["arg"][0] == 0 and cache["g"][0] == 2.0
+        # g = (2, 0): h3_0 = relu(2) = 2 is active, so d out0 / d g0 = 1, routed
+        # to the first tied point; there dz1 = (1, 0, 0) and dW1[0] = (x, y)
+        g = net.backward(cache, np.array([1.0, 0.0]))
+        assert g["W1"][0, 0] == 2.0 and g["W1"][0, 1] == first_y
+
+
+def test_target_at_known_angles():
+    """(cos 2phi, sin 2phi) of the line angle phi in the normalised frame,
+    where a slope theta1 becomes theta1 * sx / sy."""
+    cases = [(0.0, 1.0, 1.0, (1.0, 0.0)),          # horizontal line
+             (1.0, 1.0, 1.0, (0.0, 1.0)),          # 45 degrees: 2 phi = 90
+             (-1.0, 2.0, 2.0, (0.0, -1.0)),        # -45 degrees
+             (np.sqrt(3.0), 1.0, 1.0, (-0.5, np.sqrt(3.0) / 2)),  # 60 degrees
+             (0.5, 2.0, 1.0, (0.0, 1.0)),          # slope 0.5 in a frame scaled 2:1 -> 45
+             (1e300, 1.0, 1.0, (-1.0, 0.0))]       # near vertical: 2 phi -> 180
+    for th, sx, sy, want in cases:
+        t = net.target_from_slope(th, sx, sy)
+        assert np.allclose(t, want, atol=1e-12), (th, sx, sy, t)
+    assert abs(net.slope_from_output(np.array([0.0, 1.0]), 1.0, 1.0) - 1.0) < 1e-12
+    assert abs(net.slope_from_output(np.array([0.0, 3.0]), 2.0, 6.0) - 3.0) < 1e-12
+    assert net.slope_from_output(np.array([2.0, 0.0]), 1.0, 1.0) == 0.0
