@@ -242,6 +242,107 @@ lms_status lms_net_adam(float* d_params, float* d_m, float* d_v, const float* d_
 lms_status lms_net_slopes(const float* d_out, const double* d_scale, int64_t B, double* d_theta,
                           void* stream);
 
+/* ---- Algorithm 1 as stated (the ablation lms_solve is measured against) ----
+ * Section 3.4, Algorithm 1, with the kernels of Section 3.6: every vertex of
+ * the dual arrangement (pair slope) is materialised in an array; each vertex
+ * gets one workgroup that computes all n intercepts z_k = fma(-theta, x_k,
+ * y_k) at its slope, sorts them (bitonic, LDS, +inf padding to a power of
+ * two) and reads the bracelet hanging from the vertex, h - 1 ranks away; a
+ * min-reduction over the bracelet array gives the answer. The pair's own two
+ * intercepts are set to exactly z_i, and the vertex occupies every rank
+ * holding that value, r_lo..r_hi.
+ *   LMS_RULE_TIED:    upward from r_lo or downward to r_hi, the shorter that
+ *                     fits. The minimum is the LMS width (equioscillation puts
+ *                     the optimal slab's edge through a vertex, Section 3.3).
+ *   LMS_RULE_LITERAL: the printed far end X[(k + |P|/2) mod |P|] with
+ *                     k = r_lo (up from k if it fits, else down to k): the rule
+ *                     as printed, which leaves the tie open and can miss the
+ *                     optimum.
+ * d_xy: device, n x 2 FP64 interleaved, 2 <= n <= LMS_ALG1_MAX_N; h as for
+ * lms_solve. d_out: device, one lms_result: the minimum bracelet by (length,
+ * theta, lower end), then (i, j); survivors = candidates (every vertex is
+ * sorted). Argument errors return LMS_ERR_ARG before anything is enqueued;
+ * non-finite input gives status LMS_ERR_NONFINITE in the result; all x equal
+ * gives LMS_OK_DEGENERATE with slope 0. Work O(n^3 log^2 n), workspace about
+ * 48 n^2 / 2 bytes (library-owned, per stream). */
+#define LMS_ALG1_MAX_N 2048
+#define LMS_RULE_TIED 0
+#define LMS_RULE_LITERAL 1
+lms_status lms_solve_bracelets(const double* d_xy, int64_t n, int64_t h, int32_t rule,
+                               lms_result* d_out, void* stream);
+
+/* ---- Random sampling before the exact search (approximate) ----
+ * Section 5: the LMS step of the line detector can be accelerated by randomly
+ * sampling the feature points that voted for a Hough cell. Draws m of the n
+ * points without replacement and returns the exact LMS line of the sample
+ * (lms_solve on the sample, with `opt`); the line is an estimate of the whole
+ * set's, not its exact LMS line. The sample is the m points with the smallest
+ * keys mix64(seed + (k + 1) * 0x9E3779B97F4A7C15), the (k+1)-th SplitMix64
+ * output for state `seed` (Steele, Lea and Flood, OOPSLA 2014), taken in index
+ * order; equal keys go to the lower index.
+ * d_xy: device, n x 2 FP64, 2 <= n <= LMS_SAMPLE_MAX_N. m: 2 <= m <= min(n,
+ * LMS_MAX_N); m = n gives the exact solve. h: 0 for the sample's low median
+ * floor(m/2) + 1, else the same fraction of the sample, ceil(h m / n) (at
+ * least 2). d_out: device, one lms_result of the sample's solve (candidates
+ * and vertical count the sample's pairs); pair_i and pair_j are indices into
+ * d_xy. Argument errors return LMS_ERR_ARG before anything is enqueued. The
+ * sample buffer is a library-owned workspace per stream. */
+#define LMS_SAMPLE_MAX_N (1 << 30)
+lms_status lms_solve_sampled(const double* d_xy, int64_t n, int64_t h, int64_t m, uint64_t seed,
+                             lms_result* d_out, const lms_options* opt, void* stream);
+
+/* ---- Line detection: coarse Hough transform, then LMS per peak ----
+ * Section 5: a standard Hough transform with a coarse polar accumulator only
+ * locates the feature points of each putative line; an exact LMS fit of the
+ * points that voted for each accumulator peak then gives the line, so that up
+ * to half of a cell's points may be noise or belong to another structure.
+ *   - Accumulator: angle bins theta_b = b * d_theta (degrees, converted as
+ *     b * (d_theta * pi/180)), b = 0 .. ceil(180 / d_theta) - 1, with cos and
+ *     sin taken on the host (libm); rho = x cos theta_b + y sin theta_b in
+ *     FP64 (two products and a sum), bin floor((rho + width - 1) / d_rho),
+ *     floor((2 (width - 1) + height - 1) / d_rho) + 1 bins. Every pixel votes
+ *     once per angle bin.
+ *   - Peaks: cells with at least min_votes votes that are local maxima of
+ *     their 3x3 neighbourhood (above the earlier neighbours in cell order, at
+ *     least equal to the later ones); the max_lines strongest, by votes, then
+ *     lower cell index.
+ *   - Supporting set of a peak: the pixels that voted for it. Sets larger than
+ *     max_support are sampled down to max_support points, the pixels with the
+ *     smallest keys mix64(seed + (p + 1) * 0x9E3779B97F4A7C15) by pixel index
+ *     p (the draw of lms_solve_sampled; the paper's random sampling of a
+ *     cell's points). A steep line (normal within 45 degrees of the x axis,
+ *     |cos theta_b| > |sin theta_b|) is fitted transposed, as x = theta1 y +
+ *     theta2.
+ *   - Fits: lms_solve_batched on all sets, h = floor(n/2) + 1.
+ * d_pix: device, N x 2 int32 (x, y) pixel coordinates, 0 <= x < width,
+ * 0 <= y < height (others vote nowhere). d_acc: optional device array of
+ * n_theta x n_rho int32 that receives the accumulator (row = angle bin); NULL
+ * keeps it in the library's workspace. lines: HOST array of max_lines; the
+ * number of peaks found goes to *n_lines (host). Synchronous: it waits once
+ * for the supporting-set sizes (the batched fit is planned from them) and
+ * once for the fits. Argument errors return LMS_ERR_ARG. */
+#define LMS_HOUGH_MAX_LINES 1024
+typedef struct lms_hough_params {
+  uint32_t struct_size;   /* sizeof(lms_hough_params) */
+  int32_t width, height;  /* image size in pixels, 1 .. 2^20 */
+  int32_t max_lines;      /* peaks to fit, 1 .. LMS_HOUGH_MAX_LINES */
+  double d_rho;           /* rho bin width in pixels (>= 0.25) */
+  double d_theta_deg;     /* angle bin width in degrees, (0, 180] */
+  int32_t min_votes;      /* votes a peak needs (>= 2) */
+  int32_t max_support;    /* largest set fitted, 2 .. LMS_BATCH_MAX_N */
+  uint64_t seed;          /* seed of the sampling of larger sets */
+} lms_hough_params;
+typedef struct lms_line {
+  int32_t theta_bin, rho_bin; /* the peak's cell */
+  int32_t votes;              /* its votes (= the supporting pixels) */
+  int32_t support, fitted;    /* supporting pixels; points fitted (after sampling) */
+  int32_t transposed;         /* 1: result is the fit x = theta1 y + theta2 */
+  int32_t reserved[2];
+  lms_result result;          /* the LMS fit of the (transposed) set */
+} lms_line;
+lms_status lms_detect_lines(const int32_t* d_pix, int64_t N, const lms_hough_params* params,
+                            int32_t* d_acc, lms_line* lines, int32_t* n_lines, void* stream);
+
 const char* lms_status_str(int status);
 /* Message for the last failing call on this thread ("" if none). */
 const char* lms_last_error(void);

@@ -180,3 +180,26 @@ def bracelets(xy, h: int = 0, rule: int = RULE_TIED, nthreads: int = 0) -> Oracl
     r = _Result()
     lib().lms_oracle_bracelets(_dp(a), a.shape[0], h, rule, nthreads, ctypes.byref(r))
     return OracleResult(**{f: getattr(r, f) for f, _ in _Result._fields_})
+
+
+def sample_indices(n: int, m: int, seed: int) -> np.ndarray:
+    """Indices (ascending) of the m points with the smallest SplitMix64 keys,
+    key_k = output k of SplitMix64 started at `seed`; equal keys go to the
+    lower index. The random draw of the sampled solve."""
+    from workloads.gen import splitmix64
+    keys = splitmix64(seed, n)
+    order = np.lexsort((np.arange(n), keys))
+    return np.sort(order[:m])
+
+
+def solve_sampled(xy, m: int, seed: int, h: int = 0) -> OracleResult:
+    """Exact LMS line of the m-point sample (h = 0: the sample's low median;
+    else ceil(h m / n), at least 2), pair indices in the input's numbering."""
+    a = _xy(xy)
+    n = a.shape[0]
+    idx = sample_indices(n, m, seed)
+    hm = 0 if h == 0 else max(2, -(-h * m // n))
+    r = solve(a[idx], h=hm)
+    if r.pair_i >= 0:
+        r.pair_i, r.pair_j = int(idx[r.pair_i]), int(idx[r.pair_j])
+    return r

@@ -29,6 +29,8 @@ LMS_F_GRAPH = 2
 LMS_F_RANGE = 4
 LMS_F_NO_RANGE = 8
 BATCH_MAX_N = 4096
+ALG1_MAX_N = 2048
+RULE_TIED, RULE_LITERAL = 0, 1
 MAX_N = 16384
 RESULT_BYTES = 128
 
@@ -60,6 +62,21 @@ class _Tuning(ctypes.Structure):
     _fields_ = [("tile_regs", ctypes.c_int32), ("tile_batches", ctypes.c_int32),
                 ("seed_pairs", ctypes.c_int32), ("bins_log2", ctypes.c_int32),
                 ("ms", ctypes.c_double)]
+
+
+class _HoughParams(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("width", ctypes.c_int32),
+                ("height", ctypes.c_int32), ("max_lines", ctypes.c_int32),
+                ("d_rho", ctypes.c_double), ("d_theta_deg", ctypes.c_double),
+                ("min_votes", ctypes.c_int32), ("max_support", ctypes.c_int32),
+                ("seed", ctypes.c_uint64)]
+
+
+class _Line(ctypes.Structure):
+    _fields_ = [("theta_bin", ctypes.c_int32), ("rho_bin", ctypes.c_int32),
+                ("votes", ctypes.c_int32), ("support", ctypes.c_int32),
+                ("fitted", ctypes.c_int32), ("transposed", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2), ("result", _Result)]
 
 
 @dataclass
@@ -123,6 +140,14 @@ def load():
     L.lms_profile_begin.restype = None
     L.lms_profile_end.argtypes = [ctypes.POINTER(ctypes.c_double)]
     L.lms_profile_end.restype = ctypes.c_int64
+    L.lms_solve_bracelets.argtypes = [vp, i64, i64, ctypes.c_int32, vp, vp]
+    L.lms_solve_bracelets.restype = i32
+    L.lms_solve_sampled.argtypes = [vp, i64, i64, i64, ctypes.c_uint64, vp,
+                                    ctypes.POINTER(_Options), vp]
+    L.lms_solve_sampled.restype = i32
+    L.lms_detect_lines.argtypes = [vp, i64, ctypes.POINTER(_HoughParams), vp,
+                                   ctypes.POINTER(_Line), ctypes.POINTER(ctypes.c_int32), vp]
+    L.lms_detect_lines.restype = i32
     L.lms_shutdown.argtypes = []
     L.lms_shutdown.restype = None
     _lib = L
@@ -335,6 +360,84 @@ def screen_pairs(xy: torch.Tensor, pairs: torch.Tensor, W: float, h: int = 0,
                                  pairs.shape[0], out.data_ptr(), _stream(stream))
     _check(st)
     return out
+
+
+def solve_bracelets_async(xy: torch.Tensor, h: int = 0, rule: int = RULE_TIED,
+                          out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Enqueue Algorithm 1 as stated: every vertex materialised, one sort per
+    vertex, the bracelet hanging from it, a min-reduction (n <= 2048).
+    rule RULE_TIED (exact) or RULE_LITERAL (the printed rank offset)."""
+    xy = _points(xy)
+    if out is None:
+        out = torch.empty(RESULT_BYTES, dtype=torch.uint8, device=xy.device)
+    _check(load().lms_solve_bracelets(xy.data_ptr(), xy.shape[0], h, rule, out.data_ptr(),
+                                      _stream(stream)))
+    return out
+
+
+def solve_bracelets(xy: torch.Tensor, h: int = 0, rule: int = RULE_TIED) -> LmsResult:
+    """Algorithm 1 as stated (synchronises); see solve_bracelets_async."""
+    return parse(solve_bracelets_async(xy, h, rule))
+
+
+def solve_sampled_async(xy: torch.Tensor, m: int, seed: int = 0, h: int = 0,
+                        out: torch.Tensor | None = None, stream=None, **kw) -> torch.Tensor:
+    """Enqueue the exact LMS of m points drawn without replacement (an
+    estimate of the whole set's line); kw as for solve_async."""
+    xy = _points(xy)
+    if out is None:
+        out = torch.empty(RESULT_BYTES, dtype=torch.uint8, device=xy.device)
+    flags = (LMS_F_GRAPH if kw.pop("graph", False) else 0)
+    opt = _options(flags, **kw)
+    _check(load().lms_solve_sampled(xy.data_ptr(), xy.shape[0], h, m, seed & ((1 << 64) - 1),
+                                    out.data_ptr(), ctypes.byref(opt), _stream(stream)))
+    return out
+
+
+def solve_sampled(xy: torch.Tensor, m: int, seed: int = 0, h: int = 0, **kw) -> LmsResult:
+    """Exact LMS line of a random m-point sample (synchronises)."""
+    return parse(solve_sampled_async(xy, m, seed, h, **kw))
+
+
+def detect_lines(pix: torch.Tensor, width: int, height: int, d_rho: float = 20.0,
+                 d_theta_deg: float = 2.0, max_lines: int = 1, min_votes: int = 2,
+                 max_support: int = BATCH_MAX_N, seed: int = 0, acc: torch.Tensor | None = None,
+                 stream=None) -> list[dict]:
+    """Coarse Hough transform of edge pixels (CUDA int32 (N, 2) of (x, y)),
+    then the exact LMS line of each peak's supporting pixels (synchronous).
+    Returns per peak: theta_bin, rho_bin, votes, support, fitted, transposed
+    and the LmsResult of the fit (x = theta1 y + theta2 when transposed).
+    acc: optional CUDA int32 tensor (n_theta, n_rho) for the accumulator."""
+    if not (pix.is_cuda and pix.dtype == torch.int32 and pix.dim() == 2 and pix.shape[1] == 2):
+        raise ValueError("pix must be a CUDA int32 tensor of shape (N, 2)")
+    pix = pix.contiguous()
+    p = _HoughParams()
+    p.struct_size = ctypes.sizeof(_HoughParams)
+    p.width, p.height, p.max_lines = width, height, max_lines
+    p.d_rho, p.d_theta_deg = float(d_rho), float(d_theta_deg)
+    p.min_votes, p.max_support, p.seed = min_votes, max_support, seed & ((1 << 64) - 1)
+    lines = (_Line * max_lines)()
+    n = ctypes.c_int32(0)
+    if acc is not None and not (acc.is_cuda and acc.dtype == torch.int32 and acc.is_contiguous()):
+        raise ValueError("acc must be a contiguous CUDA int32 tensor")
+    _check(load().lms_detect_lines(pix.data_ptr(), pix.shape[0], ctypes.byref(p),
+                                   None if acc is None else acc.data_ptr(), lines,
+                                   ctypes.byref(n), _stream(stream)))
+    out = []
+    for k in range(n.value):
+        L = lines[k]
+        r = L.result
+        out.append(dict(theta_bin=L.theta_bin, rho_bin=L.rho_bin, votes=L.votes,
+                        support=L.support, fitted=L.fitted, transposed=L.transposed,
+                        result=LmsResult(**{f: getattr(r, f) for f, _ in _Result._fields_})))
+    return out
+
+
+def hough_grid(width: int, height: int, d_rho: float, d_theta_deg: float) -> tuple[int, int]:
+    """(n_theta, n_rho) of the accumulator lms_detect_lines uses."""
+    import math
+    return (math.ceil(180.0 / d_theta_deg),
+            math.floor(float(2 * (width - 1) + (height - 1)) / d_rho) + 1)
 
 
 STAGES = ("prep", "seed", "bins", "screen", "recheck", "finalize")

@@ -12,7 +12,8 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRCS = [os.path.join(HERE, "csrc", f) for f in ("lms.hip", "lms_batched.hip", "lms_net.hip", "lms_host.cpp")]
+SRCS = [os.path.join(HERE, "csrc", f) for f in ("lms.hip", "lms_batched.hip", "lms_net.hip", "lms_alg1.hip", "lms_sample.hip", "lms_hough.hip",
+                                                    "lms_host.cpp")]
 LIB = os.path.join(HERE, "liblms.so")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -50,6 +50,15 @@ def _mix64(z: np.ndarray) -> np.ndarray:
     return z
 
 
+def splitmix64(state: int, count: int) -> np.ndarray:
+    """The first `count` outputs of SplitMix64 started at `state`: output k
+    (0-based) is mix64(state + (k+1) * gamma)."""
+    k = np.arange(1, count + 1, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = np.uint64(state & _M64) + k * np.uint64(_GAMMA)
+    return _mix64(z)
+
+
 def _key(seed: int, stream: int) -> int:
     """Starting state of an independent stream for (seed, stream)."""
     s = np.array([(seed * 0x2545F4914F6CDD1D + stream * _GAMMA + 0x1234567) & _M64],
@@ -308,6 +317,37 @@ def rotated_line(count: int, n: int, seed: int, f_lo: float = 0.0, f_hi: float =
     xy[:, 1] = y[order]
     offsets = np.arange(count + 1, dtype=np.int64) * n
     return np.ascontiguousarray(xy), offsets
+
+
+def line_image(p_noise: float, seed: int, size: int = 1024, p_line: float = 0.5,
+               min_len: float = 400.0, margin: int = 16):
+    """Edge pixels of a synthetic size x size image: one line segment whose
+    pixels are kept with probability p_line, plus salt noise, each pixel on
+    with probability p_noise (the line-detection images of Section 5.1).
+
+    The segment joins two points uniform in [margin, size-1-margin]^2, redrawn
+    until it is at least min_len long; it is rasterised at unit steps along its
+    longer axis. Returns (pix int32 (N, 2) of (x, y) in raster order,
+    on_line bool (N,), segment (x0, y0, x1, y1) float64).
+    """
+    st = Stream(seed, 7)
+    lo, hi = float(margin), float(size - 1 - margin)
+    while True:
+        x0, y0, x1, y1 = st.uniform(4, lo, hi)
+        if (x1 - x0) ** 2 + (y1 - y0) ** 2 >= min_len ** 2:
+            break
+    steps = int(np.ceil(max(abs(x1 - x0), abs(y1 - y0))))
+    t = np.arange(steps + 1, dtype=np.float64) / steps
+    lx = np.round(x0 + t * (x1 - x0)).astype(np.int64)
+    ly = np.round(y0 + t * (y1 - y0)).astype(np.int64)
+    keep = st.uniform(steps + 1) < p_line
+    on = np.zeros(size * size, dtype=bool)
+    on[(ly * size + lx)[keep]] = True
+    line_mask = on.copy()
+    on |= st.uniform(size * size) < p_noise
+    idx = np.flatnonzero(on)
+    pix = np.stack([idx % size, idx // size], 1).astype(np.int32)
+    return np.ascontiguousarray(pix), line_mask[idx], np.array([x0, y0, x1, y1])
 
 
 # --------------------------------------------------------------------------
