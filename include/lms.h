@@ -47,7 +47,9 @@ typedef enum {
   LMS_ERR_NONFINITE = -2, /* a coordinate is NaN or infinite (device check) */
   LMS_ERR_DEVICE = -3,    /* a HIP call failed */
   LMS_ERR_NOMEM = -4,     /* workspace allocation failed */
-  LMS_ERR_CAPACITY = -5   /* more screen survivors than the workspace holds */
+  LMS_ERR_CAPACITY = -5   /* lms_solve under a max_workspace limit: more screen
+                             survivors than the limited list holds. (No seed error
+                             exists: any seed slope, even NaN, is only a bound.) */
 } lms_status;
 
 /* Result of one solve. 128 bytes, written to device memory by lms_solve.
@@ -117,6 +119,23 @@ typedef struct lms_options {
                            (tuned, else about 2n); -1 = no slope-bin screen (every
                            pair goes through the FP32 test) */
   int32_t reserved;
+  uint64_t max_workspace; /* 0 = no limit. Otherwise the most device memory, in bytes,
+                           that the call's own workspace may take: lms_solve shrinks
+                           the slope-bin pass list first (an overflowing list makes
+                           the exhaustive FP32 screen run instead, same result) and
+                           then the survivor list (more survivors than it holds give
+                           LMS_ERR_CAPACITY); lms_solve_batched shrinks its pass
+                           and survivor lists the same way and re-solves the
+                           problems whose survivors did not fit (see there). If
+                           even the fixed part does not fit: LMS_ERR_NOMEM.
+                           Read only when struct_size covers it. */
+  const float* d_net_params; /* lms_solve: device, LMS_NET_PARAMS FP32 seed-network
+                           parameters, or NULL. When set, the solve first runs the
+                           network on the points (lms_net_infer, max_points 2048)
+                           and uses its slope as the device seed slope (exclusive
+                           with d_seed_theta; window_pairs applies to it). The
+                           result stays exact whatever the network predicts. Read
+                           only when struct_size covers it. */
 } lms_options;
 
 /* Tile choice found by the autotuner for one size class. */
@@ -134,6 +153,11 @@ typedef struct lms_tuning {
 lms_status lms_solve(const double* d_xy, int64_t n, int64_t h, lms_result* d_out,
                      const lms_options* opt, void* stream);
 
+/* Device bytes of the workspace lms_solve would use for (n, h, opt) (after
+ * any max_workspace limit), into *bytes; LMS_ERR_ARG or LMS_ERR_NOMEM as
+ * lms_solve would return them. Enqueues nothing. */
+lms_status lms_workspace_size(int64_t n, int64_t h, const lms_options* opt, uint64_t* bytes);
+
 /* Exact LMS lines of B independent point sets in one pass (Section 5 applies
  * one LMS per Hough peak; this is that many-small-problems form).
  * d_xy: device, all points, n_b x 2 FP64 interleaved per problem.
@@ -147,7 +171,14 @@ lms_status lms_solve(const double* d_xy, int64_t n, int64_t h, lms_result* d_out
  * d_out: device, B results. opt->seed_pairs is per problem (default 31).
  * With LMS_F_GRAPH the kernels are captured in a hipGraph on the first call
  * and replayed afterwards; the inputs may change between calls, the pointers
- * and offsets may not (otherwise the plan and graph are rebuilt). */
+ * and offsets may not (otherwise the plan and graph are rebuilt).
+ * Capacity: survivors of all problems share one list. When the batch has more
+ * pairs than that list holds (by default above 2^24 pairs, or under
+ * opt->max_workspace), the call waits for the batch once, and every problem
+ * whose survivors did not fit is solved again by lms_solve (whose list holds
+ * all pairs of a problem of this size) into its own result: every valid
+ * problem gets its exact answer. Otherwise the call only enqueues.
+ * Problems are limited to 2^30 points in all (d_offsets[B] <= 2^30). */
 #define LMS_BATCH_MAX_N 4096
 lms_status lms_solve_batched(const double* d_xy, const int64_t* d_offsets,
                              const int64_t* h_offsets, int64_t B, const int32_t* d_h,
@@ -217,9 +248,12 @@ int64_t lms_profile_end(double* ms);
  * Sets are CSR like lms_solve_batched (d_offsets, B+1 int64). */
 #define LMS_NET_PARAMS 8642
 
-/* Per set: midrange centre and half-range scale of x and y (1 for a zero
- * range). Writes d_pts (float2 per point, in [-1,1]^2) and d_scale
- * (B x 4 FP64: cx, cy, sx, sy). */
+/* Per set, per coordinate, a robust frame: the centre is the lower median
+ * (rank floor((m-1)/2)) of a fixed sample of m points (all points up to 255,
+ * else indices floor(k n / 255), k < 255), the scale the lower median of the
+ * absolute deviations from it (the MAD), else the largest deviation, else 1;
+ * up to half of the points being outliers moves neither. Writes d_pts (float2
+ * per point, (p - centre) / scale) and d_scale (B x 4 FP64: cx, cy, sx, sy). */
 lms_status lms_net_prepare(const double* d_xy, const int64_t* d_offsets, int64_t B, float* d_pts,
                            double* d_scale, void* stream);
 /* Forward pass: d_out (B x 2 FP32) and, if d_g is not NULL, the pooled
@@ -238,6 +272,18 @@ lms_status lms_net_backward(const float* d_params, const float* d_pts, const int
 /* One bias-corrected Adam step (step >= 1) on the FP32 masters. */
 lms_status lms_net_adam(float* d_params, float* d_m, float* d_v, const float* d_grad, int64_t step,
                         float lr, float beta1, float beta2, float eps, void* stream);
+/* Inference for B sets, spread over many workgroups per set (the max-pool is
+ * order-free, so the pooled features, outputs and slopes equal those of
+ * lms_net_prepare + lms_net_forward + lms_net_slopes on the same points): the
+ * frame of each set, then the features pooled over at most max_points points
+ * of it (a set of n > max_points points is read at indices
+ * floor(j n / max_points), j < max_points; the frame always comes from the
+ * whole set), the head and the seed slope into d_theta (device, B FP64); the
+ * raw outputs into d_out (device, B x 2 FP32) if not NULL. max_set bounds the
+ * largest set (it sizes the grid). Scratch is a library workspace per stream. */
+lms_status lms_net_infer(const float* d_params, const double* d_xy, const int64_t* d_offsets,
+                         int64_t B, int64_t max_set, int32_t max_points, double* d_theta,
+                         float* d_out, void* stream);
 /* Seed slopes in the original frames: tan(atan2(out1, out0)/2) * sy / sx. */
 lms_status lms_net_slopes(const float* d_out, const double* d_scale, int64_t B, double* d_theta,
                           void* stream);

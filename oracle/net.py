@@ -8,7 +8,8 @@ any slope it proposes only sets the exact search's initial width bound, since
 F(theta) >= the optimum for every theta (Eq. (1)). The search stays exact
 whatever the network predicts.
 
-Architecture, for one set of n points p_k in a [-1, 1]^2 frame:
+Architecture, for one set of n points p_k in the set's robust frame (see
+normalise: coordinate-wise median and MAD of a fixed sample of the points):
     h1_k = relu(W1 p_k + b1)            (64)
     h2_k = relu(W2 bf16(h1_k) + b2)     (64)
     g    = max_k h2_k                   (64, per channel)
@@ -39,12 +40,38 @@ def bf16(a: np.ndarray) -> np.ndarray:
     return u.astype(np.uint32).view(np.float32).astype(np.float64)
 
 
+SAMPLE = 255  # points of a set that fix its frame
+
+
+def frame_sample(n: int) -> np.ndarray:
+    """Indices that fix a set's frame: all points up to SAMPLE of them, else
+    floor(k n / SAMPLE) for k = 0 .. SAMPLE - 1."""
+    if n <= SAMPLE:
+        return np.arange(n)
+    return (np.arange(SAMPLE, dtype=np.int64) * n) // SAMPLE
+
+
+def _lower_median(v: np.ndarray) -> float:
+    """The value of rank floor((m - 1) / 2) among m values."""
+    return float(np.sort(v, kind="stable")[(len(v) - 1) // 2])
+
+
 def normalise(xy: np.ndarray):
-    """Midrange centre and half-range scale per coordinate (1 if the range is 0)."""
-    lo, hi = xy.min(0), xy.max(0)
-    c = lo + 0.5 * (hi - lo)
-    s = np.maximum(np.abs(lo - c), np.abs(hi - c))
-    s = np.where(s > 0, s, 1.0)
+    """Robust frame per coordinate: centre = the lower median of the sampled
+    values, scale = the lower median of their absolute deviations from it (the
+    MAD), else the largest deviation, else 1. Outliers, up to half of the
+    points, move neither. Returns (points in that frame, centre, scale)."""
+    smp = xy[frame_sample(len(xy))]
+    c = np.empty(2)
+    s = np.empty(2)
+    for a in range(2):
+        c[a] = _lower_median(smp[:, a])
+        dev = np.abs(smp[:, a] - c[a])
+        s[a] = _lower_median(dev)
+        if not s[a] > 0:
+            s[a] = dev.max()
+        if not s[a] > 0:
+            s[a] = 1.0
     return (xy - c) / s, c, s
 
 
@@ -132,3 +159,18 @@ def init_params(seed: int) -> dict:
         else:
             p[k] = np.zeros(shp)
     return p
+
+
+def predict(params: dict, xy: np.ndarray, max_points: int = 2048):
+    """Inference on one raw set: the frame of the whole set (normalise), the
+    features pooled over at most max_points points (a larger set is read at
+    indices floor(j n / max_points)), the head; returns (out, slope in the
+    original frame)."""
+    pts, c, s = normalise(xy)
+    n = len(xy)
+    if n > max_points:
+        pts = pts[(np.arange(max_points, dtype=np.int64) * n) // max_points]
+    # the GPU rounds the framed points to FP32
+    pts = pts.astype(np.float32).astype(np.float64)
+    out, _ = forward(params, pts)
+    return out, slope_from_output(out, s[0], s[1])

@@ -55,7 +55,8 @@ class _Options(ctypes.Structure):
                 ("seed_pairs", ctypes.c_int32), ("tile_regs", ctypes.c_int32),
                 ("d_seed_theta", ctypes.c_void_p), ("n_seed_theta", ctypes.c_int64),
                 ("tile_batches", ctypes.c_int32), ("window_pairs", ctypes.c_int32),
-                ("bins_log2", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("bins_log2", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("max_workspace", ctypes.c_uint64), ("d_net_params", ctypes.c_void_p)]
 
 
 class _Tuning(ctypes.Structure):
@@ -148,6 +149,9 @@ def load():
     L.lms_detect_lines.argtypes = [vp, i64, ctypes.POINTER(_HoughParams), vp,
                                    ctypes.POINTER(_Line), ctypes.POINTER(ctypes.c_int32), vp]
     L.lms_detect_lines.restype = i32
+    L.lms_workspace_size.argtypes = [i64, i64, ctypes.POINTER(_Options),
+                                     ctypes.POINTER(ctypes.c_uint64)]
+    L.lms_workspace_size.restype = i32
     L.lms_shutdown.argtypes = []
     L.lms_shutdown.restype = None
     _lib = L
@@ -180,8 +184,15 @@ def _stream(stream) -> int:
 
 
 def _options(flags=0, seed_pairs=None, seed_theta: torch.Tensor | None = None, tile_regs=0,
-             tile_batches=0, window_pairs=0, bins_log2=0):
+             tile_batches=0, window_pairs=0, bins_log2=0, max_workspace=0,
+             net_params: torch.Tensor | None = None):
     o = _Options()
+    o.max_workspace = int(max_workspace)
+    if net_params is not None:
+        if not (net_params.is_cuda and net_params.dtype == torch.float32
+                and net_params.is_contiguous() and net_params.numel() == 8642):
+            raise ValueError("net_params must be a contiguous CUDA float32 vector of 8642")
+        o.d_net_params = net_params.data_ptr()
     o.struct_size = ctypes.sizeof(_Options)
     o.flags = flags
     o.tile_regs = int(tile_regs)
@@ -210,13 +221,16 @@ def solve_async(xy: torch.Tensor, h: int = 0, out: torch.Tensor | None = None, *
                 seed_theta: torch.Tensor | None = None, tile_regs: int = 0,
                 tile_batches: int = 0, window_pairs: int = 0, bins_log2: int = 0,
                 graph: bool = False, slope_range: bool | None = None,
+                max_workspace: int = 0, net_params: torch.Tensor | None = None,
                 stream=None) -> torch.Tensor:
     """Enqueue one exact LMS solve; returns the device uint8[128] result buffer.
 
     seed_theta: optional CUDA float64 slopes whose exact widths seed the bound;
     window_pairs: with seed_theta, pairs drawn from the best seed line's window
     (two rounds) as further seeds. bins_log2: slope bins per anchor of the
-    first screen (0 automatic, -1 off). graph=True captures the solve in a
+    first screen (0 automatic, -1 off). net_params: the seed network's packed
+    FP32 parameters (CUDA); its slope, computed inside the solve, is the seed
+    slope (exclusive with seed_theta). graph=True captures the solve in a
     hipGraph on the first call and replays it on later calls with the same
     buffers and options. slope_range: None automatic (above 4096 points),
     True at any n, False never."""
@@ -227,11 +241,20 @@ def solve_async(xy: torch.Tensor, h: int = 0, out: torch.Tensor | None = None, *
     if slope_range is not None:
         flags |= LMS_F_RANGE if slope_range else LMS_F_NO_RANGE
     opt = _options(flags, seed_pairs, seed_theta, tile_regs, tile_batches, window_pairs,
-                   bins_log2)
+                   bins_log2, max_workspace, net_params)
     st = load().lms_solve(xy.data_ptr(), xy.shape[0], h, out.data_ptr(), ctypes.byref(opt),
                           _stream(stream))
     _check(st)
     return out
+
+
+def workspace_size(n: int, h: int = 0, max_workspace: int = 0, **kw) -> int:
+    """Device bytes lms_solve's workspace takes for n points (and options)."""
+    flags = 0
+    opt = _options(flags, max_workspace=max_workspace, **kw)
+    b = ctypes.c_uint64(0)
+    _check(load().lms_workspace_size(n, h, ctypes.byref(opt), ctypes.byref(b)))
+    return b.value
 
 
 def solve(xy: torch.Tensor, h: int = 0, **kw) -> LmsResult:
@@ -263,7 +286,7 @@ def parse_batch(raw: torch.Tensor):
 def solve_batched_async(xy: torch.Tensor, offsets, h: torch.Tensor | None = None,
                         out: torch.Tensor | None = None, *, graph: bool = False,
                         seed_pairs: int | None = None, bins_log2: int = 0,
-                        stream=None) -> torch.Tensor:
+                        max_workspace: int = 0, stream=None) -> torch.Tensor:
     """Enqueue exact LMS fits of B point sets; problem b is xy[offsets[b]:offsets[b+1]].
 
     offsets: B+1 int64 (host array or tensor; a device copy is made if needed).
@@ -285,7 +308,8 @@ def solve_batched_async(xy: torch.Tensor, offsets, h: torch.Tensor | None = None
         out = torch.empty((B, RESULT_BYTES), dtype=torch.uint8, device=xy.device)
     if h is not None and not (h.is_cuda and h.dtype == torch.int32 and h.numel() == B):
         raise ValueError("h must be a CUDA int32 tensor with B values")
-    opt = _options(LMS_F_GRAPH if graph else 0, seed_pairs, bins_log2=bins_log2)
+    opt = _options(LMS_F_GRAPH if graph else 0, seed_pairs, bins_log2=bins_log2,
+                   max_workspace=max_workspace)
     st = load().lms_solve_batched(xy.data_ptr(), off_d.data_ptr(), off_h.ctypes.data, B,
                                   None if h is None else h.data_ptr(), out.data_ptr(),
                                   ctypes.byref(opt), _stream(stream))

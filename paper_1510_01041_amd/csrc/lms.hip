@@ -31,6 +31,7 @@
 #include <hip/hip_runtime.h>
 
 #include <climits>
+#include <cstddef>
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
@@ -56,6 +57,7 @@ constexpr int kDefaultSeeds = 255;
 constexpr long long kScreenCap = 1ll << 24;     // survivor slots beyond the seeds
 constexpr int kRegChunks = 64;                  // points per lane kept in VGPRs (max)
 constexpr int kPathSingle = 0;                  // tuning-table key of lms_solve
+constexpr int kNetPoints = 2048;                // points the seed network pools over
 
 // Per-solve state in device memory.
 struct __align__(16) Ctx {
@@ -1662,14 +1664,14 @@ __global__ __launch_bounds__(1024) void k_finalize(Ctx* ctx, const uint2* __rest
 // ---------------------------------------------------------------- host side
 
 struct Layout {
-  size_t ctx, xy32, entries, res, rec, cands, sort_tmp, grid, range, total;
+  size_t ctx, xy32, entries, res, rec, cands, sort_tmp, grid, range, net, total;
 };
 
 // n_rec: windows of the device seed slopes (kept only for window pairs);
 // cand_cap: list of the slope-bin screen's passes; sort_tmp: doubles of the
 // split FP64 re-evaluation
 Layout layout(int n_pad, long long cap, long long n_rec = 0, long long cand_cap = 0,
-              long long sort_tmp = 0) {
+              long long sort_tmp = 0, bool net = false) {
   auto up = [](size_t v) { return (v + 255) & ~size_t(255); };
   Layout L;
   L.ctx = 0;
@@ -1681,7 +1683,9 @@ Layout layout(int n_pad, long long cap, long long n_rec = 0, long long cand_cap 
   L.sort_tmp = L.cands + up((size_t)cand_cap * sizeof(uint2));
   L.grid = L.sort_tmp + up((size_t)sort_tmp * sizeof(double));
   L.range = L.grid + up(2 * kGrid * (sizeof(double) + sizeof(double4)));
-  L.total = L.range + up((size_t)n_pad * (sizeof(unsigned) + sizeof(uint2) + sizeof(double2)));
+  L.net = L.range + up((size_t)n_pad * (sizeof(unsigned) + sizeof(uint2) + sizeof(double2)));
+  // the network's slope (one double), then its inference scratch
+  L.total = L.net + (net ? up(sizeof(double)) + up(lms_host::net_infer_bytes(1)) : 0);
   return L;
 }
 
@@ -2067,6 +2071,7 @@ struct Setup {
   int seeds = 0, window_pairs = 0, bins_log2 = 0, G = 1, ipa = 1;
   int final_slots = 0;
   bool no_prune = false, use_bins = false;
+  const float* net = nullptr;  // seed-network parameters (the slope is computed in the solve)
   bool range = false, refine = false;  // slope range: first grid; second grid
   const double* seed_theta = nullptr;
   int64_t n_seed_theta = 0;
@@ -2076,7 +2081,8 @@ struct Setup {
 
 lms_status make_setup(const double* d_xy, int64_t n, int64_t h, lms_result* d_out,
                       const lms_options* opt, Setup* S) {
-  if (opt && opt->struct_size < sizeof(lms_options)) return fail(LMS_ERR_ARG, "bad options size");
+  if (opt && opt->struct_size < offsetof(lms_options, max_workspace))
+    return fail(LMS_ERR_ARG, "bad options size");
   // automatic tiles and seeds: the autotuned choice for this size class, if any
   lms_tuning tuned{0, 0, -1, 0, 0.0};
   const bool have_tuned = n >= 2 && n <= LMS_MAX_N &&
@@ -2110,6 +2116,12 @@ lms_status make_setup(const double* d_xy, int64_t n, int64_t h, lms_result* d_ou
     window_pairs = opt->window_pairs;
     if (window_pairs < 0 || window_pairs > (1 << 16))
       return fail(LMS_ERR_ARG, "window_pairs must be in [0, 65536]");
+    if (opt->struct_size >= offsetof(lms_options, d_net_params) + sizeof(void*) &&
+        opt->d_net_params) {
+      if (n_seed_theta) return fail(LMS_ERR_ARG, "d_net_params and d_seed_theta are exclusive");
+      S->net = opt->d_net_params;
+      n_seed_theta = 1;  // the network's slope, computed on the device
+    }
   }
   const long long pairs = (long long)p.n * (p.n - 1) / 2;
   const bool no_prune = (flags & LMS_F_NO_PRUNE) != 0;
@@ -2153,7 +2165,30 @@ lms_status make_setup(const double* d_xy, int64_t n, int64_t h, lms_result* d_ou
   // split re-evaluation slots: the usual number of survivors
   S->final_slots = split_slots(p.n, p.n > 4096 ? kFinalSlotsLarge : kFinalSlots);
   const long long tmp = (long long)S->final_slots * next_pow2(p.n);
-  S->L = layout(p.n_pad, p.cap, n_seed_theta, S->cand_cap, tmp);
+  S->L = layout(p.n_pad, p.cap, n_seed_theta, S->cand_cap, tmp, S->net != nullptr);
+  // A workspace limit shrinks the slope-bin pass list first (its overflow
+  // sends the solve to the exhaustive FP32 screen: same result, slower), then
+  // the survivor list (its overflow is reported as LMS_ERR_CAPACITY).
+  const uint64_t max_ws =
+      opt && opt->struct_size >= offsetof(lms_options, max_workspace) + sizeof(uint64_t)
+          ? opt->max_workspace : 0;
+  if (max_ws && S->L.total > max_ws) {
+    const long long kMinList = 1024;
+    if (S->cand_cap > kMinList) {
+      const long long over = (long long)(S->L.total - max_ws);
+      S->cand_cap = std::max(kMinList, S->cand_cap - (over + 7) / 8 - 64);
+      S->L = layout(p.n_pad, p.cap, n_seed_theta, S->cand_cap, tmp, S->net != nullptr);
+    }
+    if (S->L.total > max_ws && p.cap - p.n_seeds > kMinList) {
+      const long long over = (long long)(S->L.total - max_ws);
+      const long long per = (long long)(sizeof(uint2) + sizeof(double4));
+      p.cap = p.n_seeds + std::max(kMinList, p.cap - p.n_seeds - (over + per - 1) / per - 16);
+      S->L = layout(p.n_pad, p.cap, n_seed_theta, S->cand_cap, tmp, S->net != nullptr);
+    }
+    if (S->L.total > max_ws)
+      return fail(LMS_ERR_NOMEM, "max_workspace below the " + std::to_string(S->L.total) +
+                                     " bytes this solve needs at the least");
+  }
   return LMS_OK;
 }
 
@@ -2175,6 +2210,15 @@ lms_status enqueue_solve(const Setup& S, char* base, hipStream_t s, lms_host::St
   hipLaunchKernelGGL(k_prep, dim3(1), dim3(1024), 0, s, d_xy, p.n, p.h, p.n_pad, ctx, xy32,
                      entries, p.n_seeds, seeds, key, S.use_bins ? bins_count(S.bins_log2) : 0u,
                      (int)p.cap);
+  // the seed network's slope, as the device seed slope
+  const double* seed_theta = S.seed_theta;
+  if (S.net) {
+    double* th = (double*)(base + L.net);
+    const lms_status st = lms_host::net_infer_enqueue(S.net, d_xy, nullptr, 1, p.n, kNetPoints,
+                                                      th, nullptr, base + L.net + 256, s);
+    if (st != LMS_OK) return st;
+    seed_theta = th;
+  }
   mark();
   // Seeds: exact FP64 widths of a few slopes set the screen's bound: the
   // device seed slopes, the extreme-x and random pairs, and with window pairs
@@ -2182,7 +2226,7 @@ lms_status enqueue_solve(const Setup& S, char* base, hipStream_t s, lms_host::St
   // pruning the bound stays +inf and the screen keeps every pair whose
   // anchored window can hold h points at all.
   if (n_seed_theta > 0 && !S.no_prune)
-    launch_eval(s, (int)std::min<int64_t>(n_seed_theta, 4 * cu), d_xy, p.n, p.h, S.seed_theta,
+    launch_eval(s, (int)std::min<int64_t>(n_seed_theta, 4 * cu), d_xy, p.n, p.h, seed_theta,
                 (int)n_seed_theta, nullptr, ctx, rec);
   const int first_w = 1 + seeds;
   if (window_pairs)
@@ -2272,15 +2316,17 @@ struct SolveKey {
   const void* xy;
   const void* out;
   const void* seed_theta;
+  const void* net;
   void* stream;
   int64_t n_seed_theta;
   int n, h, seeds, window_pairs, bins_log2, R, G;
   unsigned flags;
+  long long cand_cap, cap;
   bool operator<(const SolveKey& o) const {
-    return std::tie(xy, out, seed_theta, stream, n_seed_theta, n, h, seeds, window_pairs,
-                    bins_log2, R, G, flags) <
-           std::tie(o.xy, o.out, o.seed_theta, o.stream, o.n_seed_theta, o.n, o.h, o.seeds,
-                    o.window_pairs, o.bins_log2, o.R, o.G, o.flags);
+    return std::tie(xy, out, seed_theta, net, stream, n_seed_theta, n, h, seeds, window_pairs,
+                    bins_log2, R, G, flags, cand_cap, cap) <
+           std::tie(o.xy, o.out, o.seed_theta, o.net, o.stream, o.n_seed_theta, o.n, o.h, o.seeds,
+                    o.window_pairs, o.bins_log2, o.R, o.G, o.flags, o.cand_cap, o.cap);
   }
 };
 struct SolveGraph {
@@ -2292,8 +2338,10 @@ std::mutex g_smu;
 std::map<SolveKey, SolveGraph> g_solves;
 
 lms_status solve_graph(const Setup& S, hipStream_t s) {
-  const SolveKey key{S.xy, S.out, S.seed_theta, (void*)s, S.n_seed_theta, S.p.n, S.p.h, S.seeds,
-                     S.window_pairs, S.bins_log2, S.p.R, S.G, S.flags};
+  const SolveKey key{S.xy,       S.out,         S.seed_theta,  S.net,    (void*)s,
+                     S.n_seed_theta, S.p.n,     S.p.h,         S.seeds,  S.window_pairs,
+                     S.bins_log2, S.p.R,        S.G,           S.flags,  S.cand_cap,
+                     S.p.cap};
   std::lock_guard<std::mutex> lk(g_smu);
   auto it = g_solves.find(key);
   if (it == g_solves.end()) {
@@ -2381,6 +2429,19 @@ lms_status lms_solve(const double* d_xy, int64_t n, int64_t h, lms_result* d_out
   st = enqueue_solve(S, base, s, &prof);
   prof.finish();
   return st;
+}
+
+lms_status lms_workspace_size(int64_t n, int64_t h, const lms_options* opt, uint64_t* bytes) {
+  lms_host::clear_error();
+  if (!bytes) return fail(LMS_ERR_ARG, "null pointer");
+  Setup S;
+  // the setup only reads the pointers' values: any non-null placeholder works
+  static const double dummy_xy[2] = {0.0, 0.0};
+  static lms_result dummy_out;
+  const lms_status st = make_setup(dummy_xy, n, h, &dummy_out, opt, &S);
+  if (st != LMS_OK) return st;
+  *bytes = (uint64_t)S.L.total;
+  return LMS_OK;
 }
 
 lms_status lms_autotune(const double* d_xy, int64_t n, int64_t h, int32_t reps, void* stream,

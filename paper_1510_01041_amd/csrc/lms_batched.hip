@@ -38,6 +38,8 @@
 #include <tuple>
 #include <vector>
 
+#include <cstddef>
+
 #include "lms.h"
 #include "lms_device.h"
 #include "lms_host.h"
@@ -58,7 +60,8 @@ constexpr int kPathBatched = 1;   // tuning-table key of lms_solve_batched
 // Per-problem state in device memory.
 struct __align__(16) PMeta {
   int off, n, h, pad_off;
-  int R, status, all_x_equal, pad;
+  int R, status, all_x_equal;
+  unsigned overflow;  // a survivor of this problem found no list slot
   double xh, yh, xabs, yabs;
   unsigned long long wbound;
   unsigned long long best_w, best_th, best_lo, best_pair;
@@ -335,8 +338,12 @@ __global__ __launch_bounds__(256, 3) void k_bscreen(
         base = __shfl(base, 0);
         if ((kept >> lane) & 1ull) {
           const unsigned idx = base + (unsigned)__popcll(kept & ((1ull << lane) - 1ull));
-          if (idx < (unsigned)cap) entries[idx] = make_uint2((unsigned)b, pack_pair(lo, hi));
-          else atomicOr(&state->overflow, 1u);
+          if (idx < (unsigned)cap) {
+            entries[idx] = make_uint2((unsigned)b, pack_pair(lo, hi));
+          } else {
+            atomicOr(&state->overflow, 1u);
+            atomicOr(&meta[b].overflow, 1u);
+          }
         }
         n_keep += cnt;
       }
@@ -472,8 +479,12 @@ __global__ __launch_bounds__(NT) void k_bbins(const double* __restrict__ xy, PMe
         base = __shfl(base, 0);
         if (force) {
           const unsigned idx = base + (unsigned)__popcll(mf & ((1ull << lane) - 1ull));
-          if (idx < (unsigned)cap) entries[idx] = make_uint2((unsigned)b, pack_pair(lo, hi));
-          else atomicOr(&state->overflow, 1u);
+          if (idx < (unsigned)cap) {
+            entries[idx] = make_uint2((unsigned)b, pack_pair(lo, hi));
+          } else {
+            atomicOr(&state->overflow, 1u);
+            atomicOr(&meta[b].overflow, 1u);
+          }
         }
       }
       if (mp) {
@@ -637,7 +648,10 @@ __global__ __launch_bounds__(256, 3) void k_bscreen_list(
           got = __shfl(got, 0);
           e_next = got;
           e_end = got >= (unsigned)cap ? got : min(got + want, (unsigned)cap);
-          if (e_end - e_next < cnt && lane == 0) atomicOr(&state->overflow, 1u);
+          if (e_end - e_next < cnt && lane == 0) {
+            atomicOr(&state->overflow, 1u);
+            atomicOr(&meta[b].overflow, 1u);
+          }
         }
         if ((kept >> lane) & 1ull) {
           const unsigned idx = e_next + (unsigned)__popcll(kept & ((1ull << lane) - 1ull));
@@ -780,7 +794,7 @@ __global__ __launch_bounds__(256) void k_bfinal(const PMeta* __restrict__ meta, 
   memset(&o, 0, sizeof(o));
   o.h = m.h;
   int st = m.status;
-  if (st >= 0 && state->overflow) st = LMS_ERR_CAPACITY;
+  if (st >= 0 && m.overflow) st = LMS_ERR_CAPACITY;  // re-solved by the host
   if (st >= 0 && m.best_w == ~0ull) st = LMS_ERR_DEVICE;
   if (st >= 0 && m.all_x_equal) st = LMS_OK_DEGENERATE;
   o.status = st;
@@ -821,6 +835,7 @@ __global__ __launch_bounds__(256) void k_bfinal(const PMeta* __restrict__ meta, 
 struct BPlan {
   int B = 0, S = 0, max_n = 0;
   long long pad_total = 0, pairs = 0, cap = 0;
+  bool may_overflow = false;  // more pairs than survivor slots: check after the pass
   int n_probs[kClasses] = {};
   int n_items[kClasses] = {};
   long long pairs_c[kClasses] = {};   // pairs per register class
@@ -837,7 +852,9 @@ struct BPlan {
 
 size_t up256(size_t v) { return (v + 255) & ~size_t(255); }
 
-lms_status plan_batch(const int64_t* h_off, int B, int S, BPlan* P) {
+void layout_batch(BPlan* P);
+
+lms_status plan_batch(const int64_t* h_off, int B, int S, uint64_t max_ws, BPlan* P) {
   P->B = B;
   P->S = S;
   P->h_pad.assign(B, 0);
@@ -863,6 +880,9 @@ lms_status plan_batch(const int64_t* h_off, int B, int S, BPlan* P) {
     }
   }
   if (h_off[0] < 0) return fail(LMS_ERR_ARG, "offsets must be >= 0");
+  // the kernels index points and padded chunks with 32-bit offsets
+  if (h_off[B] > (1ll << 30) || pad > (1ll << 30))
+    return fail(LMS_ERR_ARG, "a batch holds at most 2^30 points");
   P->pad_total = pad;
   P->h_items.clear();
   for (int c = 0; c < kClasses; ++c) {
@@ -889,13 +909,51 @@ lms_status plan_batch(const int64_t* h_off, int B, int S, BPlan* P) {
   // slack for the survivor slots each wavefront reserves ahead
   P->cap = seeds + std::min<long long>(P->pairs, kBatchScreenCap) + (1ll << 20);
   if (P->cap > INT_MAX) return fail(LMS_ERR_ARG, "batch too large");
+  for (int c = 0; c < kClasses; ++c)
+    // slack for the slots each block reserves ahead and may leave unused
+    P->cand_cap[c] = P->pairs_c[c] ? std::min<long long>(P->pairs_c[c] + (1ll << 20), kBatchCandCap)
+                                   : 0;
+  layout_batch(P);
+  if (max_ws && P->total > max_ws) {
+    // a workspace limit shrinks the pass lists (an overflowing class runs the
+    // exhaustive screen instead), then the survivor list (its problems that
+    // lose survivors are re-solved on their own)
+    const long long kMinList = 4096;
+    for (int c = 0; c < kClasses && P->total > max_ws; ++c) {
+      if (P->cand_cap[c] <= kMinList) continue;
+      const long long over = (long long)(P->total - max_ws);
+      P->cand_cap[c] = std::max(kMinList, P->cand_cap[c] - (over + 7) / 8 - 64);
+      layout_batch(P);
+    }
+    while (P->total > max_ws && P->cap - seeds > kMinList) {
+      // entries, windows, slot and representative per survivor, and the
+      // equal-slope set (about two slots per survivor)
+      const long long per = (long long)(sizeof(uint2) + sizeof(double4) + 2 * sizeof(unsigned) +
+                                        2 * sizeof(Slot));
+      const long long over = (long long)(P->total - max_ws);
+      P->cap = seeds + std::max(kMinList, P->cap - seeds - (over + per - 1) / per - 64);
+      layout_batch(P);
+    }
+    if (P->total > max_ws)
+      return fail(LMS_ERR_NOMEM, "max_workspace below the " + std::to_string(P->total) +
+                                     " bytes this batch needs at the least");
+  }
+  // every pair could survive in the worst case; beyond the list's slots the
+  // host checks for problems that lost survivors after the pass
+  P->may_overflow = P->pairs + (1ll << 20) > P->cap - seeds;
+  return LMS_OK;
+}
+
+// Offsets of the device arrays of a plan in its buffer (P->total: the size).
+void layout_batch(BPlan* P) {
+  const long long seeds = (long long)P->B * P->S;
   size_t o = 0;
   P->o_state = o; o += up256(sizeof(BState));
-  P->o_meta = o; o += up256((size_t)B * sizeof(PMeta));
-  P->o_pad = o; o += up256((size_t)B * sizeof(int));
-  P->o_chunks = o; o += up256((size_t)B * sizeof(int));
+  P->o_meta = o; o += up256((size_t)P->B * sizeof(PMeta));
+  P->o_pad = o; o += up256((size_t)P->B * sizeof(int));
+  P->o_chunks = o; o += up256((size_t)P->B * sizeof(int));
   P->o_items = o; o += up256(P->h_items.size() * sizeof(unsigned) + 8);
-  P->o_xy32 = o; o += up256((size_t)pad * sizeof(float2));
+  P->o_xy32 = o; o += up256((size_t)P->pad_total * sizeof(float2));
   P->o_entries = o; o += up256((size_t)P->cap * sizeof(uint2));
   P->o_res = o; o += up256((size_t)P->cap * sizeof(double4));
   // equal-slope set: at least twice the screen's entry capacity, at most 2^23
@@ -909,14 +967,10 @@ lms_status plan_batch(const int64_t* h_off, int B, int S, BPlan* P) {
   long long cands = 0;
   for (int c = 0; c < kClasses; ++c) {
     P->cand_off[c] = (size_t)cands;
-    // slack for the slots each block reserves ahead and may leave unused
-    P->cand_cap[c] = P->pairs_c[c] ? std::min<long long>(P->pairs_c[c] + (1ll << 20), kBatchCandCap)
-                                   : 0;
     cands += P->cand_cap[c];
   }
   P->o_cands = o; o += up256((size_t)cands * sizeof(uint2));
   P->total = o;
-  return LMS_OK;
 }
 
 template <int NMAX>
@@ -945,9 +999,10 @@ struct BatchKey {
   void* stream;
   int B, S;
   bool bins;
+  uint64_t max_ws;
   bool operator<(const BatchKey& o) const {
-    return std::tie(xy, off, h, out, stream, B, S, bins) <
-           std::tie(o.xy, o.off, o.h, o.out, o.stream, o.B, o.S, o.bins);
+    return std::tie(xy, off, h, out, stream, B, S, bins, max_ws) <
+           std::tie(o.xy, o.off, o.h, o.out, o.stream, o.B, o.S, o.bins, o.max_ws);
   }
 };
 
@@ -1143,6 +1198,42 @@ lms_status enqueue_batch(const BPlan& P, char* base, const double* d_xy, const i
   return LMS_OK;
 }
 
+// After a pass whose survivor list could overflow: wait for it, and solve
+// again, one by one with lms_solve, the problems that lost survivors (status
+// LMS_ERR_CAPACITY). lms_solve's own list holds every pair of a problem of
+// up to kBatchMaxN points, so each gets its exact answer.
+lms_status resolve_overflowed(const BatchCache& bc, const double* d_xy,
+                              const std::vector<int64_t>& off, const int32_t* d_h,
+                              lms_result* d_out, const lms_options* opt, hipStream_t s) {
+  const int B = bc.plan.B;
+  BState hs;
+  if (hipMemcpyAsync(&hs, bc.base + bc.plan.o_state, sizeof(BState), hipMemcpyDeviceToHost, s) !=
+          hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return fail(LMS_ERR_DEVICE, "reading the batch state failed");
+  if (!hs.overflow) return LMS_OK;
+  std::vector<lms_result> res(B);
+  std::vector<int32_t> hh(d_h ? B : 0);
+  if (hipMemcpyAsync(res.data(), d_out, (size_t)B * sizeof(lms_result), hipMemcpyDeviceToHost,
+                     s) != hipSuccess ||
+      (d_h && hipMemcpyAsync(hh.data(), d_h, (size_t)B * sizeof(int32_t), hipMemcpyDeviceToHost,
+                             s) != hipSuccess) ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return fail(LMS_ERR_DEVICE, "reading the batch results failed");
+  lms_options o;
+  std::memset(&o, 0, sizeof(o));
+  o.struct_size = sizeof(o);
+  o.seed_pairs = -1;
+  if (opt && opt->bins_log2 == -1) o.bins_log2 = -1;
+  for (int b = 0; b < B; ++b) {
+    if (res[b].status != LMS_ERR_CAPACITY) continue;
+    const lms_status st = lms_solve(d_xy + 2 * off[b], off[b + 1] - off[b], d_h ? hh[b] : 0,
+                                    d_out + b, &o, (void*)s);
+    if (st != LMS_OK) return st;
+  }
+  return LMS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1153,8 +1244,12 @@ lms_status lms_solve_batched(const double* d_xy, const int64_t* d_offsets,
   lms_host::clear_error();
   if (!d_xy || !d_offsets || !d_out) return fail(LMS_ERR_ARG, "null pointer");
   if (B < 1 || B > (1 << 24)) return fail(LMS_ERR_ARG, "B must be in [1, 2^24]");
-  if (opt && opt->struct_size < sizeof(lms_options)) return fail(LMS_ERR_ARG, "bad options size");
+  if (opt && opt->struct_size < offsetof(lms_options, max_workspace))
+    return fail(LMS_ERR_ARG, "bad options size");
   unsigned flags = opt ? opt->flags : 0u;
+  const uint64_t max_ws =
+      opt && opt->struct_size >= offsetof(lms_options, max_workspace) + sizeof(uint64_t)
+          ? opt->max_workspace : 0;
   if (opt && opt->seed_pairs < -1) return fail(LMS_ERR_ARG, "seed_pairs must be >= -1");
   hipStream_t s = (hipStream_t)stream;
   std::vector<int64_t> off((size_t)B + 1);
@@ -1181,7 +1276,7 @@ lms_status lms_solve_batched(const double* d_xy, const int64_t* d_offsets,
   const int S = 1 + seed_pairs;
   // slope-bin first screen unless bins_log2 = -1 (bins per class are fixed)
   const bool bins = !(opt && opt->bins_log2 == -1);
-  const BatchKey key{d_xy, d_offsets, d_h, d_out, stream, (int)B, S, bins};
+  const BatchKey key{d_xy, d_offsets, d_h, d_out, stream, (int)B, S, bins, max_ws};
   std::lock_guard<std::mutex> lk(g_bmu);
   BatchCache& bc = g_batches[key];
   const bool same = bc.plan.B == (int)B && bc.offsets == off;
@@ -1191,7 +1286,7 @@ lms_status lms_solve_batched(const double* d_xy, const int64_t* d_offsets,
       return fail(LMS_ERR_DEVICE, "hipStreamSynchronize failed");
     bc.release();
     BPlan P;
-    lms_status st = plan_batch(off.data(), (int)B, S, &P);
+    lms_status st = plan_batch(off.data(), (int)B, S, max_ws, &P);
     if (st != LMS_OK) { g_batches.erase(key); return st; }
     char* base = nullptr;
     if (hipMalloc(&base, P.total) != hipSuccess) {
@@ -1240,13 +1335,14 @@ lms_status lms_solve_batched(const double* d_xy, const int64_t* d_offsets,
     if (hipGraphLaunch(bc.exec, s) != hipSuccess) return fail(LMS_ERR_DEVICE, "hipGraphLaunch failed");
     for (int k = 0; k < LMS_NSTAGES; ++k) prof.mark();  // the whole graph is stage 0
     prof.finish();
-    return LMS_OK;
+    return bc.plan.may_overflow ? resolve_overflowed(bc, d_xy, off, d_h, d_out, opt, s) : LMS_OK;
   }
   lms_host::StageEvents prof;
   prof.start(s);
   const lms_status st = enqueue_batch(bc.plan, bc.base, d_xy, d_offsets, d_h, d_out, s, &prof, bins);
   prof.finish();
-  return st;
+  if (st != LMS_OK || !bc.plan.may_overflow) return st;
+  return resolve_overflowed(bc, d_xy, off, d_h, d_out, opt, s);
 }
 
 lms_status lms_autotune_batched(const double* d_xy, const int64_t* d_offsets,

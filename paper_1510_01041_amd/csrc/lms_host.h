@@ -33,6 +33,15 @@ bool get_tuning(int path, int size_class, lms_tuning* t);
 void set_tuning(int path, int size_class, const lms_tuning& t);
 int size_class(int n);  // next power of two >= n (>= 64)
 
+// Seed-network inference (lms_net.hip): device bytes of its scratch for B
+// sets, and the launches (frame, pooled features over many workgroups, head
+// and slope) into d_theta (and the raw outputs into d_out if not NULL).
+// d_offsets NULL: one set of max_set points at d_xy (B = 1).
+size_t net_infer_bytes(int64_t B);
+lms_status net_infer_enqueue(const float* d_params, const double* d_xy, const int64_t* d_offsets,
+                             int64_t B, int64_t max_set, int max_points, double* d_theta,
+                             float* d_out, void* scratch, hipStream_t s);
+
 // Compute units of the current device (queried once).
 int num_cu();
 

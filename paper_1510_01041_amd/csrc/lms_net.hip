@@ -98,41 +98,89 @@ __device__ __forceinline__ int wave_min_i(int v) {
 
 // ---------------------------------------------------------------- kernels
 
-// Midrange centre and half-range scale per set; FP32 points in [-1, 1]^2.
+// Frame of set b: per coordinate the lower median of a fixed sample of its
+// points (all of them up to kFrameSample, else indices floor(k n /
+// kFrameSample)), and as scale the lower median of the absolute deviations
+// from it (the MAD), else the largest deviation, else 1. Ranks among equal
+// values follow the sample order. Called by all NT threads; every thread
+// gets (cx, cy, sx, sy).
+constexpr int kFrameSample = 255;
+static_assert(kFrameSample <= NT, "one sample value per thread");
+
+__device__ double4 set_frame(const double* __restrict__ xy, int64_t o, int64_t n) {
+  __shared__ double sv[2][NT];
+  __shared__ double s_c[2], s_s[2], s_max[2];
+  const int t = threadIdx.x;
+  const int m = n < kFrameSample ? (int)n : kFrameSample;
+  const int target = m > 0 ? (m - 1) / 2 : 0;
+  if (t < m) {
+    const int64_t k = n <= kFrameSample ? t : ((int64_t)t * n) / kFrameSample;
+    sv[0][t] = xy[2 * (o + k)];
+    sv[1][t] = xy[2 * (o + k) + 1];
+  }
+  if (t < 2) {
+    s_c[t] = 0.0;
+    s_s[t] = 0.0;
+    s_max[t] = 0.0;
+  }
+  __syncthreads();
+  // the value of rank `target` (ties by sample index), per coordinate
+  auto select = [&](double* out, double* top) {
+    for (int a = 0; a < 2; ++a) {
+      if (t < m) {
+        const double v = sv[a][t];
+        int r = 0;
+        for (int u = 0; u < m; ++u) {
+          const double w = sv[a][u];
+          r += (w < v) || (w == v && u < t);
+        }
+        if (r == target) out[a] = v;
+        if (top && r == m - 1) top[a] = v;
+      }
+    }
+  };
+  select(s_c, nullptr);
+  __syncthreads();
+  double dev0 = 0.0, dev1 = 0.0;
+  if (t < m) {
+    dev0 = fabs(sv[0][t] - s_c[0]);
+    dev1 = fabs(sv[1][t] - s_c[1]);
+  }
+  __syncthreads();
+  if (t < m) {
+    sv[0][t] = dev0;
+    sv[1][t] = dev1;
+  }
+  __syncthreads();
+  select(s_s, s_max);
+  __syncthreads();
+  double sx = s_s[0], sy = s_s[1];
+  if (!(sx > 0)) sx = s_max[0];
+  if (!(sx > 0)) sx = 1.0;
+  if (!(sy > 0)) sy = s_max[1];
+  if (!(sy > 0)) sy = 1.0;
+  const double4 f = make_double4(s_c[0], s_c[1], sx, sy);
+  __syncthreads();  // the shared arrays are reused by the next call
+  return f;
+}
+
+__device__ __forceinline__ float2 to_frame(const double* __restrict__ xy, int64_t k,
+                                           const double4& f) {
+  return make_float2((float)((xy[2 * k] - f.x) / f.z), (float)((xy[2 * k + 1] - f.y) / f.w));
+}
+
+// Robust frame per set (set_frame); FP32 points in that frame.
 __global__ __launch_bounds__(NT) void k_net_prepare(const double* __restrict__ xy,
                                                     const int64_t* __restrict__ off,
                                                     float2* __restrict__ pts,
                                                     double* __restrict__ scale) {
-  __shared__ double s[4][NT];
   const int b = blockIdx.x, t = threadIdx.x;
   const int64_t o = off[b], n = off[b + 1] - off[b];
-  double mnx = INFINITY, mxx = -INFINITY, mny = INFINITY, mxy = -INFINITY;
-  for (int64_t k = t; k < n; k += NT) {
-    const double x = xy[2 * (o + k)], y = xy[2 * (o + k) + 1];
-    mnx = fmin(mnx, x); mxx = fmax(mxx, x); mny = fmin(mny, y); mxy = fmax(mxy, y);
-  }
-  s[0][t] = mnx; s[1][t] = mxx; s[2][t] = mny; s[3][t] = mxy;
-  __syncthreads();
-  for (int w = NT / 2; w > 0; w >>= 1) {
-    if (t < w) {
-      s[0][t] = fmin(s[0][t], s[0][t + w]);
-      s[1][t] = fmax(s[1][t], s[1][t + w]);
-      s[2][t] = fmin(s[2][t], s[2][t + w]);
-      s[3][t] = fmax(s[3][t], s[3][t + w]);
-    }
-    __syncthreads();
-  }
-  const double cx = s[0][0] + 0.5 * (s[1][0] - s[0][0]), cy = s[2][0] + 0.5 * (s[3][0] - s[2][0]);
-  double sx = fmax(fabs(s[0][0] - cx), fabs(s[1][0] - cx));
-  double sy = fmax(fabs(s[2][0] - cy), fabs(s[3][0] - cy));
-  if (!(sx > 0)) sx = 1.0;
-  if (!(sy > 0)) sy = 1.0;
+  const double4 f = set_frame(xy, o, n);
   if (t == 0) {
-    scale[4 * b] = cx; scale[4 * b + 1] = cy; scale[4 * b + 2] = sx; scale[4 * b + 3] = sy;
+    scale[4 * b] = f.x; scale[4 * b + 1] = f.y; scale[4 * b + 2] = f.z; scale[4 * b + 3] = f.w;
   }
-  for (int64_t k = t; k < n; k += NT)
-    pts[o + k] = make_float2((float)((xy[2 * (o + k)] - cx) / sx),
-                             (float)((xy[2 * (o + k) + 1] - cy) / sy));
+  for (int64_t k = t; k < n; k += NT) pts[o + k] = to_frame(xy, o + k, f);
 }
 
 // Max-pooled point features g (B x 64) and the head's output (B x 2).
@@ -182,6 +230,98 @@ __global__ __launch_bounds__(NT) void k_net_forward(const float* __restrict__ P,
     float a = P[OFF_B4 + t];
     for (int k = 0; k < H; ++k) a = fmaf(bf16_round(P[OFF_W4 + t * H + k]), s_h3[k], a);
     out[2 * b + t] = a;
+  }
+}
+
+// ---------------------------------------------------------------- inference
+
+// Inference spreads a set over many workgroups: the max-pool is order-free,
+// so blocks pool their slices into g with atomicMax on the float bits (every
+// h2 >= 0 after the ReLU, and non-negative floats order as their bit
+// patterns), and the head runs once g is complete. The result equals
+// k_net_forward's bit for bit. A set of more than max_points points is read
+// at max_points evenly strided indices floor(j n / max_points).
+constexpr int kPoolPoints = 512;  // points per workgroup of the pool kernel
+
+__global__ __launch_bounds__(NT) void k_net_frame(const double* __restrict__ xy,
+                                                  const int64_t* __restrict__ off,
+                                                  int64_t n_single, double* __restrict__ scale,
+                                                  unsigned* __restrict__ g) {
+  const int b = blockIdx.x, t = threadIdx.x;
+  const int64_t o = off ? off[b] : 0, n = off ? off[b + 1] - off[b] : n_single;
+  const double4 f = set_frame(xy, o, n);
+  if (t == 0) {
+    scale[4 * b] = f.x; scale[4 * b + 1] = f.y; scale[4 * b + 2] = f.z; scale[4 * b + 3] = f.w;
+  }
+  if (t < H) g[(size_t)b * H + t] = 0u;
+}
+
+__global__ __launch_bounds__(NT) void k_net_pool(const float* __restrict__ P,
+                                                 const double* __restrict__ xy,
+                                                 const int64_t* __restrict__ off, int64_t n_single,
+                                                 int max_points, const double* __restrict__ scale,
+                                                 unsigned* __restrict__ g) {
+  __shared__ PointMLP s;
+  __shared__ float s_max[NT / 64][H];
+  const int b = blockIdx.y, t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int64_t o = off ? off[b] : 0, n = off ? off[b + 1] - off[b] : n_single;
+  const int64_t m = n < max_points ? n : max_points;
+  const int64_t j0 = (int64_t)blockIdx.x * kPoolPoints;
+  if (j0 >= m) return;  // uniform over the block
+  load_point_mlp(P, s);
+  const double4 f = make_double4(scale[4 * b], scale[4 * b + 1], scale[4 * b + 2], scale[4 * b + 3]);
+  float run[H];
+#pragma unroll
+  for (int c = 0; c < H; ++c) run[c] = 0.0f;
+  const int64_t j1 = j0 + kPoolPoints < m ? j0 + kPoolPoints : m;
+  for (int64_t j = j0 + t; j < j1; j += NT) {
+    asm volatile("" ::: "memory");
+    const int64_t k = n <= max_points ? j : (j * n) / max_points;
+    const float2 p = to_frame(xy, o + k, f);
+    unsigned h1[H / 2];
+    layer1(s, p.x, p.y, h1);
+#pragma unroll
+    for (int c = 0; c < H; ++c) run[c] = fmaxf(run[c], fmaxf(layer2(s, h1, c), 0.0f));
+  }
+#pragma unroll
+  for (int c = 0; c < H; ++c) {
+    const float mx = wave_max(run[c]);
+    if (lane == 0) s_max[wv][c] = mx;
+  }
+  __syncthreads();
+  if (t < H) {
+    float mx = s_max[0][t];
+    for (int w = 1; w < NT / 64; ++w) mx = fmaxf(mx, s_max[w][t]);
+    // clear the sign bit: a -0 from the ReLU orders as +0
+    atomicMax(&g[(size_t)b * H + t], __float_as_uint(mx) & 0x7FFFFFFFu);
+  }
+}
+
+// Head and slope of set b: out = W4 relu(W3 g + b3) + b4 (as k_net_forward),
+// theta = tan(atan2(out1, out0) / 2) sy / sx.
+__global__ __launch_bounds__(H) void k_net_head(const float* __restrict__ P,
+                                                const unsigned* __restrict__ g,
+                                                const double* __restrict__ scale,
+                                                float* __restrict__ out,
+                                                double* __restrict__ theta) {
+  __shared__ float s_g[H], s_h3[H], s_out[2];
+  const int b = blockIdx.x, t = threadIdx.x;
+  s_g[t] = __uint_as_float(g[(size_t)b * H + t]);
+  __syncthreads();
+  float a = P[OFF_B3 + t];
+  for (int k = 0; k < H; ++k) a = fmaf(bf16_round(P[OFF_W3 + t * H + k]), s_g[k], a);
+  s_h3[t] = fmaxf(a, 0.0f);
+  __syncthreads();
+  if (t < 2) {
+    float a2 = P[OFF_B4 + t];
+    for (int k = 0; k < H; ++k) a2 = fmaf(bf16_round(P[OFF_W4 + t * H + k]), s_h3[k], a2);
+    s_out[t] = a2;
+    if (out) out[2 * b + t] = a2;
+  }
+  __syncthreads();
+  if (t == 0) {
+    const double phi = 0.5 * atan2((double)s_out[1], (double)s_out[0]);
+    theta[b] = tan(phi) * scale[4 * b + 3] / scale[4 * b + 2];
   }
 }
 
@@ -337,6 +477,38 @@ __global__ void k_net_slopes(const float* __restrict__ out, const double* __rest
   theta[b] = tan(phi) * scale[4 * b + 3] / scale[4 * b + 2];
 }
 
+}  // namespace
+
+namespace lms_host {
+
+size_t net_infer_bytes(int64_t B) {
+  return ((size_t)B * 4 * sizeof(double) + 255 & ~size_t(255)) + (size_t)B * H * sizeof(unsigned);
+}
+
+lms_status net_infer_enqueue(const float* d_params, const double* d_xy, const int64_t* d_offsets,
+                             int64_t B, int64_t max_set, int max_points, double* d_theta,
+                             float* d_out, void* scratch, hipStream_t s) {
+  // without offsets: one set of max_set points
+  const int64_t n_single = d_offsets ? 0 : max_set;
+  double* scale = (double*)scratch;
+  unsigned* g = (unsigned*)((char*)scratch + ((B * 4 * sizeof(double) + 255) & ~size_t(255)));
+  hipLaunchKernelGGL(k_net_frame, dim3((unsigned)B), dim3(NT), 0, s, d_xy, d_offsets, n_single,
+                     scale, g);
+  const int64_t m = std::min<int64_t>(max_set, max_points);
+  const unsigned gx = (unsigned)std::max<int64_t>(1, (m + kPoolPoints - 1) / kPoolPoints);
+  hipLaunchKernelGGL(k_net_pool, dim3(gx, (unsigned)B), dim3(NT), 0, s, d_params, d_xy, d_offsets,
+                     n_single, max_points, scale, g);
+  hipLaunchKernelGGL(k_net_head, dim3((unsigned)B), dim3(H), 0, s, d_params, g, scale, d_out,
+                     d_theta);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(LMS_ERR_DEVICE, std::string("net launch: ") + hipGetErrorString(e));
+  return LMS_OK;
+}
+
+}  // namespace lms_host
+
+namespace {
+
 lms_status check(const char* what) {
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(LMS_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
@@ -392,6 +564,20 @@ lms_status lms_net_adam(float* d_params, float* d_m, float* d_v, const float* d_
   hipLaunchKernelGGL(k_net_adam, dim3((N_PARAMS + NT - 1) / NT), dim3(NT), 0, (hipStream_t)stream,
                      d_params, d_m, d_v, d_grad, lr, beta1, beta2, eps, c1, c2);
   return check("k_net_adam");
+}
+
+lms_status lms_net_infer(const float* d_params, const double* d_xy, const int64_t* d_offsets,
+                         int64_t B, int64_t max_set, int32_t max_points, double* d_theta,
+                         float* d_out, void* stream) {
+  lms_host::clear_error();
+  if (!d_params || !d_xy || !d_offsets || !d_theta || B < 1 || B > (1 << 24) || max_set < 1 ||
+      max_points < 1)
+    return fail(LMS_ERR_ARG, "bad arguments");
+  char* ws = nullptr;
+  const lms_status st = lms_host::get_workspace(6, stream, lms_host::net_infer_bytes(B), &ws);
+  if (st != LMS_OK) return st;
+  return lms_host::net_infer_enqueue(d_params, d_xy, d_offsets, B, max_set, max_points, d_theta,
+                                     d_out, ws, (hipStream_t)stream);
 }
 
 lms_status lms_net_slopes(const float* d_out, const double* d_scale, int64_t B, double* d_theta,

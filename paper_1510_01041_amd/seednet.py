@@ -20,7 +20,7 @@ from . import _check, _stream, load
 
 N_PARAMS = 8642
 HIDDEN = 64
-MAX_POINTS = 2048  # points the network sees per set (larger sets are subsampled)
+MAX_POINTS = 2048  # points the network pools per set (larger sets are read strided)
 # packed parameter layout (row-major W[out][in])
 LAYOUT = (("W1", (HIDDEN, 2)), ("b1", (HIDDEN,)), ("W2", (HIDDEN, HIDDEN)), ("b2", (HIDDEN,)),
           ("W3", (HIDDEN, HIDDEN)), ("b3", (HIDDEN,)), ("W4", (2, HIDDEN)), ("b4", (2,)))
@@ -36,8 +36,9 @@ def _lib():
         f = ctypes.c_float
         L.lms_net_adam.argtypes = [vp, vp, vp, vp, i64, f, f, f, f, vp]
         L.lms_net_slopes.argtypes = [vp, vp, i64, vp, vp]
+        L.lms_net_infer.argtypes = [vp, vp, vp, i64, i64, ctypes.c_int32, vp, vp, vp]
         for fn in ("lms_net_prepare", "lms_net_forward", "lms_net_backward", "lms_net_adam",
-                   "lms_net_slopes"):
+                   "lms_net_slopes", "lms_net_infer"):
             getattr(L, fn).restype = ctypes.c_int
         L._lms_net_ready = True
     return L
@@ -136,33 +137,26 @@ class SeedNet:
         return loss
 
     # -- inference ------------------------------------------------------------
-    def plan(self, offsets, max_points: int = MAX_POINTS):
-        """Gather plan for inference: a set of n > max_points points is read at
-        max_points evenly strided indices (the network was trained on sets of
-        up to MAX_POINTS). Returns (device index or None, device offsets); it
-        can be reused for every call with the same offsets."""
-        off = np.asarray(offsets.cpu() if isinstance(offsets, torch.Tensor) else offsets,
-                         dtype=np.int64)
-        n = np.diff(off)
-        if np.all(n <= max_points):
-            return None, _offsets_dev(off, self.device)
-        m = np.minimum(n, max_points)
-        idx = np.concatenate([off[b] + (np.arange(m[b]) * n[b]) // m[b] for b in range(len(n))])
-        new_off = np.concatenate([[0], np.cumsum(m)]).astype(np.int64)
-        return (torch.as_tensor(idx, device=self.device), _offsets_dev(new_off, self.device))
-
-    def predict_slopes(self, xy: torch.Tensor, offsets=None, plan=None,
+    def predict_slopes(self, xy: torch.Tensor, offsets, max_set: int | None = None,
+                       max_points: int = MAX_POINTS, out: torch.Tensor | None = None,
                        stream=None) -> torch.Tensor:
-        """Seed slope per set, FP64 on the device. With a plan from plan() there
-        is no host synchronisation or host-to-device copy."""
-        idx, off = plan if plan is not None else self.plan(offsets)
-        src = xy if idx is None else xy.index_select(0, idx)
-        pts, scale, off = self.prepare(src, off, stream)
-        out, _ = self.forward(pts, off, False, stream)
+        """Seed slope per set, FP64 on the device (lms_net_infer: the features
+        of each set pooled over many workgroups; a set above max_points points
+        is read at evenly strided indices). offsets: host array or device
+        tensor (B+1); max_set: the largest set (taken from host offsets)."""
+        if isinstance(offsets, torch.Tensor) and offsets.is_cuda:
+            off = offsets.to(torch.int64).contiguous()
+            if max_set is None:
+                max_set = int((off[1:] - off[:-1]).max())
+        else:
+            h = np.asarray(offsets, dtype=np.int64)
+            max_set = int(np.diff(h).max()) if max_set is None else max_set
+            off = torch.as_tensor(h, device=self.device)
         B = off.numel() - 1
         theta = torch.empty(B, dtype=torch.float64, device=self.device)
-        _check(_lib().lms_net_slopes(out.data_ptr(), scale.data_ptr(), B, theta.data_ptr(),
-                                     _stream(stream)))
+        _check(_lib().lms_net_infer(self.P.data_ptr(), xy.data_ptr(), off.data_ptr(), B,
+                                    max_set, max_points, theta.data_ptr(),
+                                    None if out is None else out.data_ptr(), _stream(stream)))
         return theta
 
     # -- persistence ------------------------------------------------------------

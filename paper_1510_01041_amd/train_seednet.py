@@ -1,6 +1,6 @@
 """Train the seed network on exact LMS solutions.
 
-    python -m paper_1510_01041_amd.train_seednet --sets 65536 --n 2048 --epochs 20 \\
+    python -m paper_1510_01041_amd.train_seednet --sets 200000 --n 2048 --epochs 20 \\
         --out paper_1510_01041_amd/seednet_weights.npy
 
 Training data: seeded rotated-line sets (workloads.gen.rotated_line: outlier
@@ -8,7 +8,9 @@ fraction U[0, 0.45], line angle U[-pi/2, pi/2)). Each set is labelled by the
 exact batched GPU solver and kept resident in HBM. Each batch trains on one
 random subset of m points of its sets, m drawn log-uniformly from
 [min_points, n], so that the network works at every size it will see
-(inference subsamples larger sets to seednet.MAX_POINTS). Forward, backward
+(inference reads larger sets strided, at seednet.MAX_POINTS points). Each set's
+frame is its robust one (coordinate-wise median and MAD of a fixed sample of
+its points), so that the outliers do not set it. Forward, backward
 and Adam run in the library's kernels. PyTorch only holds the buffers and
 gathers each batch into one contiguous block.
 """
@@ -33,31 +35,14 @@ from workloads import gen  # noqa: E402
 
 
 def label(d: torch.Tensor, off: np.ndarray, log=print):
-    """Exact LMS slope of every set in one batch (FP64, host array).
-
-    A batch whose survivor list overflows (every set then reports
-    LMS_ERR_CAPACITY) is split in halves and solved again; a single set that
-    still overflows goes to the single-problem solver."""
-    B = off.shape[0] - 1
+    """Exact LMS slope of every set in one batch (FP64, host array). The
+    batched solver re-solves on its own any set whose survivors did not fit
+    its shared list, so every set gets its exact answer."""
     res = lms.solve_batched(d, off)
     st = np.asarray(res.status)
-    if np.all(st >= 0):
-        return np.asarray(res.theta1, dtype=np.float64)
-    if np.any((st < 0) & (st != lms.LMS_ERR_CAPACITY)):
-        bad = np.unique(st[st < 0]).tolist()
-        raise RuntimeError(f"labelling failed with status {bad}")
-    if B == 1:
-        r = lms.solve(d[int(off[0]):int(off[1])].contiguous())
-        if r.status < 0:
-            raise RuntimeError(f"labelling failed with status {r.status}")
-        return np.array([r.theta1])
-    log(f"survivor list overflow on a batch of {B} sets: splitting it")
-    m = B // 2
-    a = off[:m + 1]
-    b = off[m:]
-    ta = label(d[int(a[0]):int(a[-1])].contiguous(), a - a[0], log)
-    tb = label(d[int(b[0]):int(b[-1])].contiguous(), b - b[0], log)
-    return np.concatenate([ta, tb])
+    if np.any(st < 0):
+        raise RuntimeError(f"labelling failed with status {np.unique(st[st < 0]).tolist()}")
+    return np.asarray(res.theta1, dtype=np.float64)
 
 
 def build_dataset(n_sets, n, seed, chunk, net, log=print):
@@ -95,7 +80,7 @@ def angle_error(out: np.ndarray, tgt: np.ndarray) -> np.ndarray:
     return np.abs(d) / 2
 
 
-def train(n_sets=65536, n=2048, epochs=20, batch=256, lr=2e-3, seed=1, chunk=4096,
+def train(n_sets=200000, n=2048, epochs=20, batch=256, lr=2e-3, seed=1, chunk=4096,
           test_frac=0.05, min_points=256, log=print, net=None):
     net = net or seednet.SeedNet(seed=seed)
     xy, theta = build_dataset(n_sets, n, seed, chunk, net, log)
@@ -136,7 +121,7 @@ def train(n_sets=65536, n=2048, epochs=20, batch=256, lr=2e-3, seed=1, chunk=409
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--sets", type=int, default=65536)
+    ap.add_argument("--sets", type=int, default=200000)
     ap.add_argument("--n", type=int, default=2048)
     ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--batch", type=int, default=256)

@@ -39,10 +39,14 @@ def test_bracelets_bitwise(gpu, orc, n):
             print(n, rule, r.width, o.width, flush=True)
             assert fields(r) == fields(o), (n, rule)
         if n <= 300:
+            # the bracelet sets the pair's own two intercepts to one value,
+            # the window search computes both: the widths agree to rounding
+            # of the intercepts (a few ulp of the largest |z|)
             s = orc.solve(xy)
             t = gpu.solve_bracelets(dev(xy))
-            assert abs(t.width - s.width) <= 1e-9 * s.width
-            assert orc.window(xy, t.theta1)[0] <= t.width
+            ulp = 8 * 2.0 ** -53 * (np.abs(xy[:, 1]).max() + abs(t.theta1) * np.abs(xy[:, 0]).max())
+            assert abs(t.width - s.width) <= 1e-9 * s.width + ulp
+            assert orc.window(xy, t.theta1)[0] <= t.width + ulp
 
 
 @pytest.mark.parametrize("n,h", [(64, 2), (64, 40), (64, 64), (129, 100), (256, 129)])

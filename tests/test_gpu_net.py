@@ -101,20 +101,59 @@ def test_seed_slope_keeps_result_exact(gpu):
         assert (a.width, a.theta1, a.z_lo) == (b.width, b.theta1, b.z_lo)
 
 
-def test_inference_subsamples_large_sets(gpu):
-    """Sets above MAX_POINTS points are read at evenly strided indices, the
-    same as solving the strided subset directly; smaller sets are untouched."""
+def test_inference_matches_reference_and_forward(gpu):
+    """lms_net_infer (features pooled over many workgroups; sets above 2048
+    points read strided, frame from the whole set) against the FP64 reference
+    of the same inference, and bit for bit against the one-block forward pass
+    on the same framed points."""
     from paper_1510_01041_amd import seednet
     from workloads.gen import planted
-    net = seednet.SeedNet(seed=5)
-    xy = np.concatenate([planted(5000, 0.4, 77), planted(300, 0.4, 78)])
-    off = np.array([0, 5000, 5300])
-    idx, doff = net.plan(off)
-    assert idx.numel() == seednet.MAX_POINTS + 300
-    assert doff.cpu().tolist() == [0, seednet.MAX_POINTS, seednet.MAX_POINTS + 300]
-    th = net.predict_slopes(torch.from_numpy(xy).cuda(), plan=(idx, doff)).cpu().numpy()
-    keep = (np.arange(seednet.MAX_POINTS) * 5000) // seednet.MAX_POINTS
-    sub = np.concatenate([xy[keep], xy[5000:]])
-    th2 = net.predict_slopes(torch.from_numpy(sub).cuda(),
-                             np.array([0, seednet.MAX_POINTS, seednet.MAX_POINTS + 300]))
-    assert np.array_equal(th, th2.cpu().numpy())
+    params = ref.init_params(15)
+    st = Stream(16, 160)
+    for k in params:
+        if k.startswith("b"):
+            params[k] = st.uniform(params[k].size, -0.2, 0.2).reshape(params[k].shape)
+    p32 = {k: np.asarray(v, dtype=np.float32).astype(np.float64) for k, v in params.items()}
+    net = seednet.SeedNet(seednet.pack(p32))
+    sets = [planted(5000, 0.4, 77), planted(300, 0.4, 78), planted(2048, 0.45, 79),
+            planted(16384, 0.45, 80)]
+    off = np.concatenate([[0], np.cumsum([len(a) for a in sets])])
+    xy = np.concatenate(sets)
+    d = torch.from_numpy(xy).cuda()
+    out = torch.empty((len(sets), 2), dtype=torch.float32, device="cuda:0")
+    th = net.predict_slopes(d, off, out=out).cpu().numpy()
+    o = out.cpu().numpy().astype(np.float64)
+    for b, a in enumerate(sets):
+        ro, rth = ref.predict(p32, a)
+        assert np.allclose(o[b], ro, rtol=1e-4, atol=1e-5), (b, o[b], ro)
+        assert abs(np.arctan(th[b]) - np.arctan(rth)) < 1e-3, (b, th[b], rth)
+    # small sets: the same as prepare + one-block forward, bit for bit
+    small = np.array([0, 300, 300 + 2048])
+    xs = np.concatenate([sets[1], sets[2]])
+    ds = torch.from_numpy(xs).cuda()
+    out2 = torch.empty((2, 2), dtype=torch.float32, device="cuda:0")
+    net.predict_slopes(ds, small, out=out2)
+    pts, scale, doff = net.prepare(ds, small)
+    fo, _ = net.forward(pts, doff, want_g=False)
+    assert torch.equal(out2, fo)
+
+
+def test_network_inside_the_solve(gpu):
+    """opt.d_net_params runs the network inside lms_solve: the same as passing
+    its slope as the device seed slope, and the exact answer either way."""
+    from paper_1510_01041_amd import seednet
+    from workloads.gen import planted
+    net = seednet.SeedNet(seed=7)
+    for xy in (gen.make("c1", 101), planted(3000, 0.45, 81), planted(9000, 0.45, 82)):
+        d = torch.from_numpy(xy).cuda()
+        th = net.predict_slopes(d, np.array([0, len(xy)]))
+        a = gpu.solve(d, seed_pairs=0, net_params=net.P, window_pairs=63)
+        b = gpu.solve(d, seed_pairs=0, seed_theta=th, window_pairs=63)
+        c = gpu.solve(d)
+        assert (a.width, a.theta1, a.z_lo, a.survivors, a.band_pass, a.bin_pass) == \
+               (b.width, b.theta1, b.z_lo, b.survivors, b.band_pass, b.bin_pass)
+        assert (a.width, a.theta1, a.z_lo) == (c.width, c.theta1, c.z_lo)
+        g = gpu.parse(gpu.solve_async(d, 0, seed_pairs=0, net_params=net.P, graph=True))
+        assert (g.width, g.theta1, g.z_lo) == (c.width, c.theta1, c.z_lo)
+    with pytest.raises(gpu.LmsError):
+        gpu.solve(d, net_params=net.P, seed_theta=th)

@@ -151,3 +151,34 @@ def test_target_at_known_angles():
     assert abs(net.slope_from_output(np.array([0.0, 1.0]), 1.0, 1.0) - 1.0) < 1e-12
     assert abs(net.slope_from_output(np.array([0.0, 3.0]), 2.0, 6.0) - 3.0) < 1e-12
     assert net.slope_from_output(np.array([2.0, 0.0]), 1.0, 1.0) == 0.0
+
+
+def test_normalise_by_hand():
+    """Lower median and MAD, worked by hand."""
+    # x: sorted 1 3 5 7 9 -> centre 5; |x - 5| sorted 0 2 2 4 4 -> scale 2
+    # y: sorted 1 2 3 4 10 -> centre 3; |y - 3| sorted 0 1 1 2 7 -> scale 1
+    xy = np.array([[5.0, 10.0], [1.0, 2.0], [9.0, 3.0], [3.0, 4.0], [7.0, 1.0]])
+    pts, c, s = net.normalise(xy)
+    assert list(c) == [5.0, 3.0] and list(s) == [2.0, 1.0]
+    assert list(pts[:, 0]) == [0.0, -2.0, 2.0, -1.0, 1.0]
+    assert list(pts[:, 1]) == [7.0, -1.0, 0.0, 1.0, -2.0]
+    # even count: the lower of the two middle values; a zero MAD falls back to
+    # the largest deviation; a constant coordinate to 1
+    xy = np.array([[3.0, 4.0], [3.0, 4.0], [3.0, 4.0], [8.0, 4.0]])
+    _, c, s = net.normalise(xy)
+    assert list(c) == [3.0, 4.0] and list(s) == [5.0, 1.0]
+    _, c, s = net.normalise(np.array([[4.0, 0.0], [1.0, 0.0], [3.0, 0.0], [2.0, 1.0]]))
+    assert c[0] == 2.0 and s[0] == 1.0  # sorted 1 2 3 4 -> 2; |x - 2| 0 1 1 2 -> 1
+
+
+def test_normalise_uses_the_strided_sample():
+    """510 points: the frame comes from points 0, 2, 4, ... (floor(k 510 / 255)
+    = 2k), so the odd points, huge here, move neither centre nor scale. The
+    sampled x are 0, 2, ..., 508: centre 254 (rank 127); deviations 0, 2, 2,
+    4, 4, ...: rank 127 is 128."""
+    n = 510
+    x = np.where(np.arange(n) % 2 == 0, np.arange(n, dtype=np.float64), 1e9)
+    xy = np.stack([x, np.zeros(n)], 1)
+    assert list(net.frame_sample(n)[:4]) == [0, 2, 4, 6]
+    _, c, s = net.normalise(xy)
+    assert c[0] == 254.0 and s[0] == 128.0
