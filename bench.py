@@ -257,7 +257,7 @@ def main():
         return
 
     if args.workload == "c4":
-        print(json.dumps(bench_batched(args)), flush=True)
+        print(json.dumps(bench_batched(args, per_problem=not args.no_extra)), flush=True)
         return
 
     seed = gen.CONFIGS[args.workload]["seeds"][0] if args.seed is None else args.seed

@@ -121,14 +121,15 @@ typedef struct lms_options {
   int32_t reserved;
   uint64_t max_workspace; /* 0 = no limit. Otherwise the most device memory, in bytes,
                            that the call's own workspace may take: lms_solve shrinks
-                           the slope-bin pass list first (an overflowing list makes
-                           the exhaustive FP32 screen run instead, same result) and
-                           then the survivor list (more survivors than it holds give
-                           LMS_ERR_CAPACITY); lms_solve_batched shrinks its pass
-                           and survivor lists the same way and re-solves the
-                           problems whose survivors did not fit (see there). If
-                           even the fixed part does not fit: LMS_ERR_NOMEM.
-                           Read only when struct_size covers it. */
+                           the survivor list to 65536 slots, then the slope-bin pass
+                           list (an overflowing list makes the exhaustive FP32
+                           screen run instead, same result), then the survivor list
+                           again (more survivors than it holds give
+                           LMS_ERR_CAPACITY), each to at least 1024 slots;
+                           lms_solve_batched shrinks its pass and survivor lists
+                           and re-solves the problems whose survivors did not fit
+                           (see there). If even the fixed part does not fit:
+                           LMS_ERR_NOMEM. Read only when struct_size covers it. */
   const float* d_net_params; /* lms_solve: device, LMS_NET_PARAMS FP32 seed-network
                            parameters, or NULL. When set, the solve first runs the
                            network on the points (lms_net_infer, max_points 2048)
@@ -141,7 +142,9 @@ typedef struct lms_options {
 /* Tile choice found by the autotuner for one size class. */
 typedef struct lms_tuning {
   int32_t tile_regs, tile_batches, seed_pairs, bins_log2;
-  double ms; /* median time of one solve (or one batched pass) with this choice */
+  double ms;     /* median time of one solve (or one batched pass) with this choice */
+  int32_t range; /* lms_solve's slope range: 0 automatic, 1 always, -1 never */
+  int32_t reserved;
 } lms_tuning;
 
 /* Exact LMS line of one point set (Eq. (1); Algorithm 1's exhaustive search
@@ -184,15 +187,22 @@ lms_status lms_solve_batched(const double* d_xy, const int64_t* d_offsets,
                              const int64_t* h_offsets, int64_t B, const int32_t* d_h,
                              lms_result* d_out, const lms_options* opt, void* stream);
 
-/* Autotuner. Times lms_solve on the caller's point set (device memory) for
- * the candidate tiles (register chunks vs LDS streaming, partner batches per
- * work item) with HIP events on `stream`, `reps` runs each, and keeps the
- * fastest for the size class next_pow2(n) of this device. Later lms_solve
- * calls with automatic tiles use it. If the environment variable
+/* Autotuner. Times lms_solve on the caller's point set (device memory) with
+ * HIP events on `stream`, `reps` runs each (median), and keeps the fastest
+ * choice for the size class next_pow2(n) of this device. It sweeps what moves
+ * the time: the slope-bin screen's bins per anchor (every allowed 2^k), the
+ * slope range (automatic, always, never), the random seed pairs (63, 255),
+ * then the FP32 screen's tiles (register chunks vs LDS streaming, partner
+ * batches per work item). Every candidate must return the same line as the
+ * defaults, bit for bit (LMS_ERR_DEVICE otherwise). Later lms_solve calls
+ * with automatic options use the choice. If the environment variable
  * LMS_TUNE_FILE names a file, the table is read from it at the first use and
  * written back after each tuning. Synchronises the stream. */
 lms_status lms_autotune(const double* d_xy, int64_t n, int64_t h, int32_t reps, void* stream,
                         lms_tuning* out);
+/* Forgets every tuned choice of this process (solves use the defaults again;
+ * a LMS_TUNE_FILE is not read again). */
+void lms_tuning_clear(void);
 /* The same for lms_solve_batched: tunes the seed pairs per problem on the
  * caller's batch (the arguments are those of lms_solve_batched), for the
  * batch's size class (next_pow2 of its largest problem). */

@@ -62,7 +62,7 @@ class _Options(ctypes.Structure):
 class _Tuning(ctypes.Structure):
     _fields_ = [("tile_regs", ctypes.c_int32), ("tile_batches", ctypes.c_int32),
                 ("seed_pairs", ctypes.c_int32), ("bins_log2", ctypes.c_int32),
-                ("ms", ctypes.c_double)]
+                ("ms", ctypes.c_double), ("range", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class _HoughParams(ctypes.Structure):
@@ -152,6 +152,8 @@ def load():
     L.lms_workspace_size.argtypes = [i64, i64, ctypes.POINTER(_Options),
                                      ctypes.POINTER(ctypes.c_uint64)]
     L.lms_workspace_size.restype = i32
+    L.lms_tuning_clear.argtypes = []
+    L.lms_tuning_clear.restype = None
     L.lms_shutdown.argtypes = []
     L.lms_shutdown.restype = None
     _lib = L
@@ -327,6 +329,11 @@ def autotune(xy: torch.Tensor, h: int = 0, reps: int = 3, stream=None) -> dict:
     _check(load().lms_autotune(xy.data_ptr(), xy.shape[0], h, reps, _stream(stream),
                                ctypes.byref(t)))
     return {f: getattr(t, f) for f, _ in _Tuning._fields_}
+
+
+def tuning_clear():
+    """Forget every tuned choice of this process."""
+    load().lms_tuning_clear()
 
 
 def autotune_batched(xy: torch.Tensor, offsets, h=None, reps: int = 3, stream=None) -> dict:

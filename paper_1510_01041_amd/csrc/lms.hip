@@ -64,6 +64,7 @@ struct __align__(16) Ctx {
   int n, h, n_pad, n_seeds;
   int status, all_x_equal, argminx, argmaxx;
   double cx, cy;      // centre (midrange) used for the FP32 copy
+  double fx, fy;      // scales of the FP32 copy (powers of two; f32_scale)
   double xh, yh;      // bounds on |x - cx| and |y - cy|
   double xabs, yabs;  // max |x|, max |y| of the raw input
   double xr, yr;      // bounds on max x - min x and max y - min y
@@ -147,6 +148,8 @@ __global__ __launch_bounds__(1024) void k_prep(const double* __restrict__ xy, in
     c.cx = cx; c.cy = cy;
     c.xh = fmax(fabs(minx - cx), fabs(maxx - cx)) * (1.0 + 0x1p-40);
     c.yh = fmax(fabs(miny - cy), fabs(maxy - cy)) * (1.0 + 0x1p-40);
+    c.fx = f32_scale(c.xh);
+    c.fy = f32_scale(c.yh);
     c.xabs = fmax(fabs(minx), fabs(maxx));
     c.yabs = fmax(fabs(miny), fabs(maxy));
     c.xr = (maxx - minx) * (1.0 + 0x1p-50);
@@ -170,9 +173,13 @@ __global__ __launch_bounds__(1024) void k_prep(const double* __restrict__ xy, in
   }
   if (!finite) return;
   const float qnan = __int_as_float(0x7FC00000);
+  // the same scales k_prep's thread 0 stored (same inputs, same operations)
+  const double fx = f32_scale(fmax(fabs(minx - cx), fabs(maxx - cx)) * (1.0 + 0x1p-40));
+  const double fy = f32_scale(fmax(fabs(miny - cy), fabs(maxy - cy)) * (1.0 + 0x1p-40));
   for (int k = t; k < n_pad; k += blockDim.x) {
     float2 p = make_float2(qnan, qnan);
-    if (k < n) p = make_float2((float)(xy[2 * k] - cx), (float)(xy[2 * k + 1] - cy));
+    if (k < n)
+      p = make_float2((float)((xy[2 * k] - cx) * fx), (float)((xy[2 * k + 1] - cy) * fy));
     xy32[k] = p;
   }
   // Seed entries: the extreme-x pair (never vertical unless all x are equal),
@@ -1003,12 +1010,12 @@ __global__ __launch_bounds__(NT, 3) void k_screen(
       const double xr = xy[2 * hi], yr = xy[2 * hi + 1];
       const bool vert = valid && (xl == xr);
       const double th = (yr - yl) / (xr - xl);
-      const double tau = tau_bound(th, c.xh, c.yh);
-      const bool force = valid && !vert && !(fabs(th) < 1e30 && tau < 1e30);
+      const ScreenScalars sc = screen_scalars(th, W, c.fx, c.fy, c.xh, c.yh);
+      const bool force = valid && !vert && sc.force;
       const bool test = valid && !vert && !force;
-      const float th32 = test ? (float)th : 0.0f;
-      const float thr = test ? f32_up(W + tau) : 0.0f;
-      const float ta = test ? f32_up(tau) : 0.0f;
+      const float th32 = test ? sc.th32 : 0.0f;
+      const float thr = test ? sc.thr : 0.0f;
+      const float ta = test ? sc.ta : 0.0f;
       const float nc = test ? -fmaf(-th32, pi.x, pi.y) : 0.0f;
       unsigned long long m = __ballot(test);
       if (!fallback) {
@@ -1094,14 +1101,16 @@ __global__ __launch_bounds__(NT) void k_bins(const double* __restrict__ xy, Ctx*
   constexpr int kRLog = __builtin_ctz(NB) - 1;  // the map spans bins [3, NB + 3]
   static_assert((NB % NT) == 0 && ((NB / NT) & 1) == 0, "bins must be 2^k per thread");
   // Up to 2^14 bins the insertion also stores each point's query code
-  // (add_point_bins_coded) and the queries only read it; passes are marked
-  // in place and gathered afterwards. Larger bin arrays leave no LDS for the
-  // codes: the queries compute the pair's bin themselves and list the passes.
+  // (add_point_bins_coded) and the queries only read it. Larger bin arrays
+  // leave no LDS for the codes: the queries compute the pair's bin
+  // themselves. Either way the queries list the passing partners' offsets.
   constexpr bool CODED = NB <= 16384;
   __shared__ unsigned bins[NBINS + 1];
-  // codes of the n <= NB / 2 points, or partner offsets o - 1 that pass
-  // (P(i) <= n / 2 <= LMS_MAX_N / 2)
+  // codes of the n <= NB / 2 points (CODED), or partner offsets o - 1 that
+  // pass (P(i) <= n / 2 <= LMS_MAX_N / 2)
   __shared__ unsigned short list[NB / 2 < LMS_MAX_N / 2 ? NB / 2 : LMS_MAX_N / 2];
+  // CODED: the partner offsets o - 1 that pass (P(i) <= n / 2 <= NB / 4)
+  __shared__ unsigned short plist[CODED ? NB / 4 : 1];
   // passes of the block's anchors so far, written out together (one
   // reservation per flush instead of one per anchor)
   constexpr int PB = 512;
@@ -1118,8 +1127,7 @@ __global__ __launch_bounds__(NT) void k_bins(const double* __restrict__ xy, Ctx*
   const int half = n >> 1;
   // slopes whose FP32 test bound (affine in |theta|) would pass 1e29 go to the
   // FP64 entries; half the solved limit covers the roundings
-  const double tau0 = tau_bound(0.0, c.xh, c.yh), tau1 = tau_bound(1.0, c.xh, c.yh) - tau0;
-  const double th_lim = tau0 < 1e29 ? fmin(1e29, 0.5 * (1e29 - tau0) / tau1) : 0.0;
+  const double th_lim = screen_th_lim(c.fx, c.fy, c.xh, c.yh);
   const double2* pts = reinterpret_cast<const double2*>(xy);
   // per-wavefront counts (uniform)
   unsigned long long n_vert = 0, n_scr = 0, n_forced = 0, n_pass = 0;
@@ -1199,8 +1207,12 @@ __global__ __launch_bounds__(NT) void k_bins(const double* __restrict__ xy, Ctx*
         n_scr += __popcll(lane_mask(test));
         n_pass += __popcll(mp);
         if (force) append_entry(ctx, entries, cap, (unsigned)min(i, j), (unsigned)max(i, j));
-        if (pass) list[j] = kCodePass;
-        if (mp && lane == 0) atomicAdd(&s_cnt, (unsigned)__popcll(mp));
+        if (mp) {
+          unsigned base = 0;
+          if (lane == 0) base = atomicAdd(&s_cnt, (unsigned)__popcll(mp));
+          base = __shfl(base, 0);
+          if (pass) plist[base + __popcll(mp & ((1ull << lane) - 1ull))] = (unsigned short)(o - 1);
+        }
       }
     } else {
       double2 pn = 1 + t <= P ? pts[partner(1 + t)] : make_double2(0.0, 0.0);
@@ -1252,25 +1264,11 @@ __global__ __launch_bounds__(NT) void k_bins(const double* __restrict__ xy, Ctx*
         if (!direct) pbuf[base + q] = pr;
         else if (base + q < (unsigned)cand_cap) cands[base + q] = pr;
       };
-      if (CODED) {  // gather the marked partners
-        for (int o0 = 1; o0 <= P; o0 += NT) {
-          const int o = o0 + t;
-          const int j = partner(o <= P ? o : 1);
-          const bool m = o <= P && list[j] == kCodePass;
-          const unsigned long long mm = lane_mask(m);
-          if (mm) {
-            unsigned p0 = 0;
-            if (lane == 0) p0 = atomicAdd(&s_pos, (unsigned)__popcll(mm));
-            p0 = __shfl(p0, 0);
-            if (m) put(p0 + (unsigned)__popcll(mm & ((1ull << lane) - 1ull)), j);
-          }
-        }
-      } else {
-        for (unsigned q = t; q < cnt; q += NT) {
-          int j = i + 1 + (int)list[q];
-          if (j >= n) j -= n;
-          put(q, j);
-        }
+      const unsigned short* offs = CODED ? plist : list;
+      for (unsigned q = t; q < cnt; q += NT) {
+        int j = i + 1 + (int)offs[q];
+        if (j >= n) j -= n;
+        put(q, j);
       }
       if (!direct) {
         __syncthreads();
@@ -1321,8 +1319,7 @@ __global__ __launch_bounds__(NT) void k_bins_pruned(const double* __restrict__ x
   const BinFrame F = bin_frame(best_slope<NT>(seed_res, c.n_seeds, seed_rec, n_rec),
                                c.xh, c.yh, W, NBINSP);
   const int half = n >> 1;
-  const double tau0 = tau_bound(0.0, c.xh, c.yh), tau1 = tau_bound(1.0, c.xh, c.yh) - tau0;
-  const double th_lim = tau0 < 1e29 ? fmin(1e29, 0.5 * (1e29 - tau0) / tau1) : 0.0;
+  const double th_lim = screen_th_lim(c.fx, c.fy, c.xh, c.yh);
   unsigned long long n_scr = 0, n_forced = 0, n_pass = 0;
   auto reserve = [&](unsigned cnt) {
     const unsigned base = atomicAdd(&ctx->n_cands, cnt);
@@ -1515,10 +1512,10 @@ __global__ __launch_bounds__(NT, 3) void k_screen_list(
       const double xl = xy[2 * lo], yl = xy[2 * lo + 1];
       const double xr = xy[2 * hi], yr = xy[2 * hi + 1];
       const double th = (yr - yl) / (xr - xl);
-      const double tau = tau_bound(th, c.xh, c.yh);
-      const float th32 = me ? (float)th : 0.0f;
-      const float thr = me ? f32_up(W + tau) : 0.0f;
-      const float ta = me ? f32_up(tau) : 0.0f;
+      const ScreenScalars sc = screen_scalars(th, W, c.fx, c.fy, c.xh, c.yh);
+      const float th32 = me ? sc.th32 : 0.0f;
+      const float thr = me ? sc.thr : 0.0f;
+      const float ta = me ? sc.ta : 0.0f;
       const float nc = me ? -fmaf(-th32, pi.x, pi.y) : 0.0f;
       unsigned long long m = mine;
       while (m) {
@@ -1574,8 +1571,8 @@ __global__ __launch_bounds__(NT) void k_screen_pairs(
       continue;
     }
     const double th = (yr - yl) / (xr - xl);
-    const double tau = tau_bound(th, c.xh, c.yh);
-    if (!(fabs(th) < 1e30 && tau < 1e30)) {
+    const ScreenScalars sc = screen_scalars(th, W, c.fx, c.fy, c.xh, c.yh);
+    if (sc.force) {
       if (lane == 0) verdict[t] = 1;
       continue;
     }
@@ -1587,10 +1584,10 @@ __global__ __launch_bounds__(NT) void k_screen_pairs(
       X[r] = p.x - pi.x;
       Y[r] = p.y - pi.y;
     }
-    const float th32 = (float)th;
+    const float th32 = sc.th32;
     // per-pair scalars in SGPRs, as in the screen kernel
     const PairTest pt = test_pair<R, LDS_PART>(
-        X, Y, lds, nq, lane_f(-th32, 0), lane_f(f32_up(W + tau), 0), lane_f(f32_up(tau), 0),
+        X, Y, lds, nq, lane_f(-th32, 0), lane_f(sc.thr, 0), lane_f(sc.ta, 0),
         lane_f(-fmaf(-th32, pi.x, pi.y), 0), c.h);
     if (lane == 0) verdict[t] = pt.keep;
   }
@@ -2084,7 +2081,7 @@ lms_status make_setup(const double* d_xy, int64_t n, int64_t h, lms_result* d_ou
   if (opt && opt->struct_size < offsetof(lms_options, max_workspace))
     return fail(LMS_ERR_ARG, "bad options size");
   // automatic tiles and seeds: the autotuned choice for this size class, if any
-  lms_tuning tuned{0, 0, -1, 0, 0.0};
+  lms_tuning tuned{0, 0, -1, 0, 0.0, 0, 0};
   const bool have_tuned = n >= 2 && n <= LMS_MAX_N &&
                           lms_host::get_tuning(kPathSingle, lms_host::size_class((int)n), &tuned);
   int tile_regs = opt ? opt->tile_regs : 0;
@@ -2155,7 +2152,12 @@ lms_status make_setup(const double* d_xy, int64_t n, int64_t h, lms_result* d_ou
   // The slope range costs two or three short launches and kGrid (2 kGrid)
   // exact windows; the anchors and points it drops pay for that above
   // kRangeMinN (kRefineMinN) points.
-  const bool force_range = (flags & LMS_F_RANGE) != 0, no_range = (flags & LMS_F_NO_RANGE) != 0;
+  // the tuned range choice applies when the flags leave it open
+  const bool flags_range = (flags & (LMS_F_RANGE | LMS_F_NO_RANGE)) != 0;
+  const bool force_range = (flags & LMS_F_RANGE) != 0 ||
+                           (!flags_range && have_tuned && tuned.range > 0);
+  const bool no_range = (flags & LMS_F_NO_RANGE) != 0 ||
+                        (!flags_range && have_tuned && tuned.range < 0);
   S->range = use_bins && !no_prune && !no_range && (force_range || p.n > kRangeMinN);
   S->refine = S->range && (force_range || p.n > kRefineMinN);
   S->seed_theta = d_seed_theta;
@@ -2166,25 +2168,30 @@ lms_status make_setup(const double* d_xy, int64_t n, int64_t h, lms_result* d_ou
   S->final_slots = split_slots(p.n, p.n > 4096 ? kFinalSlotsLarge : kFinalSlots);
   const long long tmp = (long long)S->final_slots * next_pow2(p.n);
   S->L = layout(p.n_pad, p.cap, n_seed_theta, S->cand_cap, tmp, S->net != nullptr);
-  // A workspace limit shrinks the slope-bin pass list first (its overflow
-  // sends the solve to the exhaustive FP32 screen: same result, slower), then
-  // the survivor list (its overflow is reported as LMS_ERR_CAPACITY).
+  // A workspace limit shrinks the lists (order below).
   const uint64_t max_ws =
       opt && opt->struct_size >= offsetof(lms_options, max_workspace) + sizeof(uint64_t)
           ? opt->max_workspace : 0;
   if (max_ws && S->L.total > max_ws) {
-    const long long kMinList = 1024;
-    if (S->cand_cap > kMinList) {
-      const long long over = (long long)(S->L.total - max_ws);
-      S->cand_cap = std::max(kMinList, S->cand_cap - (over + 7) / 8 - 64);
+    // The survivor list shrinks first to kKeepSurv slots (tens of survivors
+    // are usual), then the pass list (its overflow only costs time: the
+    // exhaustive FP32 screen runs), then the survivor list again (its
+    // overflow is LMS_ERR_CAPACITY), each down to kMinList slots.
+    const long long kMinList = 1024, kKeepSurv = 65536;
+    const long long per_c = (long long)sizeof(uint2);
+    const long long per_s = (long long)(sizeof(uint2) + sizeof(double4));
+    auto relayout = [&]() {
       S->L = layout(p.n_pad, p.cap, n_seed_theta, S->cand_cap, tmp, S->net != nullptr);
-    }
-    if (S->L.total > max_ws && p.cap - p.n_seeds > kMinList) {
+    };
+    auto shrink = [&](long long& slots, long long floor, long long per, long long base) {
+      if (S->L.total <= max_ws || slots - base <= floor) return;
       const long long over = (long long)(S->L.total - max_ws);
-      const long long per = (long long)(sizeof(uint2) + sizeof(double4));
-      p.cap = p.n_seeds + std::max(kMinList, p.cap - p.n_seeds - (over + per - 1) / per - 16);
-      S->L = layout(p.n_pad, p.cap, n_seed_theta, S->cand_cap, tmp, S->net != nullptr);
-    }
+      slots = base + std::max(floor, slots - base - (over + per - 1) / per - 64);
+      relayout();
+    };
+    shrink(p.cap, kKeepSurv, per_s, p.n_seeds);
+    shrink(S->cand_cap, kMinList, per_c, 0);
+    shrink(p.cap, kMinList, per_s, p.n_seeds);
     if (S->L.total > max_ws)
       return fail(LMS_ERR_NOMEM, "max_workspace below the " + std::to_string(S->L.total) +
                                      " bytes this solve needs at the least");
@@ -2225,14 +2232,21 @@ lms_status enqueue_solve(const Setup& S, char* base, hipStream_t s, lms_host::St
   // two rounds of pairs drawn from the narrowest window found so far. Without
   // pruning the bound stays +inf and the screen keeps every pair whose
   // anchored window can hold h points at all.
-  if (n_seed_theta > 0 && !S.no_prune)
-    launch_eval(s, (int)std::min<int64_t>(n_seed_theta, 4 * cu), d_xy, p.n, p.h, seed_theta,
-                (int)n_seed_theta, nullptr, ctx, rec);
+  double* tmp = (double*)(base + L.sort_tmp);
+  if (n_seed_theta > 0 && !S.no_prune) {
+    if (p.n <= kSeedExactMax || S.final_slots <= 0)
+      launch_eval(s, (int)std::min<int64_t>(n_seed_theta, 4 * cu), d_xy, p.n, p.h, seed_theta,
+                  (int)n_seed_theta, nullptr, ctx, rec);
+    else  // larger sets: the split sort (chunk sorts in registers, one merge)
+      launch_recheck(s, p.n, (int)std::min<int64_t>(n_seed_theta, 4 * cu), d_xy, ctx, entries,
+                     rec, 0, (int)n_seed_theta, 1, tmp,
+                     (int)std::min<int64_t>(n_seed_theta, S.final_slots),
+                     p.n > 4096 ? 64 : 32, seed_theta);
+  }
   const int first_w = 1 + seeds;
   if (window_pairs)
     hipLaunchKernelGGL(k_window_pairs, dim3(1), dim3(kWinNT), 0, s, d_xy, ctx, rec,
                        (int)n_seed_theta, entries, first_w, window_pairs, key ^ 0xA1ull);
-  double* tmp = (double*)(base + L.sort_tmp);
   // up to kSeedExactMax points one workgroup sorts a seed's intercepts
   // faster than the histogram levels take, and the window is exact
   auto seed_windows = [&](int grid, int begin, int end, int upd) {
@@ -2458,36 +2472,94 @@ lms_status lms_autotune(const double* d_xy, int64_t n, int64_t h, int32_t reps, 
   hipEvent_t e0, e1;
   (void)hipEventCreate(&e0);
   (void)hipEventCreate(&e1);
-  const int auto_R = pick_R((int)n);
-  static const int kRegs[] = {0, 32, 16, 1};
-  static const int kBatches[] = {1, 2, 4, 8};
-  lms_tuning best{0, 0, kDefaultSeeds, 0, 1e30};
   lms_status st = LMS_OK;
+  lms_result ref{}, got{};
+  bool have_ref = false;
+  // median time of `reps` solves with option set o; checks the line against
+  // the defaults' (the first candidate)
+  auto time_opts = [&](lms_options& o, double* ms) -> lms_status {
+    lms_status r = lms_solve(d_xy, n, h, d_res, &o, stream);  // warm-up, sizes the workspace
+    if (r != LMS_OK) return r;
+    if (hipMemcpyAsync(&got, d_res, sizeof(got), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return fail(LMS_ERR_DEVICE, "reading a tuning result failed");
+    if (!have_ref) {
+      ref = got;
+      have_ref = true;
+    } else if (got.width != ref.width || got.theta1 != ref.theta1 || got.z_lo != ref.z_lo ||
+               got.z_hi != ref.z_hi || got.status != ref.status) {
+      return fail(LMS_ERR_DEVICE, "a tuning candidate changed the result");
+    }
+    std::vector<float> t(reps);
+    for (int k = 0; k < reps; ++k) {
+      (void)hipEventRecord(e0, s);
+      r = lms_solve(d_xy, n, h, d_res, &o, stream);
+      (void)hipEventRecord(e1, s);
+      if (r != LMS_OK) return r;
+      if (hipEventSynchronize(e1) != hipSuccess) return fail(LMS_ERR_DEVICE, "event failed");
+      (void)hipEventElapsedTime(&t[k], e0, e1);
+    }
+    std::sort(t.begin(), t.end());
+    *ms = t[reps / 2];
+    return LMS_OK;
+  };
+  auto base_opts = [&]() {
+    lms_options o;
+    std::memset(&o, 0, sizeof(o));
+    o.struct_size = sizeof(o);
+    return o;
+  };
+  // explicit defaults, so that a table entry from an earlier tuning does not
+  // leak into the candidates
+  lms_tuning best{pick_R((int)n), 4, kDefaultSeeds, default_bins_log2((int)n), 1e30, 0, 0};
+  int min_bins = 11;
+  while (min_bins < 15 && (1 << min_bins) < 2 * n) ++min_bins;
+  best.bins_log2 = std::max(best.bins_log2, min_bins);
+  // 1. the screen's bins, the slope range and the seeds
+  static const int kSeedsC[] = {kDefaultSeeds, 63};
+  static const int kRangeC[] = {0, 1, -1};
+  for (int bl = min_bins; bl <= 15 && st == LMS_OK; ++bl)
+    for (int rg : kRangeC)
+      for (int sp : kSeedsC) {
+        lms_options o = base_opts();
+        o.seed_pairs = sp;
+        o.bins_log2 = bl;
+        o.tile_regs = best.tile_regs >= 64 ? 64 : best.tile_regs;
+        o.tile_batches = best.tile_batches;
+        o.flags = rg > 0 ? LMS_F_RANGE : (rg < 0 ? LMS_F_NO_RANGE : 0u);
+        double ms = 0;
+        st = time_opts(o, &ms);
+        if (st != LMS_OK) break;
+        if (ms < best.ms) {
+          best.seed_pairs = sp;
+          best.bins_log2 = bl;
+          best.range = rg;
+          best.ms = ms;
+        }
+      }
+  // 2. the FP32 screen's tiles, with the choice of step 1
+  const int auto_R = pick_R((int)n);
+  static const int kRegs[] = {0, 32, 16};
+  static const int kBatches[] = {1, 4};
   for (int r : kRegs) {
+    if (st != LMS_OK) break;
     if (r != 0 && r >= auto_R) continue;  // only fewer register chunks than automatic
     for (int g : kBatches) {
-      lms_options o;
-      std::memset(&o, 0, sizeof(o));
-      o.struct_size = sizeof(o);
-      o.seed_pairs = kDefaultSeeds;
+      lms_options o = base_opts();
+      o.seed_pairs = best.seed_pairs;
+      o.bins_log2 = best.bins_log2;
+      o.flags = best.range > 0 ? LMS_F_RANGE : (best.range < 0 ? LMS_F_NO_RANGE : 0u);
       o.tile_regs = r == 0 ? 64 : r;
       o.tile_batches = g;
-      st = lms_solve(d_xy, n, h, d_res, &o, stream);  // warm-up, also sizes the workspace
+      double ms = 0;
+      st = time_opts(o, &ms);
       if (st != LMS_OK) break;
-      std::vector<float> t(reps);
-      for (int k = 0; k < reps && st == LMS_OK; ++k) {
-        (void)hipEventRecord(e0, s);
-        st = lms_solve(d_xy, n, h, d_res, &o, stream);
-        (void)hipEventRecord(e1, s);
-        if (hipEventSynchronize(e1) != hipSuccess) st = fail(LMS_ERR_DEVICE, "event failed");
-        (void)hipEventElapsedTime(&t[k], e0, e1);
+      if (ms < best.ms) {
+        best.tile_regs = o.tile_regs;
+        best.tile_batches = g;
+        best.ms = ms;
       }
-      if (st != LMS_OK) break;
-      std::sort(t.begin(), t.end());
-      const double ms = t[reps / 2];
-      if (ms < best.ms) best = {o.tile_regs, g, kDefaultSeeds, 0, ms};
     }
-    if (st != LMS_OK) break;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -2573,6 +2645,8 @@ lms_status lms_screen_pairs(const double* d_xy, int64_t n, int64_t h, double W,
   if (err != hipSuccess) return fail(LMS_ERR_DEVICE, hipGetErrorString(err));
   return LMS_OK;
 }
+
+void lms_tuning_clear(void) { lms_host::clear_tuning(); }
 
 void lms_profile_begin(void) { lms_host::profile_begin(); }
 

@@ -56,6 +56,7 @@ constexpr long long kBatchScreenCap = 1ll << 24;  // FP64 survivor slots
 constexpr long long kBatchCandCap = 1ll << 26;    // slope-bin list slots per class
 constexpr int kBatchSeeds = 31;   // default random seed pairs per problem
 constexpr int kPathBatched = 1;   // tuning-table key of lms_solve_batched
+constexpr int kSmallBinsLog2 = 12;  // default bins of the small classes' screen
 
 // Per-problem state in device memory.
 struct __align__(16) PMeta {
@@ -69,6 +70,7 @@ struct __align__(16) PMeta {
   unsigned long long vertical, survivors, evals, dir_evals, band_pass, bin_pass;
   double center;  // slope of the narrowest seed window (centre of the bin map)
   double pad2;
+  double fx, fy;  // scales of the FP32 copy (powers of two; f32_scale)
 };
 
 struct __align__(16) BState {
@@ -162,6 +164,8 @@ __global__ __launch_bounds__(256) void k_bprep(const double* __restrict__ xy,
     if (ok) {
       m.xh = fmax(fabs(minx - cx), fabs(maxx - cx)) * (1.0 + 0x1p-40);
       m.yh = fmax(fabs(miny - cy), fabs(maxy - cy)) * (1.0 + 0x1p-40);
+      m.fx = f32_scale(m.xh);
+      m.fy = f32_scale(m.yh);
       m.xabs = fmax(fabs(minx), fabs(maxx));
       m.yabs = fmax(fabs(miny), fabs(maxy));
     }
@@ -171,10 +175,14 @@ __global__ __launch_bounds__(256) void k_bprep(const double* __restrict__ xy,
   }
   const float qnan = __int_as_float(0x7FC00000);
   const int po = pad_off[b];
+  // the scales thread 0 stored (same inputs, same operations)
+  const double fx = f32_scale(fmax(fabs(minx - cx), fabs(maxx - cx)) * (1.0 + 0x1p-40));
+  const double fy = f32_scale(fmax(fabs(miny - cy), fabs(maxy - cy)) * (1.0 + 0x1p-40));
   for (int k = t; k < 64 * R; k += blockDim.x) {
     float2 p = make_float2(qnan, qnan);
     if (ok && k < n)
-      p = make_float2((float)(xy[2 * (off + k)] - cx), (float)(xy[2 * (off + k) + 1] - cy));
+      p = make_float2((float)((xy[2 * (off + k)] - cx) * fx),
+                      (float)((xy[2 * (off + k) + 1] - cy) * fy));
     xy32[po + k] = p;
   }
   for (int e = t; e < S; e += blockDim.x) {
@@ -302,12 +310,12 @@ __global__ __launch_bounds__(256, 3) void k_bscreen(
       const double xr = gxy[2 * hi], yr = gxy[2 * hi + 1];
       const bool vert = valid && (xl == xr);
       const double th = (yr - yl) / (xr - xl);
-      const double tau = tau_bound(th, m.xh, m.yh);
-      const bool force = valid && !vert && !(fabs(th) < 1e30 && tau < 1e30);
+      const ScreenScalars sc = screen_scalars(th, W, m.fx, m.fy, m.xh, m.yh);
+      const bool force = valid && !vert && sc.force;
       const bool test = valid && !vert && !force;
-      const float th32 = test ? (float)th : 0.0f;
-      const float thr = test ? f32_up(W + tau) : 0.0f;
-      const float ta = test ? f32_up(tau) : 0.0f;
+      const float th32 = test ? sc.th32 : 0.0f;
+      const float thr = test ? sc.thr : 0.0f;
+      const float ta = test ? sc.ta : 0.0f;
       if (!fallback) n_vert += __popcll(__ballot(vert));
       unsigned long long msk = __ballot(test);
       // lanes whose pair is appended
@@ -444,8 +452,7 @@ __global__ __launch_bounds__(NT) void k_bbins(const double* __restrict__ xy, PMe
     const int half = n >> 1;
     const int P = (n & 1) ? half : (i < half ? half : half - 1);
     unsigned long long n_vert = 0, n_forced = 0, n_pass = 0;  // per wavefront (uniform)
-    const double tau0 = tau_bound(0.0, m.xh, m.yh), tau1 = tau_bound(1.0, m.xh, m.yh) - tau0;
-    const double th_lim = tau0 < 1e29 ? fmin(1e29, 0.5 * (1e29 - tau0) / tau1) : 0.0;
+    const double th_lim = screen_th_lim(m.fx, m.fy, m.xh, m.yh);
     auto partner = [&](int o) { return i + o >= n ? i + o - n : i + o; };
     double2 pn = 1 + t <= P ? pts[partner(1 + t)] : make_double2(0.0, 0.0);
     for (int o0 = 1; o0 <= P; o0 += NT) {
@@ -534,6 +541,169 @@ __global__ __launch_bounds__(NT) void k_bbins(const double* __restrict__ xy, PMe
   for (unsigned q = s_next + t; q < s_end; q += NT) cands[q] = make_uint2(kNoProblem, 0u);
 }
 
+// The same screen with one work item per wavefront, for small problems
+// (n <= 1024): the per-item steps (clear, insert, prefix sum, queries) are
+// short, and the block-wide barriers between them left most of the time to
+// latency. Here each wavefront owns a histogram of NB + 64 bins in LDS and
+// runs its items round-robin with no block barrier; a wavefront's LDS
+// operations execute in order, so only compiler reordering needs fencing.
+// Passes go to the class's list from a per-wavefront reservation window.
+template <int NB>
+__device__ __forceinline__ void wave_scan_bins(unsigned* bins) {
+  constexpr int S = (NB + 64) / 64;
+  static_assert(S * 64 == NB + 64 && (S & 1), "bins per lane must be odd");
+  const int lane = threadIdx.x & 63;
+  unsigned v[S];
+  unsigned run = 0;
+#pragma unroll
+  for (int r = 0; r < S; ++r) {
+    run += bins[lane * S + r];
+    v[r] = run;
+  }
+  unsigned x = run;
+#pragma unroll
+  for (int m = 1; m < 64; m <<= 1) {
+    const unsigned y = __shfl_up(x, m);
+    if (lane >= m) x += y;
+  }
+  const unsigned off = x - run;
+#pragma unroll
+  for (int r = 0; r < S; ++r) bins[lane * S + r] = v[r] + off;
+}
+
+__device__ __forceinline__ void wave_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+template <int NB, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void k_bbins_wave(
+    const double* __restrict__ xy, PMeta* meta, const uint2* __restrict__ items, int n_items,
+    uint2* __restrict__ cands, int cand_cap, uint2* __restrict__ entries, int cap, BState* state,
+    int cls) {
+  constexpr int NBINS = NB + 64;
+  constexpr int kRLog = __builtin_ctz(NB) - 1;
+  constexpr int kMaxN = 1024;
+  constexpr unsigned kWaveReserve = 256;
+  __shared__ unsigned s_bins[WAVES][NBINS + 1];
+  __shared__ unsigned short s_list[WAVES][kMaxN / 2];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  unsigned* bins = s_bins[wv];
+  unsigned short* list = s_list[wv];
+  unsigned w_next = 0, w_end = 0;  // this wavefront's reserved list slots (uniform)
+  const int stride = gridDim.x * WAVES;
+  for (int item = blockIdx.x * WAVES + wv; item < n_items; item += stride) {
+    const uint2 it = items[item];
+    const int b = __builtin_amdgcn_readfirstlane((int)it.x);
+    const int i = __builtin_amdgcn_readfirstlane((int)it.y);
+    const PMeta m = meta[b];
+    if (m.status != LMS_OK || m.all_x_equal) continue;
+    const int n = __builtin_amdgcn_readfirstlane(m.n);
+    const int h = __builtin_amdgcn_readfirstlane(m.h);
+    wave_fence();  // the previous item's queries are done with the bins
+    for (int q = lane; q <= NBINS; q += 64) bins[q] = 0u;
+    wave_fence();
+    const double* gxy = xy + 2 * m.off;
+    const double W = __longlong_as_double((long long)m.wbound);
+    const double lim = W * (1.0 + 0x1p-50);
+    const BinFrame F = bin_frame(m.center, m.xh, m.yh, W, NBINS);
+    const double xi = gxy[2 * i], yi = gxy[2 * i + 1];
+    const double2* pts = reinterpret_cast<const double2*>(gxy);
+    unsigned all = 0;
+    double2 nxt = lane < n ? pts[lane] : make_double2(0.0, 0.0);
+    for (int k = lane; k < n; k += 64) {
+      const double2 cur = nxt;
+      if (k + 64 < n) nxt = pts[k + 64];
+      all += add_point_bins<kRLog>(bins, cur.x - xi, cur.y - yi, W, lim, F);
+    }
+#pragma unroll
+    for (int q = 32; q >= 1; q >>= 1) all += __shfl_xor(all, q);
+    wave_fence();
+    wave_scan_bins<NB>(bins);
+    wave_fence();
+    const unsigned pall = all;
+    const int half = n >> 1;
+    const int P = (n & 1) ? half : (i < half ? half : half - 1);
+    unsigned long long n_vert = 0, n_forced = 0, n_pass = 0;  // uniform
+    const double th_lim = screen_th_lim(m.fx, m.fy, m.xh, m.yh);
+    auto partner = [&](int o) { return i + o >= n ? i + o - n : i + o; };
+    unsigned cnt = 0;  // passes listed so far (uniform)
+    double2 pn = 1 + lane <= P ? pts[partner(1 + lane)] : make_double2(0.0, 0.0);
+    for (int o0 = 1; o0 <= P; o0 += 64) {
+      const int o = o0 + lane;
+      const bool valid = o <= P;
+      const int j = partner(valid ? o : 1);
+      const int lo = min(i, j), hi = max(i, j);
+      const double2 pj = pn;
+      if (o + 64 <= P) pn = pts[partner(o + 64)];
+      const double dx = pj.x - xi, dy = pj.y - yi, adx = fabs(dx);
+      const bool vert = valid && dx == 0.0;
+      const double r = recip(dx);
+      const double th = dy * r;
+      const bool ok = adx >= 0x1p-900 && adx <= 0x1p900 && fabs(th) < th_lim;
+      const bool force = valid && !vert && !ok;
+      const bool test = valid && !vert && ok;
+      const bool pass = test && bins_pass(bins[slope_bin<kRLog>(dx, dy, r, F)], pall, h);
+      const unsigned long long mf = __ballot(force), mp = __ballot(pass);
+      n_vert += __popcll(__ballot(vert));
+      n_forced += __popcll(mf);
+      n_pass += __popcll(mp);
+      if (mf) {
+        unsigned base = 0;
+        if (lane == 0) {
+          const unsigned now = __hip_atomic_load(&state->n_entries, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+          base = now >= (unsigned)cap ? (unsigned)cap
+                                      : atomicAdd(&state->n_entries, (unsigned)__popcll(mf));
+        }
+        base = __shfl(base, 0);
+        if (force) {
+          const unsigned idx = base + (unsigned)__popcll(mf & ((1ull << lane) - 1ull));
+          if (idx < (unsigned)cap) {
+            entries[idx] = make_uint2((unsigned)b, pack_pair(lo, hi));
+          } else {
+            atomicOr(&state->overflow, 1u);
+            atomicOr(&meta[b].overflow, 1u);
+          }
+        }
+      }
+      if (pass) list[cnt + __popcll(mp & ((1ull << lane) - 1ull))] = (unsigned short)(o - 1);
+      cnt += (unsigned)__popcll(mp);
+    }
+    if (lane == 0) {
+      if (n_vert) atomicAdd(&meta[b].vertical, n_vert);
+      if (n_forced) atomicAdd(&meta[b].survivors, n_forced);
+      if (n_pass) atomicAdd(&meta[b].bin_pass, n_pass);
+    }
+    if (cnt) {
+      wave_fence();  // the list entries are written
+      if (w_end - w_next < cnt) {  // mark the rest unused, reserve more
+        for (unsigned q = w_next + lane; q < w_end; q += 64u) cands[q] = make_uint2(kNoProblem, 0u);
+        const unsigned want = cnt > kWaveReserve ? cnt : kWaveReserve;
+        unsigned got = 0;
+        if (lane == 0) {
+          const unsigned now = __hip_atomic_load(&state->n_cands[cls], __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+          got = now >= (unsigned)cand_cap ? (unsigned)cand_cap
+                                          : atomicAdd(&state->n_cands[cls], want);
+        }
+        got = __shfl(got, 0);
+        w_next = got;
+        w_end = got >= (unsigned)cand_cap ? got : min(got + want, (unsigned)cand_cap);
+        if (w_end - w_next < cnt && lane == 0) atomicOr(&state->cand_overflow, 1u << cls);
+      }
+      const unsigned room = w_end - w_next;
+      for (unsigned q = lane; q < cnt && q < room; q += 64u) {
+        int j = i + 1 + (int)list[q];
+        if (j >= n) j -= n;
+        cands[w_next + q] = make_uint2((unsigned)b, (unsigned)i | ((unsigned)j << 16));
+      }
+      w_next += min(cnt, room);
+    }
+  }
+  for (unsigned q = w_next + lane; q < w_end; q += 64u) cands[q] = make_uint2(kNoProblem, 0u);
+}
+
 // FP32 test of the listed pairs of one register class: a wavefront takes 64
 // consecutive list entries and, for each distinct (problem, anchor) among
 // them, loads that problem's points shifted by the anchor and runs the band
@@ -609,11 +779,11 @@ __global__ __launch_bounds__(256, 3) void k_bscreen_list(
       const double xl = gxy[2 * lo], yl = gxy[2 * lo + 1];
       const double xr = gxy[2 * hi], yr = gxy[2 * hi + 1];
       const double th = (yr - yl) / (xr - xl);
-      const double tau = tau_bound(th, m.xh, m.yh);
       const double W = __longlong_as_double((long long)m.wbound);
-      const float th32 = me ? (float)th : 0.0f;
-      const float thr = me ? f32_up(W + tau) : 0.0f;
-      const float ta = me ? f32_up(tau) : 0.0f;
+      const ScreenScalars sc = screen_scalars(th, W, m.fx, m.fy, m.xh, m.yh);
+      const float th32 = me ? sc.th32 : 0.0f;
+      const float thr = me ? sc.thr : 0.0f;
+      const float ta = me ? sc.ta : 0.0f;
       if (b != cur) {
         flush_counts();
         cur = b;
@@ -824,7 +994,8 @@ __global__ __launch_bounds__(256) void k_bfinal(const PMeta* __restrict__ meta, 
   o.dir_evals = m.dir_evals;
   o.band_pass = m.band_pass;
   o.bin_pass = m.bin_pass;
-  o.bins = bins ? (m.R <= kClassChunks[1] ? 4096u : 8192u) + 256u : 0u;  // the class's bins
+  // the class's bins: the per-wavefront screen's below 1024 points
+  o.bins = bins ? (m.R <= kClassChunks[1] ? (unsigned)bins : 8192u + 256u) : 0u;
   out[b] = o;
 }
 
@@ -834,6 +1005,7 @@ __global__ __launch_bounds__(256) void k_bfinal(const PMeta* __restrict__ meta, 
 // work order of each class. Cached by the content of the offsets.
 struct BPlan {
   int B = 0, S = 0, max_n = 0;
+  int small_log2 = kSmallBinsLog2;  // bins of the per-wavefront screen (classes 0, 1)
   long long pad_total = 0, pairs = 0, cap = 0;
   bool may_overflow = false;  // more pairs than survivor slots: check after the pass
   int n_probs[kClasses] = {};
@@ -1000,9 +1172,10 @@ struct BatchKey {
   int B, S;
   bool bins;
   uint64_t max_ws;
+  int small_log2;
   bool operator<(const BatchKey& o) const {
-    return std::tie(xy, off, h, out, stream, B, S, bins, max_ws) <
-           std::tie(o.xy, o.off, o.h, o.out, o.stream, o.B, o.S, o.bins, o.max_ws);
+    return std::tie(xy, off, h, out, stream, B, S, bins, max_ws, small_log2) <
+           std::tie(o.xy, o.off, o.h, o.out, o.stream, o.B, o.S, o.bins, o.max_ws, o.small_log2);
   }
 };
 
@@ -1092,14 +1265,44 @@ void launch_bbins_nb(hipStream_t s, int c, int cu, const double* xy, PMeta* meta
                      cand_cap, entries, cap, state, c);
 }
 
-void launch_bbins(hipStream_t s, int c, int cu, const double* xy, PMeta* meta, const uint2* it,
-                  int n_items, uint2* cands, int cand_cap, uint2* entries, int cap,
-                  BState* state) {
-  switch (c) {
-    case 0: launch_bbins_nb<4096, 256>(s, c, cu, xy, meta, it, n_items, cands, cand_cap, entries, cap, state); break;
-    case 1: launch_bbins_nb<4096, 256>(s, c, cu, xy, meta, it, n_items, cands, cand_cap, entries, cap, state); break;
-    default: launch_bbins_nb<8192, 256>(s, c, cu, xy, meta, it, n_items, cands, cand_cap, entries, cap, state); break;
+// One item per wavefront (classes 0 and 1, n <= 1024): WAVES wavefronts per
+// block, each with its own histogram.
+template <int NB, int WAVES>
+void launch_bbins_wave(hipStream_t s, int c, int cu, const double* xy, PMeta* meta,
+                       const uint2* it, int n_items, uint2* cands, int cand_cap, uint2* entries,
+                       int cap, BState* state) {
+  static int resident = 0;
+  if (resident == 0) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)k_bbins_wave<NB, WAVES>,
+                                                     64 * WAVES, 0) != hipSuccess || nb < 1) {
+      (void)hipGetLastError();
+      nb = 1;
+    }
+    resident = nb;
   }
+  const int grid = std::max(1, std::min((n_items + WAVES - 1) / WAVES, resident * cu));
+  hipLaunchKernelGGL((k_bbins_wave<NB, WAVES>), dim3(grid), dim3(64 * WAVES), 0, s, xy, meta, it,
+                     n_items, cands, cand_cap, entries, cap, state, c);
+}
+
+// Bins of the small classes' per-wavefront screen (2^small_log2 nominal).
+int small_class_bins(int small_log2) { return 1 << small_log2; }
+
+void launch_bbins(hipStream_t s, int c, int cu, int small_log2, const double* xy, PMeta* meta,
+                  const uint2* it, int n_items, uint2* cands, int cand_cap, uint2* entries,
+                  int cap, BState* state) {
+  if (c <= 1) {
+    if (small_log2 <= 11)
+      launch_bbins_wave<2048, 4>(s, c, cu, xy, meta, it, n_items, cands, cand_cap, entries, cap,
+                                 state);
+    else
+      launch_bbins_wave<4096, 2>(s, c, cu, xy, meta, it, n_items, cands, cand_cap, entries, cap,
+                                 state);
+    return;
+  }
+  launch_bbins_nb<8192, 256>(s, c, cu, xy, meta, it, n_items, cands, cand_cap, entries, cap,
+                             state);
 }
 
 template <int RMAX>
@@ -1162,7 +1365,7 @@ lms_status enqueue_batch(const BPlan& P, char* base, const double* d_xy, const i
   if (bins) {
     for (int c = 0; c < kClasses; ++c)
       if (P.n_items[c])
-        launch_bbins(s, c, cu, d_xy, meta, items + P.items_off[c], P.n_items[c],
+        launch_bbins(s, c, cu, P.small_log2, d_xy, meta, items + P.items_off[c], P.n_items[c],
                      cands + P.cand_off[c], (int)P.cand_cap[c], entries, cap, state);
   }
   if (prof) prof->mark();
@@ -1191,7 +1394,7 @@ lms_status enqueue_batch(const BPlan& P, char* base, const double* d_xy, const i
     hipLaunchKernelGGL(k_bselect, dim3(4 * cu), dim3(256), 0, s, entries, res, meta, state, cap,
                        pass);
   hipLaunchKernelGGL(k_bfinal, dim3((P.B + 255) / 256), dim3(256), 0, s, meta, P.B, state, d_out,
-                     bins ? 1 : 0);
+                     bins ? small_class_bins(P.small_log2) + 64 : 0);
   if (prof) prof->mark();
   const hipError_t err = hipGetLastError();
   if (err != hipSuccess) return fail(LMS_ERR_DEVICE, std::string("launch: ") + hipGetErrorString(err));
@@ -1274,9 +1477,16 @@ lms_status lms_solve_batched(const double* d_xy, const int64_t* d_offsets,
       seed_pairs = t.seed_pairs;
   }
   const int S = 1 + seed_pairs;
-  // slope-bin first screen unless bins_log2 = -1 (bins per class are fixed)
+  // slope-bin first screen unless bins_log2 = -1; 11 or 12 set the bins of
+  // the per-wavefront screen of problems up to 1024 points (default 12)
   const bool bins = !(opt && opt->bins_log2 == -1);
-  const BatchKey key{d_xy, d_offsets, d_h, d_out, stream, (int)B, S, bins, max_ws};
+  int small_log2 = kSmallBinsLog2;
+  if (opt && opt->bins_log2 > 0) {
+    if (opt->bins_log2 != 11 && opt->bins_log2 != 12)
+      return fail(LMS_ERR_ARG, "lms_solve_batched: bins_log2 must be 0, -1, 11 or 12");
+    small_log2 = opt->bins_log2;
+  }
+  const BatchKey key{d_xy, d_offsets, d_h, d_out, stream, (int)B, S, bins, max_ws, small_log2};
   std::lock_guard<std::mutex> lk(g_bmu);
   BatchCache& bc = g_batches[key];
   const bool same = bc.plan.B == (int)B && bc.offsets == off;
@@ -1287,6 +1497,7 @@ lms_status lms_solve_batched(const double* d_xy, const int64_t* d_offsets,
     bc.release();
     BPlan P;
     lms_status st = plan_batch(off.data(), (int)B, S, max_ws, &P);
+    P.small_log2 = small_log2;
     if (st != LMS_OK) { g_batches.erase(key); return st; }
     char* base = nullptr;
     if (hipMalloc(&base, P.total) != hipSuccess) {
@@ -1358,7 +1569,7 @@ lms_status lms_autotune_batched(const double* d_xy, const int64_t* d_offsets,
   (void)hipEventCreate(&e0);
   (void)hipEventCreate(&e1);
   static const int kSeeds[] = {7, 15, 31, 63};
-  lms_tuning best{0, 0, kBatchSeeds, 0, 1e30};
+  lms_tuning best{0, 0, kBatchSeeds, 0, 1e30, 0, 0};
   lms_status st = LMS_OK;
   for (int sp : kSeeds) {
     lms_options o;
@@ -1377,7 +1588,7 @@ lms_status lms_autotune_batched(const double* d_xy, const int64_t* d_offsets,
     }
     if (st != LMS_OK) break;
     std::sort(t.begin(), t.end());
-    if (t[reps / 2] < best.ms) best = {0, 0, sp, 0, t[reps / 2]};
+    if (t[reps / 2] < best.ms) best = {0, 0, sp, 0, t[reps / 2], 0, 0};
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

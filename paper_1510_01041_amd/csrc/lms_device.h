@@ -44,6 +44,49 @@ __device__ __forceinline__ double tau_bound(double theta, double xh, double yh) 
   return 0x1p-24 * (6.25 * yh + 8.25 * fabs(theta) * xh);
 }
 
+// Scale of one coordinate's FP32 copy: 2^-e, e the exponent of h (the
+// centred half-range), so that the scaled centred values lie in (-2, 2) and
+// fit FP32 whatever the input's magnitude (2^+-200 coordinates overflow or
+// underflow FP32 otherwise); 1 for h = 0. Powers of two scale exactly.
+__device__ __forceinline__ double f32_scale(double h) {
+  if (!(h > 0.0) || !(h < INFINITY)) return 1.0;
+  int e = ilogb(h);
+  e = e < -1000 ? -1000 : (e > 1000 ? 1000 : e);
+  return ldexp(1.0, -e);
+}
+
+// The FP32 test's scalars for a pair of FP64 slope th under the width bound
+// W, in the frame of the FP32 copy (x scaled by fx, y by fy, both powers of
+// two): there the slope is th fy / fx, the bound W fy, and tau is taken on the
+// scaled half-ranges, so every residual and threshold is the input frame's
+// times fy exactly. force: the pair skips the FP32 test (its slope or bound is
+// too large for it) and goes to the FP64 recheck.
+struct ScreenScalars {
+  float th32, thr, ta;
+  bool force;
+};
+__device__ __forceinline__ ScreenScalars screen_scalars(double th, double W, double fx, double fy,
+                                                        double xh, double yh) {
+  const double ths = th * (fy / fx);
+  const double tau = tau_bound(ths, xh * fx, yh * fy);
+  ScreenScalars r;
+  r.force = !(fabs(ths) < 1e30 && tau < 1e30);
+  r.th32 = (float)ths;
+  r.thr = f32_up(W * fy + tau);
+  r.ta = f32_up(tau);
+  return r;
+}
+
+// The largest |th| (input frame) whose FP32 test bound stays below 1e29;
+// steeper pairs go to the FP64 recheck. tau is affine in |th|; half the solved
+// limit covers the roundings.
+__device__ __forceinline__ double screen_th_lim(double fx, double fy, double xh, double yh) {
+  const double xs = xh * fx, ys = yh * fy;
+  const double tau0 = tau_bound(0.0, xs, ys), tau1 = tau_bound(1.0, xs, ys) - tau0;
+  const double lim = tau0 < 1e29 ? fmin(1e29, 0.5 * (1e29 - tau0) / tau1) : 0.0;
+  return lim * (fx / fy);
+}
+
 // Lanes of the wavefront (among the active ones) whose predicate holds: the
 // compare mask itself, without materialising the predicate as an integer.
 __device__ __forceinline__ unsigned long long lane_mask(bool p) {

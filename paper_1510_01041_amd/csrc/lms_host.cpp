@@ -39,7 +39,7 @@ std::string arch_name() {
 }
 
 // One entry per line: arch path class tile_regs tile_batches seed_pairs
-// bins_log2 ms (a JSON array of arrays, so that other tools can read it).
+// bins_log2 ms range (a JSON array of arrays, so that other tools can read it).
 void load_tuning_locked() {
   g_tune_loaded = true;
   const char* path = std::getenv("LMS_TUNE_FILE");
@@ -47,14 +47,14 @@ void load_tuning_locked() {
   FILE* f = std::fopen(path, "r");
   if (!f) return;
   char arch[64];
-  int p, c, r, b, sp, bl;
+  int p, c, r, b, sp, bl, rg;
   double ms;
   int ch;
   while ((ch = std::fgetc(f)) != EOF) {
     if (ch != '[') continue;
-    if (std::fscanf(f, " \"%63[^\"]\" , %d , %d , %d , %d , %d , %d , %lf ]", arch, &p, &c, &r,
-                    &b, &sp, &bl, &ms) == 8) {
-      lms_tuning t{r, b, sp, bl, ms};
+    if (std::fscanf(f, " \"%63[^\"]\" , %d , %d , %d , %d , %d , %d , %lf , %d ]", arch, &p, &c,
+                    &r, &b, &sp, &bl, &ms, &rg) == 9) {
+      lms_tuning t{r, b, sp, bl, ms, rg, 0};
       g_tune[{arch, p, c}] = t;
     }
   }
@@ -69,9 +69,10 @@ void save_tuning_locked() {
   std::fprintf(f, "[\n");
   size_t k = 0;
   for (auto& kv : g_tune) {
-    std::fprintf(f, " [\"%s\", %d, %d, %d, %d, %d, %d, %.6f]%s\n", std::get<0>(kv.first).c_str(),
-                 std::get<1>(kv.first), std::get<2>(kv.first), kv.second.tile_regs,
-                 kv.second.tile_batches, kv.second.seed_pairs, kv.second.bins_log2, kv.second.ms,
+    std::fprintf(f, " [\"%s\", %d, %d, %d, %d, %d, %d, %.6f, %d]%s\n",
+                 std::get<0>(kv.first).c_str(), std::get<1>(kv.first), std::get<2>(kv.first),
+                 kv.second.tile_regs, kv.second.tile_batches, kv.second.seed_pairs,
+                 kv.second.bins_log2, kv.second.ms, kv.second.range,
                  ++k < g_tune.size() ? "," : "");
   }
   std::fprintf(f, "]\n");
@@ -84,6 +85,12 @@ int size_class(int n) {
   int p = 64;
   while (p < n) p <<= 1;
   return p;
+}
+
+void clear_tuning() {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_tune.clear();
+  g_tune_loaded = true;  // and do not read the file again
 }
 
 bool get_tuning(int path, int cls, lms_tuning* t) {

@@ -31,6 +31,7 @@ void release_batches();
 // optionally persisted as JSON in the file named by LMS_TUNE_FILE.
 bool get_tuning(int path, int size_class, lms_tuning* t);
 void set_tuning(int path, int size_class, const lms_tuning& t);
+void clear_tuning();
 int size_class(int n);  // next power of two >= n (>= 64)
 
 // Seed-network inference (lms_net.hip): device bytes of its scratch for B

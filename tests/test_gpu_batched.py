@@ -174,3 +174,51 @@ def test_full_c4_sample(gpu, orc):
         check_pair(xy[off[b]:off[b + 1]], res[b])
     for b in st.integers(6, 0, len(off) - 2):
         check_tied(orc, xy[off[b]:off[b + 1]], res[b])
+
+
+def test_small_class_bin_counts_agree(gpu, orc):
+    """The per-wavefront screen of problems up to 1024 points with 2048 or
+    4096 bins, and without slope bins: the same lines (tied pixel data: the
+    same widths, each certified by the oracle)."""
+    xy, off = gen.hough_patches(300, 41, n_lo=32, n_hi=1024)
+    d = dev(xy)
+    a = gpu.solve_batched(d, off)
+    b = gpu.solve_batched(d, off, bins_log2=11)
+    c = gpu.solve_batched(d, off, bins_log2=-1)
+    assert np.all(a.status == 0) and np.all(b.status == 0)
+    assert np.array_equal(a.width, b.width) and np.array_equal(a.width, c.width)
+    assert set(np.unique(a.bins[np.diff(off) <= 1024])) == {4096 + 64}
+    assert set(np.unique(b.bins[np.diff(off) <= 1024])) == {2048 + 64}
+    for k in range(0, 300, 37):
+        p = xy[off[k]:off[k + 1]]
+        assert orc.window(p, float(b.theta1[k])) == (b.width[k], b.z_lo[k], b.z_hi[k])
+
+
+def test_all_c4_problems_match_stored_oracle(gpu, orc):
+    """All 20,000 problems of the batched workload in one pass against the
+    oracle's stored results (tests/golden/c4_401_oracle.npz, written by
+    make_golden.py from the oracle alone): every width to 1e-9 (pixel data:
+    exact ties between slopes), every status and vertical count, and the
+    oracle's window at each GPU slope equal to the GPU's window."""
+    import hashlib
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "c4_401_oracle.npz")
+    if not os.path.exists(path):
+        pytest.skip("the stored c4 oracle results are not written yet")
+    g = np.load(path)
+    xy, off = gen.make("c4", 401)
+    assert str(g["xy_sha256"]) == hashlib.sha256(xy.tobytes()).hexdigest()
+    res = gpu.solve_batched(dev(xy), off, graph=True)
+    rec, meta = g["rec"], g["meta"]
+    B = len(off) - 1
+    assert np.array_equal(res.status, meta[:, 4].astype(res.status.dtype))
+    assert np.array_equal(res.vertical.astype(np.int64), meta[:, 3])
+    w = rec[:, 0]
+    ok = (np.abs(res.width - w) <= 1e-9 * np.maximum(res.width, w)) | (res.width == w)
+    assert ok.all(), np.flatnonzero(~ok)[:10]
+    bad = []
+    for b in range(B):
+        p = xy[off[b]:off[b + 1]]
+        if orc.window(p, float(res.theta1[b])) != (res.width[b], res.z_lo[b], res.z_hi[b]):
+            bad.append(b)
+    assert not bad, bad[:10]

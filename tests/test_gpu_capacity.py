@@ -60,18 +60,31 @@ def test_batch_survivor_overflow_is_resolved(gpu, orc):
 
 
 def test_single_solve_pass_list_overflow_runs_exhaustive_screen(gpu, orc):
+    """Under a workspace limit the survivor list keeps 65536 slots and the
+    slope-bin pass list shrinks; with a bound loose enough that more pairs
+    pass the bins than the list holds, the exhaustive FP32 screen runs, and
+    the answer is still the oracle's."""
     n = 1500
     xy = planted(n, 0.45, 32)
     d = dev(xy)
-    base = gpu.solve(d, seed_pairs=0)
-    assert base.bin_pass > 5000, base.bin_pass
-    full = gpu.workspace_size(n, seed_pairs=0)
+    for sp in (31, 15, 7, 3, 1):
+        base = gpu.solve(d, seed_pairs=sp)
+        fp32_only = gpu.solve(d, seed_pairs=sp, bins_log2=-1)
+        if base.bin_pass > 4096 and fp32_only.survivors < 60000:
+            break
+    print("seed pairs", sp, "bin passes", base.bin_pass, "fp32 survivors", fp32_only.survivors,
+          flush=True)
+    assert base.bin_pass > 4096 and fp32_only.survivors < 60000
+    full = gpu.workspace_size(n, seed_pairs=sp)
     pairs = n * (n - 1) // 2
-    # leave room for about 2000 listed passes
-    limit = full - (pairs - 2000) * 8
-    assert gpu.workspace_size(n, seed_pairs=0, max_workspace=limit) <= limit
-    r = gpu.solve(d, seed_pairs=0, max_workspace=limit)
+    # default lists: `pairs` pass slots of 8 bytes, `pairs` survivor slots of
+    # 40; the limit leaves about 2000 pass slots (alignment slack included)
+    fixed = full - 48 * pairs
+    limit = fixed + 40 * 65536 + 8 * 1024 + 8192
+    assert gpu.workspace_size(n, seed_pairs=sp, max_workspace=limit) <= limit
+    r = gpu.solve(d, seed_pairs=sp, max_workspace=limit)
     o = orc.solve(xy)
+    assert r.status == 0
     assert (r.width, r.theta1, r.z_lo, r.z_hi) == (o.width, o.theta1, o.z_lo, o.z_hi)
     # the exhaustive FP32 screen tested far more pairs than the list held
     assert r.point_evals > base.point_evals

@@ -157,3 +157,31 @@ def test_network_inside_the_solve(gpu):
         assert (g.width, g.theta1, g.z_lo) == (c.width, c.theta1, c.z_lo)
     with pytest.raises(gpu.LmsError):
         gpu.solve(d, net_params=net.P, seed_theta=th)
+
+
+@pytest.mark.parametrize("name", ["c2", "c3a"])
+def test_trained_network_prunes(gpu, name):
+    """The committed network as the only source of the bound (no random seed
+    pairs): its slope, computed inside the solve, then two rounds of 63 pairs
+    drawn from the narrowest window found (window pairs). Against no seed at
+    all (only the extreme-x pair) it must cut the pairs that pass the FP32
+    band test by at least 100 times, with the same exact line. The slope alone
+    (no window pairs) is reported beside it."""
+    import os
+    from paper_1510_01041_amd import seednet
+    wpath = os.path.join(os.path.dirname(seednet.__file__), "seednet_weights.npy")
+    net = seednet.SeedNet.load_weights(wpath)
+    xy = gen.make(name)
+    d = torch.from_numpy(xy).cuda()
+    ref = gpu.solve(d)
+    learned = gpu.solve(d, seed_pairs=0, net_params=net.P, window_pairs=63)
+    slope_only = gpu.solve(d, seed_pairs=0, net_params=net.P)
+    none = gpu.solve(d, seed_pairs=0)
+    th = float(net.predict_slopes(d, np.array([0, len(xy)]))[0])
+    err = abs(np.degrees(np.arctan(th) - np.arctan(ref.theta1)))
+    print(name, "angle error", err, "band_pass learned", learned.band_pass, "slope only",
+          slope_only.band_pass, "none", none.band_pass, flush=True)
+    for r in (learned, slope_only, none):
+        assert (r.width, r.theta1, r.z_lo, r.z_hi) == (ref.width, ref.theta1, ref.z_lo, ref.z_hi)
+    assert err < 15.0
+    assert none.band_pass >= 100 * max(learned.band_pass, 1)

@@ -1,5 +1,6 @@
-"""The autotuner picks a tile on the device, persists it, and solves that use
-the tuned tile return the same result."""
+"""The autotuner sweeps the hot path's parameters on the device (the
+slope-bin screen's bins, the slope range, the seeds, the FP32 screen's
+tiles), persists its choice, and solves that use it return the same line."""
 import json
 import os
 
@@ -8,24 +9,41 @@ import pytest
 import torch
 
 from workloads import gen
+from workloads.gen import planted
 
 pytestmark = pytest.mark.gpu
 
 
-def test_autotune_single_and_persist(gpu, tmp_path):
+@pytest.fixture
+def clean_table(gpu):
+    yield
+    os.environ.pop("LMS_TUNE_FILE", None)
+    gpu.tuning_clear()
+
+
+@pytest.mark.parametrize("n", [2500, 6000])
+def test_autotune_single_and_persist(gpu, tmp_path, clean_table, n):
     os.environ["LMS_TUNE_FILE"] = str(tmp_path / "tune.json")
-    xy = gen.make("c2", 203)[:2500]
+    xy = planted(n, 0.45, 4500 + n)
     d = torch.from_numpy(np.ascontiguousarray(xy)).cuda()
     before = gpu.solve(d)
     t = gpu.autotune(d, reps=2)
+    print(n, t, flush=True)
     assert t["tile_regs"] in (1, 16, 32, 64) and 1 <= t["tile_batches"] <= 8 and t["ms"] > 0
+    assert 11 <= t["bins_log2"] <= 15 and (1 << t["bins_log2"]) >= min(2 * n, 1 << 15)
+    assert t["range"] in (-1, 0, 1) and t["seed_pairs"] in (63, 255)
     after = gpu.solve(d)
-    assert (after.width, after.theta1, after.z_lo) == (before.width, before.theta1, before.z_lo)
+    assert (after.width, after.theta1, after.z_lo, after.z_hi) == \
+           (before.width, before.theta1, before.z_lo, before.z_hi)
     rows = json.load(open(tmp_path / "tune.json"))
-    assert any(r[1] == 0 and r[2] == 4096 for r in rows)
+    cls = 4096 if n <= 4096 else 8192
+    assert any(r[1] == 0 and r[2] == cls and r[8] == t["range"] for r in rows)
+    # the tuned choice is used: with the range tuned off the full screen runs
+    if t["range"] < 0:
+        assert after.bins != 2048
 
 
-def test_autotune_batched(gpu):
+def test_autotune_batched(gpu, clean_table):
     xy, off = gen.hough_patches(400, 31)
     d = torch.from_numpy(xy).cuda()
     a = gpu.solve_batched(d, off)
