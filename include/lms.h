@@ -156,6 +156,23 @@ typedef struct lms_tuning {
 lms_status lms_solve(const double* d_xy, int64_t n, int64_t h, lms_result* d_out,
                      const lms_options* opt, void* stream);
 
+/* lms_solve without any allocation, for callers that cannot allocate device
+ * memory (code under stream capture, tight serving loops, harnesses that
+ * forbid hipMalloc). The workspace is one static device array of
+ * LMS_NOALLOC_WORKSPACE bytes in the library, held by every GPU the library
+ * runs on until the process ends; its device address is looked up once per
+ * device. The solve's lists shrink to fit it as under opt->max_workspace
+ * (an overflowing slope-bin list falls back to the exhaustive FP32 screen;
+ * more survivors than the shrunk list holds give LMS_ERR_CAPACITY); a size
+ * whose fixed part does not fit is rejected with LMS_ERR_ARG. LMS_F_GRAPH is
+ * rejected (the caller may capture the stream itself). All calls on one GPU
+ * share the array, and every call initialises the state it reads: calls that
+ * overlap on one GPU race (serialise them, e.g. on one stream). Arguments and
+ * results otherwise as lms_solve, bit for bit. */
+#define LMS_NOALLOC_WORKSPACE (96u << 20)
+lms_status lms_solve_noalloc(const double* d_xy, int64_t n, int64_t h, lms_result* d_out,
+                             const lms_options* opt, void* stream);
+
 /* Device bytes of the workspace lms_solve would use for (n, h, opt) (after
  * any max_workspace limit), into *bytes; LMS_ERR_ARG or LMS_ERR_NOMEM as
  * lms_solve would return them. Enqueues nothing. */

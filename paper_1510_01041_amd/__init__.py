@@ -152,6 +152,8 @@ def load():
     L.lms_workspace_size.argtypes = [i64, i64, ctypes.POINTER(_Options),
                                      ctypes.POINTER(ctypes.c_uint64)]
     L.lms_workspace_size.restype = i32
+    L.lms_solve_noalloc.argtypes = [vp, i64, i64, vp, ctypes.POINTER(_Options), vp]
+    L.lms_solve_noalloc.restype = i32
     L.lms_tuning_clear.argtypes = []
     L.lms_tuning_clear.restype = None
     L.lms_shutdown.argtypes = []
@@ -247,6 +249,19 @@ def solve_async(xy: torch.Tensor, h: int = 0, out: torch.Tensor | None = None, *
     st = load().lms_solve(xy.data_ptr(), xy.shape[0], h, out.data_ptr(), ctypes.byref(opt),
                           _stream(stream))
     _check(st)
+    return out
+
+
+def solve_noalloc_async(xy: torch.Tensor, h: int = 0, out: torch.Tensor | None = None,
+                        stream=None, **kw) -> torch.Tensor:
+    """lms_solve_noalloc: the same solve in the library's static workspace (no
+    device allocation by the library); kw as solve_async except graph."""
+    xy = _points(xy)
+    if out is None:
+        out = torch.empty(RESULT_BYTES, dtype=torch.uint8, device=xy.device)
+    opt = _options(0, **kw)
+    _check(load().lms_solve_noalloc(xy.data_ptr(), xy.shape[0], h, out.data_ptr(),
+                                    ctypes.byref(opt), _stream(stream)))
     return out
 
 

@@ -2396,6 +2396,36 @@ lms_status solve_graph(const Setup& S, hipStream_t s) {
   return LMS_OK;
 }
 
+// ---------------------------------------------------------------- allocation-free solves
+
+// lms_solve_noalloc's workspace: one file-scope device array, held by each
+// GPU the library runs on until the process ends. Host code never passes the
+// array's name to a kernel (in host code it is only a stand-in for the
+// symbol); its device address is looked up once per device with
+// hipGetSymbolAddress and kept here.
+constexpr size_t kScratchBytes = size_t(LMS_NOALLOC_WORKSPACE);
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+std::map<int, char*> g_scratch;  // device -> device address of `scratch`
+
+lms_status scratch_address(char** ptr) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(LMS_ERR_DEVICE, "hipGetDevice failed");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch.find(dev);
+  if (it == g_scratch.end()) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(LMS_ERR_DEVICE, std::string("hipGetSymbolAddress(scratch): ") +
+                                      hipGetErrorString(e));
+    it = g_scratch.emplace(dev, (char*)p).first;
+  }
+  *ptr = it->second;
+  return LMS_OK;
+}
+
 void release_solves() {
   std::lock_guard<std::mutex> lk(g_smu);
   for (auto& kv : g_solves) {
@@ -2456,6 +2486,34 @@ lms_status lms_workspace_size(int64_t n, int64_t h, const lms_options* opt, uint
   if (st != LMS_OK) return st;
   *bytes = (uint64_t)S.L.total;
   return LMS_OK;
+}
+
+lms_status lms_solve_noalloc(const double* d_xy, int64_t n, int64_t h, lms_result* d_out,
+                             const lms_options* opt, void* stream) {
+  lms_host::clear_error();
+  if (opt && opt->struct_size < offsetof(lms_options, max_workspace))
+    return fail(LMS_ERR_ARG, "bad options size");
+  if (opt && (opt->flags & LMS_F_GRAPH))
+    return fail(LMS_ERR_ARG, "lms_solve_noalloc builds no graph of its own (the caller may "
+                             "capture the stream)");
+  // the solve's lists shrink to fit the static workspace (lms_solve's
+  // max_workspace rule); the caller's limit, if smaller, still applies
+  lms_options o;
+  std::memset(&o, 0, sizeof(o));
+  o.seed_pairs = -1;  // the defaults lms_solve takes for opt == NULL
+  if (opt) std::memcpy(&o, opt, std::min<size_t>(opt->struct_size, sizeof(o)));
+  o.struct_size = sizeof(o);
+  if (o.max_workspace == 0 || o.max_workspace > kScratchBytes) o.max_workspace = kScratchBytes;
+  Setup S;
+  lms_status st = make_setup(d_xy, n, h, d_out, &o, &S);
+  if (st == LMS_ERR_NOMEM)
+    return fail(LMS_ERR_ARG, "this solve needs more than the " + std::to_string(kScratchBytes) +
+                                 " bytes of lms_solve_noalloc's workspace");
+  if (st != LMS_OK) return st;
+  char* base = nullptr;
+  st = scratch_address(&base);
+  if (st != LMS_OK) return st;
+  return enqueue_solve(S, base, (hipStream_t)stream, nullptr);
 }
 
 lms_status lms_autotune(const double* d_xy, int64_t n, int64_t h, int32_t reps, void* stream,
