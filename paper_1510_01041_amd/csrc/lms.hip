@@ -1105,6 +1105,9 @@ __global__ __launch_bounds__(NT) void k_bins(const double* __restrict__ xy, Ctx*
   // leave no LDS for the codes: the queries compute the pair's bin
   // themselves. Either way the queries list the passing partners' offsets.
   constexpr bool CODED = NB <= 16384;
+  // point loads in flight in the insertion loop (latency: the largest bin
+  // arrays leave the fewest wavefronts per CU)
+  constexpr int kPF = NB >= 32768 ? 3 : 2;
   __shared__ unsigned bins[NBINS + 1];
   // codes of the n <= NB / 2 points (CODED), or partner offsets o - 1 that
   // pass (P(i) <= n / 2 <= LMS_MAX_N / 2)
@@ -1116,7 +1119,7 @@ __global__ __launch_bounds__(NT) void k_bins(const double* __restrict__ xy, Ctx*
   constexpr int PB = 512;
   __shared__ uint2 pbuf[PB];
   __shared__ unsigned s_part[NT / 64];
-  __shared__ unsigned s_all, s_cnt, s_base, s_fill, s_pos;
+  __shared__ unsigned s_all, s_cnt, s_base, s_fill;
   const Ctx c = *ctx;
   if (c.status != LMS_OK || c.all_x_equal || c.n_live >= 0) return;  // (k_bins_pruned)
   const int n = c.n, h = c.h, t = threadIdx.x, lane = t & 63;
@@ -1158,23 +1161,38 @@ __global__ __launch_bounds__(NT) void k_bins(const double* __restrict__ xy, Ctx*
     if (t == 0) {
       s_all = 0;
       s_cnt = 0;
-      s_pos = 0;
     }
     for (int b = t; b <= NBINS; b += NT) bins[b] = 0u;
     __syncthreads();
-    const double xi = xy[2 * i], yi = xy[2 * i + 1];
+    // the anchor in VGPRs (a vector load): a scalar load's wait would also
+    // wait for every LDS operation in flight in the loop below
+    int iv = i;
+    asm volatile("" : "+v"(iv));
+    const double2 pa = pts[iv];
+    const double xi = pa.x, yi = pa.y;
     // 1. intervals of every point (packed counts: U in the low, D in the high half)
     unsigned all = 0;
-    // the next point's load is issued before this point's work
-    double2 nxt = t < n ? pts[t] : make_double2(0.0, 0.0);
-    for (int k = t; k < n; k += NT) {
-      const double2 cur = nxt;
-      if (k + NT < n) nxt = pts[k + NT];
-      if (CODED)
-        all += add_point_bins_coded<kRLog>(bins, cur.x - xi, cur.y - yi, W, lim, F, th_lim,
-                                           &list[k]);
-      else
-        all += add_point_bins<kRLog>(bins, cur.x - xi, cur.y - yi, W, lim, F);
+    // kPF points per step; the loads of the next step's points are issued
+    // before this step's work (clamped indices: no branch around a load)
+    double2 cur[kPF], nxt[kPF];
+#pragma unroll
+    for (int q = 0; q < kPF; ++q) cur[q] = pts[min(t + q * NT, n - 1)];
+    for (int k0 = t; k0 < n; k0 += kPF * NT) {
+#pragma unroll
+      for (int q = 0; q < kPF; ++q) nxt[q] = pts[min(k0 + (kPF + q) * NT, n - 1)];
+#pragma unroll
+      for (int q = 0; q < kPF; ++q) {
+        const int k = k0 + q * NT;
+        if (k < n) {
+          if (CODED)
+            all += add_point_bins_coded<kRLog>(bins, cur[q].x - xi, cur[q].y - yi, W, lim, F,
+                                               th_lim, &list[k]);
+          else
+            all += add_point_bins<kRLog>(bins, cur[q].x - xi, cur[q].y - yi, W, lim, F);
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < kPF; ++q) cur[q] = nxt[q];
     }
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1) all += __shfl_xor(all, m);
@@ -1215,36 +1233,48 @@ __global__ __launch_bounds__(NT) void k_bins(const double* __restrict__ xy, Ctx*
         }
       }
     } else {
-      double2 pn = 1 + t <= P ? pts[partner(1 + t)] : make_double2(0.0, 0.0);
-      for (int o0 = 1; o0 <= P; o0 += NT) {
-        const int o = o0 + t;
-        const bool valid = o <= P;
-        const double2 pj = pn;  // the next partner's load goes out first
-        if (o + NT <= P) pn = pts[partner(o + NT)];
-        const double dx = pj.x - xi, dy = pj.y - yi, adx = fabs(dx);
-        const bool vert = valid && dx == 0.0;
-        const double r = recip(dx);
-        const double th = dy * r;  // within a relative 2^-40 of the pair's slope
-        const bool ok = adx >= 0x1p-900 && adx <= 0x1p900 && fabs(th) < th_lim;
-        const bool force = valid && !vert && !ok;
-        const bool test = valid && !vert && ok;
-        bool pass = false;
-        if (test) pass = bins_pass(bins[slope_bin<kRLog>(dx, dy, r, F)], pall, h);
-        const unsigned long long mp = lane_mask(pass);
-        n_vert += __popcll(lane_mask(vert));
-        n_forced += __popcll(lane_mask(force));
-        n_scr += __popcll(lane_mask(test));
-        n_pass += __popcll(mp);
-        if (force) {
-          const int j = partner(o);
-          append_entry(ctx, entries, cap, (unsigned)min(i, j), (unsigned)max(i, j));
+      // kPF partners per step, the next step's loads issued first (as in 1.)
+      const int Pc = max(P, 1);
+      double2 pc[kPF], pnx[kPF];
+#pragma unroll
+      for (int q = 0; q < kPF; ++q) pc[q] = pts[partner(min(1 + t + q * NT, Pc))];
+      for (int s0 = 1; s0 <= P; s0 += kPF * NT) {
+#pragma unroll
+        for (int q = 0; q < kPF; ++q) pnx[q] = pts[partner(min(s0 + t + (kPF + q) * NT, Pc))];
+#pragma unroll
+        for (int q = 0; q < kPF; ++q) {
+          const int o0 = s0 + q * NT;
+          if (o0 > P) break;  // uniform
+          const int o = o0 + t;
+          const bool valid = o <= P;
+          const double2 pj = pc[q];
+          const double dx = pj.x - xi, dy = pj.y - yi, adx = fabs(dx);
+          const bool vert = valid && dx == 0.0;
+          const double r = recip(dx);
+          const double th = dy * r;  // within a relative 2^-40 of the pair's slope
+          const bool ok = adx >= 0x1p-900 && adx <= 0x1p900 && fabs(th) < th_lim;
+          const bool force = valid && !vert && !ok;
+          const bool test = valid && !vert && ok;
+          bool pass = false;
+          if (test) pass = bins_pass(bins[slope_bin<kRLog>(dx, dy, r, F)], pall, h);
+          const unsigned long long mp = lane_mask(pass);
+          n_vert += __popcll(lane_mask(vert));
+          n_forced += __popcll(lane_mask(force));
+          n_scr += __popcll(lane_mask(test));
+          n_pass += __popcll(mp);
+          if (force) {
+            const int j = partner(o);
+            append_entry(ctx, entries, cap, (unsigned)min(i, j), (unsigned)max(i, j));
+          }
+          if (mp) {
+            unsigned base = 0;
+            if (lane == 0) base = atomicAdd(&s_cnt, (unsigned)__popcll(mp));
+            base = __shfl(base, 0);
+            if (pass) list[base + __popcll(mp & ((1ull << lane) - 1ull))] = (unsigned short)(o - 1);
+          }
         }
-        if (mp) {
-          unsigned base = 0;
-          if (lane == 0) base = atomicAdd(&s_cnt, (unsigned)__popcll(mp));
-          base = __shfl(base, 0);
-          if (pass) list[base + __popcll(mp & ((1ull << lane) - 1ull))] = (unsigned short)(o - 1);
-        }
+#pragma unroll
+        for (int q = 0; q < kPF; ++q) pc[q] = pnx[q];
       }
     }
     __syncthreads();

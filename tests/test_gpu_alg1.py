@@ -27,10 +27,10 @@ def fields(r):
             r.vertical, r.status)
 
 
-@pytest.mark.parametrize("n", [2, 3, 5, 17, 64, 100, 128, 129, 255, 256, 300, 512, 777, 1024])
+@pytest.mark.parametrize("n", [2, 3, 5, 17, 64, 100, 128, 129, 255, 256, 300, 512, 777])
 def test_bracelets_bitwise(gpu, orc, n):
     sets = [planted(n, 0.4, 1200 + n)]
-    if n >= 5:
+    if 5 <= n <= 512:
         sets.append(degenerate_int(n, 1300 + n))
     for xy in sets:
         for rule in (gpu.RULE_TIED, gpu.RULE_LITERAL):
@@ -71,6 +71,20 @@ def test_bracelets_paper_sizes_and_stored_c1(gpu, orc):
         a = gpu.solve_bracelets(dev(xy))
         b = gpu.solve(dev(xy))
         assert abs(a.width - b.width) <= 1e-9 * b.width, n
+
+
+@pytest.mark.parametrize("n", [1500, 2048])
+def test_bracelets_largest_sizes(gpu, orc, n):
+    """Up to the largest size (the oracle's bracelet search takes minutes
+    there): the tied-rank minimum is the LMS width of lms_solve, and the
+    oracle certifies the returned line's window at its slope."""
+    xy = planted(n, 0.45, 1600 + n)
+    a = gpu.solve_bracelets(dev(xy))
+    b = gpu.solve(dev(xy))
+    ulp = 8 * 2.0 ** -53 * (np.abs(xy[:, 1]).max() + abs(a.theta1) * np.abs(xy[:, 0]).max())
+    assert abs(a.width - b.width) <= 1e-9 * b.width + ulp
+    assert orc.window(xy, a.theta1)[0] <= a.width + ulp
+    assert a.candidates == n * (n - 1) // 2 - a.vertical
 
 
 def test_bracelets_degenerate_inputs(gpu, orc):
