@@ -545,9 +545,13 @@ __global__ __launch_bounds__(NT) void k_bbins(const double* __restrict__ xy, PMe
 // (n <= 1024): the per-item steps (clear, insert, prefix sum, queries) are
 // short, and the block-wide barriers between them left most of the time to
 // latency. Here each wavefront owns a histogram of NB + 64 bins in LDS and
-// runs its items round-robin with no block barrier; a wavefront's LDS
-// operations execute in order, so only compiler reordering needs fencing.
-// Passes go to the class's list from a per-wavefront reservation window.
+// runs its items with no block barrier; a wavefront's LDS operations execute
+// in order, so only compiler reordering needs fencing. A wavefront takes
+// chunks of kItemChunk consecutive items (mostly anchors of one problem),
+// keeps the problem's points in registers while the problem lasts, and stores
+// each point's query code in LDS during the insertion (add_point_bins_coded),
+// so the queries read LDS only. Passes go to the class's list from a
+// per-wavefront reservation window.
 template <int NB>
 __device__ __forceinline__ void wave_scan_bins(unsigned* bins) {
   constexpr int S = (NB + 64) / 64;
@@ -576,6 +580,16 @@ __device__ __forceinline__ void wave_fence() {
   __builtin_amdgcn_wave_barrier();
 }
 
+// Lane l's value of v (uniform).
+__device__ __forceinline__ double lane_d(double v, int l) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+constexpr int kItemChunk = 16;
+
 template <int NB, int WAVES>
 __global__ __launch_bounds__(64 * WAVES) void k_bbins_wave(
     const double* __restrict__ xy, PMeta* meta, const uint2* __restrict__ items, int n_items,
@@ -583,122 +597,152 @@ __global__ __launch_bounds__(64 * WAVES) void k_bbins_wave(
     int cls) {
   constexpr int NBINS = NB + 64;
   constexpr int kRLog = __builtin_ctz(NB) - 1;
-  constexpr int kMaxN = 1024;
+  constexpr int kMaxN = 1024, RMAX = kMaxN / 64;
   constexpr unsigned kWaveReserve = 256;
   __shared__ unsigned s_bins[WAVES][NBINS + 1];
   __shared__ unsigned short s_list[WAVES][kMaxN / 2];
+  __shared__ unsigned short s_code[WAVES][kMaxN];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   unsigned* bins = s_bins[wv];
   unsigned short* list = s_list[wv];
+  unsigned short* code = s_code[wv];
   unsigned w_next = 0, w_end = 0;  // this wavefront's reserved list slots (uniform)
+  const int n_chunks = (n_items + kItemChunk - 1) / kItemChunk;
   const int stride = gridDim.x * WAVES;
-  for (int item = blockIdx.x * WAVES + wv; item < n_items; item += stride) {
-    const uint2 it = items[item];
-    const int b = __builtin_amdgcn_readfirstlane((int)it.x);
-    const int i = __builtin_amdgcn_readfirstlane((int)it.y);
-    const PMeta m = meta[b];
-    if (m.status != LMS_OK || m.all_x_equal) continue;
-    const int n = __builtin_amdgcn_readfirstlane(m.n);
-    const int h = __builtin_amdgcn_readfirstlane(m.h);
-    wave_fence();  // the previous item's queries are done with the bins
-    for (int q = lane; q <= NBINS; q += 64) bins[q] = 0u;
-    wave_fence();
-    const double* gxy = xy + 2 * m.off;
-    const double W = __longlong_as_double((long long)m.wbound);
-    const double lim = W * (1.0 + 0x1p-50);
-    const BinFrame F = bin_frame(m.center, m.xh, m.yh, W, NBINS);
-    const double xi = gxy[2 * i], yi = gxy[2 * i + 1];
-    const double2* pts = reinterpret_cast<const double2*>(gxy);
-    unsigned all = 0;
-    double2 nxt = lane < n ? pts[lane] : make_double2(0.0, 0.0);
-    for (int k = lane; k < n; k += 64) {
-      const double2 cur = nxt;
-      if (k + 64 < n) nxt = pts[k + 64];
-      all += add_point_bins<kRLog>(bins, cur.x - xi, cur.y - yi, W, lim, F);
-    }
+  // the current problem (uniform): its metadata and points (lane l holds
+  // points l + 64 r, r < R)
+  int cur = -1, n = 0, h = 0, R = 0;
+  bool skip = true;
+  double W = 0.0, lim = 0.0, th_lim = 0.0;
+  BinFrame F{0.0, 0.0, 0.0};
+  double X[RMAX], Y[RMAX];
+  for (int ch = blockIdx.x * WAVES + wv; ch < n_chunks; ch += stride) {
+    const int i0 = ch * kItemChunk;
+    const int cnt_items = min(kItemChunk, n_items - i0);
+    const uint2 my = lane < cnt_items ? items[i0 + lane] : make_uint2(0u, 0u);
+    for (int q = 0; q < cnt_items; ++q) {
+      const int b = __builtin_amdgcn_readlane((int)my.x, q);
+      const int i = __builtin_amdgcn_readlane((int)my.y, q);
+      if (b != cur) {
+        cur = b;
+        const PMeta m = meta[b];
+        skip = m.status != LMS_OK || m.all_x_equal;
+        n = __builtin_amdgcn_readfirstlane(m.n);
+        h = __builtin_amdgcn_readfirstlane(m.h);
+        R = (n + 63) >> 6;
+        W = __longlong_as_double((long long)m.wbound);
+        lim = W * (1.0 + 0x1p-50);
+        F = bin_frame(m.center, m.xh, m.yh, W, NBINS);
+        th_lim = screen_th_lim(m.fx, m.fy, m.xh, m.yh);
+        const double2* pts = reinterpret_cast<const double2*>(xy + 2 * m.off);
 #pragma unroll
-    for (int q = 32; q >= 1; q >>= 1) all += __shfl_xor(all, q);
-    wave_fence();
-    wave_scan_bins<NB>(bins);
-    wave_fence();
-    const unsigned pall = all;
-    const int half = n >> 1;
-    const int P = (n & 1) ? half : (i < half ? half : half - 1);
-    unsigned long long n_vert = 0, n_forced = 0, n_pass = 0;  // uniform
-    const double th_lim = screen_th_lim(m.fx, m.fy, m.xh, m.yh);
-    auto partner = [&](int o) { return i + o >= n ? i + o - n : i + o; };
-    unsigned cnt = 0;  // passes listed so far (uniform)
-    double2 pn = 1 + lane <= P ? pts[partner(1 + lane)] : make_double2(0.0, 0.0);
-    for (int o0 = 1; o0 <= P; o0 += 64) {
-      const int o = o0 + lane;
-      const bool valid = o <= P;
-      const int j = partner(valid ? o : 1);
-      const int lo = min(i, j), hi = max(i, j);
-      const double2 pj = pn;
-      if (o + 64 <= P) pn = pts[partner(o + 64)];
-      const double dx = pj.x - xi, dy = pj.y - yi, adx = fabs(dx);
-      const bool vert = valid && dx == 0.0;
-      const double r = recip(dx);
-      const double th = dy * r;
-      const bool ok = adx >= 0x1p-900 && adx <= 0x1p900 && fabs(th) < th_lim;
-      const bool force = valid && !vert && !ok;
-      const bool test = valid && !vert && ok;
-      const bool pass = test && bins_pass(bins[slope_bin<kRLog>(dx, dy, r, F)], pall, h);
-      const unsigned long long mf = __ballot(force), mp = __ballot(pass);
-      n_vert += __popcll(__ballot(vert));
-      n_forced += __popcll(mf);
-      n_pass += __popcll(mp);
-      if (mf) {
-        unsigned base = 0;
-        if (lane == 0) {
-          const unsigned now = __hip_atomic_load(&state->n_entries, __ATOMIC_RELAXED,
-                                                 __HIP_MEMORY_SCOPE_AGENT);
-          base = now >= (unsigned)cap ? (unsigned)cap
-                                      : atomicAdd(&state->n_entries, (unsigned)__popcll(mf));
-        }
-        base = __shfl(base, 0);
-        if (force) {
-          const unsigned idx = base + (unsigned)__popcll(mf & ((1ull << lane) - 1ull));
-          if (idx < (unsigned)cap) {
-            entries[idx] = make_uint2((unsigned)b, pack_pair(lo, hi));
-          } else {
-            atomicOr(&state->overflow, 1u);
-            atomicOr(&meta[b].overflow, 1u);
+        for (int r = 0; r < RMAX; ++r) {
+          if (r < R) {
+            const double2 p = pts[min(lane + 64 * r, n - 1)];
+            X[r] = p.x;
+            Y[r] = p.y;
           }
         }
       }
-      if (pass) list[cnt + __popcll(mp & ((1ull << lane) - 1ull))] = (unsigned short)(o - 1);
-      cnt += (unsigned)__popcll(mp);
-    }
-    if (lane == 0) {
-      if (n_vert) atomicAdd(&meta[b].vertical, n_vert);
-      if (n_forced) atomicAdd(&meta[b].survivors, n_forced);
-      if (n_pass) atomicAdd(&meta[b].bin_pass, n_pass);
-    }
-    if (cnt) {
-      wave_fence();  // the list entries are written
-      if (w_end - w_next < cnt) {  // mark the rest unused, reserve more
-        for (unsigned q = w_next + lane; q < w_end; q += 64u) cands[q] = make_uint2(kNoProblem, 0u);
-        const unsigned want = cnt > kWaveReserve ? cnt : kWaveReserve;
-        unsigned got = 0;
-        if (lane == 0) {
-          const unsigned now = __hip_atomic_load(&state->n_cands[cls], __ATOMIC_RELAXED,
-                                                 __HIP_MEMORY_SCOPE_AGENT);
-          got = now >= (unsigned)cand_cap ? (unsigned)cand_cap
-                                          : atomicAdd(&state->n_cands[cls], want);
+      if (skip) continue;
+      // the anchor, read from the lane that holds it
+      const int ri = i >> 6, li = i & 63;
+      double xi = 0.0, yi = 0.0;
+#pragma unroll
+      for (int r = 0; r < RMAX; ++r) {
+        if (r == ri) {
+          xi = lane_d(X[r], li);
+          yi = lane_d(Y[r], li);
         }
-        got = __shfl(got, 0);
-        w_next = got;
-        w_end = got >= (unsigned)cand_cap ? got : min(got + want, (unsigned)cand_cap);
-        if (w_end - w_next < cnt && lane == 0) atomicOr(&state->cand_overflow, 1u << cls);
       }
-      const unsigned room = w_end - w_next;
-      for (unsigned q = lane; q < cnt && q < room; q += 64u) {
-        int j = i + 1 + (int)list[q];
-        if (j >= n) j -= n;
-        cands[w_next + q] = make_uint2((unsigned)b, (unsigned)i | ((unsigned)j << 16));
+      wave_fence();  // the previous item's queries are done with the bins and codes
+      for (int q2 = lane; q2 <= NBINS; q2 += 64) bins[q2] = 0u;
+      wave_fence();
+      unsigned all = 0;
+#pragma unroll
+      for (int r = 0; r < RMAX; ++r) {
+        const int k = lane + 64 * r;
+        if (r < R && k < n)
+          all += add_point_bins_coded<kRLog>(bins, X[r] - xi, Y[r] - yi, W, lim, F, th_lim,
+                                             &code[k]);
       }
-      w_next += min(cnt, room);
+#pragma unroll
+      for (int q2 = 32; q2 >= 1; q2 >>= 1) all += __shfl_xor(all, q2);
+      wave_fence();
+      wave_scan_bins<NB>(bins);
+      wave_fence();
+      const unsigned pall = all;
+      const int half = n >> 1;
+      const int P = (n & 1) ? half : (i < half ? half : half - 1);
+      unsigned long long n_vert = 0, n_forced = 0, n_pass = 0;  // uniform
+      auto partner = [&](int o) { return i + o >= n ? i + o - n : i + o; };
+      unsigned cnt = 0;  // passes listed so far (uniform)
+      for (int o0 = 1; o0 <= P; o0 += 64) {
+        const int o = o0 + lane;
+        const bool valid = o <= P;
+        const int j = partner(valid ? o : 1);
+        const unsigned cj = code[j];
+        const bool vert = valid && cj == kCodeVertical;
+        const bool force = valid && cj == kCodeFP64;
+        const bool test = valid && cj > kCodePass;
+        const bool pass = test && bins_pass(bins[cj], pall, h);
+        const unsigned long long mf = __ballot(force), mp = __ballot(pass);
+        n_vert += __popcll(__ballot(vert));
+        n_forced += __popcll(mf);
+        n_pass += __popcll(mp);
+        if (mf) {
+          unsigned base = 0;
+          if (lane == 0) {
+            const unsigned now = __hip_atomic_load(&state->n_entries, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+            base = now >= (unsigned)cap ? (unsigned)cap
+                                        : atomicAdd(&state->n_entries, (unsigned)__popcll(mf));
+          }
+          base = __shfl(base, 0);
+          if (force) {
+            const unsigned idx = base + (unsigned)__popcll(mf & ((1ull << lane) - 1ull));
+            if (idx < (unsigned)cap) {
+              entries[idx] = make_uint2((unsigned)b, pack_pair(min(i, j), max(i, j)));
+            } else {
+              atomicOr(&state->overflow, 1u);
+              atomicOr(&meta[b].overflow, 1u);
+            }
+          }
+        }
+        if (pass) list[cnt + __popcll(mp & ((1ull << lane) - 1ull))] = (unsigned short)(o - 1);
+        cnt += (unsigned)__popcll(mp);
+      }
+      if (lane == 0) {
+        if (n_vert) atomicAdd(&meta[b].vertical, n_vert);
+        if (n_forced) atomicAdd(&meta[b].survivors, n_forced);
+        if (n_pass) atomicAdd(&meta[b].bin_pass, n_pass);
+      }
+      if (cnt) {
+        wave_fence();  // the list entries are written
+        if (w_end - w_next < cnt) {  // mark the rest unused, reserve more
+          for (unsigned q2 = w_next + lane; q2 < w_end; q2 += 64u)
+            cands[q2] = make_uint2(kNoProblem, 0u);
+          const unsigned want = cnt > kWaveReserve ? cnt : kWaveReserve;
+          unsigned got = 0;
+          if (lane == 0) {
+            const unsigned now = __hip_atomic_load(&state->n_cands[cls], __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+            got = now >= (unsigned)cand_cap ? (unsigned)cand_cap
+                                            : atomicAdd(&state->n_cands[cls], want);
+          }
+          got = __shfl(got, 0);
+          w_next = got;
+          w_end = got >= (unsigned)cand_cap ? got : min(got + want, (unsigned)cand_cap);
+          if (w_end - w_next < cnt && lane == 0) atomicOr(&state->cand_overflow, 1u << cls);
+        }
+        const unsigned room = w_end - w_next;
+        for (unsigned q2 = lane; q2 < cnt && q2 < room; q2 += 64u) {
+          int j = i + 1 + (int)list[q2];
+          if (j >= n) j -= n;
+          cands[w_next + q2] = make_uint2((unsigned)b, (unsigned)i | ((unsigned)j << 16));
+        }
+        w_next += min(cnt, room);
+      }
     }
   }
   for (unsigned q = w_next + lane; q < w_end; q += 64u) cands[q] = make_uint2(kNoProblem, 0u);
