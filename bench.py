@@ -46,13 +46,37 @@ LDS_INST_PEAK = 256 * 2.4e9
 COUNTERS = os.path.join(ROOT, "profiles", "counters.json")
 
 
+def kernel_source_sha():
+    """SHA-256 of the HIP sources (csrc/*.hip, *.h in name order): the
+    counters in profiles/counters.json hold only for the sources they were
+    taken from."""
+    import hashlib
+    d = os.path.join(ROOT, "paper_1510_01041_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".h")):
+            h.update(f.encode())
+            h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()
+
+
+def _counters():
+    """The committed counter summary, or None if absent or taken from other
+    kernel sources than these."""
+    if not os.path.exists(COUNTERS):
+        return None
+    c = json.load(open(COUNTERS))
+    return c if c.get("source_sha256") == kernel_source_sha() else None
+
+
 def issued(kernel, workload, ms):
     """Issued-VALU and LDS fractions of a kernel: its per-launch instruction
     counts (rocprofv3 --pmc, committed under profiles/) over the launch time
-    measured here. Counts are per launch of this workload; None if absent."""
-    if not os.path.exists(COUNTERS):
-        return None
-    c = json.load(open(COUNTERS)).get(kernel, {}).get(workload)
+    measured here, and its HBM traffic per launch (FETCH_SIZE and WRITE_SIZE
+    scaled by what they read for a plain copy of known size). None if the
+    counters are absent or stale."""
+    cs = _counters()
+    c = cs and cs["kernels"].get(kernel, {}).get(workload)
     if not c or not ms:
         return None
     t = ms * 1e-3
@@ -61,13 +85,29 @@ def issued(kernel, workload, ms):
         out["valu_lane_ops_per_s"] = c["SQ_INSTS_VALU"] * 64 / t
         out["valu_frac"] = c["SQ_INSTS_VALU"] * 64 / t / VALU_PEAK_LANE_OPS
     if "SQ_INSTS_LDS" in c:
-        # one LDS instruction per wavefront moves up to 64 lanes x 4 bytes
+        # one LDS instruction per CU per clock
         out["lds_insts_per_s"] = c["SQ_INSTS_LDS"] / t
         out["lds_frac_of_issue"] = c["SQ_INSTS_LDS"] / t / (LDS_INST_PEAK)
     if "SQ_LDS_BANK_CONFLICT" in c and "SQ_INSTS_LDS" in c:
         out["bank_conflict_cycles_per_lds_inst"] = c["SQ_LDS_BANK_CONFLICT"] / max(
             c["SQ_INSTS_LDS"], 1)
+    if "SQ_ACTIVE_INST_VALU" in c and "SQ_BUSY_CYCLES" in c:
+        out["valu_active_per_busy_cycle"] = c["SQ_ACTIVE_INST_VALU"] / max(c["SQ_BUSY_CYCLES"], 1)
+    tr = traffic(kernel, workload)
+    if tr is not None:
+        out["hbm_bytes_per_launch"] = tr
+        out["hbm_gb_per_s"] = tr / t / 1e9
     return out
+
+
+def traffic(kernel, workload):
+    """HBM bytes per launch from the counter summary (None if absent)."""
+    cs = _counters()
+    c = cs and cs["kernels"].get(kernel, {}).get(workload)
+    cal = cs and cs.get("copy")
+    if not c or not cal or "FETCH_SIZE" not in c or "WRITE_SIZE" not in c:
+        return None
+    return 1024.0 * (c["FETCH_SIZE"] * cal["fetch_scale"] + c["WRITE_SIZE"] * cal["write_scale"])
 
 
 def roofline(stage_ms, n, pairs, r, workload):
@@ -88,7 +128,8 @@ def roofline(stage_ms, n, pairs, r, workload):
     achieved = ops / (ms * 1e-3)
     out = {"bound": "alu", "kernel": name, "achieved": achieved / 1e12,
            "peak": VALU_PEAK_LANE_OPS / 1e12, "unit": "T lane-op/s",
-           "frac": achieved / VALU_PEAK_LANE_OPS, "traffic": None, "ops_per_launch": ops,
+           "frac": achieved / VALU_PEAK_LANE_OPS, "traffic": traffic(name, workload),
+           "ops_per_launch": ops,
            "kernel_ms": ms,
            "kernels": {k: {"ms": v[1], "ops": v[0], "frac": v[0] / (v[1] * 1e-3) /
                            VALU_PEAK_LANE_OPS} for k, v in kernels.items()}}
@@ -112,6 +153,8 @@ def parse_args():
                     help="slope bins per anchor, 2^k (0 = automatic, -1 = no slope-bin screen)")
     ap.add_argument("--seed-pairs", type=int, default=None,
                     help="random seed pairs of a single solve (default: the library's)")
+    ap.add_argument("--slope-range", choices=["auto", "on", "off"], default="auto",
+                    help="slope-range pruning before the slope-bin screen (auto: the library's)")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the seeding comparison")
     ap.add_argument("--no-extra", action="store_true",
@@ -261,7 +304,8 @@ def main():
         return
 
     seed = gen.CONFIGS[args.workload]["seeds"][0] if args.seed is None else args.seed
-    kw = dict(tile_regs=args.tile_regs, bins_log2=args.bins_log2, seed_pairs=args.seed_pairs)
+    kw = dict(tile_regs=args.tile_regs, bins_log2=args.bins_log2, seed_pairs=args.seed_pairs,
+              slope_range={"auto": None, "on": True, "off": False}[args.slope_range])
     M = measure_single(lms, args.workload, seed, args.steps, args.warmup, kw)
     r, n, cfg = M["r"], M["n"], M["cfg"]
     line = {
@@ -542,13 +586,16 @@ def bench_batched(args, steps=None, warmup=None, per_problem=True):
     kernels = {"k_bscreen_list": (OPS_BAND * int(res.point_evals.sum()) +
                                   OPS_DIR * int(res.dir_evals.sum()), stage_ms["screen"])}
     if int(res.bins.max()) > 0:
-        kernels["k_bbins"] = (int((OPS_INSERT * nb * (nb - 1) + OPS_BIN * nb * res.bins.astype(np.int64)
+        # problems up to 1024 points take the one-wavefront-per-anchor kernel
+        bname = "k_bbins_wave" if int(nb.max()) <= 1024 else "k_bbins"
+        kernels[bname] = (int((OPS_INSERT * nb * (nb - 1) + OPS_BIN * nb * res.bins.astype(np.int64)
                                    + OPS_QUERY * (nb * (nb - 1) // 2)).sum()), stage_ms["bins"])
     name = max(kernels, key=lambda k: kernels[k][1])
     ops, kms = kernels[name]
     line["roofline"] = {"bound": "alu", "kernel": name, "achieved": ops / (kms * 1e-3) / 1e12,
                         "peak": VALU_PEAK_LANE_OPS / 1e12, "unit": "T lane-op/s",
-                        "frac": ops / (kms * 1e-3) / VALU_PEAK_LANE_OPS, "traffic": None,
+                        "frac": ops / (kms * 1e-3) / VALU_PEAK_LANE_OPS,
+                        "traffic": traffic(name, "c4"),
                         "ops_per_launch": ops, "kernel_ms": kms,
                         "issued": issued(name, "c4", kms),
                         "kernels": {k: {"ms": v[1], "ops": v[0],

@@ -220,9 +220,12 @@ lms_status lms_autotune(const double* d_xy, int64_t n, int64_t h, int32_t reps, 
 /* Forgets every tuned choice of this process (solves use the defaults again;
  * a LMS_TUNE_FILE is not read again). */
 void lms_tuning_clear(void);
-/* The same for lms_solve_batched: tunes the seed pairs per problem on the
- * caller's batch (the arguments are those of lms_solve_batched), for the
- * batch's size class (next_pow2 of its largest problem). */
+/* The same for lms_solve_batched, on the caller's batch (the arguments are
+ * those of lms_solve_batched), for the batch's size class (next_pow2 of its
+ * largest problem): the random seed pairs per problem (15, 31, 63) times the
+ * bins of the per-wavefront screen of problems up to 1024 points (2^12,
+ * 2^11; out->bins_log2). A choice is kept only if every problem gets the
+ * default settings' status and width bit for bit. */
 lms_status lms_autotune_batched(const double* d_xy, const int64_t* d_offsets,
                                 const int64_t* h_offsets, int64_t B, const int32_t* d_h,
                                 lms_result* d_out, int32_t reps, void* stream, lms_tuning* out);

@@ -352,7 +352,8 @@ def tuning_clear():
 
 
 def autotune_batched(xy: torch.Tensor, offsets, h=None, reps: int = 3, stream=None) -> dict:
-    """Tune the seed pairs per problem of lms_solve_batched on this batch."""
+    """Tune lms_solve_batched on this batch: seed pairs per problem and the small
+    classes' bins (kept only if every width equals the default's)."""
     import numpy as np
     xy = _points(xy)
     off_h = np.ascontiguousarray(np.asarray(offsets.cpu() if isinstance(offsets, torch.Tensor)

@@ -103,9 +103,10 @@ __global__ __launch_bounds__(1024) void k_prep(const double* __restrict__ xy, in
                                                uint2* __restrict__ entries, int n_seeds,
                                                int n_random, unsigned long long seed_key,
                                                unsigned bins, int cap) {
-  __shared__ double s_mn[1024], s_mx[1024], s_my[1024], s_My[1024];
-  __shared__ int s_amn[1024], s_amx[1024], s_fin[1024];
-  const int t = threadIdx.x;
+  // extremes by wavefront (shuffles), then across the 16 wavefronts (LDS)
+  __shared__ double s_mn[16], s_mx[16], s_my[16], s_My[16];
+  __shared__ int s_amn[16], s_amx[16], s_fin[16];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   double mnx = INFINITY, mxx = -INFINITY, mny = INFINITY, mxy = -INFINITY;
   int amn = INT_MAX, amx = INT_MAX, fin = 1;
   for (int k = t; k < n; k += blockDim.x) {
@@ -116,24 +117,33 @@ __global__ __launch_bounds__(1024) void k_prep(const double* __restrict__ xy, in
     mny = fmin(mny, y);
     mxy = fmax(mxy, y);
   }
-  s_mn[t] = mnx; s_mx[t] = mxx; s_my[t] = mny; s_My[t] = mxy;
-  s_amn[t] = amn; s_amx[t] = amx; s_fin[t] = fin;
-  __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if (t < s) {
-      const int u = t + s;
-      if (s_mn[u] < s_mn[t] || (s_mn[u] == s_mn[t] && s_amn[u] < s_amn[t])) {
-        s_mn[t] = s_mn[u]; s_amn[t] = s_amn[u];
-      }
-      if (s_mx[u] > s_mx[t] || (s_mx[u] == s_mx[t] && s_amx[u] < s_amx[t])) {
-        s_mx[t] = s_mx[u]; s_amx[t] = s_amx[u];
-      }
-      s_my[t] = fmin(s_my[t], s_my[u]);
-      s_My[t] = fmax(s_My[t], s_My[u]);
-      s_fin[t] &= s_fin[u];
-    }
-    __syncthreads();
+  // the smaller x (the lower index among equal ones), the larger x (the
+  // lower index among equal ones), the y extremes and the finiteness flag
+  auto merge = [&](double mn2, int amn2, double mx2, int amx2, double my2, double My2,
+                   int fin2) {
+    if (mn2 < mnx || (mn2 == mnx && amn2 < amn)) { mnx = mn2; amn = amn2; }
+    if (mx2 > mxx || (mx2 == mxx && amx2 < amx)) { mxx = mx2; amx = amx2; }
+    mny = fmin(mny, my2);
+    mxy = fmax(mxy, My2);
+    fin &= fin2;
+  };
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1)
+    merge(__shfl_xor(mnx, m), __shfl_xor(amn, m), __shfl_xor(mxx, m), __shfl_xor(amx, m),
+          __shfl_xor(mny, m), __shfl_xor(mxy, m), __shfl_xor(fin, m));
+  if (lane == 0) {
+    s_mn[wv] = mnx; s_mx[wv] = mxx; s_my[wv] = mny; s_My[wv] = mxy;
+    s_amn[wv] = amn; s_amx[wv] = amx; s_fin[wv] = fin;
   }
+  __syncthreads();
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w)
+    merge(s_mn[w], s_amn[w], s_mx[w], s_amx[w], s_my[w], s_My[w], s_fin[w]);
+  __syncthreads();
+  if (t == 0) {
+    s_mn[0] = mnx; s_mx[0] = mxx; s_my[0] = mny; s_My[0] = mxy;
+    s_amn[0] = amn; s_amx[0] = amx; s_fin[0] = fin;
+  }
+  __syncthreads();
   const bool finite = s_fin[0] != 0;
   const double minx = s_mn[0], maxx = s_mx[0], miny = s_my[0], maxy = s_My[0];
   const double cx = minx + 0.5 * (maxx - minx), cy = miny + 0.5 * (maxy - miny);
@@ -1089,7 +1099,7 @@ __global__ __launch_bounds__(NT, 3) void k_screen(
 // and of the partner's slope), so a bin's count is never below the exact count of any slope in
 // it. Pairs whose bound reaches h are listed for the FP32 test.
 
-template <int NB, int NT>
+template <int NB, int NT, bool WIDE>
 __global__ __launch_bounds__(NT) void k_bins(const double* __restrict__ xy, Ctx* ctx,
                                              uint2* __restrict__ cands, int cand_cap,
                                              uint2* __restrict__ entries, int cap,
@@ -1104,14 +1114,16 @@ __global__ __launch_bounds__(NT) void k_bins(const double* __restrict__ xy, Ctx*
   // (add_point_bins_coded) and the queries only read it. Larger bin arrays
   // leave no LDS for the codes: the queries compute the pair's bin
   // themselves. Either way the queries list the passing partners' offsets.
-  constexpr bool CODED = NB <= 16384;
+  // WIDE: for sets of more than NB / 2 points (fewer bins than 2 n, so more
+  // workgroups fit a CU); no codes then.
+  constexpr bool CODED = NB <= 16384 && !WIDE;
   // point loads in flight in the insertion loop (latency: the largest bin
   // arrays leave the fewest wavefronts per CU)
   constexpr int kPF = NB >= 32768 ? 3 : 2;
   __shared__ unsigned bins[NBINS + 1];
   // codes of the n <= NB / 2 points (CODED), or partner offsets o - 1 that
   // pass (P(i) <= n / 2 <= LMS_MAX_N / 2)
-  __shared__ unsigned short list[NB / 2 < LMS_MAX_N / 2 ? NB / 2 : LMS_MAX_N / 2];
+  __shared__ unsigned short list[WIDE || NB / 2 >= LMS_MAX_N / 2 ? LMS_MAX_N / 2 : NB / 2];
   // CODED: the partner offsets o - 1 that pass (P(i) <= n / 2 <= NB / 4)
   __shared__ unsigned short plist[CODED ? NB / 4 : 1];
   // passes of the block's anchors so far, written out together (one
@@ -1185,10 +1197,10 @@ __global__ __launch_bounds__(NT) void k_bins(const double* __restrict__ xy, Ctx*
         const int k = k0 + q * NT;
         if (k < n) {
           if (CODED)
-            all += add_point_bins_coded<kRLog>(bins, cur[q].x - xi, cur[q].y - yi, W, lim, F,
-                                               th_lim, &list[k]);
+            add_point_bins_coded<kRLog>(bins, cur[q].x - xi, cur[q].y - yi, W, lim, F, th_lim,
+                                        &list[k], all);
           else
-            all += add_point_bins<kRLog>(bins, cur[q].x - xi, cur[q].y - yi, W, lim, F);
+            add_point_bins<kRLog>(bins, cur[q].x - xi, cur[q].y - yi, W, lim, F, all);
         }
       }
 #pragma unroll
@@ -1405,8 +1417,8 @@ __global__ __launch_bounds__(NT) void k_bins_pruned(const double* __restrict__ x
       const double2 cur = nxt;
       if (p + NT < len) nxt = rxy[p + NT];
       pidx[p] = (unsigned short)run[p];
-      all += add_point_bins_coded<kRLogP>(bins, cur.x - xi, cur.y - yi, W, lim, FP, th_lim,
-                                          &pcode[p]);
+      add_point_bins_coded<kRLogP>(bins, cur.x - xi, cur.y - yi, W, lim, FP, th_lim, &pcode[p],
+                                   all);
     }
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1) all += __shfl_xor(all, m);
@@ -1928,7 +1940,7 @@ constexpr int bins_threads() {
   return NB >= 32768 ? 1024 : (NB >= 8192 ? 512 : 256);
 }
 
-template <int NB>
+template <int NB, bool WIDE>
 hipError_t launch_bins_nb(hipStream_t s, int cu, int n, const double* xy, Ctx* ctx, uint2* cands,
                           int cand_cap, uint2* e, int cap, const double4* res,
                           const double4* rec, int n_rec) {
@@ -1936,16 +1948,16 @@ hipError_t launch_bins_nb(hipStream_t s, int cu, int n, const double* xy, Ctx* c
   static int resident = 0;
   if (resident == 0) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)k_bins<NB, nt>, nt, 0) !=
-            hipSuccess || nb < 1) {
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)k_bins<NB, nt, WIDE>, nt,
+                                                     0) != hipSuccess || nb < 1) {
       (void)hipGetLastError();
       nb = 1;
     }
     resident = nb;
   }
   const int grid = std::max(1, std::min(n, cu * resident));
-  hipLaunchKernelGGL((k_bins<NB, nt>), dim3(grid), dim3(nt), 0, s, xy, ctx, cands, cand_cap, e,
-                     cap, res, rec, rec ? n_rec : 0);
+  hipLaunchKernelGGL((k_bins<NB, nt, WIDE>), dim3(grid), dim3(nt), 0, s, xy, ctx, cands, cand_cap,
+                     e, cap, res, rec, rec ? n_rec : 0);
   return hipGetLastError();
 }
 
@@ -1977,12 +1989,18 @@ hipError_t launch_bins(hipStream_t s, int nb_log2, int cu, int n, const double* 
   // the full screen, then (with a slope range; each kernel returns at once
   // when the other one's case holds) the pruned one
   hipError_t err;
-  switch (nb_log2) {
-    case 11: err = launch_bins_nb<2048>(s, cu, n, xy, ctx, cands, cand_cap, e, cap, res, rec, n_rec); break;
-    case 12: err = launch_bins_nb<4096>(s, cu, n, xy, ctx, cands, cand_cap, e, cap, res, rec, n_rec); break;
-    case 13: err = launch_bins_nb<8192>(s, cu, n, xy, ctx, cands, cand_cap, e, cap, res, rec, n_rec); break;
-    case 14: err = launch_bins_nb<16384>(s, cu, n, xy, ctx, cands, cand_cap, e, cap, res, rec, n_rec); break;
-    default: err = launch_bins_nb<32768>(s, cu, n, xy, ctx, cands, cand_cap, e, cap, res, rec, n_rec); break;
+  // fewer bins than 2 n: the WIDE form (no codes, room for n / 2 passes)
+  const bool wide = (1 << nb_log2) < 2 * n;
+  switch (nb_log2 * 2 + (wide ? 1 : 0)) {
+    case 22: err = launch_bins_nb<2048, false>(s, cu, n, xy, ctx, cands, cand_cap, e, cap, res, rec, n_rec); break;
+    case 23: err = launch_bins_nb<2048, true>(s, cu, n, xy, ctx, cands, cand_cap, e, cap, res, rec, n_rec); break;
+    case 24: err = launch_bins_nb<4096, false>(s, cu, n, xy, ctx, cands, cand_cap, e, cap, res, rec, n_rec); break;
+    case 25: err = launch_bins_nb<4096, true>(s, cu, n, xy, ctx, cands, cand_cap, e, cap, res, rec, n_rec); break;
+    case 26: err = launch_bins_nb<8192, false>(s, cu, n, xy, ctx, cands, cand_cap, e, cap, res, rec, n_rec); break;
+    case 27: err = launch_bins_nb<8192, true>(s, cu, n, xy, ctx, cands, cand_cap, e, cap, res, rec, n_rec); break;
+    case 28: err = launch_bins_nb<16384, false>(s, cu, n, xy, ctx, cands, cand_cap, e, cap, res, rec, n_rec); break;
+    case 29: err = launch_bins_nb<16384, true>(s, cu, n, xy, ctx, cands, cand_cap, e, cap, res, rec, n_rec); break;
+    default: err = launch_bins_nb<32768, false>(s, cu, n, xy, ctx, cands, cand_cap, e, cap, res, rec, n_rec); break;
   }
   if (err != hipSuccess || !live) return err;
   const int nb_full = 1 << nb_log2;
@@ -2054,9 +2072,13 @@ unsigned bins_count(int nb_log2) {
   return (unsigned)(nb + (nb >= 32768 ? 1024 : (nb >= 8192 ? 512 : 256)));
 }
 
+// 2 n bins up to 4096 points (codes in LDS); above, 2^13 in the WIDE form:
+// at 16384 points it keeps two workgroups per CU where 2^15 bins keep one,
+// and its full screen took 0.80 ms against 1.03 ms (integer set, 16384
+// points, MI355X).
 int default_bins_log2(int n) {
   int b = 11;
-  while (b < 15 && (1 << b) < 2 * n) ++b;
+  while (b < 13 && (1 << b) < 2 * n) ++b;
   return b;
 }
 
@@ -2164,7 +2186,6 @@ lms_status make_setup(const double* d_xy, int64_t n, int64_t h, lms_result* d_ou
   const bool use_bins = bins_log2 != -1;
   if (use_bins) {
     if (bins_log2 == 0) bins_log2 = default_bins_log2(p.n);
-    while (bins_log2 < 15 && (1 << bins_log2) < 2 * p.n) ++bins_log2;
   }
   const int Pmax = p.n / 2;
   const int batches = (Pmax + 63) / 64;
@@ -2600,8 +2621,9 @@ lms_status lms_autotune(const double* d_xy, int64_t n, int64_t h, int32_t reps, 
   // explicit defaults, so that a table entry from an earlier tuning does not
   // leak into the candidates
   lms_tuning best{pick_R((int)n), 4, kDefaultSeeds, default_bins_log2((int)n), 1e30, 0, 0};
+  // bins per anchor down to n / 2 (below 2 n the screen takes its WIDE form)
   int min_bins = 11;
-  while (min_bins < 15 && (1 << min_bins) < 2 * n) ++min_bins;
+  while (min_bins < 15 && (1 << min_bins) < n / 2) ++min_bins;
   best.bins_log2 = std::max(best.bins_log2, min_bins);
   // 1. the screen's bins, the slope range and the seeds
   static const int kSeedsC[] = {kDefaultSeeds, 63};

@@ -213,7 +213,8 @@ template <int N2, int NT>
 __device__ __forceinline__ void sort_regs(double (&v)[N2 / NT], double* z) {
   constexpr int E = N2 / NT;
   static_assert(N2 % NT == 0 && NT % 64 == 0, "block must tile the sort");
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  // NT = 64: one wavefront sorts on its own (any wavefront of the block)
+  const int t = threadIdx.x, lane = t & 63, wave = NT == 64 ? 0 : t >> 6;
 #pragma unroll
   for (int k = 2; k <= N2; k <<= 1) {
 #pragma unroll
@@ -413,16 +414,21 @@ __device__ __forceinline__ int slope_bin(double dx, double dy, double r, const B
 // computed bin (ends here, a pair's slope_bin) is within one of the exact
 // map's bin, so the two-bin margins keep every exact slope of an interval
 // inside the bins it adds to. A point outside the check's range, or with
-// Dx = 0 and in a window, is counted in that window at every slope (returned
-// packed: 1 = upper window, 65536 = lower window), which can only raise the
-// bounds.
+// Dx = 0 and in a window, is counted in that window at every slope (added to
+// `all`, packed: 1 = upper window, 65536 = lower window), which can only
+// raise the bounds. Only those rare cases touch `all`.
 template <int RLOG>
-__device__ __forceinline__ unsigned add_point_bins(unsigned* bins, double dx, double dy, double W,
-                                                   double lim, const BinFrame& F) {
+__device__ __forceinline__ void add_point_bins(unsigned* bins, double dx, double dy, double W,
+                                               double lim, const BinFrame& F, unsigned& all) {
   const double adx = fabs(dx), ady = fabs(dy);
-  if (dx == 0.0)
-    return (dy >= 0.0 && dy <= lim ? 1u : 0u) + (dy <= 0.0 && dy >= -lim ? 65536u : 0u);
-  if (!(adx >= fma(ady, F.q, 0x1p-900)) || adx > 0x1p900) return 1u + 65536u;
+  if (dx == 0.0) {
+    all += (dy >= 0.0 && dy <= lim ? 1u : 0u) + (dy <= 0.0 && dy >= -lim ? 65536u : 0u);
+    return;
+  }
+  if (!(adx >= fma(ady, F.q, 0x1p-900)) || adx > 0x1p900) {
+    all += 1u + 65536u;
+    return;
+  }
   const double s = F.sc * recip(dx);
   const double a = fma(-F.tc, dx, dy);
   const int b0 = fbin<RLOG>((a - W) * s), b1 = fbin<RLOG>(a * s), b2 = fbin<RLOG>((a + W) * s);
@@ -431,7 +437,6 @@ __device__ __forceinline__ unsigned add_point_bins(unsigned* bins, double dx, do
   atomicAdd(&bins[max(b0, b1) + 3], 0xFFFFFFFFu);
   atomicAdd(&bins[min(b1, b2) - 2], 65536u);
   atomicAdd(&bins[max(b1, b2) + 3], 0xFFFF0000u);
-  return 0u;
 }
 
 // add_point_bins, and the point's code for the queries of this anchor's
@@ -442,30 +447,35 @@ __device__ __forceinline__ unsigned add_point_bins(unsigned* bins, double dx, do
 // of the exact bin whatever the far-point check says.
 constexpr unsigned short kCodeVertical = 0, kCodeFP64 = 1, kCodePass = 2;
 template <int RLOG>
-__device__ __forceinline__ unsigned add_point_bins_coded(unsigned* bins, double dx, double dy,
-                                                         double W, double lim, const BinFrame& F,
-                                                         double th_lim, unsigned short* code) {
+__device__ __forceinline__ void add_point_bins_coded(unsigned* bins, double dx, double dy,
+                                                     double W, double lim, const BinFrame& F,
+                                                     double th_lim, unsigned short* code,
+                                                     unsigned& all) {
   const double adx = fabs(dx), ady = fabs(dy);
   if (dx == 0.0) {
     *code = kCodeVertical;
-    return (dy >= 0.0 && dy <= lim ? 1u : 0u) + (dy <= 0.0 && dy >= -lim ? 65536u : 0u);
+    all += (dy >= 0.0 && dy <= lim ? 1u : 0u) + (dy <= 0.0 && dy >= -lim ? 65536u : 0u);
+    return;
   }
   if (!(adx >= 0x1p-900) || adx > 0x1p900) {
     *code = kCodeFP64;
-    return 1u + 65536u;
+    all += 1u + 65536u;
+    return;
   }
   const double r = recip(dx);
   const double s = F.sc * r;
   const double a = fma(-F.tc, dx, dy);
   const int b1 = fbin<RLOG>(a * s);
   *code = fabs(dy * r) < th_lim ? (unsigned short)b1 : kCodeFP64;
-  if (!(adx >= fma(ady, F.q, 0x1p-900))) return 1u + 65536u;
+  if (!(adx >= fma(ady, F.q, 0x1p-900))) {
+    all += 1u + 65536u;
+    return;
+  }
   const int b0 = fbin<RLOG>((a - W) * s), b2 = fbin<RLOG>((a + W) * s);
   atomicAdd(&bins[min(b0, b1) - 2], 1u);
   atomicAdd(&bins[max(b0, b1) + 3], 0xFFFFFFFFu);
   atomicAdd(&bins[min(b1, b2) - 2], 65536u);
   atomicAdd(&bins[max(b1, b2) + 3], 0xFFFF0000u);
-  return 0u;
 }
 
 // Slope of the narrowest of the candidate windows (width, theta, z_lo, z_hi)

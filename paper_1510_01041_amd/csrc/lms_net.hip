@@ -21,6 +21,7 @@
 #include <string>
 
 #include "lms.h"
+#include "lms_device.h"
 #include "lms_host.h"
 
 namespace {
@@ -101,66 +102,90 @@ __device__ __forceinline__ int wave_min_i(int v) {
 // Frame of set b: per coordinate the lower median of a fixed sample of its
 // points (all of them up to kFrameSample, else indices floor(k n /
 // kFrameSample)), and as scale the lower median of the absolute deviations
-// from it (the MAD), else the largest deviation, else 1. Ranks among equal
-// values follow the sample order. Called by all NT threads; every thread
-// gets (cx, cy, sx, sy).
+// from it (the MAD), else the largest deviation, else 1. The sample is
+// sorted in LDS (a value of given rank does not depend on how equal values
+// are ordered). Called by all NT threads; every thread gets (cx, cy, sx, sy).
 constexpr int kFrameSample = 255;
 static_assert(kFrameSample <= NT, "one sample value per thread");
 
+// Ascending bitonic sort of 256 doubles in LDS by one wavefront (two pairs
+// per lane per stage). A wavefront's LDS operations execute in order, so a
+// stage sees the previous one's writes; the fence only keeps the compiler
+// from reordering them.
+__device__ void wave_sort256(double* a) {
+  const int lane = threadIdx.x & 63;
+  for (int k = 2; k <= 256; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int pidx = lane + 64 * q;
+        const int lo = 2 * pidx - (pidx & (j - 1)), hi = lo + j;
+        const bool up = (lo & k) == 0;
+        const double x = a[lo], y = a[hi];
+        if ((x > y) == up) {
+          a[lo] = y;
+          a[hi] = x;
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+    }
+  }
+}
+
+// set_frame: wavefront 0 takes x, wavefront 1 takes y, each on its own LDS
+// array: sort the sample values, read the median (a value, so the order of
+// equal values does not matter), then sort the absolute deviations from it
+// and read their median and largest value. One block barrier at the end.
 __device__ double4 set_frame(const double* __restrict__ xy, int64_t o, int64_t n) {
-  __shared__ double sv[2][NT];
-  __shared__ double s_c[2], s_s[2], s_max[2];
-  const int t = threadIdx.x;
+  static_assert(NT >= 128 && kFrameSample < 256, "two wavefronts, 256 slots");
+  __shared__ double sv[2][256];
+  __shared__ double s_out[6];  // medians x, y; MADs x, y; largest deviations x, y
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const int m = n < kFrameSample ? (int)n : kFrameSample;
   const int target = m > 0 ? (m - 1) / 2 : 0;
-  if (t < m) {
-    const int64_t k = n <= kFrameSample ? t : ((int64_t)t * n) / kFrameSample;
-    sv[0][t] = xy[2 * (o + k)];
-    sv[1][t] = xy[2 * (o + k) + 1];
-  }
-  if (t < 2) {
-    s_c[t] = 0.0;
-    s_s[t] = 0.0;
-    s_max[t] = 0.0;
-  }
-  __syncthreads();
-  // the value of rank `target` (ties by sample index), per coordinate
-  auto select = [&](double* out, double* top) {
-    for (int a = 0; a < 2; ++a) {
-      if (t < m) {
-        const double v = sv[a][t];
-        int r = 0;
-        for (int u = 0; u < m; ++u) {
-          const double w = sv[a][u];
-          r += (w < v) || (w == v && u < t);
-        }
-        if (r == target) out[a] = v;
-        if (top && r == m - 1) top[a] = v;
+  if (wv < 2) {
+    double* a = sv[wv];
+    double orig[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int v = r * 64 + lane;
+      double val = INFINITY;
+      if (v < m) {
+        const int64_t q = n <= kFrameSample ? v : ((int64_t)v * n) / kFrameSample;
+        val = xy[2 * (o + q) + wv];
       }
+      orig[r] = val;
+      a[v] = val;
     }
-  };
-  select(s_c, nullptr);
-  __syncthreads();
-  double dev0 = 0.0, dev1 = 0.0;
-  if (t < m) {
-    dev0 = fabs(sv[0][t] - s_c[0]);
-    dev1 = fabs(sv[1][t] - s_c[1]);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    wave_sort256(a);
+    const double c = m > 0 ? a[target] : 0.0;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int v = r * 64 + lane;
+      a[v] = v < m ? fabs(orig[r] - c) : INFINITY;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    wave_sort256(a);
+    if (lane == 0) {
+      s_out[wv] = c;
+      s_out[2 + wv] = m > 0 ? a[target] : 0.0;
+      s_out[4 + wv] = m > 0 ? a[m - 1] : 0.0;
+    }
   }
   __syncthreads();
-  if (t < m) {
-    sv[0][t] = dev0;
-    sv[1][t] = dev1;
-  }
-  __syncthreads();
-  select(s_s, s_max);
-  __syncthreads();
-  double sx = s_s[0], sy = s_s[1];
-  if (!(sx > 0)) sx = s_max[0];
+  double sx = s_out[2], sy = s_out[3];
+  if (!(sx > 0)) sx = s_out[4];
   if (!(sx > 0)) sx = 1.0;
-  if (!(sy > 0)) sy = s_max[1];
+  if (!(sy > 0)) sy = s_out[5];
   if (!(sy > 0)) sy = 1.0;
-  const double4 f = make_double4(s_c[0], s_c[1], sx, sy);
-  __syncthreads();  // the shared arrays are reused by the next call
+  const double4 f = make_double4(s_out[0], s_out[1], sx, sy);
+  __syncthreads();  // the shared values are reused by the next call
   return f;
 }
 
@@ -241,13 +266,39 @@ __global__ __launch_bounds__(NT) void k_net_forward(const float* __restrict__ P,
 // patterns), and the head runs once g is complete. The result equals
 // k_net_forward's bit for bit. A set of more than max_points points is read
 // at max_points evenly strided indices floor(j n / max_points).
-constexpr int kPoolPoints = 512;  // points per workgroup of the pool kernel
+// Inference spreads each set over many workgroups: the frame kernel finds
+// the set's frame (set_frame), the pool kernel gives every workgroup
+// kPoolPoints points (one per lane) and each of its NT / 64 wavefronts a
+// quarter of the channels.
+constexpr int NTF = 256;
+constexpr int kPoolPoints = 64;
+constexpr int kPoolChannels = H / (NT / 64);
 
-__global__ __launch_bounds__(NT) void k_net_frame(const double* __restrict__ xy,
-                                                  const int64_t* __restrict__ off,
-                                                  int64_t n_single, double* __restrict__ scale,
-                                                  unsigned* __restrict__ g) {
+// The point MLP's weights as the pool kernel reads them, written by the
+// frame kernel's block 0 from the FP32 masters: W1 rounded to BF16 (as FP32),
+// b1, b2, then W2 as BF16 pairs (the PointMLP layout). The pool kernel reads
+// them with wave-uniform addresses, so they come through the scalar cache.
+constexpr int WPK_W1 = 0, WPK_B1 = WPK_W1 + 2 * H, WPK_B2 = WPK_B1 + H, WPK_W2 = WPK_B2 + H,
+              WPK_WORDS = WPK_W2 + H * H / 2;
+
+__global__ __launch_bounds__(NTF) void k_net_frame(const float* __restrict__ P,
+                                                   const double* __restrict__ xy,
+                                                   const int64_t* __restrict__ off,
+                                                   int64_t n_single, double* __restrict__ scale,
+                                                   unsigned* __restrict__ g,
+                                                   unsigned* __restrict__ wpk) {
   const int b = blockIdx.x, t = threadIdx.x;
+  // the wavefronts that set_frame leaves idle pack the weights meanwhile
+  if (b == 0 && t >= 128) {
+    const int u = t - 128, nu = NTF - 128;
+    for (int i = u; i < 2 * H; i += nu) wpk[WPK_W1 + i] = __float_as_uint(bf16_round(P[OFF_W1 + i]));
+    for (int i = u; i < H; i += nu) {
+      wpk[WPK_B1 + i] = __float_as_uint(P[OFF_B1 + i]);
+      wpk[WPK_B2 + i] = __float_as_uint(P[OFF_B2 + i]);
+    }
+    for (int i = u; i < H * H / 2; i += nu)
+      wpk[WPK_W2 + i] = pack2(P[OFF_W2 + 2 * i], P[OFF_W2 + 2 * i + 1]);
+  }
   const int64_t o = off ? off[b] : 0, n = off ? off[b + 1] - off[b] : n_single;
   const double4 f = set_frame(xy, o, n);
   if (t == 0) {
@@ -256,65 +307,118 @@ __global__ __launch_bounds__(NT) void k_net_frame(const double* __restrict__ xy,
   if (t < H) g[(size_t)b * H + t] = 0u;
 }
 
-__global__ __launch_bounds__(NT) void k_net_pool(const float* __restrict__ P,
+// Lane = point, wavefront = a quarter of the channels: layer 1 (each
+// wavefront computes it for its 64 points), then its channels of layer 2
+// (the same products in the same order as layer1/layer2) and their ReLU; the
+// channel maxima over the wavefront by a halving exchange (each step keeps
+// half of a lane's channels and takes the partner lane's values for them:
+// 8 + 4 + 2 + 1 + 1 + 1 shuffles for 16 channels); the workgroup's maxima
+// merge into g. The workgroup copies the packed weights to LDS first (one
+// global latency), and the wavefronts read them as broadcasts.
+__global__ __launch_bounds__(NT) void k_net_pool(const unsigned* __restrict__ wpk,
                                                  const double* __restrict__ xy,
                                                  const int64_t* __restrict__ off, int64_t n_single,
                                                  int max_points, const double* __restrict__ scale,
                                                  unsigned* __restrict__ g) {
-  __shared__ PointMLP s;
-  __shared__ float s_max[NT / 64][H];
+  static_assert(kPoolChannels == 16, "four halving steps");
+  static_assert(WPK_WORDS % 4 == 0, "uint4 copy");
+  __shared__ float s_max[H];
+  __shared__ uint4 s_w[WPK_WORDS / 4];  // the packed weights, one copy per workgroup
   const int b = blockIdx.y, t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const int64_t o = off ? off[b] : 0, n = off ? off[b + 1] - off[b] : n_single;
   const int64_t m = n < max_points ? n : max_points;
   const int64_t j0 = (int64_t)blockIdx.x * kPoolPoints;
   if (j0 >= m) return;  // uniform over the block
-  load_point_mlp(P, s);
+  // the point's load, then the weights' (all in flight together), one wait
+  const int64_t j = j0 + lane;
+  const bool live = j < m;
+  const int64_t k = n <= max_points ? j : (j * n) / max_points;
+  const double2 pt = live ? reinterpret_cast<const double2*>(xy)[o + k] : make_double2(0.0, 0.0);
+  const uint4* wsrc = reinterpret_cast<const uint4*>(wpk);
+  for (int e = t; e < WPK_WORDS / 4; e += NT) s_w[e] = wsrc[e];
+  __syncthreads();
   const double4 f = make_double4(scale[4 * b], scale[4 * b + 1], scale[4 * b + 2], scale[4 * b + 3]);
-  float run[H];
+  const float2 p = make_float2((float)((pt.x - f.x) / f.z), (float)((pt.y - f.y) / f.w));
+  const unsigned* sw = reinterpret_cast<const unsigned*>(s_w);
+  const float* w1 = reinterpret_cast<const float*>(sw + WPK_W1);
+  const float* b1 = reinterpret_cast<const float*>(sw + WPK_B1);
+  unsigned h1[H / 2];
 #pragma unroll
-  for (int c = 0; c < H; ++c) run[c] = 0.0f;
-  const int64_t j1 = j0 + kPoolPoints < m ? j0 + kPoolPoints : m;
-  for (int64_t j = j0 + t; j < j1; j += NT) {
-    asm volatile("" ::: "memory");
-    const int64_t k = n <= max_points ? j : (j * n) / max_points;
-    const float2 p = to_frame(xy, o + k, f);
-    unsigned h1[H / 2];
-    layer1(s, p.x, p.y, h1);
-#pragma unroll
-    for (int c = 0; c < H; ++c) run[c] = fmaxf(run[c], fmaxf(layer2(s, h1, c), 0.0f));
+  for (int q = 0; q < H / 2; ++q) {
+    const float a = fmaxf(fmaf(w1[4 * q + 1], p.y, fmaf(w1[4 * q], p.x, b1[2 * q])), 0.0f);
+    const float c = fmaxf(fmaf(w1[4 * q + 3], p.y, fmaf(w1[4 * q + 2], p.x, b1[2 * q + 1])), 0.0f);
+    h1[q] = pack2(a, c);
   }
+  const int c0 = wv * kPoolChannels;
+  const uint4* w2v = s_w + (WPK_W2 + c0 * (H / 2)) / 4;
+  const float* b2v = reinterpret_cast<const float*>(sw + WPK_B2 + c0);
+  float r[kPoolChannels];
 #pragma unroll
-  for (int c = 0; c < H; ++c) {
-    const float mx = wave_max(run[c]);
-    if (lane == 0) s_max[wv][c] = mx;
+  for (int cc = 0; cc < kPoolChannels; ++cc) {
+    uint4 w[H / 8];
+#pragma unroll
+    for (int q4 = 0; q4 < H / 8; ++q4) w[q4] = w2v[cc * (H / 8) + q4];
+    float acc = b2v[cc];
+#pragma unroll
+    for (int q4 = 0; q4 < H / 8; ++q4) {
+      acc = dot2(w[q4].x, h1[4 * q4], acc);
+      acc = dot2(w[q4].y, h1[4 * q4 + 1], acc);
+      acc = dot2(w[q4].z, h1[4 * q4 + 2], acc);
+      acc = dot2(w[q4].w, h1[4 * q4 + 3], acc);
+    }
+    // relu; a lane past the set's end contributes 0 (every h2 >= 0)
+    r[cc] = live ? fmaxf(acc, 0.0f) : 0.0f;
+  }
+  // halving exchange: after the steps with partner distance 32, 16, 8, 4,
+  // lane l holds the maximum over its group of the channel
+  // 8 b5 + 4 b4 + 2 b3 + b2 (b_k: bit k of l), then 2 and 1 finish it
+#pragma unroll
+  for (int step = 0, half = kPoolChannels / 2, d = 32; step < 4; ++step, half >>= 1, d >>= 1) {
+    const bool hi = (lane & d) != 0;
+#pragma unroll
+    for (int i = 0; i < half; ++i) {
+      const float send = hi ? r[i] : r[i + half];
+      const float keep = hi ? r[i + half] : r[i];
+      r[i] = fmaxf(keep, __shfl_xor(send, d));
+    }
+  }
+  float mx = fmaxf(r[0], __shfl_xor(r[0], 2));
+  mx = fmaxf(mx, __shfl_xor(mx, 1));
+  if ((lane & 3) == 0) {
+    const int ch = ((lane >> 5) & 1) * 8 + ((lane >> 4) & 1) * 4 + ((lane >> 3) & 1) * 2 +
+                   ((lane >> 2) & 1);
+    s_max[c0 + ch] = mx;
   }
   __syncthreads();
-  if (t < H) {
-    float mx = s_max[0][t];
-    for (int w = 1; w < NT / 64; ++w) mx = fmaxf(mx, s_max[w][t]);
-    // clear the sign bit: a -0 from the ReLU orders as +0
-    atomicMax(&g[(size_t)b * H + t], __float_as_uint(mx) & 0x7FFFFFFFu);
-  }
+  // clear the sign bit: a -0 from the ReLU orders as +0
+  if (t < H) atomicMax(&g[(size_t)b * H + t], __float_as_uint(s_max[t]) & 0x7FFFFFFFu);
 }
 
-// Head and slope of set b: out = W4 relu(W3 g + b3) + b4 (as k_net_forward),
-// theta = tan(atan2(out1, out0) / 2) sy / sx.
-__global__ __launch_bounds__(H) void k_net_head(const float* __restrict__ P,
-                                                const unsigned* __restrict__ g,
-                                                const double* __restrict__ scale,
-                                                float* __restrict__ out,
-                                                double* __restrict__ theta) {
+// Head and slope of set b: out = W4 relu(W3 g + b3) + b4 (as k_net_forward,
+// the same products in the same order), theta = tan(atan2(out1, out0) / 2)
+// sy / sx. The block first copies W3 (transposed, so that the lanes of a
+// wavefront read distinct banks) and W4 to LDS with coalesced loads.
+__global__ __launch_bounds__(NT) void k_net_head(const float* __restrict__ P,
+                                                 const unsigned* __restrict__ g,
+                                                 const double* __restrict__ scale,
+                                                 float* __restrict__ out,
+                                                 double* __restrict__ theta) {
+  __shared__ float s_w3t[H * H], s_w4[2 * H];
   __shared__ float s_g[H], s_h3[H], s_out[2];
   const int b = blockIdx.x, t = threadIdx.x;
-  s_g[t] = __uint_as_float(g[(size_t)b * H + t]);
+  for (int e = t; e < H * H; e += NT) s_w3t[(e % H) * H + e / H] = bf16_round(P[OFF_W3 + e]);
+  for (int e = t; e < 2 * H; e += NT) s_w4[e] = bf16_round(P[OFF_W4 + e]);
+  if (t < H) s_g[t] = __uint_as_float(g[(size_t)b * H + t]);
   __syncthreads();
-  float a = P[OFF_B3 + t];
-  for (int k = 0; k < H; ++k) a = fmaf(bf16_round(P[OFF_W3 + t * H + k]), s_g[k], a);
-  s_h3[t] = fmaxf(a, 0.0f);
+  if (t < H) {
+    float a = P[OFF_B3 + t];
+    for (int k = 0; k < H; ++k) a = fmaf(s_w3t[k * H + t], s_g[k], a);
+    s_h3[t] = fmaxf(a, 0.0f);
+  }
   __syncthreads();
   if (t < 2) {
     float a2 = P[OFF_B4 + t];
-    for (int k = 0; k < H; ++k) a2 = fmaf(bf16_round(P[OFF_W4 + t * H + k]), s_h3[k], a2);
+    for (int k = 0; k < H; ++k) a2 = fmaf(s_w4[t * H + k], s_h3[k], a2);
     s_out[t] = a2;
     if (out) out[2 * b + t] = a2;
   }
@@ -482,7 +586,8 @@ __global__ void k_net_slopes(const float* __restrict__ out, const double* __rest
 namespace lms_host {
 
 size_t net_infer_bytes(int64_t B) {
-  return ((size_t)B * 4 * sizeof(double) + 255 & ~size_t(255)) + (size_t)B * H * sizeof(unsigned);
+  return ((size_t)B * 4 * sizeof(double) + 255 & ~size_t(255)) +
+         ((size_t)B * H * sizeof(unsigned) + 255 & ~size_t(255)) + WPK_WORDS * sizeof(unsigned);
 }
 
 lms_status net_infer_enqueue(const float* d_params, const double* d_xy, const int64_t* d_offsets,
@@ -492,13 +597,14 @@ lms_status net_infer_enqueue(const float* d_params, const double* d_xy, const in
   const int64_t n_single = d_offsets ? 0 : max_set;
   double* scale = (double*)scratch;
   unsigned* g = (unsigned*)((char*)scratch + ((B * 4 * sizeof(double) + 255) & ~size_t(255)));
-  hipLaunchKernelGGL(k_net_frame, dim3((unsigned)B), dim3(NT), 0, s, d_xy, d_offsets, n_single,
-                     scale, g);
+  unsigned* wpk = (unsigned*)((char*)g + ((B * H * sizeof(unsigned) + 255) & ~size_t(255)));
+  hipLaunchKernelGGL(k_net_frame, dim3((unsigned)B), dim3(NTF), 0, s, d_params, d_xy, d_offsets,
+                     n_single, scale, g, wpk);
   const int64_t m = std::min<int64_t>(max_set, max_points);
   const unsigned gx = (unsigned)std::max<int64_t>(1, (m + kPoolPoints - 1) / kPoolPoints);
-  hipLaunchKernelGGL(k_net_pool, dim3(gx, (unsigned)B), dim3(NT), 0, s, d_params, d_xy, d_offsets,
+  hipLaunchKernelGGL(k_net_pool, dim3(gx, (unsigned)B), dim3(NT), 0, s, wpk, d_xy, d_offsets,
                      n_single, max_points, scale, g);
-  hipLaunchKernelGGL(k_net_head, dim3((unsigned)B), dim3(H), 0, s, d_params, g, scale, d_out,
+  hipLaunchKernelGGL(k_net_head, dim3((unsigned)B), dim3(NT), 0, s, d_params, g, scale, d_out,
                      d_theta);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(LMS_ERR_DEVICE, std::string("net launch: ") + hipGetErrorString(e));

@@ -205,7 +205,10 @@ def test_bin_screen_equals_exhaustive(gpu, orc, n):
         if n <= 1000:
             o = orc.solve(xy)
             assert close(ref.width, o.width)
-        for b, rng in ((0, None), (11, None), (13, None), (15, None), (0, True), (13, True)):
+        # fewer bins than 2 n (11 above 1023 points, 12 above 2047) take the
+        # screen's WIDE form
+        for b, rng in ((0, None), (11, None), (12, None), (13, None), (15, None), (0, True),
+                       (13, True)):
             r = gpu.solve(dev(xy), bins_log2=b, slope_range=rng)
             assert (r.width, r.theta1, r.z_lo, r.z_hi) == \
                    (ref.width, ref.theta1, ref.z_lo, ref.z_hi), (n, b, rng)
@@ -432,3 +435,22 @@ def test_default_path_matches_stored_oracle(gpu, orc, key):
                 float.fromhex(g["z_hi"]), float.fromhex(g["theta2"]))
         # planted data: the slope range is narrow, so the pruned screen ran
         assert r.bins == 2048, r.bins
+
+
+@pytest.mark.parametrize("key,bins_log2", [("c3b/302", 13), ("c3b/302", 12),
+                                           ("degenerate_int_9000/902", 12),
+                                           ("planted_9000/901", 13)])
+def test_wide_screen_matches_stored_oracle(gpu, orc, key, bins_log2):
+    """The full slope-bin screen with fewer bins than 2 n (its WIDE form: no
+    per-point codes, the partners' bins computed in the queries) against the
+    oracle's stored minimum at 9000 and 16384 points, without the slope
+    range so that the full screen runs."""
+    g = json.load(open(GOLD)).get(key)
+    name, seed = key.split("/")
+    xy = _stored_input(name, int(seed))
+    r = gpu.solve(dev(xy), bins_log2=bins_log2, slope_range=False)
+    assert r.status == g["status"] == 0
+    assert r.bins == (1 << bins_log2) + (256 if bins_log2 <= 12 else 512)
+    assert r.vertical == g["vertical"] and r.candidates == g["candidates"]
+    assert close(r.width, float.fromhex(g["width"]))
+    assert orc.window(xy, r.theta1) == (r.width, r.z_lo, r.z_hi)
