@@ -349,7 +349,7 @@ def main():
                     line["learned_vs_plain"]["c3a"] = seeding_comparison(
                         lms, X["d"], X["r"], 5, net, with_no_seed=False)
                 line["sampling"] = sampling_block(lms, X["d"], X["r"])
-        line["c4"] = bench_batched(args, steps=3, warmup=1, per_problem=False)
+        line["c4"] = bench_batched(args, steps=5, warmup=2, per_problem=True)
         line["paper_alg1"] = alg1_block(lms)
         line["line_detection"] = line_detection_block(lms)
     if args.cpu_seconds > 0:
@@ -583,8 +583,10 @@ def bench_batched(args, steps=None, warmup=None, per_problem=True):
                           "status_ok": int((res.status >= 0).sum())}
 
     nb = np.diff(off).astype(np.int64)
-    kernels = {"k_bscreen_list": (OPS_BAND * int(res.point_evals.sum()) +
-                                  OPS_DIR * int(res.dir_evals.sum()), stage_ms["screen"])}
+    # problems up to 512 points take the one-pair-per-lane FP32 screen
+    sname = "k_bscreen_lanes" if int(nb.max()) <= 512 else "k_bscreen_list"
+    kernels = {sname: (OPS_BAND * int(res.point_evals.sum()) +
+                       OPS_DIR * int(res.dir_evals.sum()), stage_ms["screen"])}
     if int(res.bins.max()) > 0:
         # problems up to 1024 points take the one-wavefront-per-anchor kernel
         bname = "k_bbins_wave" if int(nb.max()) <= 1024 else "k_bbins"
