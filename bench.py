@@ -369,7 +369,7 @@ def seeding_comparison(lms, d, ref, steps, net, with_no_seed=True):
     """The same solve under different initial width bounds, each replayed from
     its own hipGraph (network inference, when used, runs inside the graph).
 
-    plain: 255 random pair slopes (the default). no_seed: only the extreme-x
+    plain: 127 random pair slopes (the default). no_seed: only the extreme-x
     pair. learned: no random pairs; the seed network's slope, computed inside
     the solve, is the only seed. learned+window: the same, then two rounds of
     63 pairs drawn from the narrowest window found. exact_slope: the LMS slope

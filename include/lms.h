@@ -95,7 +95,7 @@ typedef struct lms_options {
   uint32_t flags;       /* LMS_F_* */
   int32_t seed_pairs;   /* random pair slopes evaluated exactly before the screen
                            to set the initial width bound; -1 = automatic (the tuned
-                           value, else 255 for lms_solve and 31 per problem for
+                           value, else 127 for lms_solve and 31 per problem for
                            lms_solve_batched) */
   int32_t tile_regs;    /* 0 = automatic (tuned, else all points in registers up to
                            4096). Otherwise the number of 64-point chunks of the
@@ -208,7 +208,7 @@ lms_status lms_solve_batched(const double* d_xy, const int64_t* d_offsets,
  * HIP events on `stream`, `reps` runs each (median), and keeps the fastest
  * choice for the size class next_pow2(n) of this device. It sweeps what moves
  * the time: the slope-bin screen's bins per anchor (every allowed 2^k), the
- * slope range (automatic, always, never), the random seed pairs (63, 255),
+ * slope range (automatic, always, never), the random seed pairs (127, 63, 255),
  * then the FP32 screen's tiles (register chunks vs LDS streaming, partner
  * batches per work item). Every candidate must return the same line as the
  * defaults, bit for bit (LMS_ERR_DEVICE otherwise). Later lms_solve calls

@@ -53,7 +53,7 @@ namespace {
 
 using namespace lms_dev;
 using lms_host::fail;
-constexpr int kDefaultSeeds = 255;
+constexpr int kDefaultSeeds = 127;
 constexpr long long kScreenCap = 1ll << 24;     // survivor slots beyond the seeds
 constexpr int kRegChunks = 64;                  // points per lane kept in VGPRs (max)
 constexpr int kPathSingle = 0;                  // tuning-table key of lms_solve
@@ -98,119 +98,159 @@ __device__ __forceinline__ void stat_add(Ctx* ctx, int k, unsigned long long v) 
 
 // ---------------------------------------------------------------- prep
 
-__global__ __launch_bounds__(1024) void k_prep(const double* __restrict__ xy, int n, int h,
-                                               int n_pad, Ctx* ctx, float2* __restrict__ xy32,
-                                               uint2* __restrict__ entries, int n_seeds,
-                                               int n_random, unsigned long long seed_key,
-                                               unsigned bins, int cap) {
-  // extremes by wavefront (shuffles), then across the 16 wavefronts (LDS)
-  __shared__ double s_mn[16], s_mx[16], s_my[16], s_My[16];
-  __shared__ int s_amn[16], s_amx[16], s_fin[16];
+// Extremes of a range of points: the smallest x (the lowest index among
+// equal ones), the largest x (the lowest index among equal ones), the y
+// extremes and whether every coordinate is finite. Merging is exact and
+// order-free.
+struct __align__(16) PrepPart {
+  double mnx, mxx, mny, mxy;
+  int amn, amx, fin, pad;
+};
+
+__device__ __forceinline__ void prep_merge(PrepPart& a, double mn2, int amn2, double mx2, int amx2,
+                                           double my2, double My2, int fin2) {
+  if (mn2 < a.mnx || (mn2 == a.mnx && amn2 < a.amn)) { a.mnx = mn2; a.amn = amn2; }
+  if (mx2 > a.mxx || (mx2 == a.mxx && amx2 < a.amx)) { a.mxx = mx2; a.amx = amx2; }
+  a.mny = fmin(a.mny, my2);
+  a.mxy = fmax(a.mxy, My2);
+  a.fin &= fin2;
+}
+
+constexpr int kPrepNT = 256;
+// workgroups of the prep kernels: about 1024 points each, at most 64
+int prep_blocks(int n) { return std::max(1, std::min(64, (n + 1023) / 1024)); }
+
+// Partial extremes of each workgroup's points (strided over the grid).
+__global__ __launch_bounds__(kPrepNT) void k_prep_part(const double* __restrict__ xy, int n,
+                                                        PrepPart* __restrict__ part) {
+  __shared__ PrepPart s_p[kPrepNT / 64];
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-  double mnx = INFINITY, mxx = -INFINITY, mny = INFINITY, mxy = -INFINITY;
-  int amn = INT_MAX, amx = INT_MAX, fin = 1;
-  for (int k = t; k < n; k += blockDim.x) {
-    const double x = xy[2 * k], y = xy[2 * k + 1];
-    if (!isfinite(x) || !isfinite(y)) fin = 0;
-    if (x < mnx) { mnx = x; amn = k; }
-    if (x > mxx) { mxx = x; amx = k; }
-    mny = fmin(mny, y);
-    mxy = fmax(mxy, y);
+  PrepPart a{INFINITY, -INFINITY, INFINITY, -INFINITY, INT_MAX, INT_MAX, 1, 0};
+  const double2* pts = reinterpret_cast<const double2*>(xy);
+  const int stride = gridDim.x * kPrepNT;
+  // four loads in flight before their merges
+  for (int k0 = blockIdx.x * kPrepNT + t; k0 < n; k0 += 4 * stride) {
+    double2 q[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) q[u] = k0 + u * stride < n ? pts[k0 + u * stride] : q[0];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int k = k0 + u * stride;
+      if (k < n)
+        prep_merge(a, q[u].x, k, q[u].x, k, q[u].y, q[u].y,
+                   isfinite(q[u].x) && isfinite(q[u].y) ? 1 : 0);
+    }
   }
-  // the smaller x (the lower index among equal ones), the larger x (the
-  // lower index among equal ones), the y extremes and the finiteness flag
-  auto merge = [&](double mn2, int amn2, double mx2, int amx2, double my2, double My2,
-                   int fin2) {
-    if (mn2 < mnx || (mn2 == mnx && amn2 < amn)) { mnx = mn2; amn = amn2; }
-    if (mx2 > mxx || (mx2 == mxx && amx2 < amx)) { mxx = mx2; amx = amx2; }
-    mny = fmin(mny, my2);
-    mxy = fmax(mxy, My2);
-    fin &= fin2;
-  };
 #pragma unroll
   for (int m = 32; m >= 1; m >>= 1)
-    merge(__shfl_xor(mnx, m), __shfl_xor(amn, m), __shfl_xor(mxx, m), __shfl_xor(amx, m),
-          __shfl_xor(mny, m), __shfl_xor(mxy, m), __shfl_xor(fin, m));
-  if (lane == 0) {
-    s_mn[wv] = mnx; s_mx[wv] = mxx; s_my[wv] = mny; s_My[wv] = mxy;
-    s_amn[wv] = amn; s_amx[wv] = amx; s_fin[wv] = fin;
-  }
-  __syncthreads();
-  for (int w = 0; w < (int)(blockDim.x >> 6); ++w)
-    merge(s_mn[w], s_amn[w], s_mx[w], s_amx[w], s_my[w], s_My[w], s_fin[w]);
+    prep_merge(a, __shfl_xor(a.mnx, m), __shfl_xor(a.amn, m), __shfl_xor(a.mxx, m),
+               __shfl_xor(a.amx, m), __shfl_xor(a.mny, m), __shfl_xor(a.mxy, m),
+               __shfl_xor(a.fin, m));
+  if (lane == 0) s_p[wv] = a;
   __syncthreads();
   if (t == 0) {
-    s_mn[0] = mnx; s_mx[0] = mxx; s_my[0] = mny; s_My[0] = mxy;
-    s_amn[0] = amn; s_amx[0] = amx; s_fin[0] = fin;
+    for (int w = 1; w < kPrepNT / 64; ++w)
+      prep_merge(a, s_p[w].mnx, s_p[w].amn, s_p[w].mxx, s_p[w].amx, s_p[w].mny, s_p[w].mxy,
+                 s_p[w].fin);
+    part[blockIdx.x] = a;
   }
-  __syncthreads();
-  const bool finite = s_fin[0] != 0;
-  const double minx = s_mn[0], maxx = s_mx[0], miny = s_my[0], maxy = s_My[0];
+}
+
+// Every workgroup merges the G partials (the same values in each), writes
+// its share of the FP32 copy; workgroup 0 also writes the context, zeroes the
+// search counters and writes the seed pairs.
+__global__ __launch_bounds__(kPrepNT) void k_prep(const double* __restrict__ xy, int n, int h,
+                                                  int n_pad, Ctx* ctx, float2* __restrict__ xy32,
+                                                  uint2* __restrict__ entries, int n_seeds,
+                                                  int n_random, unsigned long long seed_key,
+                                                  unsigned bins, int cap,
+                                                  const PrepPart* __restrict__ part, int G) {
+  const int t = threadIdx.x;
+  PrepPart a = part[0];
+  for (int g = 1; g < G; ++g)
+    prep_merge(a, part[g].mnx, part[g].amn, part[g].mxx, part[g].amx, part[g].mny, part[g].mxy,
+               part[g].fin);
+  const bool finite = a.fin != 0;
+  const double minx = a.mnx, maxx = a.mxx, miny = a.mny, maxy = a.mxy;
   const double cx = minx + 0.5 * (maxx - minx), cy = miny + 0.5 * (maxy - miny);
-  if (t == 0) {
-    Ctx c;
-    memset(&c, 0, sizeof(c));
-    c.n = n; c.h = h; c.n_pad = n_pad; c.n_seeds = n_seeds;
-    c.bins = bins;
-    c.status = finite ? LMS_OK : LMS_ERR_NONFINITE;
-    c.all_x_equal = finite && (minx == maxx);
-    c.argminx = s_amn[0]; c.argmaxx = s_amx[0];
-    c.cx = cx; c.cy = cy;
-    c.xh = fmax(fabs(minx - cx), fabs(maxx - cx)) * (1.0 + 0x1p-40);
-    c.yh = fmax(fabs(miny - cy), fabs(maxy - cy)) * (1.0 + 0x1p-40);
-    c.fx = f32_scale(c.xh);
-    c.fy = f32_scale(c.yh);
-    c.xabs = fmax(fabs(minx), fabs(maxx));
-    c.yabs = fmax(fabs(miny), fabs(maxy));
-    c.xr = (maxx - minx) * (1.0 + 0x1p-50);
-    c.yr = (maxy - miny) * (1.0 + 0x1p-50);
-    c.th_lo = -INFINITY;
-    c.th_hi = INFINITY;
-    c.n_live = -1;
-    c.wbound = 0x7FF0000000000000ull;  // +inf
-    c.n_entries = (unsigned)n_seeds;
-    // all x equal: slope 0 is the answer; it is re-evaluated exactly as the
-    // one survivor (the seeds give bounds only)
-    if (c.all_x_equal && n_seeds < cap) {
-      entries[n_seeds] = make_uint2(kDegenerate, kDegenerate);
-      c.n_entries = (unsigned)n_seeds + 1u;
+  if (blockIdx.x == 0) {
+    if (t == 0) {
+      Ctx c;
+      memset(&c, 0, sizeof(c));
+      c.n = n; c.h = h; c.n_pad = n_pad; c.n_seeds = n_seeds;
+      c.bins = bins;
+      c.status = finite ? LMS_OK : LMS_ERR_NONFINITE;
+      c.all_x_equal = finite && (minx == maxx);
+      c.argminx = a.amn; c.argmaxx = a.amx;
+      c.cx = cx; c.cy = cy;
+      c.xh = fmax(fabs(minx - cx), fabs(maxx - cx)) * (1.0 + 0x1p-40);
+      c.yh = fmax(fabs(miny - cy), fabs(maxy - cy)) * (1.0 + 0x1p-40);
+      c.fx = f32_scale(c.xh);
+      c.fy = f32_scale(c.yh);
+      c.xabs = fmax(fabs(minx), fabs(maxx));
+      c.yabs = fmax(fabs(miny), fabs(maxy));
+      c.xr = (maxx - minx) * (1.0 + 0x1p-50);
+      c.yr = (maxy - miny) * (1.0 + 0x1p-50);
+      c.th_lo = -INFINITY;
+      c.th_hi = INFINITY;
+      c.n_live = -1;
+      c.wbound = 0x7FF0000000000000ull;  // +inf
+      c.n_entries = (unsigned)n_seeds;
+      // all x equal: slope 0 is the answer; it is re-evaluated exactly as the
+      // one survivor (the seeds give bounds only)
+      if (c.all_x_equal && n_seeds < cap) {
+        entries[n_seeds] = make_uint2(kDegenerate, kDegenerate);
+        c.n_entries = (unsigned)n_seeds + 1u;
+      }
+      *ctx = c;
     }
-    *ctx = c;
-  }
-  {
     Stats* st = reinterpret_cast<Stats*>(reinterpret_cast<char*>(ctx) + kStatsOffset);
-    for (int k = t; k < kStats * kSlots; k += blockDim.x) (&st->v[0][0])[k] = 0ull;
+    for (int k = t; k < kStats * kSlots; k += kPrepNT) (&st->v[0][0])[k] = 0ull;
+    // Seed entries: the extreme-x pair (never vertical unless all x are
+    // equal), then n_random random pairs from a counter-based SplitMix64
+    // stream. Slots past those (window pairs, written later) start as the
+    // extreme-x pair.
+    if (finite) {
+      for (int e = t; e < n_seeds; e += kPrepNT) {
+        uint2 p;
+        if ((e == 0 || e > n_random) && minx == maxx) {
+          p = make_uint2(kDegenerate, kDegenerate);
+        } else if (e == 0 || e > n_random) {
+          p = make_uint2((unsigned)min(a.amn, a.amx), (unsigned)max(a.amn, a.amx));
+        } else {
+          const unsigned long long r =
+              mix64(seed_key + 0x9E3779B97F4A7C15ull * (unsigned long long)(e + 1));
+          const unsigned aa = (unsigned)((r >> 32) % (unsigned long long)n);
+          unsigned bb = (unsigned)((r & 0xFFFFFFFFull) % (unsigned long long)(n - 1));
+          if (bb >= aa) ++bb;
+          p = make_uint2(min(aa, bb), max(aa, bb));
+        }
+        entries[e] = p;
+      }
+    }
   }
   if (!finite) return;
   const float qnan = __int_as_float(0x7FC00000);
-  // the same scales k_prep's thread 0 stored (same inputs, same operations)
+  // the same scales thread 0 of workgroup 0 stores (same inputs, same operations)
   const double fx = f32_scale(fmax(fabs(minx - cx), fabs(maxx - cx)) * (1.0 + 0x1p-40));
   const double fy = f32_scale(fmax(fabs(miny - cy), fabs(maxy - cy)) * (1.0 + 0x1p-40));
-  for (int k = t; k < n_pad; k += blockDim.x) {
+  for (int k = blockIdx.x * kPrepNT + t; k < n_pad; k += gridDim.x * kPrepNT) {
     float2 p = make_float2(qnan, qnan);
     if (k < n)
       p = make_float2((float)((xy[2 * k] - cx) * fx), (float)((xy[2 * k + 1] - cy) * fy));
     xy32[k] = p;
   }
-  // Seed entries: the extreme-x pair (never vertical unless all x are equal),
-  // then n_random random pairs from a counter-based SplitMix64 stream. Slots
-  // past those (window pairs, written later) start as the extreme-x pair.
-  for (int e = t; e < n_seeds; e += blockDim.x) {
-    uint2 p;
-    if ((e == 0 || e > n_random) && minx == maxx) {
-      p = make_uint2(kDegenerate, kDegenerate);
-    } else if (e == 0 || e > n_random) {
-      const int a = s_amn[0], b = s_amx[0];
-      p = make_uint2((unsigned)min(a, b), (unsigned)max(a, b));
-    } else {
-      const unsigned long long r = mix64(seed_key + 0x9E3779B97F4A7C15ull * (unsigned long long)(e + 1));
-      const unsigned a = (unsigned)((r >> 32) % (unsigned long long)n);
-      unsigned b = (unsigned)((r & 0xFFFFFFFFull) % (unsigned long long)(n - 1));
-      if (b >= a) ++b;
-      p = make_uint2(min(a, b), max(a, b));
-    }
-    entries[e] = p;
-  }
+}
+
+// The two prep kernels; part: at least prep_blocks(n) PrepPart of scratch
+// (the slope range's region, which is written only later).
+void launch_prep(hipStream_t s, const double* xy, int n, int h, int n_pad, Ctx* ctx,
+                 float2* xy32, uint2* entries, int n_seeds, int n_random,
+                 unsigned long long seed_key, unsigned bins, int cap, PrepPart* part) {
+  const int G = prep_blocks(n);
+  hipLaunchKernelGGL(k_prep_part, dim3(G), dim3(kPrepNT), 0, s, xy, n, part);
+  hipLaunchKernelGGL(k_prep, dim3(G), dim3(kPrepNT), 0, s, xy, n, h, n_pad, ctx, xy32, entries,
+                     n_seeds, n_random, seed_key, bins, cap, part, G);
 }
 
 // ---------------------------------------------------------------- FP64 window
@@ -276,12 +316,15 @@ __global__ __launch_bounds__(NT) void k_sort_chunks(const double* __restrict__ x
                                                     const Ctx* ctx,
                                                     const uint2* __restrict__ entries, int begin,
                                                     int cap, int slots, double* __restrict__ tmp,
-                                                    int np, const double* __restrict__ thetas) {
+                                                    int np, const double* __restrict__ thetas,
+                                                    int direct_max) {
   constexpr int E = C / NT;
   __shared__ double z[C];
   if (ctx->status < 0) return;
-  const unsigned end = min(thetas ? (unsigned)cap : min(ctx->n_entries, (unsigned)cap),
-                           (unsigned)begin + (unsigned)slots);
+  const unsigned all_end = thetas ? (unsigned)cap : min(ctx->n_entries, (unsigned)cap);
+  // few entries: k_merge_window sorts each one whole, one per workgroup
+  if (all_end <= (unsigned)begin + (unsigned)direct_max) return;
+  const unsigned end = min(all_end, (unsigned)begin + (unsigned)slots);
   const int n = ctx->n, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int k0 = blockIdx.x * C;
   for (unsigned y = blockIdx.y; begin + y < end; y += gridDim.y) {
@@ -307,12 +350,17 @@ __global__ __launch_bounds__(NT) void k_merge_window(const double* __restrict__ 
                                                      double4* __restrict__ res, int begin,
                                                      int cap, int update_bound,
                                                      const double* __restrict__ tmp, int slots,
-                                                     const double* __restrict__ thetas) {
+                                                     const double* __restrict__ thetas,
+                                                     int direct_max) {
   __shared__ double z[NP + NP / 16];  // merge_slot layout (NP for whole sorts)
   const Ctx c = *ctx;
   if (c.status < 0) return;
   const unsigned end = thetas ? (unsigned)cap : min(c.n_entries, (unsigned)cap);
-  const unsigned split_end = min(end, (unsigned)begin + (unsigned)slots);
+  // up to direct_max entries (no more than the workgroups): whole sorts only,
+  // and k_sort_chunks has returned at once
+  const unsigned split_end =
+      end <= (unsigned)begin + (unsigned)direct_max ? (unsigned)begin
+                                                     : min(end, (unsigned)begin + (unsigned)slots);
   auto finish = [&](unsigned e, double w, double theta, double lo, double hi) {
     if (threadIdx.x == 0) {
       res[e] = make_double4(w, theta, lo, hi);
@@ -1637,10 +1685,11 @@ __global__ __launch_bounds__(NT) void k_screen_pairs(
 
 // ---------------------------------------------------------------- finalize
 
-__global__ __launch_bounds__(1024) void k_finalize(Ctx* ctx, const uint2* __restrict__ entries,
-                                                   const double4* __restrict__ res, int cap,
-                                                   lms_result* out) {
-  __shared__ Best sb[1024];
+constexpr int kFinalNT = 256;
+__global__ __launch_bounds__(kFinalNT) void k_finalize(Ctx* ctx, const uint2* __restrict__ entries,
+                                                       const double4* __restrict__ res, int cap,
+                                                       lms_result* out) {
+  __shared__ Best sb[kFinalNT / 64];
   __shared__ unsigned long long s_stat[kStats];
   const Ctx c = *ctx;
   const int t = threadIdx.x;
@@ -1659,14 +1708,19 @@ __global__ __launch_bounds__(1024) void k_finalize(Ctx* ctx, const uint2* __rest
     const Best q = {r.x, r.y, r.z, r.w, p.x, p.y};
     if (better(q, b)) b = q;
   }
-  sb[t] = b;
-  __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if (t < s && better(sb[t + s], sb[t])) sb[t] = sb[t + s];
-    __syncthreads();
+  // the canonical minimum: by wavefront (shuffles), then across wavefronts
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    const Best q = {__shfl_xor(b.w, m), __shfl_xor(b.th, m), __shfl_xor(b.lo, m),
+                    __shfl_xor(b.hi, m), (unsigned)__shfl_xor((int)b.a, m),
+                    (unsigned)__shfl_xor((int)b.b, m)};
+    if (better(q, b)) b = q;
   }
+  if ((t & 63) == 0) sb[t >> 6] = b;
+  __syncthreads();
   if (t != 0) return;
-  b = sb[0];
+  for (int w = 1; w < kFinalNT / 64; ++w)
+    if (better(sb[w], b)) b = sb[w];
   lms_result o;
   memset(&o, 0, sizeof(o));
   o.h = c.h;
@@ -1758,10 +1812,14 @@ void launch_split_np(hipStream_t s, int grid, int gy, int slots, const double* x
                      const uint2* e, double4* res, int begin, int cap, int upd, double* tmp,
                      const double* thetas) {
   constexpr int NT = NP >= 2048 ? 1024 : 256;
+  // as many entries as workgroups or fewer: each sorted whole by one of them
+  // (a split sort then only adds a launch and a pass through memory)
+  const int direct_max = grid;
   hipLaunchKernelGGL((k_sort_chunks<kSplitChunk, kSplitNT>), dim3(NP / kSplitChunk, gy),
-                     dim3(kSplitNT), 0, s, xy, ctx, e, begin, cap, slots, tmp, NP, thetas);
+                     dim3(kSplitNT), 0, s, xy, ctx, e, begin, cap, slots, tmp, NP, thetas,
+                     direct_max);
   hipLaunchKernelGGL((k_merge_window<NP, NT>), dim3(grid), dim3(NT), 0, s, xy, ctx, e, res, begin,
-                     cap, upd, tmp, slots, thetas);
+                     cap, upd, tmp, slots, thetas, direct_max);
 }
 
 // Number of entries that one split launch pair sorts in pieces (0: whole-sort
@@ -2265,9 +2323,8 @@ lms_status enqueue_solve(const Setup& S, char* base, hipStream_t s, lms_host::St
   const int64_t n_seed_theta = S.n_seed_theta;
   auto mark = [&]() { if (prof) prof->mark(); };
   const unsigned long long key = 0x5EEDull + (unsigned long long)p.n * 0x100000001ull;
-  hipLaunchKernelGGL(k_prep, dim3(1), dim3(1024), 0, s, d_xy, p.n, p.h, p.n_pad, ctx, xy32,
-                     entries, p.n_seeds, seeds, key, S.use_bins ? bins_count(S.bins_log2) : 0u,
-                     (int)p.cap);
+  launch_prep(s, d_xy, p.n, p.h, p.n_pad, ctx, xy32, entries, p.n_seeds, seeds, key,
+              S.use_bins ? bins_count(S.bins_log2) : 0u, (int)p.cap, (PrepPart*)(base + L.range));
   // the seed network's slope, as the device seed slope
   const double* seed_theta = S.seed_theta;
   if (S.net) {
@@ -2368,7 +2425,8 @@ lms_status enqueue_solve(const Setup& S, char* base, hipStream_t s, lms_host::St
                  entries, res, p.n_seeds, (int)p.cap, 0, tmp, S.final_slots,
                  p.n > 4096 ? 64 : 32);
   mark();
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, s, ctx, entries, res, (int)p.cap, S.out);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFinalNT), 0, s, ctx, entries, res, (int)p.cap,
+                     S.out);
   mark();
   err = hipGetLastError();
   if (err != hipSuccess) return fail(LMS_ERR_DEVICE, std::string("launch: ") + hipGetErrorString(err));
@@ -2626,7 +2684,7 @@ lms_status lms_autotune(const double* d_xy, int64_t n, int64_t h, int32_t reps, 
   while (min_bins < 15 && (1 << min_bins) < n / 2) ++min_bins;
   best.bins_log2 = std::max(best.bins_log2, min_bins);
   // 1. the screen's bins, the slope range and the seeds
-  static const int kSeedsC[] = {kDefaultSeeds, 63};
+  static const int kSeedsC[] = {kDefaultSeeds, 63, 255};
   static const int kRangeC[] = {0, 1, -1};
   for (int bl = min_bins; bl <= 15 && st == LMS_OK; ++bl)
     for (int rg : kRangeC)
@@ -2749,8 +2807,8 @@ lms_status lms_screen_pairs(const double* d_xy, int64_t n, int64_t h, double W,
   Ctx* ctx = (Ctx*)(base + L.ctx);
   float2* xy32 = (float2*)(base + L.xy32);
   uint2* entries = (uint2*)(base + L.entries);
-  hipLaunchKernelGGL(k_prep, dim3(1), dim3(1024), 0, s, d_xy, p.n, p.h, p.n_pad, ctx, xy32,
-                     entries, 1, 0, 0ull, 0u, 0);
+  launch_prep(s, d_xy, p.n, p.h, p.n_pad, ctx, xy32, entries, 1, 0, 0ull, 0u, 0,
+              (PrepPart*)(base + L.range));
   hipError_t err = launch_pairs(s, p.R, p.lds, d_xy, xy32, ctx, W, d_pairs, (int)m, d_verdict, p.nq);
   if (err != hipSuccess) return fail(LMS_ERR_DEVICE, hipGetErrorString(err));
   return LMS_OK;
