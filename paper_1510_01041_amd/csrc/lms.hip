@@ -316,15 +316,12 @@ __global__ __launch_bounds__(NT) void k_sort_chunks(const double* __restrict__ x
                                                     const Ctx* ctx,
                                                     const uint2* __restrict__ entries, int begin,
                                                     int cap, int slots, double* __restrict__ tmp,
-                                                    int np, const double* __restrict__ thetas,
-                                                    int direct_max) {
+                                                    int np, const double* __restrict__ thetas) {
   constexpr int E = C / NT;
   __shared__ double z[C];
   if (ctx->status < 0) return;
-  const unsigned all_end = thetas ? (unsigned)cap : min(ctx->n_entries, (unsigned)cap);
-  // few entries: k_merge_window sorts each one whole, one per workgroup
-  if (all_end <= (unsigned)begin + (unsigned)direct_max) return;
-  const unsigned end = min(all_end, (unsigned)begin + (unsigned)slots);
+  const unsigned end = min(thetas ? (unsigned)cap : min(ctx->n_entries, (unsigned)cap),
+                           (unsigned)begin + (unsigned)slots);
   const int n = ctx->n, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int k0 = blockIdx.x * C;
   for (unsigned y = blockIdx.y; begin + y < end; y += gridDim.y) {
@@ -350,17 +347,12 @@ __global__ __launch_bounds__(NT) void k_merge_window(const double* __restrict__ 
                                                      double4* __restrict__ res, int begin,
                                                      int cap, int update_bound,
                                                      const double* __restrict__ tmp, int slots,
-                                                     const double* __restrict__ thetas,
-                                                     int direct_max) {
+                                                     const double* __restrict__ thetas) {
   __shared__ double z[NP + NP / 16];  // merge_slot layout (NP for whole sorts)
   const Ctx c = *ctx;
   if (c.status < 0) return;
   const unsigned end = thetas ? (unsigned)cap : min(c.n_entries, (unsigned)cap);
-  // up to direct_max entries (no more than the workgroups): whole sorts only,
-  // and k_sort_chunks has returned at once
-  const unsigned split_end =
-      end <= (unsigned)begin + (unsigned)direct_max ? (unsigned)begin
-                                                     : min(end, (unsigned)begin + (unsigned)slots);
+  const unsigned split_end = min(end, (unsigned)begin + (unsigned)slots);
   auto finish = [&](unsigned e, double w, double theta, double lo, double hi) {
     if (threadIdx.x == 0) {
       res[e] = make_double4(w, theta, lo, hi);
@@ -1168,7 +1160,8 @@ __global__ __launch_bounds__(NT) void k_bins(const double* __restrict__ xy, Ctx*
   // point loads in flight in the insertion loop (latency: the largest bin
   // arrays leave the fewest wavefronts per CU)
   constexpr int kPF = NB >= 32768 ? 3 : 2;
-  __shared__ unsigned bins[NBINS + 1];
+  // (rounded up to whole 16-byte words for the clearing stores)
+  __shared__ __align__(16) unsigned bins[(NBINS + 4) & ~3];
   // codes of the n <= NB / 2 points (CODED), or partner offsets o - 1 that
   // pass (P(i) <= n / 2 <= LMS_MAX_N / 2)
   __shared__ unsigned short list[WIDE || NB / 2 >= LMS_MAX_N / 2 ? LMS_MAX_N / 2 : NB / 2];
@@ -1184,13 +1177,16 @@ __global__ __launch_bounds__(NT) void k_bins(const double* __restrict__ xy, Ctx*
   if (c.status != LMS_OK || c.all_x_equal || c.n_live >= 0) return;  // (k_bins_pruned)
   const int n = c.n, h = c.h, t = threadIdx.x, lane = t & 63;
   const double W = __longlong_as_double((long long)c.wbound);
-  const double lim = W * (1.0 + 0x1p-50);
-  const BinFrame F = bin_frame(best_slope<NT>(seed_res, c.n_seeds, seed_rec, n_rec),
-                               c.xh, c.yh, W, NBINS);
+  const double lim = uniform(W * (1.0 + 0x1p-50));
+  BinFrame F = bin_frame(best_slope<NT>(seed_res, c.n_seeds, seed_rec, n_rec),
+                         c.xh, c.yh, W, NBINS);
+  F.tc = uniform(F.tc);  // (uniform values in scalar registers)
+  F.sc = uniform(F.sc);
+  F.q = uniform(F.q);
   const int half = n >> 1;
   // slopes whose FP32 test bound (affine in |theta|) would pass 1e29 go to the
   // FP64 entries; half the solved limit covers the roundings
-  const double th_lim = screen_th_lim(c.fx, c.fy, c.xh, c.yh);
+  const double th_lim = uniform(screen_th_lim(c.fx, c.fy, c.xh, c.yh));
   const double2* pts = reinterpret_cast<const double2*>(xy);
   // per-wavefront counts (uniform)
   unsigned long long n_vert = 0, n_scr = 0, n_forced = 0, n_pass = 0;
@@ -1222,24 +1218,25 @@ __global__ __launch_bounds__(NT) void k_bins(const double* __restrict__ xy, Ctx*
       s_all = 0;
       s_cnt = 0;
     }
-    for (int b = t; b <= NBINS; b += NT) bins[b] = 0u;
+    for (int b = t; b < (NBINS + 4) / 4; b += NT) reinterpret_cast<uint4*>(bins)[b] = uint4{};
     __syncthreads();
     // the anchor in VGPRs (a vector load): a scalar load's wait would also
     // wait for every LDS operation in flight in the loop below
     int iv = i;
     asm volatile("" : "+v"(iv));
     const double2 pa = pts[iv];
-    const double xi = pa.x, yi = pa.y;
+    const double xi = uniform(pa.x), yi = uniform(pa.y);
     // 1. intervals of every point (packed counts: U in the low, D in the high half)
     unsigned all = 0;
     // kPF points per step; the loads of the next step's points are issued
     // before this step's work (clamped indices: no branch around a load)
+    auto load = [&](int k) { return pts[(unsigned)min(k, n - 1)]; };
     double2 cur[kPF], nxt[kPF];
 #pragma unroll
-    for (int q = 0; q < kPF; ++q) cur[q] = pts[min(t + q * NT, n - 1)];
+    for (int q = 0; q < kPF; ++q) cur[q] = load(t + q * NT);
     for (int k0 = t; k0 < n; k0 += kPF * NT) {
 #pragma unroll
-      for (int q = 0; q < kPF; ++q) nxt[q] = pts[min(k0 + (kPF + q) * NT, n - 1)];
+      for (int q = 0; q < kPF; ++q) nxt[q] = load(k0 + (kPF + q) * NT);
 #pragma unroll
       for (int q = 0; q < kPF; ++q) {
         const int k = k0 + q * NT;
@@ -1273,18 +1270,22 @@ __global__ __launch_bounds__(NT) void k_bins(const double* __restrict__ xy, Ctx*
       for (int o0 = 1; o0 <= P; o0 += NT) {
         const int o = o0 + t;
         const bool valid = o <= P;
-        const int j = partner(valid ? o : 1);
+        const int j = partner(min(o, P));
         const unsigned cj = list[j];
-        const bool vert = valid && cj == kCodeVertical;
-        const bool force = valid && cj == kCodeFP64;
-        const bool test = valid && cj > kCodePass;
-        const bool pass = test && bins_pass(bins[cj], pall, h);
-        const unsigned long long mp = lane_mask(pass);
-        n_vert += __popcll(lane_mask(vert));
-        n_forced += __popcll(lane_mask(force));
-        n_scr += __popcll(lane_mask(test));
+        // read for every lane, with no branch (codes 0..2 read bins 0..2,
+        // which no test uses)
+        const unsigned pb = bins[cj];
+        const unsigned long long mv = lane_mask(valid);
+        const unsigned long long mt = lane_mask(cj > kCodePass) & mv;
+        const unsigned long long mf = lane_mask(cj == kCodeFP64) & mv;
+        const unsigned long long mp = lane_mask(bins_pass(pb, pall, h)) & mt;
+        n_vert += __popcll(lane_mask(cj == kCodeVertical) & mv);
+        n_forced += __popcll(mf);
+        n_scr += __popcll(mt);
         n_pass += __popcll(mp);
-        if (force) append_entry(ctx, entries, cap, (unsigned)min(i, j), (unsigned)max(i, j));
+        const bool pass = (mp >> lane) & 1ull;
+        if (mf && ((mf >> lane) & 1ull))
+          append_entry(ctx, entries, cap, (unsigned)min(i, j), (unsigned)max(i, j));
         if (mp) {
           unsigned base = 0;
           if (lane == 0) base = atomicAdd(&s_cnt, (unsigned)__popcll(mp));
@@ -1395,7 +1396,7 @@ __global__ __launch_bounds__(NT) void k_bins_pruned(const double* __restrict__ x
                                                     const uint2* __restrict__ live, int nb_full) {
   constexpr int NBP = kPrunedBins, NBINSP = NBP + NT, kRLogP = __builtin_ctz(NBP) - 1;
   static_assert((NBP % NT) == 0 && ((NBP / NT) & 1) == 0, "bins must be 2^k per thread");
-  __shared__ unsigned bins[NBINSP + 1];
+  __shared__ __align__(16) unsigned bins[(NBINSP + 4) & ~3];  // whole 16-byte words
   __shared__ unsigned short pcode[NMAX], pidx[NMAX];
   constexpr int PB = 512;
   __shared__ uint2 pbuf[PB];
@@ -1405,11 +1406,11 @@ __global__ __launch_bounds__(NT) void k_bins_pruned(const double* __restrict__ x
   if (c.status != LMS_OK || c.all_x_equal || c.n_live < 0) return;
   const int n = c.n, h = c.h, t = threadIdx.x, lane = t & 63;
   const double W = __longlong_as_double((long long)c.wbound);
-  const double lim = W * (1.0 + 0x1p-50);
+  const double lim = uniform(W * (1.0 + 0x1p-50));
   const BinFrame F = bin_frame(best_slope<NT>(seed_res, c.n_seeds, seed_rec, n_rec),
                                c.xh, c.yh, W, NBINSP);
   const int half = n >> 1;
-  const double th_lim = screen_th_lim(c.fx, c.fy, c.xh, c.yh);
+  const double th_lim = uniform(screen_th_lim(c.fx, c.fy, c.xh, c.yh));
   unsigned long long n_scr = 0, n_forced = 0, n_pass = 0;
   auto reserve = [&](unsigned cnt) {
     const unsigned base = atomicAdd(&ctx->n_cands, cnt);
@@ -1445,6 +1446,9 @@ __global__ __launch_bounds__(NT) void k_bins_pruned(const double* __restrict__ x
     blo = fbin<kRLogP>((c.th_lo - FP.tc) * FP.sc) - 2;
     bhi = fbin<kRLogP>((c.th_hi - FP.tc) * FP.sc) + 2;
   }
+  FP.tc = uniform(FP.tc);  // (uniform values in scalar registers)
+  FP.sc = uniform(FP.sc);
+  FP.q = uniform(FP.q);
   for (int q = blockIdx.x; q < n_live; q += gridDim.x) {
     __syncthreads();  // the previous anchor's queries are done with the bins
     if (t == 0) {
@@ -1452,7 +1456,7 @@ __global__ __launch_bounds__(NT) void k_bins_pruned(const double* __restrict__ x
       s_cnt = 0;
       s_pos = 0;
     }
-    for (int b = t; b <= NBINSP; b += NT) bins[b] = 0u;
+    for (int b = t; b < (NBINSP + 4) / 4; b += NT) reinterpret_cast<uint4*>(bins)[b] = uint4{};
     __syncthreads();
     const uint2 lv = live[q];
     const int i = (int)lv.x, r0 = (int)(lv.y & 0xFFFFu), len = (int)(lv.y >> 16) - r0;
@@ -1538,13 +1542,91 @@ __global__ __launch_bounds__(NT) void k_bins_pruned(const double* __restrict__ x
   }
 }
 
+// One listed pair per workgroup (see k_screen_list): chunk q of 64 points
+// (xy32[64 q + lane], NaN padding past n counts as a miss) goes to wavefront
+// q mod (NT / 64). Each wavefront counts B = #{|d| <= thr}, P = #{ta < d <=
+// thr} and N = #{-thr <= d < -ta}; the pair survives iff B >= h and (N <= B - h
+// or P <= B - h), the verdict of test_pair. Chunks below R use the
+// anchor-shifted residual, the others the LDS form, as test_pair does.
+template <int R, int NT>
+__device__ __forceinline__ void screen_list_blocks(const double* __restrict__ xy,
+                                                   const float2* __restrict__ xy32, const Ctx& c,
+                                                   Ctx* ctx, const uint2* __restrict__ cands,
+                                                   uint2* __restrict__ entries, int cap,
+                                                   unsigned total, int chunks) {
+  constexpr int NW = NT / 64;
+  constexpr int U = 4;  // chunks per step (their loads issued together)
+  __shared__ unsigned s_cnt[3];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6, h = c.h;
+  const double W = __longlong_as_double((long long)c.wbound);
+  unsigned long long n_evals = 0, n_devals = 0;
+  unsigned n_band = 0;
+  for (unsigned e = blockIdx.x; e < total; e += gridDim.x) {
+    if (t < 3) s_cnt[t] = 0u;
+    __syncthreads();
+    const uint2 cd = cands[e];
+    const int lo = (int)min(cd.x, cd.y), hi = (int)max(cd.x, cd.y);
+    const double th = (xy[2 * hi + 1] - xy[2 * lo + 1]) / (xy[2 * hi] - xy[2 * lo]);
+    const ScreenScalars sc = screen_scalars(th, W, c.fx, c.fy, c.xh, c.yh);
+    const float2 pi = xy32[cd.x];
+    const float nth = -sc.th32, thr = sc.thr, ta = sc.ta;
+    const float nc = -fmaf(-sc.th32, pi.x, pi.y);
+    unsigned band = 0, above = 0, below = 0;
+    for (int q0 = wave; q0 < chunks; q0 += U * NW) {
+      float2 p[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int q = q0 + u * NW;
+        p[u] = xy32[64 * min(q, chunks - 1) + lane];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int q = q0 + u * NW;
+        if (q < chunks) {  // uniform
+          const float d = q < R ? fmaf(nth, p[u].x - pi.x, p[u].y - pi.y)
+                                : fmaf(nth, p[u].x, p[u].y) + nc;
+          band += (unsigned)__popcll(__ballot(fabsf(d) <= thr));
+          above += (unsigned)__popcll(__ballot(d > ta && d <= thr));
+          below += (unsigned)__popcll(__ballot(d < -ta && d >= -thr));
+        }
+      }
+    }
+    if (lane == 0) {
+      atomicAdd(&s_cnt[0], band);
+      atomicAdd(&s_cnt[1], above);
+      atomicAdd(&s_cnt[2], below);
+    }
+    __syncthreads();
+    const int B = (int)s_cnt[0], P = (int)s_cnt[1], N = (int)s_cnt[2];
+    __syncthreads();  // s_cnt is cleared for the next pair
+    n_evals += (unsigned)chunks;
+    if (B >= h) {
+      ++n_band;
+      n_devals += (unsigned)chunks;
+      if (t == 0 && (N <= B - h || P <= B - h))
+        append_entry(ctx, entries, cap, (unsigned)lo, (unsigned)hi);
+    }
+  }
+  if (t == 0) {
+    stat_add(ctx, ST_BAND, n_band);
+    stat_add(ctx, ST_EVALS, 64ull * n_evals);
+    stat_add(ctx, ST_DEVALS, 64ull * n_devals);
+  }
+}
+
 // FP32 test of the listed pairs: a wavefront takes a task of up to
 // kListBlock consecutive list entries (mostly of one anchor, as the list is
 // written per anchor), loads the points shifted by each distinct anchor among
 // them, and runs the band and split tests of the exhaustive screen on every
 // pair. A pair costs up to two serial passes over the points, so tasks shrink
 // to one pair when the list is short and the wavefronts would otherwise idle.
+// A list of at most kListPerBlock pairs per workgroup (the usual tens to
+// hundreds) goes one pair per workgroup instead: its wavefronts share the
+// point chunks and count the band and both one-sided sets in one pass, with
+// the same residuals as the wavefront test (anchor-shifted form for the
+// register chunks, the LDS form past them), so the verdicts are the same.
 constexpr int kListBlock = 16;
+constexpr int kListPerBlock = 4;
 template <int R, bool LDS_PART, int NT>
 __global__ __launch_bounds__(NT, 3) void k_screen_list(
     const double* __restrict__ xy, const float2* __restrict__ xy32, Ctx* ctx,
@@ -1553,6 +1635,11 @@ __global__ __launch_bounds__(NT, 3) void k_screen_list(
   const Ctx c = *ctx;
   if (c.status != LMS_OK || c.all_x_equal || c.cand_overflow) return;
   const int h = c.h, lane = threadIdx.x & 63;
+  if (min(c.n_cands, (unsigned)cand_cap) <= (unsigned)kListPerBlock * gridDim.x) {
+    screen_list_blocks<R, NT>(xy, xy32, c, ctx, cands, entries, cap,
+                              min(c.n_cands, (unsigned)cand_cap), R + (LDS_PART ? nq : 0));
+    return;
+  }
   if (LDS_PART) {
     for (int k = threadIdx.x; k < nq * 64; k += blockDim.x) lds[k] = xy32[64 * R + k];
     __syncthreads();
@@ -1812,14 +1899,10 @@ void launch_split_np(hipStream_t s, int grid, int gy, int slots, const double* x
                      const uint2* e, double4* res, int begin, int cap, int upd, double* tmp,
                      const double* thetas) {
   constexpr int NT = NP >= 2048 ? 1024 : 256;
-  // as many entries as workgroups or fewer: each sorted whole by one of them
-  // (a split sort then only adds a launch and a pass through memory)
-  const int direct_max = grid;
   hipLaunchKernelGGL((k_sort_chunks<kSplitChunk, kSplitNT>), dim3(NP / kSplitChunk, gy),
-                     dim3(kSplitNT), 0, s, xy, ctx, e, begin, cap, slots, tmp, NP, thetas,
-                     direct_max);
+                     dim3(kSplitNT), 0, s, xy, ctx, e, begin, cap, slots, tmp, NP, thetas);
   hipLaunchKernelGGL((k_merge_window<NP, NT>), dim3(grid), dim3(NT), 0, s, xy, ctx, e, res, begin,
-                     cap, upd, tmp, slots, thetas, direct_max);
+                     cap, upd, tmp, slots, thetas);
 }
 
 // Number of entries that one split launch pair sorts in pieces (0: whole-sort

@@ -429,7 +429,7 @@ __global__ __launch_bounds__(NT) void k_bbins(const double* __restrict__ xy, PMe
   constexpr int NBINS = NB + NT;
   constexpr int kRLog = __builtin_ctz(NB) - 1;  // the map spans bins [3, NB + 3]
   static_assert((NB % NT) == 0 && ((NB / NT) & 1) == 0, "bins must be 2^k per thread");
-  __shared__ unsigned bins[NBINS + 1];
+  __shared__ __align__(16) unsigned bins[(NBINS + 4) & ~3];  // whole 16-byte words
   __shared__ unsigned short list[NB / 2];  // partner offsets o - 1 (P <= n / 2 <= NB / 2)
   __shared__ unsigned s_part[NT / 64 > 0 ? NT / 64 : 1];
   __shared__ unsigned s_all, s_cnt, s_next, s_end;
@@ -441,7 +441,7 @@ __global__ __launch_bounds__(NT) void k_bbins(const double* __restrict__ xy, PMe
       s_all = 0;
       s_cnt = 0;
     }
-    for (int b = t; b <= NBINS; b += NT) bins[b] = 0u;
+    for (int b = t; b < (NBINS + 4) / 4; b += NT) reinterpret_cast<uint4*>(bins)[b] = uint4{};
     __syncthreads();
     const uint2 it = items[item];
     const int b = __builtin_amdgcn_readfirstlane((int)it.x);

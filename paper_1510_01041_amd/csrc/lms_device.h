@@ -93,6 +93,15 @@ __device__ __forceinline__ unsigned long long lane_mask(bool p) {
   return __builtin_amdgcn_ballot_w64(p);
 }
 
+// A wavefront-uniform double moved to scalar registers (it must be uniform):
+// frees the two vector registers a loop would otherwise hold it in.
+__device__ __forceinline__ double uniform(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)b);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(b >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 // Order-preserving map of a non-NaN double to u64 (for atomicMin keys).
 __device__ __forceinline__ unsigned long long order_key(double v) {
   const unsigned long long b = (unsigned long long)__double_as_longlong(v);
