@@ -331,7 +331,8 @@ __global__ __launch_bounds__(NT) void k_sort_chunks(const double* __restrict__ x
 #pragma unroll
     for (int r = 0; r < E; ++r) {
       const int k = k0 + (wave * E + r) * 64 + lane;
-      v[r] = k < n ? fma(-theta, xy[2 * k], xy[2 * k + 1]) : INFINITY;
+      const double2 p = point_clamped(xy, k, n);
+      v[r] = k < n ? fma(-theta, p.x, p.y) : INFINITY;
     }
     sort_regs<C, NT>(v, z);
     double* out = tmp + (size_t)y * np + k0;
@@ -368,7 +369,15 @@ __global__ __launch_bounds__(NT) void k_merge_window(const double* __restrict__ 
       continue;
     }
     const double* src = tmp + (size_t)(e - begin) * NP;
-    for (int k = threadIdx.x; k < NP; k += NT) z[merge_slot(k)] = src[k];
+    {
+      // all of a thread's loads in flight together, then the LDS stores
+      constexpr int L = NP / NT;
+      double v[L];
+#pragma unroll
+      for (int r = 0; r < L; ++r) v[r] = src[threadIdx.x + r * NT];
+#pragma unroll
+      for (int r = 0; r < L; ++r) z[merge_slot(threadIdx.x + r * NT)] = v[r];
+    }
     __syncthreads();
     merge_runs<NP, NT>(z, kSplitChunk);
     double w, lo, hi;
@@ -472,7 +481,11 @@ __global__ __launch_bounds__(NT) void k_seed_bounds(const double* __restrict__ x
                                                     int cap, int update_bound) {
   constexpr int NB = kSeedBins;
   static_assert(E <= 32, "point mask is 32 bits");
+  // E >= 16: the intercepts live in LDS (128 KiB at 16384 points), which
+  // leaves the registers to the levels' counting and searches
+  constexpr bool ZL = E >= 16;
   __shared__ unsigned hist[NB + 1];
+  __shared__ double s_z[ZL ? NT * E : 1];
   __shared__ unsigned s_part[NT / 64];
   const Ctx c = *ctx;
   if (c.status < 0) return;
@@ -484,18 +497,28 @@ __global__ __launch_bounds__(NT) void k_seed_bounds(const double* __restrict__ x
       if (t == 0) res[e] = make_double4(INFINITY, NAN, NAN, NAN);
       continue;
     }
-    // the thread's intercepts z_k, k = t + r NT, stay in registers
-    double z[E];
-    unsigned alive = 0u;  // bit r: z[r] is in the current level's domain
+    // the thread's intercepts z_k, k = t + r NT: in registers, or in LDS
+    double zr[ZL ? 1 : E];
+    auto zat = [&](int r) -> double { return ZL ? s_z[t + r * NT] : zr[r]; };
+    unsigned alive = 0u;  // bit r: z_k is in the current level's domain
     double zmn = INFINITY, zmx = -INFINITY;
+    constexpr int G = E < 8 ? E : 8;  // loads in flight together
 #pragma unroll
-    for (int r = 0; r < E; ++r) {
-      const int k = t + r * NT;
-      z[r] = k < n ? fma(-theta, xy[2 * k], xy[2 * k + 1]) : 0.0;
-      if (k < n) {
-        alive |= 1u << r;
-        zmn = fmin(zmn, z[r]);
-        zmx = fmax(zmx, z[r]);
+    for (int r0 = 0; r0 < E; r0 += G) {
+      double2 p[G];
+#pragma unroll
+      for (int g = 0; g < G; ++g) p[g] = point_clamped(xy, t + (r0 + g) * NT, n);
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        const int r = r0 + g, k = t + r * NT;
+        const double z = k < n ? fma(-theta, p[g].x, p[g].y) : 0.0;
+        if (ZL) s_z[k] = z;
+        else zr[r] = z;
+        if (k < n) {
+          alive |= 1u << r;
+          zmn = fmin(zmn, z);
+          zmx = fmax(zmx, z);
+        }
       }
     }
     block_min_max<NT>(zmn, zmx);
@@ -515,7 +538,7 @@ __global__ __launch_bounds__(NT) void k_seed_bounds(const double* __restrict__ x
         __syncthreads();
 #pragma unroll
         for (int r = 0; r < E; ++r)
-          if ((alive >> r) & 1u) atomicAdd(&hist[bucket(z[r])], 1u);
+          if ((alive >> r) & 1u) atomicAdd(&hist[bucket(zat(r))], 1u);
         __syncthreads();
         prefix_counts<NB, NT>(hist, s_part);
         shortest_run<NB, NT>(hist, (unsigned)c.h, &r0, &len);
@@ -524,7 +547,7 @@ __global__ __launch_bounds__(NT) void k_seed_bounds(const double* __restrict__ x
         const int q0 = last ? r0 : max(r0 - len, 0), q1 = last ? r0 + len : min(r0 + 2 * len, NB);
 #pragma unroll
         for (int r = 0; r < E; ++r) {
-          const int b = bucket(z[r]);
+          const int b = bucket(zat(r));
           if (b < q0 || b >= q1) alive &= ~(1u << r);
         }
         if (!last) {
@@ -537,7 +560,7 @@ __global__ __launch_bounds__(NT) void k_seed_bounds(const double* __restrict__ x
       double mn = INFINITY, mx = -INFINITY;
 #pragma unroll
       for (int r = 0; r < E; ++r)
-        if ((alive >> r) & 1u) { mn = fmin(mn, z[r]); mx = fmax(mx, z[r]); }
+        if ((alive >> r) & 1u) { mn = fmin(mn, zat(r)); mx = fmax(mx, zat(r)); }
       block_min_max<NT>(mn, mx);
       if (len != INT_MAX) {
         lo = mn;

@@ -574,17 +574,21 @@ __global__ __launch_bounds__(NT) void k_bbins(const double* __restrict__ xy, PMe
 // each point's query code in LDS during the insertion (add_point_bins_coded),
 // so the queries read LDS only. Passes go to the class's list from a
 // per-wavefront reservation window.
+// Prefix sums of the NB + 64 bins by one wavefront, in two parts: lane l
+// takes bins l S .. l S + S - 1 (S odd, so the lanes read distinct banks) and
+// leaves their running sums in place; loff[l] gets the sum of the lanes before
+// it. Bin q's prefix sum is then bins[q] + loff[q / S] (wave_bin_sum), which
+// saves the second pass over the bins that adding the offsets would cost.
 template <int NB>
-__device__ __forceinline__ void wave_scan_bins(unsigned* bins) {
+__device__ __forceinline__ void wave_scan_bins(unsigned* bins, unsigned* loff) {
   constexpr int S = (NB + 64) / 64;
   static_assert(S * 64 == NB + 64 && (S & 1), "bins per lane must be odd");
   const int lane = threadIdx.x & 63;
-  unsigned v[S];
   unsigned run = 0;
 #pragma unroll
   for (int r = 0; r < S; ++r) {
     run += bins[lane * S + r];
-    v[r] = run;
+    bins[lane * S + r] = run;
   }
   unsigned x = run;
 #pragma unroll
@@ -592,9 +596,14 @@ __device__ __forceinline__ void wave_scan_bins(unsigned* bins) {
     const unsigned y = __shfl_up(x, m);
     if (lane >= m) x += y;
   }
-  const unsigned off = x - run;
-#pragma unroll
-  for (int r = 0; r < S; ++r) bins[lane * S + r] = v[r] + off;
+  loff[lane] = x - run;
+}
+
+template <int NB>
+__device__ __forceinline__ unsigned wave_bin_sum(const unsigned* bins, const unsigned* loff,
+                                                 unsigned q) {
+  constexpr unsigned S = (NB + 64) / 64;
+  return bins[q] + loff[q / S];
 }
 
 __device__ __forceinline__ void wave_fence() {
@@ -621,11 +630,14 @@ __global__ __launch_bounds__(64 * WAVES) void k_bbins_wave(
   constexpr int kRLog = __builtin_ctz(NB) - 1;
   constexpr int kMaxN = 1024, RMAX = kMaxN / 64;
   constexpr unsigned kWaveReserve = 256;
-  __shared__ unsigned s_bins[WAVES][NBINS + 1];
+  // (rows of whole 16-byte words, for the clearing stores)
+  __shared__ __align__(16) unsigned s_bins[WAVES][(NBINS + 4) & ~3];
   __shared__ unsigned short s_list[WAVES][kMaxN / 2];
   __shared__ unsigned short s_code[WAVES][kMaxN];
+  __shared__ unsigned s_loff[WAVES][64];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   unsigned* bins = s_bins[wv];
+  unsigned* loff = s_loff[wv];
   unsigned short* list = s_list[wv];
   unsigned short* code = s_code[wv];
   unsigned w_next = 0, w_end = 0;  // this wavefront's reserved list slots (uniform)
@@ -678,7 +690,9 @@ __global__ __launch_bounds__(64 * WAVES) void k_bbins_wave(
         }
       }
       wave_fence();  // the previous item's queries are done with the bins and codes
-      for (int q2 = lane; q2 <= NBINS; q2 += 64) bins[q2] = 0u;
+#pragma unroll
+      for (int q2 = lane; q2 < (NBINS + 4) / 4; q2 += 64)
+        reinterpret_cast<uint4*>(bins)[q2] = uint4{};
       wave_fence();
       unsigned all = 0;
 #pragma unroll
@@ -691,7 +705,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_bbins_wave(
 #pragma unroll
       for (int q2 = 32; q2 >= 1; q2 >>= 1) all += __shfl_xor(all, q2);
       wave_fence();
-      wave_scan_bins<NB>(bins);
+      wave_scan_bins<NB>(bins, loff);
       wave_fence();
       const unsigned pall = all;
       const int half = n >> 1;
@@ -702,14 +716,16 @@ __global__ __launch_bounds__(64 * WAVES) void k_bbins_wave(
       for (int o0 = 1; o0 <= P; o0 += 64) {
         const int o = o0 + lane;
         const bool valid = o <= P;
-        const int j = partner(valid ? o : 1);
+        const int j = partner(min(o, P));
         const unsigned cj = code[j];
-        const bool vert = valid && cj == kCodeVertical;
-        const bool force = valid && cj == kCodeFP64;
-        const bool test = valid && cj > kCodePass;
-        const bool pass = test && bins_pass(bins[cj], pall, h);
-        const unsigned long long mf = __ballot(force), mp = __ballot(pass);
-        n_vert += __popcll(__ballot(vert));
+        // read for every lane, with no branch (codes 0..2 read bins 0..2,
+        // which no test uses)
+        const unsigned pb = wave_bin_sum<NB>(bins, loff, cj);
+        const unsigned long long mv = __ballot(valid);
+        const unsigned long long mf = __ballot(cj == kCodeFP64) & mv;
+        const unsigned long long mp = __ballot(bins_pass(pb, pall, h)) & __ballot(cj > kCodePass) & mv;
+        const bool force = (mf >> lane) & 1ull, pass = (mp >> lane) & 1ull;
+        n_vert += __popcll(__ballot(cj == kCodeVertical) & mv);
         n_forced += __popcll(mf);
         n_pass += __popcll(mp);
         if (mf) {

@@ -102,6 +102,13 @@ __device__ __forceinline__ double uniform(double v) {
   return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
+// Point k of n (clamped to n - 1), loaded with no branch around the load, so
+// that the loads of an unrolled loop are all in flight together (a load under
+// a lane mask is waited for on its own).
+__device__ __forceinline__ double2 point_clamped(const double* __restrict__ xy, int k, int n) {
+  return reinterpret_cast<const double2*>(xy)[(unsigned)min(k, n - 1)];
+}
+
 // Order-preserving map of a non-NaN double to u64 (for atomicMin keys).
 __device__ __forceinline__ unsigned long long order_key(double v) {
   const unsigned long long b = (unsigned long long)__double_as_longlong(v);
@@ -287,7 +294,8 @@ __device__ __forceinline__ void window_f64(const double* __restrict__ xy, int n,
 #pragma unroll
     for (int r = 0; r < E; ++r) {
       const int g = (wave * E + r) * 64 + lane;
-      v[r] = g < n ? fma(-theta, xy[2 * g], xy[2 * g + 1]) : INFINITY;
+      const double2 p = point_clamped(xy, g, n);
+      v[r] = g < n ? fma(-theta, p.x, p.y) : INFINITY;
     }
     sort_regs<N2, NT>(v, z);
 #pragma unroll
