@@ -59,6 +59,8 @@ constexpr int kRegChunks = 64;                  // points per lane kept in VGPRs
 constexpr int kPathSingle = 0;                  // tuning-table key of lms_solve
 constexpr int kNetPoints = 2048;                // points the seed network pools over
 
+constexpr int kPrunedBins = 2048;  // bins per anchor of the pruned slope-bin screen
+
 // Per-solve state in device memory.
 struct __align__(16) Ctx {
   int n, h, n_pad, n_seeds;
@@ -80,8 +82,8 @@ struct __align__(16) Ctx {
 };
 
 // Search counters, each spread over kSlots addresses (slot = block index mod
-// kSlots) so that the waves of a launch do not all hit one address; k_finalize
-// adds the slots. They live right after the Ctx in the workspace.
+// kSlots) so that the waves of a launch do not all hit one address;
+// finalize_block adds the slots. They live right after the Ctx in the workspace.
 enum { ST_VERT, ST_SCREENED, ST_BAND, ST_EVALS, ST_DEVALS, ST_FORCED, ST_BIN, kStats };
 constexpr int kSlots = 64;
 struct Stats {
@@ -253,15 +255,98 @@ void launch_prep(hipStream_t s, const double* xy, int n, int h, int n_pad, Ctx* 
                      n_seeds, n_random, seed_key, bins, cap, part, G);
 }
 
+// ---------------------------------------------------------------- finalize
+
+// The canonical minimum over the exact records by (width, theta, z_lo, i, j)
+// and the lms_result, by the NT threads of one workgroup (k_finalize).
+template <int NT>
+__device__ void finalize_block(Ctx* ctx, const uint2* __restrict__ entries,
+                               const double4* __restrict__ res, int cap, lms_result* out) {
+  __shared__ Best sb[NT / 64];
+  __shared__ unsigned long long s_stat[kStats];
+  const Ctx c = *ctx;
+  const int t = threadIdx.x;
+  // the counters' slots: one load per thread (not a chain of kSlots loads)
+  if (t < kStats) s_stat[t] = 0ull;
+  __syncthreads();
+  {
+    const Stats* st = reinterpret_cast<const Stats*>(reinterpret_cast<char*>(ctx) + kStatsOffset);
+    for (int q = t; q < kStats * kSlots; q += NT) {
+      const unsigned long long v = (&st->v[0][0])[q];
+      if (v) atomicAdd(&s_stat[q / kSlots], v);
+    }
+  }
+  Best b = {INFINITY, INFINITY, INFINITY, INFINITY, 0xFFFFFFFFu, 0xFFFFFFFFu};
+  const unsigned end = c.status < 0 ? 0u : min(c.n_entries, (unsigned)cap);
+  for (unsigned e = t; e < end; e += blockDim.x) {
+    const double4 r = res[e];
+    if (!(r.x <= INFINITY) || r.x == INFINITY) continue;  // vertical or NaN
+    const uint2 p = entries[e];
+    const Best q = {r.x, r.y, r.z, r.w, p.x, p.y};
+    if (better(q, b)) b = q;
+  }
+  // the canonical minimum: by wavefront (shuffles), then across wavefronts
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    const Best q = {__shfl_xor(b.w, m), __shfl_xor(b.th, m), __shfl_xor(b.lo, m),
+                    __shfl_xor(b.hi, m), (unsigned)__shfl_xor((int)b.a, m),
+                    (unsigned)__shfl_xor((int)b.b, m)};
+    if (better(q, b)) b = q;
+  }
+  if ((t & 63) == 0) sb[t >> 6] = b;
+  __syncthreads();
+  if (t != 0) return;
+  for (int w = 1; w < NT / 64; ++w)
+    if (better(sb[w], b)) b = sb[w];
+  lms_result o;
+  memset(&o, 0, sizeof(o));
+  o.h = c.h;
+  const unsigned long long pairs = (unsigned long long)c.n * (unsigned long long)(c.n - 1) / 2;
+  int st = c.status;
+  if (st >= 0 && c.overflow) st = LMS_ERR_CAPACITY;
+  if (st >= 0 && c.all_x_equal) st = LMS_OK_DEGENERATE;
+  if (st >= 0 && !(b.w < INFINITY)) st = LMS_ERR_DEVICE;
+  o.status = st;
+  if (st < 0) {
+    o.theta1 = o.theta2 = o.half_width = o.width = o.z_lo = o.z_hi = NAN;
+    o.pair_i = o.pair_j = -1;
+  } else {
+    o.theta1 = b.th;
+    o.theta2 = 0.5 * (b.lo + b.hi);
+    o.width = b.w;
+    o.half_width = 0.5 * b.w;
+    o.z_lo = b.lo;
+    o.z_hi = b.hi;
+    o.pair_i = b.a == kDegenerate ? -1 : (int)b.a;
+    o.pair_j = b.b == kDegenerate ? -1 : (int)b.b;
+  }
+  o.vertical = c.all_x_equal ? pairs : s_stat[ST_VERT];
+  o.candidates = pairs - o.vertical;
+  o.survivors = c.n_entries > (unsigned)c.n_seeds ? c.n_entries - (unsigned)c.n_seeds : 0u;
+  o.point_evals = s_stat[ST_EVALS];
+  o.dir_evals = s_stat[ST_DEVALS];
+  o.band_pass = s_stat[ST_BAND];
+  o.bin_pass = s_stat[ST_BIN];
+  o.bins = c.n_live >= 0 ? (unsigned long long)kPrunedBins : c.bins;
+  *out = o;
+}
+
+constexpr int kFinalNT = 256;
+__global__ __launch_bounds__(kFinalNT) void k_finalize(Ctx* ctx, const uint2* __restrict__ entries,
+                                                       const double4* __restrict__ res, int cap,
+                                                       lms_result* out) {
+  finalize_block<kFinalNT>(ctx, entries, res, cap, out);
+}
+
 // ---------------------------------------------------------------- FP64 window
 
 // One block per entry [begin, min(n_entries, cap)): re-evaluates the pair's
 // slope in FP64. With update_bound, also lowers the width bound.
 template <int N2, int NT>
-__global__ __launch_bounds__(NT) void k_recheck(const double* __restrict__ xy, Ctx* ctx,
-                                                const uint2* __restrict__ entries,
-                                                double4* __restrict__ res, int begin, int cap,
-                                                int update_bound) {
+__device__ __forceinline__ void recheck_body(const double* __restrict__ xy, Ctx* ctx,
+                                             const uint2* __restrict__ entries,
+                                             double4* __restrict__ res, int begin, int cap,
+                                             int update_bound) {
   __shared__ double z[N2];
   const Ctx c = *ctx;
   if (c.status < 0) return;
@@ -286,6 +371,14 @@ __global__ __launch_bounds__(NT) void k_recheck(const double* __restrict__ xy, C
                   (unsigned long long)__double_as_longlong(width_bound(w, theta, c.xabs, c.yabs)));
     }
   }
+}
+
+template <int N2, int NT>
+__global__ __launch_bounds__(NT) void k_recheck(const double* __restrict__ xy, Ctx* ctx,
+                                                const uint2* __restrict__ entries,
+                                                double4* __restrict__ res, int begin, int cap,
+                                                int update_bound) {
+  recheck_body<N2, NT>(xy, ctx, entries, res, begin, cap, update_bound);
 }
 
 // The same re-evaluation split over several workgroups per entry, for
@@ -343,12 +436,12 @@ __global__ __launch_bounds__(NT) void k_sort_chunks(const double* __restrict__ x
 }
 
 template <int NP, int NT>
-__global__ __launch_bounds__(NT) void k_merge_window(const double* __restrict__ xy, Ctx* ctx,
-                                                     const uint2* __restrict__ entries,
-                                                     double4* __restrict__ res, int begin,
-                                                     int cap, int update_bound,
-                                                     const double* __restrict__ tmp, int slots,
-                                                     const double* __restrict__ thetas) {
+__device__ __forceinline__ void merge_window_body(const double* __restrict__ xy, Ctx* ctx,
+                                                  const uint2* __restrict__ entries,
+                                                  double4* __restrict__ res, int begin, int cap,
+                                                  int update_bound,
+                                                  const double* __restrict__ tmp, int slots,
+                                                  const double* __restrict__ thetas) {
   __shared__ double z[NP + NP / 16];  // merge_slot layout (NP for whole sorts)
   const Ctx c = *ctx;
   if (c.status < 0) return;
@@ -394,6 +487,16 @@ __global__ __launch_bounds__(NT) void k_merge_window(const double* __restrict__ 
     window_f64<NP, NT>(xy, c.n, c.h, theta, z, &w, &lo, &hi);
     finish(e, w, theta, lo, hi);
   }
+}
+
+template <int NP, int NT>
+__global__ __launch_bounds__(NT) void k_merge_window(const double* __restrict__ xy, Ctx* ctx,
+                                                     const uint2* __restrict__ entries,
+                                                     double4* __restrict__ res, int begin,
+                                                     int cap, int update_bound,
+                                                     const double* __restrict__ tmp, int slots,
+                                                     const double* __restrict__ thetas) {
+  merge_window_body<NP, NT>(xy, ctx, entries, res, begin, cap, update_bound, tmp, slots, thetas);
 }
 
 // Seed bounds. The screen needs only an upper bound W on the optimal width,
@@ -707,11 +810,10 @@ __device__ void slope_range(const Ctx& c, double W, const double* __restrict__ g
   *hi_out = s_lohi[1];
 }
 
-// The pruned screen spreads a slope range over kPrunedBins bins; a range so
-// wide that their centre would be over 4 times coarser than the full
-// screen's (NB bins, scale kBinMag x-range / y-range) stays with the full
-// screen.
-constexpr int kPrunedBins = 2048;
+// The pruned screen spreads a slope range over kPrunedBins bins (defined
+// with the Ctx); a range so wide that their centre would be over 4 times
+// coarser than the full screen's (NB bins, scale kBinMag x-range / y-range)
+// stays with the full screen.
 __device__ bool narrow_range(const Ctx& c, double lo, double hi) {
   if (!(lo > -INFINITY && hi < INFINITY) || c.bins == 0u) return false;
   const unsigned nb = 1u << (31 - __builtin_clz(c.bins));
@@ -818,21 +920,35 @@ __global__ __launch_bounds__(NT) void k_range(const double* __restrict__ xy, Ctx
   }
   if (!narrow_range(c, lo, hi)) return;
   if (blockIdx.x > 0) {
-    // vertical pairs (i < j, x_i == x_j)
+    // vertical pairs (i < j, x_i == x_j): every one of these workgroups
+    // hashes all x, then takes its share of the hash-ordered positions
     auto hb = [](double x) {
       const unsigned long long u = (unsigned long long)__double_as_longlong(x + 0.0);
       return (int)((u * 0x9E3779B97F4A7C15ull) >> (64 - 12));
     };
     static_assert(kRangeBuckets == 1 << 12, "hash buckets");
     for (int b = t; b < kRangeBuckets; b += NT) s_cur[b] = 0u;
+    int hk[E];  // the thread's points' hash buckets (loads all in flight together)
+    {
+      double xk[E];
+#pragma unroll
+      for (int e = 0; e < E; ++e) xk[e] = xy[2 * min(t + e * NT, n - 1)];
+#pragma unroll
+      for (int e = 0; e < E; ++e) hk[e] = hb(xk[e]);
+    }
     __syncthreads();
-    for (int k = t; k < n; k += NT) atomicAdd(&s_cur[hb(xy[2 * k])], 1u);
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+      if (t + e * NT < n) atomicAdd(&s_cur[hk[e]], 1u);
     __syncthreads();
     bucket_starts<NT>(s_start, s_cur, s_part);
-    for (int k = t; k < n; k += NT) s_xperm[atomicAdd(&s_cur[hb(xy[2 * k])], 1u)] = (unsigned short)k;
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+      if (t + e * NT < n) s_xperm[atomicAdd(&s_cur[hk[e]], 1u)] = (unsigned short)(t + e * NT);
     __syncthreads();
     unsigned long long cnt = 0;
-    for (int p = t; p < n; p += NT) {
+    const int nv = (int)gridDim.x - 1;
+    for (int p = (blockIdx.x - 1) * NT + t; p < n; p += nv * NT) {
       const double xk = xy[2 * s_xperm[p]];
       const int end = (int)s_start[hb(xk) + 1];
       for (int q = p + 1; q < end; ++q) cnt += xy[2 * s_xperm[q]] == xk ? 1u : 0u;
@@ -849,15 +965,20 @@ __global__ __launch_bounds__(NT) void k_range(const double* __restrict__ xy, Ctx
   // only the keys stay in registers (points are read again for the copy)
   double z[E];
   double mn = INFINITY, mx = -INFINITY;
-  const double2* pts = reinterpret_cast<const double2*>(xy);
 #pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const int k = t + e * NT;
-    const double2 pt = k < n ? pts[k] : make_double2(0.0, 0.0);
-    z[e] = fma(-tm, pt.x, pt.y);
-    if (k < n) {
-      mn = fmin(mn, z[e]);
-      mx = fmax(mx, z[e]);
+  for (int e0 = 0; e0 < E; e0 += 8) {  // up to 8 loads in flight together
+    constexpr int G = E < 8 ? E : 8;
+    double2 pt[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) pt[g] = point_clamped(xy, t + (e0 + g) * NT, n);
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const int e = e0 + g, k = t + e * NT;
+      z[e] = k < n ? fma(-tm, pt[g].x, pt[g].y) : 0.0;
+      if (k < n) {
+        mn = fmin(mn, z[e]);
+        mx = fmax(mx, z[e]);
+      }
     }
   }
   block_min_max<NT>(mn, mx);
@@ -912,11 +1033,18 @@ __global__ __launch_bounds__(NT) void k_range(const double* __restrict__ xy, Ctx
   for (int e = 0; e < E; ++e)
     pos[e] = t + e * NT < n ? atomicAdd(&s_cur[bucket(z[e])], 1u) : 0u;
 #pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const int k = t + e * NT;
-    if (k < n) {
-      perm[pos[e]] = (unsigned)k;
-      sxy[pos[e]] = pts[k];
+  for (int e0 = 0; e0 < E; e0 += 8) {  // up to 8 loads in flight together
+    constexpr int G = E < 8 ? E : 8;
+    double2 pt[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) pt[g] = point_clamped(xy, t + (e0 + g) * NT, n);
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const int e = e0 + g, k = t + e * NT;
+      if (k < n) {
+        perm[pos[e]] = (unsigned)k;
+        sxy[pos[e]] = pt[g];
+      }
     }
   }
   __syncthreads();
@@ -930,7 +1058,8 @@ __global__ __launch_bounds__(NT) void k_range(const double* __restrict__ xy, Ctx
 void launch_range(hipStream_t s, int n, int cu, const double* xy, Ctx* ctx,
                   const double* grid_theta, const double4* grid_res, bool refine,
                   unsigned* perm, double2* sxy, uint2* live) {
-  const int grid = 2;  // block 0: buckets and anchors; block 1: vertical pairs
+  // block 0: buckets and anchors; the others: vertical pairs, 1024 positions each
+  const int grid = 1 + std::max(1, (n + 1023) / 1024);
   (void)cu;
   if (n <= 1024)
     hipLaunchKernelGGL((k_range<1024, 1>), dim3(grid), dim3(1024), 0, s, xy, ctx, grid_theta, grid_res, refine, perm, sxy, live);
@@ -1038,7 +1167,7 @@ __device__ __forceinline__ void append_entry(Ctx* ctx, uint2* entries, int cap, 
 // fallback = 1: runs only if the slope-bin screen's list overflowed, which
 // then has already counted and listed the vertical and forced pairs.
 template <int R, bool LDS_PART, int NT>
-__global__ __launch_bounds__(NT, 3) void k_screen(
+__device__ __forceinline__ void screen_exhaustive(
     const double* __restrict__ xy, const float2* __restrict__ xy32, Ctx* ctx,
     uint2* __restrict__ entries, int cap, int G, int ipa, int n_items, int nq, int fallback) {
   extern __shared__ float2 lds[];
@@ -1143,6 +1272,13 @@ __global__ __launch_bounds__(NT, 3) void k_screen(
     stat_add(ctx, ST_DEVALS, 64ull * n_devals);
     stat_add(ctx, ST_FORCED, n_forced);
   }
+}
+
+template <int R, bool LDS_PART, int NT>
+__global__ __launch_bounds__(NT, 3) void k_screen(
+    const double* __restrict__ xy, const float2* __restrict__ xy32, Ctx* ctx,
+    uint2* __restrict__ entries, int cap, int G, int ipa, int n_items, int nq, int fallback) {
+  screen_exhaustive<R, LDS_PART, NT>(xy, xy32, ctx, entries, cap, G, ipa, n_items, nq, fallback);
 }
 
 // ---------------------------------------------------------------- slope-bin screen
@@ -1650,13 +1786,21 @@ __device__ __forceinline__ void screen_list_blocks(const double* __restrict__ xy
 // register chunks, the LDS form past them), so the verdicts are the same.
 constexpr int kListBlock = 16;
 constexpr int kListPerBlock = 4;
+// fb_items > 0: if the list overflowed, the exhaustive screen of fb_items
+// work items (G, ipa as for k_screen) runs here instead (one launch less).
 template <int R, bool LDS_PART, int NT>
 __global__ __launch_bounds__(NT, 3) void k_screen_list(
     const double* __restrict__ xy, const float2* __restrict__ xy32, Ctx* ctx,
-    const uint2* __restrict__ cands, int cand_cap, uint2* __restrict__ entries, int cap, int nq) {
+    const uint2* __restrict__ cands, int cand_cap, uint2* __restrict__ entries, int cap, int nq,
+    int G, int ipa, int fb_items) {
   extern __shared__ float2 lds[];
   const Ctx c = *ctx;
-  if (c.status != LMS_OK || c.all_x_equal || c.cand_overflow) return;
+  if (c.status != LMS_OK || c.all_x_equal) return;
+  if (c.cand_overflow) {
+    if (fb_items > 0)
+      screen_exhaustive<R, LDS_PART, NT>(xy, xy32, ctx, entries, cap, G, ipa, fb_items, nq, 1);
+    return;
+  }
   const int h = c.h, lane = threadIdx.x & 63;
   if (min(c.n_cands, (unsigned)cand_cap) <= (unsigned)kListPerBlock * gridDim.x) {
     screen_list_blocks<R, NT>(xy, xy32, c, ctx, cands, entries, cap,
@@ -1791,77 +1935,6 @@ __global__ __launch_bounds__(NT) void k_screen_pairs(
         lane_f(-fmaf(-th32, pi.x, pi.y), 0), c.h);
     if (lane == 0) verdict[t] = pt.keep;
   }
-}
-
-// ---------------------------------------------------------------- finalize
-
-constexpr int kFinalNT = 256;
-__global__ __launch_bounds__(kFinalNT) void k_finalize(Ctx* ctx, const uint2* __restrict__ entries,
-                                                       const double4* __restrict__ res, int cap,
-                                                       lms_result* out) {
-  __shared__ Best sb[kFinalNT / 64];
-  __shared__ unsigned long long s_stat[kStats];
-  const Ctx c = *ctx;
-  const int t = threadIdx.x;
-  if (t < kStats) {
-    const Stats* st = reinterpret_cast<const Stats*>(reinterpret_cast<char*>(ctx) + kStatsOffset);
-    unsigned long long v = 0;
-    for (int k = 0; k < kSlots; ++k) v += st->v[t][k];
-    s_stat[t] = v;
-  }
-  Best b = {INFINITY, INFINITY, INFINITY, INFINITY, 0xFFFFFFFFu, 0xFFFFFFFFu};
-  const unsigned end = c.status < 0 ? 0u : min(c.n_entries, (unsigned)cap);
-  for (unsigned e = t; e < end; e += blockDim.x) {
-    const double4 r = res[e];
-    if (!(r.x <= INFINITY) || r.x == INFINITY) continue;  // vertical or NaN
-    const uint2 p = entries[e];
-    const Best q = {r.x, r.y, r.z, r.w, p.x, p.y};
-    if (better(q, b)) b = q;
-  }
-  // the canonical minimum: by wavefront (shuffles), then across wavefronts
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) {
-    const Best q = {__shfl_xor(b.w, m), __shfl_xor(b.th, m), __shfl_xor(b.lo, m),
-                    __shfl_xor(b.hi, m), (unsigned)__shfl_xor((int)b.a, m),
-                    (unsigned)__shfl_xor((int)b.b, m)};
-    if (better(q, b)) b = q;
-  }
-  if ((t & 63) == 0) sb[t >> 6] = b;
-  __syncthreads();
-  if (t != 0) return;
-  for (int w = 1; w < kFinalNT / 64; ++w)
-    if (better(sb[w], b)) b = sb[w];
-  lms_result o;
-  memset(&o, 0, sizeof(o));
-  o.h = c.h;
-  const unsigned long long pairs = (unsigned long long)c.n * (unsigned long long)(c.n - 1) / 2;
-  int st = c.status;
-  if (st >= 0 && c.overflow) st = LMS_ERR_CAPACITY;
-  if (st >= 0 && c.all_x_equal) st = LMS_OK_DEGENERATE;
-  if (st >= 0 && !(b.w < INFINITY)) st = LMS_ERR_DEVICE;
-  o.status = st;
-  if (st < 0) {
-    o.theta1 = o.theta2 = o.half_width = o.width = o.z_lo = o.z_hi = NAN;
-    o.pair_i = o.pair_j = -1;
-  } else {
-    o.theta1 = b.th;
-    o.theta2 = 0.5 * (b.lo + b.hi);
-    o.width = b.w;
-    o.half_width = 0.5 * b.w;
-    o.z_lo = b.lo;
-    o.z_hi = b.hi;
-    o.pair_i = b.a == kDegenerate ? -1 : (int)b.a;
-    o.pair_j = b.b == kDegenerate ? -1 : (int)b.b;
-  }
-  o.vertical = c.all_x_equal ? pairs : s_stat[ST_VERT];
-  o.candidates = pairs - o.vertical;
-  o.survivors = c.n_entries > (unsigned)c.n_seeds ? c.n_entries - (unsigned)c.n_seeds : 0u;
-  o.point_evals = s_stat[ST_EVALS];
-  o.dir_evals = s_stat[ST_DEVALS];
-  o.band_pass = s_stat[ST_BAND];
-  o.bin_pass = s_stat[ST_BIN];
-  o.bins = c.n_live >= 0 ? (unsigned long long)kPrunedBins : c.bins;
-  *out = o;
 }
 
 // ---------------------------------------------------------------- host side
@@ -2181,7 +2254,8 @@ hipError_t launch_bins(hipStream_t s, int nb_log2, int cu, int n, const double* 
 
 template <int R, bool L>
 hipError_t launch_list_rl(hipStream_t s, int cu, const double* xy, const float2* xy32, Ctx* ctx,
-                          const uint2* cands, int cand_cap, uint2* e, int cap, int nq) {
+                          const uint2* cands, int cand_cap, uint2* e, int cap, int nq, int G,
+                          int ipa, int fb_items) {
   constexpr int nt = screen_threads<R, L>();
   const size_t shm = L ? (size_t)nq * 64 * sizeof(float2) : 0;
   if (L) {
@@ -2195,18 +2269,23 @@ hipError_t launch_list_rl(hipStream_t s, int cu, const double* xy, const float2*
     (void)hipGetLastError();
     nb = 1;
   }
-  // persistent blocks, but no more than the list could ever occupy one pair each
-  const long long need = ((long long)cand_cap + nt / 64 - 1) / (nt / 64);
+  // persistent blocks, but no more than the list (or the fallback's work
+  // items) could ever occupy one pair each
+  const long long need =
+      ((long long)std::max(cand_cap, fb_items) + nt / 64 - 1) / (nt / 64);
   const int grid = (int)std::max<long long>(1, std::min<long long>((long long)cu * nb, need));
   hipLaunchKernelGGL((k_screen_list<R, L, nt>), dim3(grid), dim3(nt), shm, s, xy, xy32, ctx,
-                     cands, cand_cap, e, cap, nq);
+                     cands, cand_cap, e, cap, nq, G, ipa, fb_items);
   return hipGetLastError();
 }
 
+// fb_items > 0: the exhaustive screen's work items, run by the same launch if
+// the list overflows.
 hipError_t launch_list(hipStream_t s, int R, bool L, int cu, const double* xy, const float2* xy32,
-                       Ctx* ctx, const uint2* cands, int cand_cap, uint2* e, int cap, int nq) {
+                       Ctx* ctx, const uint2* cands, int cand_cap, uint2* e, int cap, int nq,
+                       int G, int ipa, int fb_items) {
 #define LMS_LIST_CASE(RR, LL) \
-  return launch_list_rl<RR, LL>(s, cu, xy, xy32, ctx, cands, cand_cap, e, cap, nq)
+  return launch_list_rl<RR, LL>(s, cu, xy, xy32, ctx, cands, cand_cap, e, cap, nq, G, ipa, fb_items)
   if (L) {
     switch (R) {
       case 1: LMS_LIST_CASE(1, true);
@@ -2512,12 +2591,11 @@ lms_status enqueue_solve(const Setup& S, char* base, hipStream_t s, lms_host::St
                       (int)p.cap, res, n_seed_theta > 0 && !S.no_prune ? rec : nullptr,
                       (int)n_seed_theta, perm, sxy, S.range ? live : nullptr);
     mark();
+    // the exhaustive screen, should the list overflow, runs in the same launch
     if (err == hipSuccess)
       err = launch_list(s, p.R, p.lds, cu, d_xy, xy32, ctx, cands, (int)S.cand_cap, entries,
-                        (int)p.cap, p.nq);
-    if (err == hipSuccess && S.pairs > S.cand_cap)
-      err = launch_screen(s, p.R, p.lds, cu, d_xy, xy32, ctx, entries, (int)p.cap, S.G, S.ipa,
-                          (int)S.n_items, p.nq, 1);
+                        (int)p.cap, p.nq, S.G, S.ipa,
+                        S.pairs > S.cand_cap ? (int)S.n_items : 0);
   } else {
     mark();  // no slope-bin stage
     err = launch_screen(s, p.R, p.lds, cu, d_xy, xy32, ctx, entries, (int)p.cap, S.G, S.ipa,

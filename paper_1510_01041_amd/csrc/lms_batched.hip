@@ -690,7 +690,6 @@ __global__ __launch_bounds__(64 * WAVES) void k_bbins_wave(
         }
       }
       wave_fence();  // the previous item's queries are done with the bins and codes
-#pragma unroll
       for (int q2 = lane; q2 < (NBINS + 4) / 4; q2 += 64)
         reinterpret_cast<uint4*>(bins)[q2] = uint4{};
       wave_fence();
