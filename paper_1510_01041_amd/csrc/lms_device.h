@@ -6,6 +6,7 @@
 
 #include <climits>
 #include <cmath>
+#include <type_traits>
 
 namespace lms_dev {
 
@@ -218,6 +219,40 @@ __device__ void window_f64_rt(const double* __restrict__ xy, int n, int h, int n
   window_scan<NT>(z, n, h, width, z_lo, z_hi);
 }
 
+// Lane l's partner value v[l ^ J] for a partner distance J < 64, with every
+// lane of the wavefront active. J = 1, 2 are quad permutes; J = 4, 8 compose
+// two row permutes (half-row mirror then quad reversal gives l ^ 4, row
+// mirror then half-row mirror gives l ^ 8). These move data within the VALU
+// (DPP) instead of through the LDS crossbar as a permute does (J = 16, 32).
+template <int J>
+__device__ __forceinline__ int xor_lanes_i32(int x) {
+  constexpr int kQuadXor1 = 0xB1, kQuadXor2 = 0x4E, kQuadReverse = 0x1B;
+  constexpr int kRowMirror = 0x140, kRowHalfMirror = 0x141;
+  if constexpr (J == 1) return __builtin_amdgcn_update_dpp(0, x, kQuadXor1, 0xF, 0xF, false);
+  else if constexpr (J == 2) return __builtin_amdgcn_update_dpp(0, x, kQuadXor2, 0xF, 0xF, false);
+  else if constexpr (J == 4)
+    return __builtin_amdgcn_update_dpp(
+        0, __builtin_amdgcn_update_dpp(0, x, kRowHalfMirror, 0xF, 0xF, false), kQuadReverse, 0xF,
+        0xF, false);
+  else if constexpr (J == 8)
+    return __builtin_amdgcn_update_dpp(
+        0, __builtin_amdgcn_update_dpp(0, x, kRowMirror, 0xF, 0xF, false), kRowHalfMirror, 0xF,
+        0xF, false);
+  else return __shfl_xor(x, J);
+}
+
+template <int J>
+__device__ __forceinline__ double xor_lanes(double v) {
+  if constexpr (J <= 8) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)xor_lanes_i32<J>((int)(unsigned)b);
+    const unsigned hi = (unsigned)xor_lanes_i32<J>((int)(unsigned)(b >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+  } else {
+    return __shfl_xor(v, J);
+  }
+}
+
 // Bitonic sort of N2 values held by the NT threads of the block: value
 // g = (wave * E + r) * 64 + lane (E = N2 / NT) sits in v[r] of that lane. A
 // stage with partner distance j < 64 exchanges across lanes (wavefront
@@ -231,19 +266,31 @@ __device__ __forceinline__ void sort_regs(double (&v)[N2 / NT], double* z) {
   static_assert(N2 % NT == 0 && NT % 64 == 0, "block must tile the sort");
   // NT = 64: one wavefront sorts on its own (any wavefront of the block)
   const int t = threadIdx.x, lane = t & 63, wave = NT == 64 ? 0 : t >> 6;
+  // a stage with partner distance J < 64: the exchange across lanes
+  auto lane_stage = [&](auto jc, int k) {
+    constexpr int J = decltype(jc)::value;
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+      const int g = (wave * E + r) * 64 + lane;
+      const double p = xor_lanes<J>(v[r]);
+      const bool up = (g & k) == 0;
+      // pair (a, b) = (lower, upper) index; swap iff (a > b) == up
+      const bool sw = (g & J) == 0 ? ((v[r] > p) == up) : ((p > v[r]) == up);
+      v[r] = sw ? p : v[r];
+    }
+  };
 #pragma unroll
   for (int k = 2; k <= N2; k <<= 1) {
 #pragma unroll
     for (int j = k >> 1; j > 0; j >>= 1) {
       if (j < 64) {
-#pragma unroll
-        for (int r = 0; r < E; ++r) {
-          const int g = (wave * E + r) * 64 + lane;
-          const double p = __shfl_xor(v[r], j);
-          const bool up = (g & k) == 0;
-          // pair (a, b) = (lower, upper) index; swap iff (a > b) == up
-          const bool sw = (g & j) == 0 ? ((v[r] > p) == up) : ((p > v[r]) == up);
-          v[r] = sw ? p : v[r];
+        switch (j) {
+          case 1: lane_stage(std::integral_constant<int, 1>{}, k); break;
+          case 2: lane_stage(std::integral_constant<int, 2>{}, k); break;
+          case 4: lane_stage(std::integral_constant<int, 4>{}, k); break;
+          case 8: lane_stage(std::integral_constant<int, 8>{}, k); break;
+          case 16: lane_stage(std::integral_constant<int, 16>{}, k); break;
+          default: lane_stage(std::integral_constant<int, 32>{}, k); break;
         }
       } else if (j < 64 * E) {
         const int d = j / 64;
