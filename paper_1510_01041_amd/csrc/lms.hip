@@ -118,26 +118,25 @@ __device__ __forceinline__ void prep_merge(PrepPart& a, double mn2, int amn2, do
   a.fin &= fin2;
 }
 
-constexpr int kPrepNT = 256;
-// workgroups of the prep kernels: about 1024 points each, at most 64
-int prep_blocks(int n) { return std::max(1, std::min(64, (n + 1023) / 1024)); }
+constexpr int kPrepNT = 1024;
+// workgroups of the prep kernel: one per 1024 points, at most 16
+int prep_blocks(int n) { return std::max(1, std::min(16, (n + 1023) / 1024)); }
 
-// Partial extremes of each workgroup's points (strided over the grid).
-__global__ __launch_bounds__(kPrepNT) void k_prep_part(const double* __restrict__ xy, int n,
-                                                        PrepPart* __restrict__ part) {
+// Extremes of all n points by the whole workgroup (every workgroup of k_prep
+// computes the same ones: the merge is exact and order-free). Eight loads in
+// flight at a time.
+__device__ __forceinline__ PrepPart prep_extremes(const double* __restrict__ xy, int n) {
   __shared__ PrepPart s_p[kPrepNT / 64];
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   PrepPart a{INFINITY, -INFINITY, INFINITY, -INFINITY, INT_MAX, INT_MAX, 1, 0};
-  const double2* pts = reinterpret_cast<const double2*>(xy);
-  const int stride = gridDim.x * kPrepNT;
-  // four loads in flight before their merges
-  for (int k0 = blockIdx.x * kPrepNT + t; k0 < n; k0 += 4 * stride) {
-    double2 q[4];
+  constexpr int U = 8;
+  for (int k0 = t; k0 < n; k0 += U * kPrepNT) {
+    double2 q[U];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) q[u] = k0 + u * stride < n ? pts[k0 + u * stride] : q[0];
+    for (int u = 0; u < U; ++u) q[u] = point_clamped(xy, k0 + u * kPrepNT, n);
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int k = k0 + u * stride;
+    for (int u = 0; u < U; ++u) {
+      const int k = k0 + u * kPrepNT;
       if (k < n)
         prep_merge(a, q[u].x, k, q[u].x, k, q[u].y, q[u].y,
                    isfinite(q[u].x) && isfinite(q[u].y) ? 1 : 0);
@@ -150,28 +149,23 @@ __global__ __launch_bounds__(kPrepNT) void k_prep_part(const double* __restrict_
                __shfl_xor(a.fin, m));
   if (lane == 0) s_p[wv] = a;
   __syncthreads();
-  if (t == 0) {
-    for (int w = 1; w < kPrepNT / 64; ++w)
-      prep_merge(a, s_p[w].mnx, s_p[w].amn, s_p[w].mxx, s_p[w].amx, s_p[w].mny, s_p[w].mxy,
-                 s_p[w].fin);
-    part[blockIdx.x] = a;
-  }
+  PrepPart b = s_p[0];
+  for (int w = 1; w < kPrepNT / 64; ++w)
+    prep_merge(b, s_p[w].mnx, s_p[w].amn, s_p[w].mxx, s_p[w].amx, s_p[w].mny, s_p[w].mxy,
+               s_p[w].fin);
+  return b;
 }
 
-// Every workgroup merges the G partials (the same values in each), writes
-// its share of the FP32 copy; workgroup 0 also writes the context, zeroes the
-// search counters and writes the seed pairs.
+// Every workgroup finds the extremes of all points (the same in each) and
+// writes its share of the FP32 copy; workgroup 0 also writes the context,
+// zeroes the search counters and writes the seed pairs.
 __global__ __launch_bounds__(kPrepNT) void k_prep(const double* __restrict__ xy, int n, int h,
                                                   int n_pad, Ctx* ctx, float2* __restrict__ xy32,
                                                   uint2* __restrict__ entries, int n_seeds,
                                                   int n_random, unsigned long long seed_key,
-                                                  unsigned bins, int cap,
-                                                  const PrepPart* __restrict__ part, int G) {
+                                                  unsigned bins, int cap) {
   const int t = threadIdx.x;
-  PrepPart a = part[0];
-  for (int g = 1; g < G; ++g)
-    prep_merge(a, part[g].mnx, part[g].amn, part[g].mxx, part[g].amx, part[g].mny, part[g].mxy,
-               part[g].fin);
+  const PrepPart a = prep_extremes(xy, n);
   const bool finite = a.fin != 0;
   const double minx = a.mnx, maxx = a.mxx, miny = a.mny, maxy = a.mxy;
   const double cx = minx + 0.5 * (maxx - minx), cy = miny + 0.5 * (maxy - miny);
@@ -244,15 +238,12 @@ __global__ __launch_bounds__(kPrepNT) void k_prep(const double* __restrict__ xy,
   }
 }
 
-// The two prep kernels; part: at least prep_blocks(n) PrepPart of scratch
-// (the slope range's region, which is written only later).
 void launch_prep(hipStream_t s, const double* xy, int n, int h, int n_pad, Ctx* ctx,
                  float2* xy32, uint2* entries, int n_seeds, int n_random,
-                 unsigned long long seed_key, unsigned bins, int cap, PrepPart* part) {
+                 unsigned long long seed_key, unsigned bins, int cap) {
   const int G = prep_blocks(n);
-  hipLaunchKernelGGL(k_prep_part, dim3(G), dim3(kPrepNT), 0, s, xy, n, part);
   hipLaunchKernelGGL(k_prep, dim3(G), dim3(kPrepNT), 0, s, xy, n, h, n_pad, ctx, xy32, entries,
-                     n_seeds, n_random, seed_key, bins, cap, part, G);
+                     n_seeds, n_random, seed_key, bins, cap);
 }
 
 // ---------------------------------------------------------------- finalize
@@ -2509,7 +2500,7 @@ lms_status enqueue_solve(const Setup& S, char* base, hipStream_t s, lms_host::St
   auto mark = [&]() { if (prof) prof->mark(); };
   const unsigned long long key = 0x5EEDull + (unsigned long long)p.n * 0x100000001ull;
   launch_prep(s, d_xy, p.n, p.h, p.n_pad, ctx, xy32, entries, p.n_seeds, seeds, key,
-              S.use_bins ? bins_count(S.bins_log2) : 0u, (int)p.cap, (PrepPart*)(base + L.range));
+              S.use_bins ? bins_count(S.bins_log2) : 0u, (int)p.cap);
   // the seed network's slope, as the device seed slope
   const double* seed_theta = S.seed_theta;
   if (S.net) {
@@ -2991,8 +2982,7 @@ lms_status lms_screen_pairs(const double* d_xy, int64_t n, int64_t h, double W,
   Ctx* ctx = (Ctx*)(base + L.ctx);
   float2* xy32 = (float2*)(base + L.xy32);
   uint2* entries = (uint2*)(base + L.entries);
-  launch_prep(s, d_xy, p.n, p.h, p.n_pad, ctx, xy32, entries, 1, 0, 0ull, 0u, 0,
-              (PrepPart*)(base + L.range));
+  launch_prep(s, d_xy, p.n, p.h, p.n_pad, ctx, xy32, entries, 1, 0, 0ull, 0u, 0);
   hipError_t err = launch_pairs(s, p.R, p.lds, d_xy, xy32, ctx, W, d_pairs, (int)m, d_verdict, p.nq);
   if (err != hipSuccess) return fail(LMS_ERR_DEVICE, hipGetErrorString(err));
   return LMS_OK;
