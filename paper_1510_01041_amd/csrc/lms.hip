@@ -841,13 +841,13 @@ __global__ __launch_bounds__(64) void k_grid_refine(const Ctx* ctx, double* grid
 //
 // Block 0 sorts the points into kRangeBuckets buckets of equal key width
 // (counting sort: perm lists the points bucket by bucket, sxy holds them in
-// that order) and lists the
-// anchors that are left, with the range [r0, r1) of perm that covers the
-// intervals that can reach h (whole buckets: a superset). Block 1 counts the
-// vertical pairs (equal x), which the pruned screen no longer meets: equal x
-// share a bucket of a hash of their bits (-0 taken as +0), so a counting sort
-// by that hash and compares within each bucket find them all. Without a
-// finite range nothing changes.
+// that order) and lists the anchors that are left, each with the range
+// [r0, r1) of perm that covers the intervals that can reach h (whole
+// buckets: a superset). The other workgroups count the vertical pairs
+// (equal x), which the pruned screen no longer meets: equal x share a bucket
+// of a hash of their bits (-0 taken as +0), so a counting sort by that hash
+// and compares within each bucket find them all. Without a finite range
+// nothing changes.
 constexpr int kRangeBuckets = 4096;
 constexpr int kRangeMinN = 4096, kRefineMinN = 8192;
 
