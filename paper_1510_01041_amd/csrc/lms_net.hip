@@ -260,24 +260,23 @@ __global__ __launch_bounds__(NT) void k_net_forward(const float* __restrict__ P,
 
 // ---------------------------------------------------------------- inference
 
-// Inference spreads a set over many workgroups: the max-pool is order-free,
-// so blocks pool their slices into g with atomicMax on the float bits (every
-// h2 >= 0 after the ReLU, and non-negative floats order as their bit
-// patterns), and the head runs once g is complete. The result equals
-// k_net_forward's bit for bit. A set of more than max_points points is read
-// at max_points evenly strided indices floor(j n / max_points).
 // Inference spreads each set over many workgroups: the frame kernel finds
 // the set's frame (set_frame), the pool kernel gives every workgroup
 // kPoolPoints points (one per lane) and each of its NT / 64 wavefronts a
-// quarter of the channels.
+// quarter of the channels, and the head kernel runs once g is complete. The
+// max-pool is order-free, so the workgroups merge their maxima into g with
+// atomicMax on the float bits (every h2 >= 0 after the ReLU, and non-negative
+// floats order as their bit patterns): the result equals k_net_forward's bit
+// for bit. A set of more than max_points points is read at max_points evenly
+// strided indices floor(j n / max_points).
 constexpr int NTF = 256;
 constexpr int kPoolPoints = 64;
 constexpr int kPoolChannels = H / (NT / 64);
 
 // The point MLP's weights as the pool kernel reads them, written by the
 // frame kernel's block 0 from the FP32 masters: W1 rounded to BF16 (as FP32),
-// b1, b2, then W2 as BF16 pairs (the PointMLP layout). The pool kernel reads
-// them with wave-uniform addresses, so they come through the scalar cache.
+// b1, b2, then W2 as BF16 pairs (the PointMLP layout). Each pool workgroup
+// copies them to LDS once and its wavefronts read them as broadcasts.
 constexpr int WPK_W1 = 0, WPK_B1 = WPK_W1 + 2 * H, WPK_B2 = WPK_B1 + H, WPK_W2 = WPK_B2 + H,
               WPK_WORDS = WPK_W2 + H * H / 2;
 
