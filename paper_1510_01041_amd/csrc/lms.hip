@@ -1381,23 +1381,32 @@ __global__ __launch_bounds__(NT) void k_bins(const double* __restrict__ xy, Ctx*
     // kPF points per step; the loads of the next step's points are issued
     // before this step's work (clamped indices: no branch around a load)
     auto load = [&](int k) { return pts[(unsigned)min(k, n - 1)]; };
+    auto insert = [&](const double2& v, int k) {
+      if (CODED)
+        add_point_bins_coded<kRLog>(bins, v.x - xi, v.y - yi, W, lim, F, th_lim, &list[k], all);
+      else
+        add_point_bins<kRLog>(bins, v.x - xi, v.y - yi, W, lim, F, all);
+    };
     double2 cur[kPF], nxt[kPF];
 #pragma unroll
     for (int q = 0; q < kPF; ++q) cur[q] = load(t + q * NT);
-    for (int k0 = t; k0 < n; k0 += kPF * NT) {
+    int k0 = t;
+    // steps whose next points are all in range: no clamp, no bounds test
+    for (; k0 + (2 * kPF - 1) * NT < n; k0 += kPF * NT) {
+#pragma unroll
+      for (int q = 0; q < kPF; ++q) nxt[q] = pts[(unsigned)(k0 + (kPF + q) * NT)];
+#pragma unroll
+      for (int q = 0; q < kPF; ++q) insert(cur[q], k0 + q * NT);
+#pragma unroll
+      for (int q = 0; q < kPF; ++q) cur[q] = nxt[q];
+    }
+    // the last steps
+    for (; k0 < n; k0 += kPF * NT) {
 #pragma unroll
       for (int q = 0; q < kPF; ++q) nxt[q] = load(k0 + (kPF + q) * NT);
 #pragma unroll
-      for (int q = 0; q < kPF; ++q) {
-        const int k = k0 + q * NT;
-        if (k < n) {
-          if (CODED)
-            add_point_bins_coded<kRLog>(bins, cur[q].x - xi, cur[q].y - yi, W, lim, F, th_lim,
-                                        &list[k], all);
-          else
-            add_point_bins<kRLog>(bins, cur[q].x - xi, cur[q].y - yi, W, lim, F, all);
-        }
-      }
+      for (int q = 0; q < kPF; ++q)
+        if (k0 + q * NT < n) insert(cur[q], k0 + q * NT);
 #pragma unroll
       for (int q = 0; q < kPF; ++q) cur[q] = nxt[q];
     }
