@@ -126,3 +126,15 @@ def test_result_decoding_on_host_buffers():
     rb = lms.parse_batch(torch.stack([raw, raw]))
     assert rb.shape == (2,) and list(rb.bin_pass) == [7, 7]
     assert list(lms.STAGES) == ["prep", "seed", "bins", "screen", "recheck", "finalize"]
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py runs on one GPU only: asked for more it exits at once with a
+    message (before touching a GPU)."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    p = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert p.returncode != 0
+    assert "one GPU" in (p.stdout + p.stderr)
